@@ -1,0 +1,482 @@
+"""Pins of the FP64 oracle against facts other than itself.
+
+Each test checks the oracle against an independent source: another Philox
+implementation (ROCm's rocRAND engine), a library regression (scikit-learn's
+PLS), a Gaussian density (SciPy), closed forms of special cases (a single
+affine model gives linear dynamics; K = 1 gives delta u = eps), statistics, and
+finite differences of the oracle's own forward pass for its adjoint.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import synth
+from synth import DYN_POINTMASS2D, DYN_QUAD12, OBS_SMOOTH, W_TRAJECTORY
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------------ Philox
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND reference")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox_ref")
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1",
+                           os.path.join(HERE, "rocrand_philox_ref.cpp"), "-o", exe])
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_ref):
+    rng = np.random.default_rng(11)
+    n = 4000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64)
+    ctr[:, 1] %= 2**29  # keeps rocRAND's 4*offset inside 64 bits
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64)
+    ctr[:8] = 0
+    key[:4] = 0
+    ctr[8:16] = 2**32 - 1
+    ctr[8:16, 1] = 2**29 - 1
+    lines = "\n".join(" ".join(str(int(v)) for v in list(c) + list(k)) for c, k in zip(ctr, key))
+    out = subprocess.run([rocrand_ref], input=lines + "\n", capture_output=True, text=True,
+                         check=True).stdout.split()
+    ref = np.array(out, dtype=np.uint64).reshape(n, 4)
+    mine = np.stack([oracle.philox(c.astype(np.uint32), k.astype(np.uint32))
+                     for c, k in zip(ctr, key)]).astype(np.uint64)
+    assert np.array_equal(mine, ref)
+
+
+def test_normals_statistics():
+    # 2^17 normals from counters that sweep t and k: mean 0, variance 1, KS vs N(0,1)
+    vals = []
+    for k in range(256):
+        for t in range(128):
+            vals.append(oracle.normals(0xC0FFEE00, oracle.TAG_CTRL, 0, 0, k, 0, t, 4))
+    x = np.concatenate(vals)
+    n = x.size
+    assert abs(x.mean()) < 5.0 / np.sqrt(n)
+    assert abs(x.var() - 1.0) < 5.0 * np.sqrt(2.0 / n)
+    assert stats.kstest(x, "norm").pvalue > 1e-3
+    # the four normals of one block are independent: correlation ~ 0
+    b = x.reshape(-1, 4)
+    c = np.corrcoef(b.T)
+    assert np.all(np.abs(c - np.eye(4)) < 5.0 / np.sqrt(b.shape[0]))
+
+
+def test_streams_are_distinct():
+    a = oracle.normals(1, oracle.TAG_CTRL, 0, 0, 3, 0, 5, 8)
+    assert not np.allclose(a, oracle.normals(1, oracle.TAG_DYN, 0, 0, 3, 0, 5, 8))
+    assert not np.allclose(a, oracle.normals(1, oracle.TAG_CTRL, 1, 0, 3, 0, 5, 8))
+    assert not np.allclose(a, oracle.normals(1, oracle.TAG_CTRL, 0, 1, 3, 0, 5, 8))
+    assert not np.allclose(a, oracle.normals(1, oracle.TAG_CTRL, 0, 0, 3, 1, 5, 8))
+    assert not np.allclose(a, oracle.normals(2, oracle.TAG_CTRL, 0, 0, 3, 0, 5, 8))
+    # normals 4..7 come from the next counter block, not a repeat of 0..3
+    assert not np.allclose(a[:4], a[4:])
+
+
+# ------------------------------------------------------------------ LWPR, Eq. (1)
+
+def _model(seed=0, d=5, L=(7, 4), R=2, **kw):
+    rng = np.random.default_rng(100 + seed)
+    return synth.make_lwpr(rng, d, list(L), R, **kw)
+
+
+def _single(model, j):
+    """The LWPR model made of local model j alone (its mean is y_j(z))."""
+    m = model.copy()
+    sl = slice(j, j + 1)
+    m.n_out = 1
+    m.L_off = np.array([0, 1], np.int64)
+    m.centre, m.metric, m.proj_u = m.centre[sl], m.metric[sl], m.proj_u[sl]
+    m.proj_p = None if m.proj_p is None else m.proj_p[sl]
+    m.beta, m.sigma2 = m.beta[sl], m.sigma2[sl]
+    return m
+
+
+def test_weights_sum_to_one_and_match_gaussian_density():
+    model = _model(1, d=4, L=(6,), R=2)
+    Z = np.random.default_rng(3).uniform(-1, 1, (20, 4))
+    _, _, W = oracle.lwpr_predict(model, Z, weights=True)
+    assert np.allclose(W.sum(1), 1.0, atol=1e-15, rtol=0)
+    # w_j is proportional to a Gaussian density with covariance D_j^{-1},
+    # rescaled by sqrt(det(2 pi D_j^{-1}))
+    for n, z in enumerate(Z):
+        raw = []
+        for j in range(model.Ltot):
+            cov = np.linalg.inv(model.metric[j])
+            pdf = stats.multivariate_normal(mean=model.centre[j], cov=cov).pdf(z)
+            raw.append(pdf * np.sqrt(np.linalg.det(2 * np.pi * cov)))
+        raw = np.array(raw)
+        assert np.allclose(W[n], raw / raw.sum(), rtol=1e-10, atol=1e-300)
+
+
+def test_single_model_is_affine_with_its_own_variance():
+    model = _model(2, d=5, L=(1,), R=3)
+    rng = np.random.default_rng(4)
+    z1, z2 = rng.uniform(-1, 1, (2, 5))
+    for a in (0.0, 0.3, 1.7):
+        mu, v = oracle.lwpr_predict(model, (a * z1 + (1 - a) * z2)[None])
+        mu1, _ = oracle.lwpr_predict(model, z1[None])
+        mu2, _ = oracle.lwpr_predict(model, z2[None])
+        assert np.allclose(mu, a * mu1 + (1 - a) * mu2, rtol=1e-12, atol=1e-12)
+        assert np.allclose(v, model.sigma2[0], rtol=1e-14)
+    # at the centre the prediction is the offset beta_0
+    mu, _ = oracle.lwpr_predict(model, model.centre[:1])
+    assert np.isclose(mu[0, 0], model.beta[0, 0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("R", [1, 3, 5])
+def test_local_model_matches_sklearn_pls(R):
+    from sklearn.cross_decomposition import PLSRegression
+    rng = np.random.default_rng(5 + R)
+    d = 5
+    X = rng.normal(size=(80, d))
+    y = X @ rng.normal(size=d) + 0.3 * np.sin(X[:, 0]) + 0.05 * rng.normal(size=80)
+    pls = PLSRegression(n_components=R, scale=False).fit(X, y)
+    model = _model(0, d=d, L=(1,), R=R)
+    model.centre = pls._x_mean[None].copy()
+    model.proj_u = pls.x_weights_.T[None].copy()
+    model.proj_p = pls.x_loadings_.T[None].copy()
+    model.beta = np.concatenate([[float(np.ravel(pls._y_mean)[0])],
+                                 pls.y_loadings_.ravel()])[None]
+    Zq = rng.normal(size=(25, d))
+    mu, _ = oracle.lwpr_predict(model, Zq)
+    assert np.allclose(mu[:, 0], np.ravel(pls.predict(Zq)), rtol=1e-10, atol=1e-12)
+
+
+def test_full_rank_orthonormal_projections_reduce_to_linear_model():
+    # R = d with orthonormal directions and p = u: deflation changes nothing
+    d = 4
+    model = _model(3, d=d, L=(1,), R=d)
+    Q, _ = np.linalg.qr(np.random.default_rng(9).normal(size=(d, d)))
+    model.proj_u = Q.T[None].copy()
+    model.proj_p = None
+    z = np.random.default_rng(10).uniform(-1, 1, (6, d))
+    mu, _ = oracle.lwpr_predict(model, z)
+    expect = model.beta[0, 0] + ((z - model.centre[0]) @ Q) @ model.beta[0, 1:]
+    assert np.allclose(mu[:, 0], expect, rtol=1e-12, atol=1e-13)
+
+
+def test_equal_weights_and_mixture_moments():
+    # D = 0: every model gets weight 1/L, so the mean is the plain average of
+    # the single-model means and the variance is the mixture variance.
+    model = _model(4, d=3, L=(5,), R=2)
+    model.metric[:] = 0.0
+    z = np.random.default_rng(12).uniform(-1, 1, (3, 3))
+    mu, v, W = oracle.lwpr_predict(model, z, weights=True)
+    assert np.allclose(W, 0.2, atol=1e-15)
+    ys = np.stack([oracle.lwpr_predict(_single(model, j), z)[0][:, 0] for j in range(5)], 1)
+    assert np.allclose(mu[:, 0], ys.mean(1), rtol=1e-13)
+    mix_var = (ys ** 2 + model.sigma2[None]).mean(1) - ys.mean(1) ** 2
+    assert np.allclose(v[:, 0], mix_var, rtol=1e-11)
+
+
+def test_variance_is_the_mixture_variance_monte_carlo():
+    model = _model(5, d=3, L=(6,), R=2)
+    model.sigma2[:] = np.linspace(0.05, 0.4, 6) ** 2
+    z = np.array([[0.2, -0.1, 0.4]])
+    mu, v, W = oracle.lwpr_predict(model, z, weights=True)
+    ys = np.array([oracle.lwpr_predict(_single(model, j), z)[0][0, 0] for j in range(6)])
+    rng = np.random.default_rng(13)
+    n = 2_000_000
+    comp = rng.choice(6, size=n, p=W[0])
+    draws = ys[comp] + np.sqrt(model.sigma2[comp]) * rng.standard_normal(n)
+    assert abs(draws.mean() - mu[0, 0]) < 5 * np.sqrt(v[0, 0] / n)
+    assert abs(draws.var() - v[0, 0]) < 6 * v[0, 0] * np.sqrt(2.0 / n) * 2
+
+
+def test_permuting_models_changes_nothing():
+    model = _model(6, d=4, L=(9,), R=2)
+    perm = np.random.default_rng(1).permutation(9)
+    m2 = model.copy()
+    for name in ("centre", "metric", "proj_u", "beta", "sigma2"):
+        setattr(m2, name, getattr(model, name)[perm].copy())
+    z = np.random.default_rng(2).uniform(-1, 1, (7, 4))
+    a = oracle.lwpr_predict(model, z)
+    b = oracle.lwpr_predict(m2, z)
+    assert np.allclose(a[0], b[0], rtol=1e-13) and np.allclose(a[1], b[1], rtol=1e-13)
+
+
+def test_far_inputs_stay_finite():
+    # the max-shift keeps the normalisation finite where every exp underflows
+    model = _model(7, d=4, L=(5,), R=2)
+    mu, v = oracle.lwpr_predict(model, np.full((1, 4), 40.0))
+    assert np.all(np.isfinite(mu)) and np.all(np.isfinite(v))
+
+
+# ------------------------------------------------------------------ rollout
+
+def _affine_system(prob, model):
+    """With one local model per output the mixture is y = beta0 + b^T (z - c):
+    returns (b [n_out][d], off [n_out]) with the PLS deflation written as the
+    product of rank-one updates  r_{r+1} = (I - p_r u_r^T) r_r."""
+    d, R = model.d, model.R
+    bs, offs = [], []
+    for j in range(model.Ltot):
+        U = model.proj_u[j]
+        P = U if model.proj_p is None else model.proj_p[j]
+        Mx = np.eye(d)
+        b = np.zeros(d)
+        for r in range(R):
+            b += model.beta[j, r + 1] * (U[r] @ Mx)
+            Mx = (np.eye(d) - np.outer(P[r], U[r])) @ Mx
+        bs.append(b)
+        offs.append(model.beta[j, 0] - b @ model.centre[j])
+    return np.array(bs), np.array(offs)
+
+
+def _hand_rollout(prob, model, eps, xi=None, var=None):
+    """Steps x_{t+1} = x_t + dt (E x_t + S a_t), a = b z + off (+ sqrt(var) xi)."""
+    n_x, n_u = prob.n_x, prob.n_u
+    bs, offs = _affine_system(prob, model)
+    npos = 2 if prob.dyn == DYN_POINTMASS2D else 3
+    E = np.zeros((n_x, n_x))
+    S = np.zeros((n_x, model.n_out))
+    for a in range(npos):
+        E[a, npos + a] = 1.0
+        S[npos + a, a] = 1.0
+    if prob.dyn == DYN_QUAD12:
+        for a in range(3):
+            E[6 + a, 9 + a] = 1.0
+            S[9 + a, 3 + a] = 1.0
+    xs = [np.asarray(prob.x0, np.float64)]
+    for t in range(prob.T):
+        z = np.concatenate([xs[-1], prob.u_nom[t] + eps[t]])
+        acc = bs @ z + offs
+        if xi is not None:
+            acc = acc + np.sqrt(var) * xi[t]
+        xs.append(xs[-1] + prob.dt * (E @ xs[-1] + S @ acc))
+    return np.array(xs)
+
+
+def _goal_cost(prob, x):
+    npos = 2 if prob.dyn == DYN_POINTMASS2D else 3
+    c = sum(prob.w_pos[a] * (x[a] - prob.goal[a]) ** 2 for a in range(npos))
+    c += prob.w_vel * np.sum(x[npos:2 * npos] ** 2)
+    if prob.dyn == DYN_QUAD12:
+        c += prob.w_ang * np.sum(x[6:9] ** 2)
+    return c
+
+
+@pytest.mark.parametrize("dyn", [DYN_POINTMASS2D, DYN_QUAD12])
+def test_single_model_zero_noise_is_hand_stepped_linear_dynamics(dyn):
+    prob, model = synth.tiny_problem(1, dyn=dyn, L=1, R=3, K=3, T=7, M=0, n_obs=0)
+    prob.noise_std[:] = 0.0
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    xs = _hand_rollout(prob, model, np.zeros((prob.T, prob.n_u)))
+    for k in range(prob.K):
+        assert np.allclose(X[k, 0], xs, rtol=1e-12, atol=1e-13)
+        expect = [prob.dt * _goal_cost(prob, xs[t + 1]) for t in range(prob.T)]
+        assert np.allclose(cost[k], expect, rtol=1e-12, atol=1e-15)
+
+
+def test_single_model_with_noise_follows_its_perturbations():
+    prob, model = synth.tiny_problem(2, L=1, R=2, K=4, T=6, M=1, n_obs=0)
+    model.sigma2[:] = [0.04, 0.09]
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    eps = oracle.control_noise(prob)
+    for k in range(prob.K):
+        xi = np.stack([oracle.normals(prob.seed, oracle.TAG_DYN, prob.problem_id, 0, k, 0, t, 2)
+                       for t in range(prob.T)])
+        xs = _hand_rollout(prob, model, eps[k], xi=xi, var=model.sigma2)
+        assert np.allclose(X[k, 0], xs, rtol=1e-12, atol=1e-13)
+
+
+def test_zero_model_variance_makes_sub_rollouts_identical():
+    base, model = synth.tiny_problem(3, L=1, R=2, K=4, T=5, M=1)
+    model.sigma2[:] = 0.0
+    costs = []
+    for M in (0, 1, 3):
+        p = base.copy()
+        p.M = M
+        costs.append(oracle.rollout_cost(p, model))
+    assert np.array_equal(costs[0], costs[1]) and np.allclose(costs[1], costs[2], rtol=1e-14)
+
+
+def test_sub_rollout_costs_are_averaged():
+    prob, model = synth.tiny_problem(4, L=3, R=2, K=2, T=5, M=3, n_obs=0)
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    for k in range(prob.K):
+        per_m = [[prob.dt * _goal_cost(prob, X[k, m, t + 1]) for t in range(prob.T)]
+                 for m in range(3)]
+        assert np.allclose(cost[k], np.mean(per_m, 0), rtol=1e-13)
+        assert not np.allclose(X[k, 0], X[k, 1])  # sub-rollouts differ
+
+
+def test_rollout_k_does_not_depend_on_K():
+    prob, model = synth.tiny_problem(5, L=3, R=2, K=9, T=6, M=2)
+    full = oracle.rollout_cost(prob, model)
+    part = oracle.rollout_cost(prob, model, k_range=(4, 7))
+    small = prob.copy()
+    small.K = 5
+    assert np.array_equal(full[4:7], part)
+    assert np.array_equal(full[:5], oracle.rollout_cost(small, model))
+
+
+def test_obstacle_penalty_counts_steps_inside():
+    # constant acceleration along +x through a disc of radius 0.2 at (0, 0)
+    prob, model = synth.tiny_problem(6, L=1, R=1, K=1, T=60, M=0, n_obs=1)
+    prob.noise_std[:] = 0.0
+    prob.x0[:] = [-0.5, 0.0, 0.0, 0.0]
+    prob.obs[:] = [[0.0, 0.0, 0.2]]
+    prob.goal[:] = 0.0
+    model.beta[:] = 0.0
+    model.beta[0, 0] = 2.0      # a_x = 2
+    model.beta[1, 0] = 0.0      # a_y = 0
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    xs = X[0, 0, 1:, 0]
+    inside = (xs ** 2 < 0.04)
+    assert 0 < inside.sum() < prob.T
+    expect = prob.dt * (xs ** 2 + prob.obs_penalty * inside)
+    assert np.allclose(cost[0], expect, rtol=1e-13)
+
+
+# ------------------------------------------------------------------ update, Eq. (2)
+
+def _upd_case(seed=0, K=6, T=5, **kw):
+    prob, model = synth.tiny_problem(seed, K=K, T=T, **kw)
+    cost = np.random.default_rng(seed).uniform(0.0, 2.0, (K, T))
+    return prob, cost
+
+
+def test_update_with_one_sample_returns_its_perturbation():
+    prob, cost = _upd_case(K=1)
+    u = oracle.update(prob, cost)
+    eps = oracle.control_noise(prob)[0]
+    assert np.allclose(u - prob.u_nom, eps, rtol=1e-14, atol=1e-15)
+
+
+def test_update_with_equal_costs_is_the_mean_perturbation():
+    prob, cost = _upd_case(K=7)
+    cost[:] = 0.3
+    u = oracle.update(prob, cost)
+    assert np.allclose(u - prob.u_nom, oracle.control_noise(prob).mean(0), rtol=1e-12, atol=1e-15)
+
+
+def test_update_limits_of_lambda():
+    prob, cost = _upd_case(K=8)
+    eps = oracle.control_noise(prob)
+    S = np.cumsum(cost[:, ::-1], 1)[:, ::-1]     # cost-to-go
+    p = prob.copy()
+    p.lam = 1e-9
+    u = oracle.update(p, cost)
+    best = S.argmin(0)
+    assert np.allclose(u - prob.u_nom, eps[best, np.arange(prob.T)], rtol=1e-12, atol=1e-14)
+    p.lam = 1e12
+    u = oracle.update(p, cost)
+    assert np.allclose(u - prob.u_nom, eps.mean(0), rtol=1e-9, atol=1e-12)
+
+
+def test_update_weights_are_softmax_of_cost_to_go():
+    prob, cost = _upd_case(K=6, T=4)
+    prob.lam = 0.7
+    _, W = oracle.update(prob, cost, weights=True)
+    S = np.array([[cost[k, i:].sum() for i in range(prob.T)] for k in range(prob.K)])
+    from scipy.special import softmax
+    assert np.allclose(W, softmax(-S / prob.lam, axis=0).T, rtol=1e-12)
+    assert np.allclose(W.sum(1), 1.0, atol=1e-15)
+    # invariance to adding a constant to the costs of one step for every k
+    c2 = cost.copy()
+    c2[:, 2] += 123.0
+    assert np.allclose(oracle.update(prob, c2), oracle.update(prob, cost), rtol=1e-12)
+
+
+def test_trajectory_weighting_uses_the_first_row():
+    prob, cost = _upd_case(K=6, T=5)
+    _, Wc = oracle.update(prob, cost, weights=True)
+    p = prob.copy()
+    p.weighting = W_TRAJECTORY
+    _, Wt = oracle.update(p, cost, weights=True)
+    assert np.allclose(Wt, np.repeat(Wc[:1], prob.T, 0), rtol=1e-14)
+
+
+def test_rh_shift_moves_the_plan_and_advances_iter():
+    prob, model = synth.tiny_problem(8, K=2, T=5)
+    x, u, it = oracle.rh_shift(prob, model, prob.x0, prob.u_nom, 3)
+    assert it == 4
+    assert np.array_equal(u[:-1], prob.u_nom[1:]) and np.array_equal(u[-1], prob.u_nom[-1])
+    # velocities change by dt * a, positions by dt * v (v0 = 0)
+    assert np.allclose(x[:2], prob.x0[:2]) and not np.allclose(x[2:], prob.x0[2:])
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _fd(fun, x, idx, h):
+    xp, xm = x.copy(), x.copy()
+    xp.flat[idx] += h
+    xm.flat[idx] -= h
+    return (fun(xp) - fun(xm)) / (2 * h)
+
+
+def _J(prob, model):
+    return float(oracle.rollout_cost(prob, model).sum(1).mean())
+
+
+@pytest.mark.parametrize("dyn,M", [(DYN_POINTMASS2D, 1), (DYN_POINTMASS2D, 2), (DYN_QUAD12, 1),
+                                   (DYN_POINTMASS2D, 0)])
+def test_adjoint_matches_central_differences(dyn, M):
+    prob, model = synth.tiny_problem(9, dyn=dyn, L=3, R=2, K=3, T=6, M=M, n_obs=2,
+                                     obs_kind=OBS_SMOOTH)
+    prob.obs[:, :2] = prob.x0[:2] + 0.15  # close enough for the bump to matter
+    J, gu, gc, gD = oracle.adjoint(prob, model)
+    assert np.isclose(J, _J(prob, model), rtol=1e-13)
+    h = 1e-5
+    rng = np.random.default_rng(0)
+
+    def f_u(u):
+        p = prob.copy()
+        p.u_nom = u
+        return _J(p, model)
+
+    def f_c(c):
+        m = model.copy()
+        m.centre = c
+        return _J(prob, m)
+
+    def f_D(D):
+        m = model.copy()
+        m.metric = D
+        return _J(prob, m)
+
+    for fun, x, g in ((f_u, prob.u_nom, gu), (f_c, model.centre, gc), (f_D, model.metric, gD)):
+        for idx in rng.choice(x.size, size=min(12, x.size), replace=False):
+            fd = _fd(fun, x, idx, h)
+            assert abs(fd - g.flat[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, g.flat[idx])
+
+
+def test_adjoint_linear_quadratic_closed_form():
+    # one affine model per output, mean-only, no obstacles: the state is an
+    # affine function of the nominal controls and J is quadratic in them.
+    prob, model = synth.tiny_problem(10, dyn=DYN_QUAD12, L=1, R=3, K=2, T=5, M=0, n_obs=0)
+    _, gu, _, _ = oracle.adjoint(prob, model)
+    n_x, n_u, T = prob.n_x, prob.n_u, prob.T
+    bs, offs = _affine_system(prob, model)
+    E = np.zeros((n_x, n_x))
+    S = np.zeros((n_x, 6))
+    for a in range(3):
+        E[a, 3 + a] = E[6 + a, 9 + a] = 1.0
+        S[3 + a, a] = S[9 + a, 3 + a] = 1.0
+    Ax = np.eye(n_x) + prob.dt * (E + S @ bs[:, :n_x])
+    Bu = prob.dt * S @ bs[:, n_x:]
+    W = np.diag(np.concatenate([prob.w_pos, np.full(3, prob.w_vel), np.full(3, prob.w_ang),
+                                np.zeros(3)]))
+    g = np.concatenate([prob.goal, np.zeros(9)])
+    eps = oracle.control_noise(prob)
+    grad = np.zeros((T, n_u))
+    for k in range(prob.K):
+        xs = _hand_rollout(prob, model, eps[k])
+        # G_t = d x_t / d u_s  (s < t)
+        for t in range(1, T + 1):
+            r = 2 * prob.dt * W @ (xs[t] - g)
+            for s in range(t):
+                Gts = np.linalg.matrix_power(Ax, t - 1 - s) @ Bu
+                grad[s] += Gts.T @ r
+    grad /= prob.K
+    assert np.allclose(gu, grad, rtol=1e-11, atol=1e-13)
