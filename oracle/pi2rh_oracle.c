@@ -38,7 +38,8 @@
  *   R7  random stream: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  *       key = seed, counter = (t, k, (m << 4) | blk,
  *       tag << 30 | (problem & 0x3FF) << 20 | (iter & 0xFFFFF)),
- *       uniforms ((r >> 8) + 0.5) * 2^-24, Box-Muller pairs (u0,u1), (u2,u3).
+ *       uniforms ((r >> 9) + 0.5) * 2^-23 (exact in single and double
+ *       precision), Box-Muller pairs (u0,u1), (u2,u3).
  *   R8  adjoint: J = (1/(K max(M,1))) sum_{k,m,t} c_{k,m,t} with all noise
  *       held fixed; derivatives w.r.t. u_nom, c_j and every entry of D_j.
  */
@@ -121,7 +122,7 @@ void orc_normals(uint64_t seed, uint32_t tag, uint32_t problem_id, uint32_t iter
     ctr[3] = (tag << 30) | ((problem_id & 0x3FFu) << 20) | (iter & 0xFFFFFu);
     orc_philox(ctr, key, r);
     double u[4];
-    for (int i = 0; i < 4; ++i) u[i] = ((double)(r[i] >> 8) + 0.5) * (1.0 / 16777216.0);
+    for (int i = 0; i < 4; ++i) u[i] = ((double)(r[i] >> 9) + 0.5) * (1.0 / 8388608.0);
     double rad0 = sqrt(-2.0 * log(u[0])), rad1 = sqrt(-2.0 * log(u[2]));
     double nv[4] = {rad0 * cos(two_pi * u[1]), rad0 * sin(two_pi * u[1]),
                     rad1 * cos(two_pi * u[3]), rad1 * sin(two_pi * u[3])};
