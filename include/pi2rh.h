@@ -1,0 +1,211 @@
+/*
+ * pi2rh.h -- C ABI of the MI355X (gfx950) PI^2-RH rollout library.
+ *
+ * Receding-horizon path-integral control with a learned LWPR dynamics model,
+ * after Williams, Rombokas and Daniel, "GPU based Path Integral Control with
+ * Learned Dynamics" (arXiv:1503.00330).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked "dev" are device (HBM) pointers; "host" pointers are read
+ *    only during the call.  Every buffer is owned by the caller.  No entry
+ *    point allocates device or pinned memory; scratch space is the caller's
+ *    workspace `ws` of at least pi_workspace_bytes(...) bytes.
+ *  - All device work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and is asynchronous; results are valid once the stream has been
+ *    synchronised.  Because nothing is allocated and nothing is copied from
+ *    host memory, every call may be captured into a HIP graph.
+ *  - Validation runs before any device work.  On failure a call returns a
+ *    non-zero pi_status, enqueues nothing, writes nothing and records a
+ *    message for pi_last_error().  A failed kernel launch maps to
+ *    PI_ERR_DEVICE.  No C++ exception crosses this interface.
+ *  - `dtype` of a problem and of its model must agree.  PI_F32 computes in
+ *    single precision (the update's normalisation and weighted sums are
+ *    always double); PI_F64 runs the same method entirely in double.
+ *  - Non-finite inputs propagate; nothing is clamped.
+ */
+#ifndef PI2RH_H_
+#define PI2RH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PI_OK = 0,
+  PI_ERR_NULL = 1,        /* a required pointer is NULL                       */
+  PI_ERR_SHAPE = 2,       /* a size is out of range or inconsistent           */
+  PI_ERR_VALUE = 3,       /* a scalar is out of its domain (dt <= 0, ...)     */
+  PI_ERR_DTYPE = 4,       /* unknown dtype or problem/model dtype mismatch    */
+  PI_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than required          */
+  PI_ERR_DEVICE = 6,      /* no usable gfx950 device or a launch failed       */
+  PI_ERR_UNSUPPORTED = 7  /* valid request this build does not implement      */
+} pi_status;
+
+typedef enum { PI_F32 = 0, PI_F64 = 1 } pi_dtype;
+
+/* Dynamics families.  LWPR input is z = [state ; control] (d = n_x + n_u);
+ * outputs are accelerations integrated by explicit Euler.
+ *   POINTMASS2D: state [px,py,vx,vy], control 2, outputs [ax,ay]
+ *   QUAD12:      state [p(3), v(3), euler(3), rates(3)], control 4,
+ *                outputs [linear acc(3), angular acc(3)]                    */
+enum { PI_DYN_POINTMASS2D = 0, PI_DYN_QUAD12 = 1 };
+/* Obstacle term of the state cost q(x) (Sec. 5): an indicator with a fixed
+ * penalty for being strictly inside any disc/vertical cylinder, or the smooth
+ * form penalty * sum_i exp(-decay * (dx_i^2 + dy_i^2)).                     */
+enum { PI_OBS_INDICATOR = 0, PI_OBS_SMOOTH = 1 };
+/* Weighting of the update: Eq. (2) with the cost-to-go S(tau_i) of every
+ * time step (default), or the whole-trajectory cost S(tau_0) for all steps. */
+enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
+/* Kernel variants (autotuner / override). */
+enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2 };
+/* Operations for pi_workspace_bytes. */
+enum { PI_OP_PREDICT = 0, PI_OP_ROLLOUT = 1, PI_OP_UPDATE = 2, PI_OP_ADJOINT = 3,
+       PI_OP_RH_SHIFT = 4 };
+
+enum { PI_MAX_OUT = 8, PI_MAX_U = 4, PI_MAX_D = 16, PI_MAX_R = 16, PI_MAX_OBS = 64 };
+
+/* n_out independent LWPR mixtures over one input z in R^d (Sec. 2, Eq. 1).
+ * Local model j has centre c_j, distance metric D_j, PLS projection
+ * directions u_{j,r}, deflation loadings p_{j,r}, regression coefficients
+ * beta_{j,0..R} and a local noise variance sigma_j^2.  The models of output o
+ * are rows L_off[o] .. L_off[o+1]-1 of every array; Ltot = L_off[n_out].
+ * Arrays are dense row-major in the model's dtype.                           */
+typedef struct {
+  int32_t dtype;                   /* pi_dtype                               */
+  int32_t d, n_out, R;             /* 1<=d<=16, 1<=n_out<=8, 0<=R<=16        */
+  int32_t L_off[PI_MAX_OUT + 1];   /* host; L_off[0]=0, nondecreasing, each output >= 1 model */
+  const void *centre;              /* dev [Ltot][d]                          */
+  const void *metric;              /* dev [Ltot][d][d]  (only the symmetric part matters) */
+  const void *proj_u;              /* dev [Ltot][R][d]                       */
+  const void *proj_p;              /* dev [Ltot][R][d], or NULL for p = u    */
+  const void *beta;                /* dev [Ltot][R+1]                        */
+  const void *sigma2;              /* dev [Ltot], >= 0                       */
+} pi_lwpr;
+
+/* One PI^2-RH instance (Sec. 3.1, 3.2, 5). */
+typedef struct {
+  int32_t dtype;                   /* pi_dtype                               */
+  int32_t dyn;                     /* PI_DYN_*                               */
+  int32_t K, T;                    /* rollouts (>=1) and horizon (>=1)       */
+  int32_t M;                       /* 0: mean-only rollouts; >=1: M sampled sub-rollouts per rollout (Sec. 3.2) */
+  double dt, lambda;               /* step (>0) and temperature (>0)         */
+  double noise_std[PI_MAX_U];      /* control noise std per control (>=0)    */
+  double goal[3], w_pos[3];        /* goal and per-axis position weights     */
+  double w_ang, w_vel;             /* weights of |euler|^2 and |v|^2         */
+  int32_t obs_kind, n_obs;         /* PI_OBS_*, 0 <= n_obs <= 64             */
+  const void *obs;                 /* dev [n_obs][3] = (cx, cy, r), problem dtype; may be NULL if n_obs = 0 */
+  double obs_penalty, obs_decay;   /* indicator penalty / smooth amplitude, smooth decay */
+  int32_t weighting;               /* PI_W_*                                 */
+  uint32_t problem_id;             /* counter word of the random stream      */
+  uint64_t seed;                   /* Philox key                             */
+  int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
+  int32_t tile_samples;            /* samples per workgroup (0 = library's choice) */
+} pi_problem;
+
+/* Bytes of workspace `op` needs for this problem/model (0 is a valid answer;
+ * a NULL ws is accepted then).  Returns (size_t)-1 and sets pi_last_error()
+ * if the arguments are invalid.  For PI_OP_PREDICT, `p` may be NULL and the
+ * query count is taken as p ? p->K : 0 (prediction needs no per-query space). */
+size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m);
+
+/* Eq. (1): for N inputs Z (dev [N][d]) writes the mixture mean and variance
+ * of every output: mean, var dev [N][n_out] in the model's dtype.
+ * `variant` selects the kernel (PI_VARIANT_*).                               */
+pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, void *var,
+                       int32_t variant, void *ws, size_t ws_bytes, void *stream);
+
+/* Sampled rollouts (Sec. 3.1 cost-to-go, Sec. 3.2 sub-rollouts): for every
+ * rollout k and sub-rollout m, from x0 (dev [n_x]) under the controls
+ * u_nom[t] + eps_{k,t} (u_nom dev [T][n_u]; eps = noise_std * N(0,I) from the
+ * random stream, shared by the sub-rollouts of k), the next state is drawn
+ * from the LWPR prediction N(mean, var) (mean only when M = 0) and advanced by
+ * explicit Euler; the step cost is dt * q(x_{t+1}).  Writes
+ *   cost dev [K][T]: cbar_{k,t} = mean over sub-rollouts of the step cost,
+ * so S_k = sum_t cost[k][t].  `iter` (dev, one uint32) is the iteration
+ * counter of the random stream.                                              */
+pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
+                          const void *u_nom, const uint32_t *iter, void *cost, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Path-integral update, Eq. (2): S_{k,i} = sum_{t>=i} cost[k][t] (or S_{k,0}
+ * for PI_W_TRAJECTORY); P_{k,i} = softmax_k(-S_{k,i}/lambda);
+ * u_nom[i] += sum_k P_{k,i} eps_{k,i}, with eps regenerated from the same
+ * stream.  cost dev [K][T] (problem dtype), u_nom dev [T][n_u] in/out,
+ * weights dev [T][K] double (nullable).  Normalisation and sums in double.   */
+pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter, void *u_nom,
+                    void *weights, void *ws, size_t ws_bytes, void *stream);
+
+/* Receding-horizon advance (Sec. 3.1, last paragraph): executes u_nom[0] on
+ * the plant -- a draw from the learned model under its own stream -- writing
+ * the new state to x0 (dev [n_x], in/out), shifts u_nom left by one step
+ * (repeating the last control) and increments *iter (dev).                   */
+pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom,
+                      uint32_t *iter, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the expected rollout cost with the noise held fixed:
+ *   J = (1/(K max(M,1))) sum_{k,m,t} dt q(x_{k,m,t+1}),
+ * writes J (dev, one double) and its gradients w.r.t. the nominal controls
+ * g_u_nom dev [T][n_u], the centres g_centre dev [Ltot][d] and every entry of
+ * the metrics g_metric dev [Ltot][d][d] (problem dtype).  States are
+ * checkpointed every `ckpt_every` steps (0: library's choice, about sqrt(T))
+ * and recomputed segment by segment in the reverse sweep.  The indicator
+ * obstacle term has zero derivative almost everywhere.                      */
+pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0,
+                             const void *u_nom, const uint32_t *iter, int32_t ckpt_every,
+                             void *J, void *g_u_nom, void *g_centre, void *g_metric, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* Batched rollouts of B independent problems in one persistent launch.
+ * Step 1: pi_batched_plan fills a caller-owned HOST buffer (size from
+ * pi_batched_plan_bytes) with per-problem descriptors and a work list of
+ * (problem, sample tile) items ordered by decreasing cost.  Step 2: the
+ * caller copies that buffer to device memory of the same size.  Step 3:
+ * pi_rollout_cost_batched runs every item and writes each problem's
+ * cost[b] (dev [K_b][T_b]) exactly as pi_rollout_cost would.  Per-problem
+ * arrays are given as host arrays of B device pointers.  All problems must be
+ * PI_F32.                                                                    */
+size_t pi_batched_plan_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m);
+pi_status pi_batched_plan(int32_t B, const pi_problem *p, const pi_lwpr *m,
+                          const void *const *x0, const void *const *u_nom,
+                          const uint32_t *const *iter, void *const *cost, void *plan_host,
+                          size_t plan_bytes);
+size_t pi_batched_workspace_bytes(const void *plan_host);
+pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *ws,
+                                  size_t ws_bytes, void *stream);
+
+/* Streams of the counter-based generator (see pi_noise). */
+enum { PI_TAG_CTRL = 0, PI_TAG_DYN = 1, PI_TAG_PLANT = 2 };
+
+/* Raw Philox4x32-10 blocks (Salmon et al., SC'11) as used by every kernel:
+ * ctr dev [N][4] uint32 counters, key = (low word, high word) of `key`,
+ * out dev [N][4] uint32.                                                     */
+pi_status pi_philox4x32_10(const uint32_t *ctr, uint64_t key, uint32_t *out, int64_t N,
+                           void *stream);
+
+/* The random draws of the method exactly as the kernels form them, for
+ * rollouts k0 .. k0+nk-1 and all T steps at iteration *iter:
+ *   PI_TAG_CTRL : eps_{k,t} = noise_std * N(0, I)      out [nk][T][n_u]
+ *   PI_TAG_DYN  : xi_{k,m,t} ~ N(0, I) of sub-rollout m out [nk][T][n_out]
+ *   PI_TAG_PLANT: the plant draw of pi_rh_shift        out [n_out] (k0, nk, m ignored)
+ * The counter of draw (tag, k, m, t) is (t, k, (m << 4) | block,
+ * tag << 30 | (problem_id & 0x3FF) << 20 | (iter & 0xFFFFF)); uniforms are
+ * ((r >> 9) + 0.5) 2^-23 and normals come from Box-Muller pairs.  `out` is in
+ * the problem's dtype.                                                       */
+pi_status pi_noise(const pi_problem *p, int32_t tag, const uint32_t *iter, int32_t k0, int32_t nk,
+                   int32_t m, void *out, void *stream);
+
+/* Thread-local message of the last non-OK status ("" if none). */
+const char *pi_last_error(void);
+
+/* Library version string and the device architecture it was built for. */
+const char *pi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PI2RH_H_ */

@@ -69,6 +69,8 @@ def _load():
         lib.orc_adjoint.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, i32]
         lib.orc_adjoint.restype = C.c_double
         lib.orc_max_threads.restype = i32
+        lib.orc_philox_many.argtypes = [i64, vp, vp, vp]
+        lib.orc_noise_block.argtypes = [u64, u32, u32, u32, i64, i64, u32, i32, i32, vp]
         _lib = lib
     return _lib
 
@@ -144,14 +146,28 @@ def normals(seed, tag, problem_id, it, k, m, t, n):
     return out
 
 
-def control_noise(prob, it=0):
-    """eps_{k,t} = sigma_u * N(0, I): [K][T][n_u] (used by tests)."""
-    eps = np.zeros((prob.K, prob.T, prob.n_u))
-    for k in range(prob.K):
-        for t in range(prob.T):
-            eps[k, t] = np.asarray(prob.noise_std, np.float64) * normals(
-                prob.seed, TAG_CTRL, prob.problem_id, it, k, 0, t, prob.n_u)
-    return eps
+def philox_many(ctr, key):
+    """Philox blocks of counters ctr [N][4] under one key (2 x uint32)."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros_like(c)
+    _load().orc_philox_many(c.shape[0], _ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def noise_block(prob, tag, it=0, k0=0, nk=None, m=0, n=None):
+    """Standard normals of draws (tag, k, m, t): [nk][T][n]."""
+    nk = prob.K - k0 if nk is None else nk
+    n = (prob.n_u if tag == TAG_CTRL else prob.n_out) if n is None else n
+    out = np.zeros((nk, prob.T, n))
+    _load().orc_noise_block(int(prob.seed) & (2**64 - 1), tag, prob.problem_id, it, k0, nk, m,
+                            prob.T, n, _ptr(out))
+    return out
+
+
+def control_noise(prob, it=0, k0=0, nk=None):
+    """eps_{k,t} = sigma_u * N(0, I): [K][T][n_u]."""
+    return np.asarray(prob.noise_std, np.float64)[:prob.n_u] * noise_block(prob, TAG_CTRL, it, k0, nk)
 
 
 def lwpr_predict(model, Z, weights: bool = False, nthreads: int = 0):

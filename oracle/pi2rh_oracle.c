@@ -594,3 +594,17 @@ int32_t orc_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Batch helpers for the tests (loops over the functions above). */
+void orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out) {
+  for (int64_t i = 0; i < n; ++i) orc_philox(ctr + 4 * i, key, out + 4 * i);
+}
+
+/* out[(k - k0)][t][0..n) = normals of draw (tag, k, m, t) for k0 <= k < k0 + nk. */
+void orc_noise_block(uint64_t seed, uint32_t tag, uint32_t problem_id, uint32_t iter, int64_t k0,
+                     int64_t nk, uint32_t m, int32_t T, int32_t n, double *out) {
+  for (int64_t kk = 0; kk < nk; ++kk)
+    for (int32_t t = 0; t < T; ++t)
+      orc_normals(seed, tag, problem_id, iter, (uint32_t)(k0 + kk), m, (uint32_t)t, n,
+                  out + (kk * T + t) * n);
+}

@@ -1,0 +1,397 @@
+// C ABI of the PI^2-RH library: argument validation, workspace layout and
+// kernel dispatch.  Every check runs before the first device call; no entry
+// point allocates memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "internal.hpp"
+
+using namespace pi2rh;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+pi_status fail(pi_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+pi_status ok() {
+  g_err[0] = 0;
+  return PI_OK;
+}
+
+#define PI_TRY(expr)                  \
+  do {                                \
+    pi_status _st = (expr);           \
+    if (_st != PI_OK) return _st;     \
+  } while (0)
+
+int dyn_nx(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 4 : 12; }
+int dyn_nu(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 2 : 4; }
+int dyn_no(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 2 : 6; }
+
+pi_status check_model(const pi_lwpr *m) {
+  if (!m) return fail(PI_ERR_NULL, "model is NULL");
+  if (m->dtype != PI_F32 && m->dtype != PI_F64) return fail(PI_ERR_DTYPE, "unknown model dtype %d", m->dtype);
+  if (m->d < 1 || m->d > PI_MAX_D) return fail(PI_ERR_SHAPE, "d=%d outside [1,%d]", m->d, PI_MAX_D);
+  if (m->n_out < 1 || m->n_out > PI_MAX_OUT)
+    return fail(PI_ERR_SHAPE, "n_out=%d outside [1,%d]", m->n_out, PI_MAX_OUT);
+  if (m->R < 0 || m->R > PI_MAX_R) return fail(PI_ERR_SHAPE, "R=%d outside [0,%d]", m->R, PI_MAX_R);
+  if (m->L_off[0] != 0) return fail(PI_ERR_SHAPE, "L_off[0]=%d must be 0", m->L_off[0]);
+  for (int o = 0; o < m->n_out; ++o)
+    if (m->L_off[o + 1] <= m->L_off[o])
+      return fail(PI_ERR_SHAPE, "output %d has no local models (L_off not increasing)", o);
+  if (m->L_off[m->n_out] > (1 << 26)) return fail(PI_ERR_SHAPE, "too many local models");
+  if (!m->centre || !m->metric || !m->beta || !m->sigma2 || (m->R > 0 && !m->proj_u))
+    return fail(PI_ERR_NULL, "a required model array is NULL");
+  return PI_OK;
+}
+
+pi_status check_problem(const pi_problem *p) {
+  if (!p) return fail(PI_ERR_NULL, "problem is NULL");
+  if (p->dtype != PI_F32 && p->dtype != PI_F64) return fail(PI_ERR_DTYPE, "unknown problem dtype %d", p->dtype);
+  if (p->dyn != PI_DYN_POINTMASS2D && p->dyn != PI_DYN_QUAD12) return fail(PI_ERR_VALUE, "unknown dyn %d", p->dyn);
+  if (p->K < 1) return fail(PI_ERR_SHAPE, "K=%d must be >= 1", p->K);
+  if (p->T < 1) return fail(PI_ERR_SHAPE, "T=%d must be >= 1", p->T);
+  if (p->M < 0 || p->M > (1 << 27)) return fail(PI_ERR_SHAPE, "M=%d outside [0, 2^27]", p->M);
+  if ((int64_t)p->K * (p->M > 0 ? p->M : 1) > (int64_t)INT32_MAX)
+    return fail(PI_ERR_SHAPE, "K*max(M,1) exceeds 2^31-1");
+  if ((int64_t)p->K * p->T > (int64_t)1 << 40) return fail(PI_ERR_SHAPE, "K*T too large");
+  if (!(p->dt > 0) || !isfinite(p->dt)) return fail(PI_ERR_VALUE, "dt must be finite and > 0");
+  if (!(p->lambda > 0) || !isfinite(p->lambda)) return fail(PI_ERR_VALUE, "lambda must be finite and > 0");
+  for (int a = 0; a < dyn_nu(p->dyn); ++a)
+    if (!(p->noise_std[a] >= 0)) return fail(PI_ERR_VALUE, "noise_std[%d] must be >= 0", a);
+  if (p->obs_kind != PI_OBS_INDICATOR && p->obs_kind != PI_OBS_SMOOTH)
+    return fail(PI_ERR_VALUE, "unknown obs_kind %d", p->obs_kind);
+  if (p->n_obs < 0 || p->n_obs > PI_MAX_OBS) return fail(PI_ERR_SHAPE, "n_obs=%d outside [0,%d]", p->n_obs, PI_MAX_OBS);
+  if (p->n_obs > 0 && !p->obs) return fail(PI_ERR_NULL, "obs is NULL with n_obs > 0");
+  if (p->weighting != PI_W_COST_TO_GO && p->weighting != PI_W_TRAJECTORY)
+    return fail(PI_ERR_VALUE, "unknown weighting %d", p->weighting);
+  if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA)
+    return fail(PI_ERR_VALUE, "unknown variant %d", p->variant);
+  if (p->tile_samples < 0 || p->tile_samples > 32)
+    return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,32]", p->tile_samples);
+  return PI_OK;
+}
+
+pi_status check_pair(const pi_problem *p, const pi_lwpr *m) {
+  PI_TRY(check_problem(p));
+  PI_TRY(check_model(m));
+  if (p->dtype != m->dtype) return fail(PI_ERR_DTYPE, "problem dtype %d != model dtype %d", p->dtype, m->dtype);
+  if (m->d != dyn_nx(p->dyn) + dyn_nu(p->dyn))
+    return fail(PI_ERR_SHAPE, "model input d=%d != n_x+n_u=%d", m->d, dyn_nx(p->dyn) + dyn_nu(p->dyn));
+  if (m->n_out != dyn_no(p->dyn))
+    return fail(PI_ERR_SHAPE, "model n_out=%d != %d accelerations", m->n_out, dyn_no(p->dyn));
+  return PI_OK;
+}
+
+// Device check: a gfx950 device must be current.  Cached per device id.
+pi_status check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return fail(PI_ERR_DEVICE, "no HIP device available");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PI_ERR_DEVICE, "hipGetDevice failed");
+  static std::mutex mu;
+  static int known[64] = {0};  // 0 unknown, 1 ok, 2 wrong arch
+  if (dev < 0 || dev >= 64) return fail(PI_ERR_DEVICE, "device id out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (known[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(PI_ERR_DEVICE, "hipGetDeviceProperties failed");
+    known[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    if (known[dev] == 2) return fail(PI_ERR_DEVICE, "device arch %s is not gfx950", prop.gcnArchName);
+  }
+  if (known[dev] == 2) return fail(PI_ERR_DEVICE, "device is not gfx950");
+  return PI_OK;
+}
+
+pi_status launched(hipError_t e, const char *what) {
+  if (e != hipSuccess) return fail(PI_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+ModelArgs model_args(const pi_lwpr *m) {
+  ModelArgs a;
+  a.d = m->d;
+  a.n_out = m->n_out;
+  a.R = m->R;
+  a.Ltot = m->L_off[m->n_out];
+  for (int o = 0; o <= kMaxOut; ++o) a.L_off[o] = o <= m->n_out ? m->L_off[o] : m->L_off[m->n_out];
+  a.centre = m->centre;
+  a.metric = m->metric;
+  a.proj_u = m->proj_u;
+  a.proj_p = m->proj_p;
+  a.beta = m->beta;
+  a.sigma2 = m->sigma2;
+  return a;
+}
+
+template <typename Real>
+ProbDev<Real> prob_dev(const pi_problem *p) {
+  ProbDev<Real> d;
+  d.dyn = p->dyn;
+  d.K = p->K;
+  d.T = p->T;
+  d.M = p->M;
+  d.Ms = p->M > 0 ? p->M : 1;
+  d.n_x = dyn_nx(p->dyn);
+  d.n_u = dyn_nu(p->dyn);
+  d.n_out = dyn_no(p->dyn);
+  d.d = d.n_x + d.n_u;
+  d.dt = (Real)p->dt;
+  for (int a = 0; a < kMaxU; ++a) d.noise_std[a] = (Real)p->noise_std[a];
+  for (int a = 0; a < 3; ++a) {
+    d.goal[a] = (Real)p->goal[a];
+    d.w_pos[a] = (Real)p->w_pos[a];
+  }
+  d.w_ang = (Real)p->w_ang;
+  d.w_vel = (Real)p->w_vel;
+  d.obs_kind = p->obs_kind;
+  d.n_obs = p->n_obs;
+  d.obs = (const Real *)p->obs;
+  d.obs_penalty = (Real)p->obs_penalty;
+  d.obs_decay = (Real)p->obs_decay;
+  d.key0 = (uint32_t)p->seed;
+  d.key1 = (uint32_t)(p->seed >> 32);
+  d.problem_id = p->problem_id;
+  return d;
+}
+
+bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6); }
+
+// Rollout variant and samples per workgroup.
+struct RolloutPlan {
+  bool mfma;
+  int spw;
+};
+
+RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
+  RolloutPlan r;
+  r.mfma = p->variant == PI_VARIANT_MFMA || (p->variant == PI_VARIANT_AUTO && mfma_ok(p->dtype, m->d));
+  if (p->tile_samples > 0) {
+    r.spw = p->tile_samples;
+  } else {
+    // enough workgroups to cover the 256 compute units, at most 32 rows each
+    const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
+    r.spw = n >= 256 * 16 ? 16 : 8;
+  }
+  return r;
+}
+
+size_t fold_bytes(const pi_lwpr *m, bool mfma) {
+  if (mfma) return mfma_layout(m->d, m->n_out, m->L_off).bytes;
+  return direct_bytes(m->dtype, m->d, m->L_off[m->n_out]);
+}
+
+size_t rollout_ws(const pi_problem *p, const pi_lwpr *m) {
+  const RolloutPlan pl = rollout_plan(p, m);
+  size_t b = fold_bytes(m, pl.mfma);
+  const int Ms = p->M > 0 ? p->M : 1;
+  if (Ms > 1) b += align_up((size_t)p->K * Ms * p->T * (p->dtype == PI_F64 ? 8 : 4), 256);
+  return b;
+}
+
+pi_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(PI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given%s", need, ws_bytes,
+                ws ? "" : " (NULL)");
+  return PI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pi_last_error(void) { return g_err; }
+
+const char *pi_version(void) { return "pi2rh 0.1 (gfx950)"; }
+
+size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
+  switch (op) {
+    case PI_OP_PREDICT:
+      if (check_model(m) != PI_OK) return (size_t)-1;
+      return mfma_ok(m->dtype, m->d) ? std::max(fold_bytes(m, true), fold_bytes(m, false))
+                                     : fold_bytes(m, false);
+    case PI_OP_ROLLOUT:
+      if (check_pair(p, m) != PI_OK) return (size_t)-1;
+      return rollout_ws(p, m);
+    case PI_OP_UPDATE:
+      if (check_problem(p) != PI_OK) return (size_t)-1;
+      return update_ws_bytes(p->K, p->T);
+    case PI_OP_RH_SHIFT:
+      if (check_pair(p, m) != PI_OK) return (size_t)-1;
+      return fold_bytes(m, false);
+    case PI_OP_ADJOINT:
+      if (check_pair(p, m) != PI_OK) return (size_t)-1;
+      fail(PI_ERR_UNSUPPORTED, "adjoint workspace: not available in this build");
+      return (size_t)-1;
+  }
+  fail(PI_ERR_VALUE, "unknown op %d", op);
+  return (size_t)-1;
+}
+
+pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, void *var,
+                       int32_t variant, void *ws, size_t ws_bytes, void *stream) {
+  PI_TRY(check_model(m));
+  if (N < 0) return fail(PI_ERR_SHAPE, "N=%lld must be >= 0", (long long)N);
+  if (N > 0 && (!Z || !mean || !var)) return fail(PI_ERR_NULL, "Z, mean and var must be non-NULL");
+  if (variant < PI_VARIANT_AUTO || variant > PI_VARIANT_MFMA) return fail(PI_ERR_VALUE, "unknown variant %d", variant);
+  const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_ok(m->dtype, m->d));
+  if (use_mfma && !mfma_ok(m->dtype, m->d))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA prediction needs float32 and d in {6,16}");
+  PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, use_mfma)));
+  PI_TRY(check_device());
+  if (N == 0) return ok();
+  hipStream_t s = (hipStream_t)stream;
+  const ModelArgs a = model_args(m);
+  hipError_t e;
+  if (use_mfma) {
+    const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+    e = launch_fold_mfma(m->dtype, a, l, ws, s);
+    if (e == hipSuccess) e = launch_predict_mfma(a, l, ws, Z, N, mean, var, s);
+  } else {
+    e = launch_fold_direct(m->dtype, a, ws, s);
+    if (e == hipSuccess) e = launch_predict_direct(m->dtype, a, ws, Z, N, mean, var, s);
+  }
+  return launched(e, "lwpr_predict");
+}
+
+pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
+                          const uint32_t *iter, void *cost, void *ws, size_t ws_bytes, void *stream) {
+  PI_TRY(check_pair(p, m));
+  if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost must be non-NULL");
+  const RolloutPlan pl = rollout_plan(p, m);
+  if (pl.mfma && !mfma_ok(p->dtype, m->d)) return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  PI_TRY(check_ws(ws, ws_bytes, rollout_ws(p, m)));
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  const ModelArgs a = model_args(m);
+  const int Ms = p->M > 0 ? p->M : 1;
+  const size_t fb = fold_bytes(m, pl.mfma);
+  void *sub = Ms > 1 ? (void *)((char *)ws + fb) : cost;
+  hipError_t e;
+  if (p->dtype == PI_F64) {
+    RolloutArgs<double> ra{prob_dev<double>(p), (const double *)x0, (const double *)u_nom, iter, (double *)sub};
+    e = launch_fold_direct(PI_F64, a, ws, s);
+    if (e == hipSuccess) e = launch_rollout_direct(PI_F64, &ra, a, ws, s);
+  } else {
+    RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
+    if (pl.mfma) {
+      const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+      e = launch_fold_mfma(PI_F32, a, l, ws, s);
+      if (e == hipSuccess) e = launch_rollout_mfma(ra, a, l, ws, pl.spw, s);
+    } else {
+      e = launch_fold_direct(PI_F32, a, ws, s);
+      if (e == hipSuccess) e = launch_rollout_direct(PI_F32, &ra, a, ws, s);
+    }
+  }
+  if (e == hipSuccess && Ms > 1) e = launch_subcost_reduce(p->dtype, sub, cost, p->K, Ms, p->T, s);
+  return launched(e, "pi_rollout_cost");
+}
+
+pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter, void *u_nom,
+                    void *weights, void *ws, size_t ws_bytes, void *stream) {
+  PI_TRY(check_problem(p));
+  if (!cost || !iter || !u_nom) return fail(PI_ERR_NULL, "cost, iter and u_nom must be non-NULL");
+  PI_TRY(check_ws(ws, ws_bytes, update_ws_bytes(p->K, p->T)));
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (p->dtype == PI_F64) {
+    const ProbDev<double> d = prob_dev<double>(p);
+    e = launch_update(PI_F64, &d, cost, iter, u_nom, (double *)weights, ws, 1, p->lambda, p->weighting, s);
+  } else {
+    const ProbDev<float> d = prob_dev<float>(p);
+    e = launch_update(PI_F32, &d, cost, iter, u_nom, (double *)weights, ws, 1, p->lambda, p->weighting, s);
+  }
+  return launched(e, "pi_update");
+}
+
+pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom, uint32_t *iter,
+                      void *ws, size_t ws_bytes, void *stream) {
+  PI_TRY(check_pair(p, m));
+  if (!x0 || !u_nom || !iter) return fail(PI_ERR_NULL, "x0, u_nom and iter must be non-NULL");
+  PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, false)));
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  const ModelArgs a = model_args(m);
+  hipError_t e = launch_fold_direct(p->dtype, a, ws, s);
+  if (e == hipSuccess) {
+    if (p->dtype == PI_F64) {
+      const ProbDev<double> d = prob_dev<double>(p);
+      e = launch_rh_shift(PI_F64, &d, a, ws, x0, u_nom, iter, s);
+    } else {
+      const ProbDev<float> d = prob_dev<float>(p);
+      e = launch_rh_shift(PI_F32, &d, a, ws, x0, u_nom, iter, s);
+    }
+  }
+  return launched(e, "pi_rh_shift");
+}
+
+pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *, const void *,
+                             const uint32_t *, int32_t, void *, void *, void *, void *, void *,
+                             size_t, void *) {
+  PI_TRY(check_pair(p, m));
+  return fail(PI_ERR_UNSUPPORTED, "pi_rollout_adjoint: not available in this build");
+}
+
+pi_status pi_philox4x32_10(const uint32_t *ctr, uint64_t key, uint32_t *out, int64_t N,
+                           void *stream) {
+  if (N < 0) return fail(PI_ERR_SHAPE, "N must be >= 0");
+  if (N > 0 && (!ctr || !out)) return fail(PI_ERR_NULL, "ctr and out must be non-NULL");
+  PI_TRY(check_device());
+  return launched(launch_philox(ctr, (uint32_t)key, (uint32_t)(key >> 32), out, N, (hipStream_t)stream),
+                  "pi_philox4x32_10");
+}
+
+pi_status pi_noise(const pi_problem *p, int32_t tag, const uint32_t *iter, int32_t k0, int32_t nk,
+                   int32_t m, void *out, void *stream) {
+  PI_TRY(check_problem(p));
+  if (tag != PI_TAG_CTRL && tag != PI_TAG_DYN && tag != PI_TAG_PLANT) return fail(PI_ERR_VALUE, "unknown tag %d", tag);
+  if (!iter || !out) return fail(PI_ERR_NULL, "iter and out must be non-NULL");
+  if (tag != PI_TAG_PLANT && (k0 < 0 || nk < 0 || m < 0 || (int64_t)k0 + nk > (int64_t)UINT32_MAX))
+    return fail(PI_ERR_SHAPE, "bad rollout range");
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (p->dtype == PI_F64) {
+    const ProbDev<double> d = prob_dev<double>(p);
+    e = launch_noise(PI_F64, &d, tag, iter, k0, nk, m, out, s);
+  } else {
+    const ProbDev<float> d = prob_dev<float>(p);
+    e = launch_noise(PI_F32, &d, tag, iter, k0, nk, m, out, s);
+  }
+  return launched(e, "pi_noise");
+}
+
+size_t pi_batched_plan_bytes(int32_t, const pi_problem *, const pi_lwpr *) {
+  fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
+  return (size_t)-1;
+}
+
+pi_status pi_batched_plan(int32_t, const pi_problem *, const pi_lwpr *, const void *const *,
+                          const void *const *, const uint32_t *const *, void *const *, void *,
+                          size_t) {
+  return fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
+}
+
+size_t pi_batched_workspace_bytes(const void *) { return (size_t)-1; }
+
+pi_status pi_rollout_cost_batched(const void *, const void *, void *, size_t, void *) {
+  return fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
+}
+
+}  // extern "C"

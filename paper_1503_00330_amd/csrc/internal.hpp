@@ -1,0 +1,130 @@
+// Internal interfaces between the C ABI (capi.hip) and the kernel translation
+// units: workspace layouts of the folded LWPR model and the host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pi2rh.h"
+#include "common.hpp"
+
+namespace pi2rh {
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Raw LWPR arrays as the caller handed them (device pointers), by value.
+struct ModelArgs {
+  int d, n_out, R, Ltot;
+  int L_off[kMaxOut + 1];
+  const void *centre, *metric, *proj_u, *proj_p, *beta, *sigma2;
+};
+
+// ---- direct (VALU) folded record, one per local model ----------------------
+// [c (d) | theta (d(d+1)/2, upper triangle row-major, off-diagonal entries
+//  D_ab + D_ba) | b (d) | beta0 | sigma^2]:  q = sum_{a<=b} theta_ab dl_a dl_b,
+// y = beta0 + b . dl with dl = z - c.  b is the PLS chain
+// s_r = u_r . r_r, r_{r+1} = r_r - s_r p_r folded into one linear map.
+inline int direct_stride(int d) { return d + d * (d + 1) / 2 + d + 2; }
+inline size_t direct_bytes(int dtype, int d, int Ltot) {
+  return align_up((size_t)Ltot * direct_stride(d) * (dtype == PI_F64 ? 8 : 4), 256);
+}
+
+// ---- MFMA (FP32) folded model ---------------------------------------------
+// Models of each output are padded to tiles of 16.  For every tile the
+// B-operand fragments of v_mfma_f32_16x16x4f32 for both contractions are
+// stored lane-major:  W[tile][kb4][lane][4],  kblock kb = 4*kb4 + component,
+// B[k][n] with k = 4*kb + lane/16 (feature), n = lane%16 (model of the tile).
+// Features: kblocks [0, KQB): quadratic-form features
+//   {z_a z_b (a<=b), z_a, 1} with coefficients alpha*{theta_ab, h_a, kappa},
+//   h = -(D + D^T) c, kappa = c^T D c, alpha = -log2(e)/2, so the product is
+//   the activation in base-2 units;  kblocks [KQB, KQB+KYB): {z_a, 1} with
+//   coefficients {b_a, beta0 - b.c} giving the local prediction y.
+// Padded model columns get activation -1e30 (zero weight) and y = 0.
+struct MfmaGeom {
+  int D, NP, KQ, KQB, KY, KYB, KB, KB4;
+  __host__ __device__ static MfmaGeom make(int d) {
+    MfmaGeom g;
+    g.D = d;
+    g.NP = d * (d + 1) / 2;
+    g.KQ = g.NP + d + 1;
+    g.KQB = (g.KQ + 3) / 4;
+    g.KY = d + 1;
+    g.KYB = (g.KY + 3) / 4;
+    g.KB = g.KQB + g.KYB;
+    g.KB4 = (g.KB + 3) / 4;
+    return g;
+  }
+};
+
+struct MfmaLayout {
+  int d, n_out, n_tiles;
+  int tile_off[kMaxOut + 1];   // tile range of output o
+  size_t w_floats;             // n_tiles * KB4 * 64 * 4
+  size_t sig_floats;           // n_tiles * 16
+  size_t bytes;
+};
+
+inline MfmaLayout mfma_layout(int d, int n_out, const int *L_off) {
+  MfmaLayout l;
+  l.d = d;
+  l.n_out = n_out;
+  l.tile_off[0] = 0;
+  for (int o = 0; o < n_out; ++o) l.tile_off[o + 1] = l.tile_off[o] + (L_off[o + 1] - L_off[o] + 15) / 16;
+  for (int o = n_out; o < kMaxOut; ++o) l.tile_off[o + 1] = l.tile_off[n_out];
+  l.n_tiles = l.tile_off[n_out];
+  MfmaGeom g = MfmaGeom::make(d);
+  l.w_floats = (size_t)l.n_tiles * g.KB4 * 64 * 4;
+  l.sig_floats = (size_t)l.n_tiles * 16;
+  l.bytes = align_up(l.w_floats * 4, 256) + align_up(l.sig_floats * 4, 256);
+  return l;
+}
+
+// Device view of the folded MFMA model.
+struct MfmaModel {
+  const float4 *W;     // [n_tiles][KB4][64] float4
+  const float *sig2;   // [n_tiles*16]
+  int n_out, n_tiles;
+  int tile_off[kMaxOut + 1];
+};
+
+// ---- launchers (return the first HIP error) --------------------------------
+hipError_t launch_fold_direct(int dtype, const ModelArgs &m, void *rec, hipStream_t s);
+hipError_t launch_fold_mfma(int dtype, const ModelArgs &m, const MfmaLayout &l, void *base,
+                            hipStream_t s);
+
+hipError_t launch_predict_direct(int dtype, const ModelArgs &m, const void *rec, const void *Z,
+                                 int64_t N, void *mean, void *var, hipStream_t s);
+hipError_t launch_predict_mfma(const ModelArgs &m, const MfmaLayout &l, const void *base,
+                               const void *Z, int64_t N, void *mean, void *var, hipStream_t s);
+
+template <typename Real>
+struct RolloutArgs {
+  ProbDev<Real> p;
+  const Real *x0, *u_nom;
+  const uint32_t *iter;
+  Real *cost;       // [K][T] (Ms == 1) or sub-rollout costs [K][Ms][T]
+};
+
+hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
+                                 const void *rec, hipStream_t s);
+hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
+                               const MfmaLayout &l, const void *base, int tile_samples,
+                               hipStream_t s);
+hipError_t launch_subcost_reduce(int dtype, const void *sub, void *cost, int K, int Ms, int T,
+                                 hipStream_t s);
+
+hipError_t launch_update(int dtype, const void *pargs, const void *cost, const uint32_t *iter,
+                         void *u_nom, double *weights, void *ws, int lambda_is_double,
+                         double lambda, int weighting, hipStream_t s);
+size_t update_ws_bytes(int K, int T);
+
+hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, const void *rec,
+                           void *x0, void *u_nom, uint32_t *iter, hipStream_t s);
+
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
+                         hipStream_t s);
+hipError_t launch_noise(int dtype, const void *pargs, int tag, const uint32_t *iter, int k0, int nk,
+                        int m, void *out, hipStream_t s);
+
+}  // namespace pi2rh

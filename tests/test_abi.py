@@ -1,0 +1,155 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects invalid arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1503_00330_amd as pi
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pi2rh.h")
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names) - {"if", "while", "for", "return", "sizeof"})
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rollout_adjoint",
+                 "pi_rh_shift", "pi_rollout_cost_batched", "pi_workspace_bytes", "pi_last_error"):
+        assert must in names
+    assert sorted(pi.EXPORTED) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(pi.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert "gfx950" in pi.version()
+
+
+# Fake, never-dereferenced device addresses: every call below must fail in
+# validation, before any device work.
+FAKE = 0x10000
+
+
+def _structs(dtype=np.float32, dyn=synth.DYN_QUAD12):
+    prob, model = synth.tiny_problem(0, dyn=dyn, L=3, K=4, T=3, dtype=dtype)
+    ps = pi.pi_problem()
+    ps.dtype = pi.PI_F32 if dtype == np.float32 else pi.PI_F64
+    ps.dyn, ps.K, ps.T, ps.M = prob.dyn, prob.K, prob.T, prob.M
+    ps.dt, ps.lambda_ = prob.dt, prob.lam
+    for a in range(prob.n_u):
+        ps.noise_std[a] = prob.noise_std[a]
+    ps.obs_kind, ps.n_obs, ps.obs = 0, prob.n_obs, FAKE
+    ps.obs_penalty, ps.obs_decay = 1000.0, 10.0
+    ps.seed = 1
+    ms = pi.pi_lwpr()
+    ms.dtype = ps.dtype
+    ms.d, ms.n_out, ms.R = model.d, model.n_out, model.R
+    for i in range(pi.PI_MAX_OUT + 1):
+        ms.L_off[i] = int(model.L_off[min(i, model.n_out)])
+    ms.centre = ms.metric = ms.proj_u = ms.beta = ms.sigma2 = FAKE
+    ms.proj_p = None
+    return ps, ms
+
+
+def _rollout(ps, ms, ws=FAKE, ws_bytes=1 << 30, cost=FAKE):
+    lib = pi.load()
+    return lib.pi_rollout_cost(C.byref(ps), C.byref(ms), FAKE, FAKE, FAKE, cost, ws, ws_bytes, None)
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="validation-only test; runs where no GPU is visible")
+class TestValidation:
+    def test_null_pointers(self):
+        ps, ms = _structs()
+        assert _rollout(ps, ms, cost=None) == 1
+        assert "non-NULL" in pi.last_error()
+        lib = pi.load()
+        assert lib.pi_rollout_cost(None, C.byref(ms), FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == 1
+        ms.centre = None
+        assert _rollout(ps, ms) == 1
+
+    @pytest.mark.parametrize("field,value,code", [
+        ("K", 0, 2), ("T", 0, 2), ("M", -1, 2), ("dt", 0.0, 3), ("lambda_", -1.0, 3),
+        ("dyn", 7, 3), ("obs_kind", 5, 3), ("n_obs", 65, 2), ("weighting", 3, 3),
+        ("variant", 9, 3), ("tile_samples", 100, 3), ("dtype", 5, 4)])
+    def test_bad_problem_fields(self, field, value, code):
+        ps, ms = _structs()
+        setattr(ps, field, value)
+        assert _rollout(ps, ms) == code, pi.last_error()
+
+    def test_bad_model(self):
+        ps, ms = _structs()
+        ms.d = 17
+        assert _rollout(ps, ms) == 2
+        ps, ms = _structs()
+        ms.L_off[2] = ms.L_off[1]           # an output with no models
+        assert _rollout(ps, ms) == 2
+        ps, ms = _structs()
+        ms.n_out = 5                          # quadrotor needs 6 accelerations
+        assert _rollout(ps, ms) == 2
+        ps, ms = _structs()
+        ms.dtype = pi.PI_F64                  # problem is float32
+        assert _rollout(ps, ms) == 4
+
+    def test_negative_noise(self):
+        ps, ms = _structs()
+        ps.noise_std[1] = -0.1
+        assert _rollout(ps, ms) == 3
+
+    def test_workspace_too_small(self):
+        ps, ms = _structs()
+        need = pi.load().pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
+        assert 0 < need < (1 << 40)
+        assert _rollout(ps, ms, ws_bytes=need - 1) == 5
+        assert _rollout(ps, ms, ws=None) == 5
+
+    def test_mfma_needs_float32(self):
+        ps, ms = _structs(dtype=np.float64)
+        ps.variant = pi.PI_VARIANT_MFMA
+        assert _rollout(ps, ms) == 7
+
+    def test_valid_call_reports_missing_device(self):
+        ps, ms = _structs()
+        assert _rollout(ps, ms) == 6
+        assert "device" in pi.last_error()
+
+    def test_update_and_predict_validation(self):
+        lib = pi.load()
+        ps, ms = _structs()
+        assert lib.pi_update(C.byref(ps), None, FAKE, FAKE, None, FAKE, 1 << 30, None) == 1
+        assert lib.lwpr_predict(C.byref(ms), FAKE, -1, FAKE, FAKE, 0, FAKE, 1 << 30, None) == 2
+        assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, 4, FAKE, 1 << 30, None) == 3
+        ms.d = 5
+        assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, pi.PI_VARIANT_MFMA, FAKE,
+                                1 << 30, None) == 7
+        assert lib.pi_workspace_bytes(99, C.byref(ps), C.byref(ms)) == C.c_size_t(-1).value
+
+
+def test_workspace_sizes_scale_with_problem():
+    ps, ms = _structs()
+    lib = pi.load()
+    a = lib.pi_workspace_bytes(pi.PI_OP_UPDATE, C.byref(ps), None)
+    ps.K *= 10
+    assert lib.pi_workspace_bytes(pi.PI_OP_UPDATE, C.byref(ps), None) > a
+    ps.M = 3     # sub-rollouts need room for per-sub-rollout costs
+    r3 = lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
+    ps.M = 1
+    assert r3 > lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))

@@ -1,0 +1,244 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (spec figures; readings in the design notes):
+  * LWPR mean/variance: normwise per output, max|g-o| / max|o| <= 1e-5 for
+    FP32 (in-distribution inputs), 1e-11 for FP64;
+  * trajectory costs S_k = sum_t cbar_{k,t}: relative 1e-4 per rollout for
+    FP32 outside indicator flips (flips counted, <= 0.1 %), 1e-10 for FP64;
+  * control updates: 1e-4 absolute (teacher-forced on identical costs),
+    1e-10 for FP64 end to end;
+  * random stream: Philox blocks bit-exact; normals to rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import DYN_POINTMASS2D, DYN_QUAD12, OBS_SMOOTH, W_TRAJECTORY
+
+torch = pytest.importorskip("torch")
+pi = pytest.importorskip("paper_1503_00330_amd")
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = np.float32, np.float64
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    pi.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def nrel(g, o):
+    """Normwise error per output column: max|g - o| / max|o|, worst column."""
+    g, o = np.asarray(g, np.float64).reshape(len(g), -1), np.asarray(o, np.float64).reshape(len(o), -1)
+    return float(np.max(np.abs(g - o).max(0) / np.maximum(np.abs(o).max(0), 1e-300)))
+
+
+def cost_check(g, o, prob, tol):
+    """S_k relative errors outside rows whose obstacle indicator flips."""
+    g, o = np.asarray(g, np.float64), np.asarray(o, np.float64)
+    flip = np.abs(g - o).max(1) > 0.25 * prob.dt * prob.obs_penalty
+    Sg, So = g.sum(1), o.sum(1)
+    r = np.abs(Sg - So) / np.maximum(np.abs(So), 1e-30)
+    ok = ~flip
+    assert flip.sum() <= max(1, int(0.001 * len(g))), "indicator flips in %d rows" % flip.sum()
+    assert r[ok].max(initial=0.0) <= tol, (r[ok].max(), np.argmax(np.where(ok, r, 0)))
+    return r[ok].max(initial=0.0), int(flip.sum())
+
+
+# ------------------------------------------------------------- random stream
+
+def test_philox_blocks_bit_exact():
+    rng = np.random.default_rng(1)
+    n = 1 << 20
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = 0x0123456789ABCDEF
+    g = pi.philox4x32_10(torch.from_numpy(ctr.view(np.int32)).cuda(), key)
+    g = g.cpu().numpy().view(np.uint32)
+    ref = oracle.philox_many(ctr, [key & 0xFFFFFFFF, key >> 32])
+    assert np.array_equal(g, ref)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("tag", [oracle.TAG_CTRL, oracle.TAG_DYN])
+def test_noise_matches_oracle(dtype, tag):
+    prob, _ = synth.tiny_problem(3, dyn=DYN_QUAD12, K=300, T=11, dtype=dtype)
+    dp = pi.DeviceProblem(prob)
+    dp.iter.fill_(7)
+    m = 2 if tag == oracle.TAG_DYN else 0
+    g = pi.noise(dp, tag, m=m).cpu().numpy()
+    o = oracle.noise_block(prob, tag, it=7, m=m)
+    if tag == oracle.TAG_CTRL:
+        o = o * np.asarray(prob.noise_std, np.float64)
+    tol = 1e-13 if dtype == F64 else 4e-6
+    assert np.max(np.abs(g - o)) <= tol
+
+
+# ------------------------------------------------------------ LWPR, Eq. (1)
+
+def _models():
+    rng = np.random.default_rng(77)
+    return {
+        "cfg1": synth.config(1)[1].astype(F64),
+        "ragged16": synth.make_lwpr(rng, 16, [1, 17, 33, 5, 16, 40], 4),
+        "pm6": synth.make_lwpr(rng, 6, [16, 16], 2),
+        "d3": synth.make_lwpr(rng, 3, [7, 2], 2, loadings_equal_u=False),
+    }
+
+
+MODELS = _models()
+PRED_CASES = [("cfg1", pi.PI_VARIANT_MFMA, F32), ("cfg1", pi.PI_VARIANT_DIRECT, F32),
+              ("cfg1", pi.PI_VARIANT_DIRECT, F64), ("ragged16", pi.PI_VARIANT_MFMA, F32),
+              ("ragged16", pi.PI_VARIANT_DIRECT, F64), ("pm6", pi.PI_VARIANT_MFMA, F32),
+              ("pm6", pi.PI_VARIANT_DIRECT, F64), ("d3", pi.PI_VARIANT_DIRECT, F32),
+              ("d3", pi.PI_VARIANT_DIRECT, F64)]
+
+
+@pytest.mark.parametrize("name,variant,dtype", PRED_CASES)
+def test_lwpr_predict_parity(name, variant, dtype):
+    model = MODELS[name].astype(dtype)
+    N = 16 * 37 + 5
+    Z = np.random.default_rng(5).uniform(-1, 1, (N, model.d)).astype(dtype)
+    dm = pi.DeviceModel(model)
+    mean, var = pi.lwpr_predict(dm, torch.from_numpy(Z).cuda(), variant)
+    om, ov = oracle.lwpr_predict(model, Z)
+    tol = 1e-11 if dtype == F64 else 1e-5
+    assert nrel(mean.cpu().numpy(), om) <= tol
+    assert nrel(var.cpu().numpy(), ov) <= tol
+    assert np.all(var.cpu().numpy() > 0)
+
+
+def test_lwpr_predict_far_inputs_reported():
+    # outside the model's support the FP32 weights lose relative accuracy
+    # (error grows with q); finite and bounded is what is required there
+    model = MODELS["cfg1"].astype(F32)
+    Z = np.random.default_rng(6).uniform(-4, 4, (97, 16)).astype(F32)
+    mean, var = pi.lwpr_predict(pi.DeviceModel(model), torch.from_numpy(Z).cuda())
+    om, ov = oracle.lwpr_predict(model, Z)
+    e = nrel(mean.cpu().numpy(), om)
+    print("far-input normwise error %.2e" % e)
+    assert np.all(np.isfinite(mean.cpu().numpy())) and e < 1e-3
+
+
+def test_lwpr_predict_empty_and_single():
+    model = MODELS["pm6"].astype(F32)
+    dm = pi.DeviceModel(model)
+    z = torch.zeros((0, 6), device="cuda")
+    m, v = pi.lwpr_predict(dm, z)
+    assert m.shape == (0, 2)
+    z1 = np.full((1, 6), 0.25, F32)
+    m, v = pi.lwpr_predict(dm, torch.from_numpy(z1).cuda())
+    om, ov = oracle.lwpr_predict(model, z1)
+    assert nrel(m.cpu().numpy(), om) <= 1e-5
+
+
+# ----------------------------------------------------------------- rollouts
+
+def test_rollout_fp64_config0_strict():
+    prob, model, _ = synth.config(0)
+    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    r, flips = cost_check(cost, ref, prob, 1e-10)
+    assert flips == 0
+    assert np.max(np.abs(cost - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_MFMA, pi.PI_VARIANT_DIRECT])
+@pytest.mark.parametrize("M", [0, 1, 3])
+@pytest.mark.parametrize("spw", [0, 16, 32])
+def test_rollout_fp32_ragged(variant, M, spw):
+    if variant == pi.PI_VARIANT_DIRECT and spw:
+        pytest.skip("tile size applies to the MFMA kernel")
+    prob, model = synth.tiny_problem(11, dyn=DYN_QUAD12, L=[20, 17, 33, 16, 1, 40], R=4, K=37, T=9,
+                                     M=M, dtype=F32, n_obs=6)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    cost_check(cost, ref, prob, 1e-4)
+    assert nrel(cost, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_rollout_pointmass(dtype):
+    prob, model = synth.tiny_problem(12, dyn=DYN_POINTMASS2D, L=[9, 23], R=2, K=70, T=15, M=2,
+                                     dtype=dtype, n_obs=3, obs_kind=OBS_SMOOTH)
+    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    cost_check(cost, ref, prob, 1e-10 if dtype == F64 else 1e-4)
+
+
+def test_rollout_edge_sizes():
+    for K, T in ((1, 1), (1, 5), (17, 1)):
+        prob, model = synth.tiny_problem(13, dyn=DYN_QUAD12, L=3, R=2, K=K, T=T, M=1, dtype=F32)
+        cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+        ref = oracle.rollout_cost(prob, model)
+        assert cost.shape == (K, T)
+        cost_check(cost, ref, prob, 1e-4)
+
+
+def test_rollout_config1_full_launch_sampled_rows():
+    prob, model, _ = synth.config(1)
+    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    assert cost.shape == (2048, 100) and np.all(np.isfinite(cost))
+    rows = list(range(0, 16)) + list(range(1016, 1032)) + list(range(2032, 2048))
+    ref = np.concatenate([oracle.rollout_cost(prob, model, k_range=(a, a + 16))
+                          for a in (0, 1016, 2032)])
+    r, flips = cost_check(cost[rows], ref, prob, 1e-4)
+    print("config 1 sampled rows: max S rel %.2e, flips %d" % (r, flips))
+
+
+def test_rollout_bitwise_repeatable():
+    prob, model, _ = synth.config(1, K=512, T=20)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    a = pi.rollout_cost(dp, dm).clone()
+    b = pi.rollout_cost(dp, dm).clone()
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------- update
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("weighting", [0, W_TRAJECTORY])
+@pytest.mark.parametrize("K", [1, 333, 4100])
+def test_update_teacher_forced(dtype, weighting, K):
+    prob, _ = synth.tiny_problem(14, dyn=DYN_QUAD12, K=K, T=23, dtype=dtype)
+    prob.weighting = weighting
+    prob.lam = 0.3
+    cost = np.random.default_rng(K).uniform(0.0, 1.0, (K, prob.T)).astype(dtype)
+    dp = pi.DeviceProblem(prob)
+    dp.iter.fill_(4)
+    u, W = pi.update(dp, torch.from_numpy(cost).cuda(), weights=True)
+    ou, oW = oracle.update(prob, cost, it=4, weights=True)
+    tol = 1e-12 if dtype == F64 else 1e-4
+    assert np.max(np.abs(u.cpu().numpy() - ou)) <= tol
+    assert np.max(np.abs(W.cpu().numpy() - oW)) <= 1e-12
+
+
+def test_iteration_fp64_end_to_end():
+    prob, model, _ = synth.config(0)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    pi.iteration(dp, dm)
+    _, ou = oracle.iteration(prob, model)
+    assert np.max(np.abs(dp.u_nom.cpu().numpy() - ou)) <= 1e-10
+
+
+# ------------------------------------------------------------------ RH shift
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("dyn", [DYN_POINTMASS2D, DYN_QUAD12])
+def test_rh_shift_matches_oracle(dtype, dyn):
+    prob, model = synth.tiny_problem(15, dyn=dyn, L=[30, 40, 7, 9, 12, 3][:(2 if dyn == 0 else 6)],
+                                     R=2, K=4, T=300, dtype=dtype)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    dp.iter.fill_(5)
+    pi.rh_shift(dp, dm)
+    ox, ou, oit = oracle.rh_shift(prob, model, prob.x0, prob.u_nom, 5)
+    assert int(dp.iter.item()) == oit == 6
+    assert np.array_equal(dp.u_nom.cpu().numpy(), ou.astype(dtype))
+    tol = 1e-12 if dtype == F64 else 1e-6
+    assert np.max(np.abs(dp.x0.cpu().numpy() - ox)) <= tol * max(1.0, np.abs(ox).max())
