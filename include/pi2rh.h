@@ -103,7 +103,8 @@ typedef struct {
   uint32_t problem_id;             /* counter word of the random stream      */
   uint64_t seed;                   /* Philox key                             */
   int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
-  int32_t tile_samples;            /* samples per workgroup (0 = library's choice) */
+  int32_t tile_samples;            /* samples per workgroup, <= 32 (0 = library's choice) */
+  int32_t tile_waves;              /* waves per workgroup, 4 or 8 (0 = library's choice) */
 } pi_problem;
 
 /* Bytes of workspace `op` needs for this problem/model (0 is a valid answer;

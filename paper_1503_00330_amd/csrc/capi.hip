@@ -81,6 +81,8 @@ pi_status check_problem(const pi_problem *p) {
     return fail(PI_ERR_VALUE, "unknown variant %d", p->variant);
   if (p->tile_samples < 0 || p->tile_samples > 32)
     return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,32]", p->tile_samples);
+  if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8)
+    return fail(PI_ERR_VALUE, "tile_waves=%d must be 0, 4 or 8", p->tile_waves);
   return PI_OK;
 }
 
@@ -175,7 +177,7 @@ bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6); 
 // Rollout variant and samples per workgroup.
 struct RolloutPlan {
   bool mfma;
-  int spw;
+  int spw, waves;
 };
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
@@ -188,6 +190,7 @@ RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
     const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
     r.spw = n >= 256 * 16 ? 16 : 8;
   }
+  r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
   return r;
 }
 
@@ -233,7 +236,7 @@ size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
       return update_ws_bytes(p->K, p->T);
     case PI_OP_RH_SHIFT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
-      return fold_bytes(m, false);
+      return fold_bytes(m, false) + shift_partial_bytes(model_args(m), m->dtype);
     case PI_OP_ADJOINT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
       fail(PI_ERR_UNSUPPORTED, "adjoint workspace: not available in this build");
@@ -292,7 +295,7 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
     if (pl.mfma) {
       const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
       e = launch_fold_mfma(PI_F32, a, l, ws, s);
-      if (e == hipSuccess) e = launch_rollout_mfma(ra, a, l, ws, pl.spw, s);
+      if (e == hipSuccess) e = launch_rollout_mfma(ra, a, l, ws, pl.spw, pl.waves, s);
     } else {
       e = launch_fold_direct(PI_F32, a, ws, s);
       if (e == hipSuccess) e = launch_rollout_direct(PI_F32, &ra, a, ws, s);
@@ -324,18 +327,20 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
                       void *ws, size_t ws_bytes, void *stream) {
   PI_TRY(check_pair(p, m));
   if (!x0 || !u_nom || !iter) return fail(PI_ERR_NULL, "x0, u_nom and iter must be non-NULL");
-  PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, false)));
+  const ModelArgs a = model_args(m);
+  const size_t fb = fold_bytes(m, false);
+  PI_TRY(check_ws(ws, ws_bytes, fb + shift_partial_bytes(a, m->dtype)));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
-  const ModelArgs a = model_args(m);
+  void *part = (char *)ws + fb;
   hipError_t e = launch_fold_direct(p->dtype, a, ws, s);
   if (e == hipSuccess) {
     if (p->dtype == PI_F64) {
       const ProbDev<double> d = prob_dev<double>(p);
-      e = launch_rh_shift(PI_F64, &d, a, ws, x0, u_nom, iter, s);
+      e = launch_rh_shift(PI_F64, &d, a, ws, part, x0, u_nom, iter, s);
     } else {
       const ProbDev<float> d = prob_dev<float>(p);
-      e = launch_rh_shift(PI_F32, &d, a, ws, x0, u_nom, iter, s);
+      e = launch_rh_shift(PI_F32, &d, a, ws, part, x0, u_nom, iter, s);
     }
   }
   return launched(e, "pi_rh_shift");

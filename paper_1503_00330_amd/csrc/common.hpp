@@ -234,6 +234,11 @@ __device__ __forceinline__ MixStat<Real> mix_merge(const MixStat<Real> &a, const
   return r;
 }
 
+// e / Z for the running mean: exact division in double, the hardware
+// reciprocal (1 ulp) in float.
+__device__ __forceinline__ float ratio(float e, float Z) { return e * __builtin_amdgcn_rcpf(Z); }
+__device__ __forceinline__ double ratio(double e, double Z) { return e / Z; }
+
 // Adds one local model (activation act, prediction y, noise variance s2).
 // One exponential per model: the larger of (m, act) becomes the new shift.
 template <bool Base2, typename Real>
@@ -244,7 +249,7 @@ __device__ __forceinline__ void mix_add(MixStat<Real> &s, Real act, Real y, Real
   s.m = up ? act : s.m;
   const Real Zn = s.Z * sc + e;
   const Real dy = y - s.mu;
-  const Real mun = s.mu + dy * (e / Zn);
+  const Real mun = s.mu + dy * ratio(e, Zn);
   s.M2 = s.M2 * sc + e * dy * (y - mun);
   s.S2 = s.S2 * sc + e * s2;
   s.Z = Zn;

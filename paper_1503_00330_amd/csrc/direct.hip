@@ -8,44 +8,64 @@
 namespace pi2rh {
 
 // ----------------------------------------------------------------- fold
-// One lane per local model: copies c_j, packs the symmetric part of D_j and
-// folds the PLS chain (Sec. 2) into y = beta_0 + b . (z - c): b is the
-// derivative of y w.r.t. the centred input, accumulated backwards through the
-// deflation steps in double precision.
+// One block per 16 local models.  One lane per model folds the PLS chain
+// (Sec. 2) into y = beta_0 + b . (z - c) -- b is the derivative of y w.r.t.
+// the centred input, accumulated backwards through the deflation steps in
+// double -- then all lanes write the 16 contiguous records, coalesced:
+// [c | theta (upper triangle of D + D^T, diagonal D_aa) | b | beta_0 | sigma^2].
 template <typename Real>
-__global__ void fold_direct_kernel(ModelArgs m, Real *__restrict__ rec) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m.Ltot) return;
-  const int d = m.d, R = m.R, RS = d + d * (d + 1) / 2 + d + 2;
-  const Real *c = (const Real *)m.centre + (size_t)j * d;
-  const Real *D = (const Real *)m.metric + (size_t)j * d * d;
-  const Real *U = (const Real *)m.proj_u + (size_t)j * R * d;
-  const Real *P = m.proj_p ? (const Real *)m.proj_p + (size_t)j * R * d : U;
-  const Real *B = (const Real *)m.beta + (size_t)j * (R + 1);
-  Real *out = rec + (size_t)j * RS;
-  for (int a = 0; a < d; ++a) out[a] = c[a];
-  int idx = d;
-  for (int a = 0; a < d; ++a)
-    for (int b = a; b < d; ++b) out[idx++] = (a == b) ? D[a * d + a] : D[a * d + b] + D[b * d + a];
-  double rb[kMaxD];
-  for (int a = 0; a < d; ++a) rb[a] = 0.0;
-  for (int r = R - 1; r >= 0; --r) {
-    double pr = 0.0;
-    for (int a = 0; a < d; ++a) pr += (double)P[r * d + a] * rb[a];
-    const double sb = (double)B[r + 1] - pr;
-    for (int a = 0; a < d; ++a) rb[a] += sb * (double)U[r * d + a];
+__global__ void __launch_bounds__(256) fold_direct_kernel(ModelArgs m, Real *__restrict__ rec) {
+  __shared__ double bv[16][kMaxD];
+  const int j0 = blockIdx.x * 16, d = m.d, R = m.R, RS = d + d * (d + 1) / 2 + d + 2;
+  const int nj = min(16, m.Ltot - j0);
+  if ((int)threadIdx.x < nj) {
+    const int j = j0 + threadIdx.x;
+    const Real *U = (const Real *)m.proj_u + (size_t)j * R * d;
+    const Real *P = m.proj_p ? (const Real *)m.proj_p + (size_t)j * R * d : U;
+    const Real *B = (const Real *)m.beta + (size_t)j * (R + 1);
+    double rb[kMaxD];
+    for (int a = 0; a < d; ++a) rb[a] = 0.0;
+    for (int r = R - 1; r >= 0; --r) {
+      double pr = 0.0;
+      for (int a = 0; a < d; ++a) pr += (double)P[r * d + a] * rb[a];
+      const double sb = (double)B[r + 1] - pr;
+      for (int a = 0; a < d; ++a) rb[a] += sb * (double)U[r * d + a];
+    }
+    for (int a = 0; a < d; ++a) bv[threadIdx.x][a] = rb[a];
   }
-  for (int a = 0; a < d; ++a) out[idx++] = (Real)rb[a];
-  out[idx++] = B[0];
-  out[idx++] = ((const Real *)m.sigma2)[j];
+  __syncthreads();
+  const int np = d * (d + 1) / 2;
+  for (int e = threadIdx.x; e < nj * RS; e += blockDim.x) {
+    const int jj = e / RS, f = e % RS, j = j0 + jj;
+    Real v;
+    if (f < d) {
+      v = ((const Real *)m.centre)[(size_t)j * d + f];
+    } else if (f < d + np) {
+      int a = 0, rem = f - d;
+      while (rem >= d - a) {
+        rem -= d - a;
+        ++a;
+      }
+      const int b = a + rem;
+      const Real *D = (const Real *)m.metric + (size_t)j * d * d;
+      v = (a == b) ? D[a * d + a] : D[a * d + b] + D[b * d + a];
+    } else if (f < d + np + d) {
+      v = (Real)bv[jj][f - d - np];
+    } else if (f == d + np + d) {
+      v = ((const Real *)m.beta)[(size_t)j * (R + 1)];
+    } else {
+      v = ((const Real *)m.sigma2)[j];
+    }
+    rec[(size_t)j0 * RS + e] = v;
+  }
 }
 
 hipError_t launch_fold_direct(int dtype, const ModelArgs &m, void *rec, hipStream_t s) {
-  const int nb = (m.Ltot + 127) / 128;
+  const int nb = (m.Ltot + 15) / 16;
   if (dtype == PI_F64)
-    hipLaunchKernelGGL(fold_direct_kernel<double>, dim3(nb), dim3(128), 0, s, m, (double *)rec);
+    hipLaunchKernelGGL(fold_direct_kernel<double>, dim3(nb), dim3(256), 0, s, m, (double *)rec);
   else
-    hipLaunchKernelGGL(fold_direct_kernel<float>, dim3(nb), dim3(128), 0, s, m, (float *)rec);
+    hipLaunchKernelGGL(fold_direct_kernel<float>, dim3(nb), dim3(256), 0, s, m, (float *)rec);
   return hipGetLastError();
 }
 
@@ -297,14 +317,29 @@ size_t update_ws_bytes(int K, int T) {
          align_up((size_t)T * 2 * 8, 256);
 }
 
+// Suffix sums through an LDS transpose: a block of 256 rollouts walks the
+// horizon backwards in chunks of 16 steps; chunk loads read 64-byte row
+// segments and every S row write is coalesced over k.
 template <typename Real>
-__global__ void suffix_kernel(const Real *__restrict__ cost, int K, int T, double *__restrict__ S) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+__global__ void __launch_bounds__(256) suffix_kernel(const Real *__restrict__ cost, int K, int T,
+                                                     double *__restrict__ S) {
+  __shared__ double tile[256][17];
+  const int k0 = blockIdx.x * 256, k = k0 + threadIdx.x;
+  const int nk = min(256, K - k0);
   double acc = 0.0;
-  for (int t = T - 1; t >= 0; --t) {
-    acc += (double)cost[(int64_t)k * T + t];
-    S[(int64_t)t * K + k] = acc;
+  for (int hi = T; hi > 0; hi -= 16) {
+    const int lo = max(0, hi - 16), w = hi - lo;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256 * 16; e += 256) {
+      const int r = e / 16, c = e % 16;
+      if (r < nk && c < w) tile[r][c] = (double)cost[(int64_t)(k0 + r) * T + lo + c];
+    }
+    __syncthreads();
+    if (k < K)
+      for (int c = w - 1; c >= 0; --c) {
+        acc += tile[threadIdx.x][c];
+        S[(int64_t)(lo + c) * K + k] = acc;
+      }
   }
 }
 
@@ -419,60 +454,76 @@ hipError_t launch_update(int dtype, const void *pargs, const void *cost, const u
 }
 
 // ------------------------------------------------------------ RH shift
-// One block: the plant step executes u_nom[0] under the PLANT stream (models
-// split across lanes, statistics merged in a fixed tree order), then the plan
-// is shifted left by one step (last control repeated) and iter advanced.
-constexpr int kShiftThreads = 256;
+// The plant step executes u_nom[0] under the PLANT stream.  Kernel 1: block
+// (o, c) evaluates 64 local models of output o at z = [x0 ; u_nom[0]], one per
+// lane, and merges them into one partial statistic (fixed tree order).
+// Kernel 2 (one block): merges the partials of every output in order, samples
+// the accelerations, steps Euler, shifts the plan left by one step (last
+// control repeated) and advances iter.
+constexpr int kShiftThreads = 64;
+
+size_t shift_partial_bytes(const ModelArgs &m, int dtype) {
+  int Lmax = 1;
+  for (int o = 0; o < m.n_out; ++o) Lmax = max(Lmax, m.L_off[o + 1] - m.L_off[o]);
+  const int C = (Lmax + kShiftThreads - 1) / kShiftThreads;
+  return align_up((size_t)m.n_out * C * 5 * (dtype == PI_F64 ? 8 : 4), 256);
+}
 
 template <typename Real, int DYN>
-__global__ void __launch_bounds__(kShiftThreads) rh_shift_kernel(ProbDev<Real> p, ModelArgs m,
-                                                                 const Real *__restrict__ rec,
-                                                                 Real *__restrict__ x0,
-                                                                 Real *__restrict__ u_nom,
-                                                                 uint32_t *__restrict__ iter) {
+__global__ void __launch_bounds__(kShiftThreads) plant_partial_kernel(ModelArgs m,
+                                                                      const Real *__restrict__ rec,
+                                                                      const Real *__restrict__ x0,
+                                                                      const Real *__restrict__ u_nom,
+                                                                      MixStat<Real> *__restrict__ part) {
   using DD = DynDims<DYN>;
-  constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
+  constexpr int D = DD::D, NX = DD::NX, NU = DD::NU;
   constexpr int RS = rec_stride<Real, D>();
   __shared__ MixStat<Real> red[kShiftThreads];
-  __shared__ Real acc[kMaxOut];
-  __shared__ Real xnew[kMaxX];
-  __shared__ uint32_t it_s;
+  const int o = blockIdx.y, c = blockIdx.x, C = gridDim.x;
   Real z[D];
 #pragma unroll
   for (int a = 0; a < NX; ++a) z[a] = x0[a];
 #pragma unroll
   for (int a = 0; a < NU; ++a) z[NX + a] = u_nom[a];
-  if (threadIdx.x == 0) it_s = *iter;
+  MixStat<Real> st = mix_empty<Real>();
+  const int j = m.L_off[o] + c * kShiftThreads + threadIdx.x;
+  if (j < m.L_off[o + 1]) {
+    Real q, y;
+    eval_record<Real, D>(rec + (size_t)j * RS, z, q, y);
+    mix_add<false>(st, (Real)-0.5 * q, y, rec[(size_t)j * RS + RS - 1]);
+  }
+  red[threadIdx.x] = st;
   __syncthreads();
-  const uint32_t it = it_s;
-  for (int o = 0; o < NO; ++o) {
-    MixStat<Real> st = mix_empty<Real>();
-    for (int j = m.L_off[o] + threadIdx.x; j < m.L_off[o + 1]; j += blockDim.x) {
-      Real q, y;
-      eval_record<Real, D>(rec + (size_t)j * RS, z, q, y);
-      mix_add<false>(st, (Real)-0.5 * q, y, rec[(size_t)j * RS + RS - 1]);
-    }
-    red[threadIdx.x] = st;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] = mix_merge<false>(red[threadIdx.x], red[threadIdx.x + w]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      Real mu, v;
-      mix_finish(red[0], &mu, &v);
-      Real xi[8];
-      normals<Real, NO>(p.key0, p.key1, stream_word(kTagPlant, p.problem_id, it), 0u, 0u, 0u, xi);
-      acc[o] = mu + sqrt_(v) * xi[o];
-    }
+  for (int w = kShiftThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = mix_merge<false>(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
+  if (threadIdx.x == 0) part[o * C + c] = red[0];
+}
+
+template <typename Real, int DYN>
+__global__ void __launch_bounds__(256) plant_apply_kernel(ProbDev<Real> p, int C,
+                                                          const MixStat<Real> *__restrict__ part,
+                                                          Real *__restrict__ x0, Real *__restrict__ u_nom,
+                                                          uint32_t *__restrict__ iter) {
+  using DD = DynDims<DYN>;
+  constexpr int NX = DD::NX, NU = DD::NU, NO = DD::NO;
+  __shared__ Real xnew[kMaxX];
+  __shared__ uint32_t it_s;
   if (threadIdx.x == 0) {
-    Real xs[NX], an[NO];
+    const uint32_t it = *iter;
+    it_s = it;
+    Real xi[8], acc[NO], xs[NX], xn[NX];
+    normals<Real, NO>(p.key0, p.key1, stream_word(kTagPlant, p.problem_id, it), 0u, 0u, 0u, xi);
+    for (int o = 0; o < NO; ++o) {
+      MixStat<Real> st = part[o * C];
+      for (int c = 1; c < C; ++c) st = mix_merge<false>(st, part[o * C + c]);
+      Real mu, v;
+      mix_finish(st, &mu, &v);
+      acc[o] = mu + sqrt_(v) * xi[o];
+    }
     for (int a = 0; a < NX; ++a) xs[a] = x0[a];
-    for (int o = 0; o < NO; ++o) an[o] = acc[o];
-    Real xn[NX];
-    euler_step<Real>(DYN, p.dt, xs, an, xn);
+    euler_step<Real>(DYN, p.dt, xs, acc, xn);
     for (int a = 0; a < NX; ++a) xnew[a] = xn[a];
   }
   __syncthreads();
@@ -489,26 +540,35 @@ __global__ void __launch_bounds__(kShiftThreads) rh_shift_kernel(ProbDev<Real> p
     __syncthreads();
   }
   if (threadIdx.x < NX) x0[threadIdx.x] = xnew[threadIdx.x];
-  if (threadIdx.x == 0) *iter = it + 1u;
+  if (threadIdx.x == 0) *iter = it_s + 1u;
 }
 
 template <typename Real>
-static hipError_t rh_shift_t(const ProbDev<Real> &p, const ModelArgs &m, const void *rec, void *x0,
-                             void *u_nom, uint32_t *iter, hipStream_t s) {
-  if (p.dyn == kDynPointMass2D)
-    hipLaunchKernelGGL((rh_shift_kernel<Real, kDynPointMass2D>), dim3(1), dim3(kShiftThreads), 0, s,
-                       p, m, (const Real *)rec, (Real *)x0, (Real *)u_nom, iter);
-  else
-    hipLaunchKernelGGL((rh_shift_kernel<Real, kDynQuad12>), dim3(1), dim3(kShiftThreads), 0, s, p,
-                       m, (const Real *)rec, (Real *)x0, (Real *)u_nom, iter);
+static hipError_t rh_shift_t(const ProbDev<Real> &p, const ModelArgs &m, const void *rec, void *part,
+                             void *x0, void *u_nom, uint32_t *iter, hipStream_t s) {
+  int Lmax = 1;
+  for (int o = 0; o < m.n_out; ++o) Lmax = max(Lmax, m.L_off[o + 1] - m.L_off[o]);
+  const int C = (Lmax + kShiftThreads - 1) / kShiftThreads;
+  const dim3 grid(C, m.n_out);
+  if (p.dyn == kDynPointMass2D) {
+    hipLaunchKernelGGL((plant_partial_kernel<Real, kDynPointMass2D>), grid, dim3(kShiftThreads), 0, s, m,
+                       (const Real *)rec, (const Real *)x0, (const Real *)u_nom, (MixStat<Real> *)part);
+    hipLaunchKernelGGL((plant_apply_kernel<Real, kDynPointMass2D>), dim3(1), dim3(256), 0, s, p, C,
+                       (const MixStat<Real> *)part, (Real *)x0, (Real *)u_nom, iter);
+  } else {
+    hipLaunchKernelGGL((plant_partial_kernel<Real, kDynQuad12>), grid, dim3(kShiftThreads), 0, s, m,
+                       (const Real *)rec, (const Real *)x0, (const Real *)u_nom, (MixStat<Real> *)part);
+    hipLaunchKernelGGL((plant_apply_kernel<Real, kDynQuad12>), dim3(1), dim3(256), 0, s, p, C,
+                       (const MixStat<Real> *)part, (Real *)x0, (Real *)u_nom, iter);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, const void *rec,
-                           void *x0, void *u_nom, uint32_t *iter, hipStream_t s) {
+                           void *part, void *x0, void *u_nom, uint32_t *iter, hipStream_t s) {
   return dtype == PI_F64
-             ? rh_shift_t<double>(*(const ProbDev<double> *)pargs, m, rec, x0, u_nom, iter, s)
-             : rh_shift_t<float>(*(const ProbDev<float> *)pargs, m, rec, x0, u_nom, iter, s);
+             ? rh_shift_t<double>(*(const ProbDev<double> *)pargs, m, rec, part, x0, u_nom, iter, s)
+             : rh_shift_t<float>(*(const ProbDev<float> *)pargs, m, rec, part, x0, u_nom, iter, s);
 }
 
 // ------------------------------------------------------ stream access

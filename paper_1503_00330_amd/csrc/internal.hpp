@@ -110,7 +110,7 @@ hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &
                                  const void *rec, hipStream_t s);
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
                                const MfmaLayout &l, const void *base, int tile_samples,
-                               hipStream_t s);
+                               int waves, hipStream_t s);
 hipError_t launch_subcost_reduce(int dtype, const void *sub, void *cost, int K, int Ms, int T,
                                  hipStream_t s);
 
@@ -120,7 +120,8 @@ hipError_t launch_update(int dtype, const void *pargs, const void *cost, const u
 size_t update_ws_bytes(int K, int T);
 
 hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, const void *rec,
-                           void *x0, void *u_nom, uint32_t *iter, hipStream_t s);
+                           void *part, void *x0, void *u_nom, uint32_t *iter, hipStream_t s);
+size_t shift_partial_bytes(const ModelArgs &m, int dtype);
 
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
                          hipStream_t s);

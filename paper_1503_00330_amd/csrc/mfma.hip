@@ -33,72 +33,99 @@ constexpr double kAlpha = -0.72134752044448170368;
 constexpr float kPadAct = -1.0e30f;
 
 // ----------------------------------------------------------------- fold
-// One lane per padded model slot (tile, column).
-__global__ void fold_mfma_kernel(ModelArgs m, MfmaLayout l, float *__restrict__ W,
-                                 float *__restrict__ sig2) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= l.n_tiles * 16) return;
-  const int tile = slot / 16, col = slot % 16, d = m.d, R = m.R;
+// One block per tile of 16 model slots.  Phase 1: one lane per model computes
+// in double the derived vectors (h = -(D + D^T) c, kappa = c^T D c, the folded
+// PLS map b and y0 = beta0 - b.c) into LDS; phase 2: every lane writes whole
+// float4 fragments, coalesced.
+constexpr int kFoldThreads = 256;
+
+__global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, MfmaLayout l,
+                                                                 float *__restrict__ W,
+                                                                 float *__restrict__ sig2) {
+  __shared__ double hv[16][kMaxD], bv[16][kMaxD], kap[16], y0v[16];
+  __shared__ int jcol[16];
+  const int tile = blockIdx.x, d = m.d, R = m.R;
   const MfmaGeom g = MfmaGeom::make(d);
   int o = 0;
   while (o + 1 < m.n_out && tile >= l.tile_off[o + 1]) ++o;
-  const int jloc = (tile - l.tile_off[o]) * 16 + col;
-  const bool valid = jloc < m.L_off[o + 1] - m.L_off[o];
-  auto put = [&](int feat, float v) {
-    const int kb = feat / 4, lane = (feat % 4) * 16 + col, kb4 = kb / 4, comp = kb % 4;
-    W[(((size_t)tile * g.KB4 + kb4) * 64 + lane) * 4 + comp] = v;
-  };
-  for (int f = 0; f < g.KB4 * 16; ++f) put(f, 0.0f);
-  if (!valid) {
-    put(g.NP + d, kPadAct);
-    sig2[slot] = 0.0f;
-    return;
+  if (threadIdx.x < 16) {
+    const int col = threadIdx.x;
+    const int jloc = (tile - l.tile_off[o]) * 16 + col;
+    const int j = jloc < m.L_off[o + 1] - m.L_off[o] ? m.L_off[o] + jloc : -1;
+    jcol[col] = j;
+    if (j >= 0) {
+      const float *c = (const float *)m.centre + (size_t)j * d;
+      const float *D = (const float *)m.metric + (size_t)j * d * d;
+      const float *U = (const float *)m.proj_u + (size_t)j * R * d;
+      const float *P = m.proj_p ? (const float *)m.proj_p + (size_t)j * R * d : U;
+      const float *B = (const float *)m.beta + (size_t)j * (R + 1);
+      double kappa = 0.0;
+      for (int a = 0; a < d; ++a) {
+        double h = 0.0;
+        for (int b = 0; b < d; ++b) {
+          h += ((double)D[a * d + b] + (double)D[b * d + a]) * (double)c[b];
+          kappa += (double)c[a] * (double)D[a * d + b] * (double)c[b];
+        }
+        hv[col][a] = -h;
+      }
+      kap[col] = kappa;
+      // y = beta0 + b.(z - c): b by reverse accumulation through the deflation chain
+      double rb[kMaxD];
+      for (int a = 0; a < d; ++a) rb[a] = 0.0;
+      for (int r = R - 1; r >= 0; --r) {
+        double pr = 0.0;
+        for (int a = 0; a < d; ++a) pr += (double)P[r * d + a] * rb[a];
+        const double sb = (double)B[r + 1] - pr;
+        for (int a = 0; a < d; ++a) rb[a] += sb * (double)U[r * d + a];
+      }
+      double y0 = (double)B[0];
+      for (int a = 0; a < d; ++a) {
+        bv[col][a] = rb[a];
+        y0 -= rb[a] * (double)c[a];
+      }
+      y0v[col] = y0;
+      sig2[tile * 16 + col] = ((const float *)m.sigma2)[j];
+    } else {
+      sig2[tile * 16 + col] = 0.0f;
+    }
   }
-  const int j = m.L_off[o] + jloc;
-  const float *c = (const float *)m.centre + (size_t)j * d;
-  const float *D = (const float *)m.metric + (size_t)j * d * d;
-  const float *U = (const float *)m.proj_u + (size_t)j * R * d;
-  const float *P = m.proj_p ? (const float *)m.proj_p + (size_t)j * R * d : U;
-  const float *B = (const float *)m.beta + (size_t)j * (R + 1);
-  int idx = 0;
-  for (int a = 0; a < d; ++a)
-    for (int b = a; b < d; ++b) {
+  __syncthreads();
+  const int NE = g.KB4 * 64 * 4;
+  float *dst = W + (size_t)tile * NE;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
+    const int f = 4 * (4 * kb4 + comp) + lane / 16, col = lane & 15;
+    const int j = jcol[col];
+    float v = 0.0f;
+    if (j < 0) {
+      v = (f == g.NP + d) ? kPadAct : 0.0f;
+    } else if (f < g.NP) {
+      int a = 0, rem = f;
+      while (rem >= d - a) {
+        rem -= d - a;
+        ++a;
+      }
+      const int b = a + rem;
+      const float *D = (const float *)m.metric + (size_t)j * d * d;
       const double th = (a == b) ? (double)D[a * d + a] : (double)D[a * d + b] + (double)D[b * d + a];
-      put(idx++, (float)(kAlpha * th));
+      v = (float)(kAlpha * th);
+    } else if (f < g.NP + d) {
+      v = (float)(kAlpha * hv[col][f - g.NP]);
+    } else if (f == g.NP + d) {
+      v = (float)(kAlpha * kap[col]);
+    } else if (f >= 4 * g.KQB && f < 4 * g.KQB + d) {
+      v = (float)bv[col][f - 4 * g.KQB];
+    } else if (f == 4 * g.KQB + d) {
+      v = (float)y0v[col];
     }
-  double kappa = 0.0;
-  for (int a = 0; a < d; ++a) {
-    double h = 0.0;
-    for (int b = 0; b < d; ++b) {
-      h += ((double)D[a * d + b] + (double)D[b * d + a]) * (double)c[b];
-      kappa += (double)c[a] * (double)D[a * d + b] * (double)c[b];
-    }
-    put(g.NP + a, (float)(kAlpha * -h));
+    dst[e] = v;
   }
-  put(g.NP + d, (float)(kAlpha * kappa));
-  // y = beta0 + b.(z - c): b by reverse accumulation through the deflation chain
-  double rb[kMaxD];
-  for (int a = 0; a < d; ++a) rb[a] = 0.0;
-  for (int r = R - 1; r >= 0; --r) {
-    double pr = 0.0;
-    for (int a = 0; a < d; ++a) pr += (double)P[r * d + a] * rb[a];
-    const double sb = (double)B[r + 1] - pr;
-    for (int a = 0; a < d; ++a) rb[a] += sb * (double)U[r * d + a];
-  }
-  double y0 = (double)B[0];
-  for (int a = 0; a < d; ++a) {
-    put(4 * g.KQB + a, (float)rb[a]);
-    y0 -= rb[a] * (double)c[a];
-  }
-  put(4 * g.KQB + d, (float)y0);
-  sig2[slot] = ((const float *)m.sigma2)[j];
 }
 
 hipError_t launch_fold_mfma(int, const ModelArgs &m, const MfmaLayout &l, void *base, hipStream_t s) {
   float *W = (float *)base;
   float *sig = (float *)((char *)base + align_up(l.w_floats * 4, 256));
-  const int n = l.n_tiles * 16;
-  hipLaunchKernelGGL(fold_mfma_kernel, dim3((n + 63) / 64), dim3(64), 0, s, m, l, W, sig);
+  hipLaunchKernelGGL(fold_mfma_kernel, dim3(l.n_tiles), dim3(kFoldThreads), 0, s, m, l, W, sig);
   return hipGetLastError();
 }
 
@@ -210,41 +237,43 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       }
   };
 
-  f32x4 Bc[G::KB4], Bn[G::KB4];
-  {
-    const float4 *src = md.W + (size_t)t0 * G::KB4 * 64 + lane;
+  // Software pipeline over tiles with two B buffers: the loads of tile i+1
+  // are issued before the MFMA chain of tile i, and scheduling barriers keep
+  // the compiler from sinking them next to their use.
+  // sigma^2 of the lane's model column travels with its tile (loads complete
+  // in order, so a later load would make the wait drain the prefetch too).
+  f32x4 B0[G::KB4], B1[G::KB4];
+  float s2_0, s2_1;
+  auto load_tile = [&](f32x4 (&Bd)[G::KB4], float &s2d, int tile) {
+    const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < G::KB4; ++q) {
-      const float4 v = src[q * 64];
-      Bc[q] = f32x4{v.x, v.y, v.z, v.w};
-    }
-  }
-  for (int tile = t0; tile < t1; ++tile) {
+    for (int q = 0; q < G::KB4; ++q) Bd[q] = src[q * 64];
+    s2d = md.sig2[tile * 16 + (lane & 15)];
+  };
+  auto compute_tile = [&](const f32x4 (&Bc)[G::KB4], float s2, int tile) {
     if (tile >= md.tile_off[o + 1]) {
       flush(o);
       while (tile >= md.tile_off[o + 1]) ++o;
     }
-    if (tile + 1 < t1) {
-      const float4 *src = md.W + (size_t)(tile + 1) * G::KB4 * 64 + lane;
-#pragma unroll
-      for (int q = 0; q < G::KB4; ++q) {
-        const float4 v = src[q * 64];
-        Bn[q] = f32x4{v.x, v.y, v.z, v.w};
-      }
-    }
-    const float s2 = md.sig2[tile * 16 + (lane & 15)];
-    f32x4 qa[MT], ya[MT];
+    f32x4 qa[MT], qb[MT], ya[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      qb[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       ya[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+    // two interleaved accumulators per row tile shorten the dependency chain
 #pragma unroll
     for (int kb = 0; kb < G::KQB; ++kb)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        qa[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
-                                                      qa[mt], 0, 0, 0);
+      for (int mt = 0; mt < MT; ++mt) {
+        if (kb & 1)
+          qb[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
+                                                        qb[mt], 0, 0, 0);
+        else
+          qa[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
+                                                        qa[mt], 0, 0, 0);
+      }
 #pragma unroll
     for (int kb = G::KQB; kb < G::KB; ++kb)
 #pragma unroll
@@ -254,9 +283,20 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) mix_add<true>(st[mt][r], qa[mt][r], ya[mt][r], s2);
-#pragma unroll
-    for (int q = 0; q < G::KB4; ++q) Bc[q] = Bn[q];
+      for (int r = 0; r < 4; ++r) mix_add<true>(st[mt][r], qa[mt][r] + qb[mt][r], ya[mt][r], s2);
+  };
+
+  load_tile(B0, s2_0, t0);
+  for (int tile = t0; tile < t1; tile += 2) {
+    if (tile + 1 < t1) load_tile(B1, s2_1, tile + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_tile(B0, s2_0, tile);
+    __builtin_amdgcn_sched_barrier(0);
+    if (tile + 1 >= t1) break;
+    if (tile + 2 < t1) load_tile(B0, s2_0, tile + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_tile(B1, s2_1, tile + 1);
+    __builtin_amdgcn_sched_barrier(0);
   }
   flush(o);
 }
@@ -409,10 +449,14 @@ static hipError_t rollout_mfma_t(const RolloutArgs<float> &ra, const MfmaModel &
 }
 
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m, const MfmaLayout &l,
-                               const void *base, int tile_samples, hipStream_t s) {
+                               const void *base, int tile_samples, int waves, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
   const int spw = tile_samples;
   if (ra.p.dyn == kDynQuad12) {
+    if (waves == 8) {
+      if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 8>(ra, md, spw, s);
+      return rollout_mfma_t<kDynQuad12, 2, 8>(ra, md, spw, s);
+    }
     if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4>(ra, md, spw, s);
     return rollout_mfma_t<kDynQuad12, 2, 4>(ra, md, spw, s);
   }
