@@ -136,16 +136,18 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
  * for PI_W_TRAJECTORY); P_{k,i} = softmax_k(-S_{k,i}/lambda);
  * u_nom[i] += sum_k P_{k,i} eps_{k,i}, with eps regenerated from the same
  * stream.  cost dev [K][T] (problem dtype), u_nom dev [T][n_u] in/out,
- * weights dev [T][K] double (nullable).  Normalisation and sums in double.   */
+ * weights dev [T][K] double (nullable).  Normalisation and sums in double.
+ * The iteration's draws are then consumed: *iter (dev) is incremented, so
+ * the next rollout of the same control step draws fresh noise.               */
 pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter, void *u_nom,
                     void *weights, void *ws, size_t ws_bytes, void *stream);
 
 /* Receding-horizon advance (Sec. 3.1, last paragraph): executes u_nom[0] on
- * the plant -- a draw from the learned model under its own stream -- writing
- * the new state to x0 (dev [n_x], in/out), shifts u_nom left by one step
- * (repeating the last control) and increments *iter (dev).                   */
+ * the plant -- a draw from the learned model under the PLANT stream at the
+ * current *iter (dev, read only) -- writing the new state to x0 (dev [n_x],
+ * in/out), and shifts u_nom left by one step (repeating the last control).  */
 pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom,
-                      uint32_t *iter, void *ws, size_t ws_bytes, void *stream);
+                      const uint32_t *iter, void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of the expected rollout cost with the noise held fixed:
  *   J = (1/(K max(M,1))) sum_{k,m,t} dt q(x_{k,m,t+1}),

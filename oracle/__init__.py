@@ -210,13 +210,14 @@ def update(prob, cost, u_nom=None, it: int = 0, weights: bool = False):
 
 
 def rh_shift(prob, model, x0, u_nom, it: int):
+    """Plant step at iteration word `it` and plan shift; returns (x0, u_nom)."""
     keep = _Keep()
     ms, ps = _model_struct(model, keep), _problem_struct(prob, keep)
     x = _f64(x0).copy()
     u = _f64(u_nom).copy()
     itv = C.c_uint32(it)
     _load().orc_rh_shift(C.byref(ps), C.byref(ms), _ptr(x), _ptr(u), C.byref(itv))
-    return x, u, int(itv.value)
+    return x, u
 
 
 def adjoint(prob, model, x0=None, u_nom=None, it: int = 0, nthreads: int = 0):
@@ -234,6 +235,22 @@ def adjoint(prob, model, x0=None, u_nom=None, it: int = 0, nthreads: int = 0):
 
 
 def iteration(prob, model, it: int = 0, nthreads: int = 0):
-    """One PI^2 iteration: rollout costs, then the update. Returns (cost, u_new)."""
+    """One PI^2 iteration at iteration word `it`: rollout costs, then the
+    update (after which the word advances to it + 1). Returns (cost, u_new)."""
     cost = rollout_cost(prob, model, it=it, nthreads=nthreads)
     return cost, update(prob, cost, it=it)
+
+
+def rh_loop(prob, model, steps: int, iterations: int = 1, x0=None, u_nom=None, it: int = 0):
+    """Receding-horizon loop: per control step `iterations` PI^2 iterations
+    (each with its own iteration word), then the plant step and plan shift.
+    Returns (x0, u_nom, it) after `steps` control steps."""
+    x = _f64(prob.x0 if x0 is None else x0).copy()
+    u = _f64(prob.u_nom if u_nom is None else u_nom).copy()
+    for _ in range(steps):
+        for _ in range(iterations):
+            cost = rollout_cost(prob, model, x0=x, u_nom=u, it=it)
+            u = update(prob, cost, u_nom=u, it=it)
+            it += 1
+        x, u = rh_shift(prob, model, x, u, it)
+    return x, u, it

@@ -406,10 +406,12 @@ void orc_update(const orc_problem *p, const double *cost, uint32_t iter, double 
 }
 
 /* Receding-horizon advance (Sec. 3.1, last paragraph): execute u_0 on the
- * plant (here a draw from the learned model under the PLANT stream), shift
- * the plan left by one step repeating the last control, advance iter. */
+ * plant (here a draw from the learned model under the PLANT stream at the
+ * current iteration word), shift the plan left by one step repeating the last
+ * control.  The iteration word counts PI^2 iterations; it advances after each
+ * update, so every iteration of a control step draws fresh noise. */
 void orc_rh_shift(const orc_problem *p, const orc_model *md, double *x0, double *u_nom,
-                  uint32_t *iter) {
+                  const uint32_t *iter) {
   const int nx = n_state(p->dyn), nu = n_control(p->dyn), no = md->n_out, T = p->T;
   const int64_t Lm = max_L(md);
   double *w = malloc(sizeof(double) * Lm), *y = malloc(sizeof(double) * Lm);
@@ -427,7 +429,6 @@ void orc_rh_shift(const orc_problem *p, const orc_model *md, double *x0, double 
   for (int a = 0; a < nx; ++a) x0[a] = xn[a];
   for (int t = 0; t + 1 < T; ++t)
     for (int a = 0; a < nu; ++a) u_nom[t * nu + a] = u_nom[(t + 1) * nu + a];
-  *iter += 1;
   free(w); free(y); free(work);
 }
 

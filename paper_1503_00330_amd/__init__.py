@@ -286,7 +286,7 @@ def rollout_cost(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, i
 
 
 def update(prob: DeviceProblem, cost, u_nom=None, iter=None, weights: bool = False):
-    """Eq. (2): updates u_nom in place; returns (u_nom, weights [T][K] or None)."""
+    """Eq. (2): updates u_nom in place and advances iter; returns (u_nom, weights [T][K] or None)."""
     torch = _torch()
     lib = load()
     u_nom = prob.u_nom if u_nom is None else u_nom
@@ -300,7 +300,7 @@ def update(prob: DeviceProblem, cost, u_nom=None, iter=None, weights: bool = Fal
 
 
 def rh_shift(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, iter=None):
-    """Executes u_nom[0] on the sampled plant, shifts the plan, iter += 1 (in place)."""
+    """Executes u_nom[0] on the sampled plant and shifts the plan (in place)."""
     lib = load()
     x0 = prob.x0 if x0 is None else x0
     u_nom = prob.u_nom if u_nom is None else u_nom

@@ -323,8 +323,8 @@ pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter,
   return launched(e, "pi_update");
 }
 
-pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom, uint32_t *iter,
-                      void *ws, size_t ws_bytes, void *stream) {
+pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom,
+                      const uint32_t *iter, void *ws, size_t ws_bytes, void *stream) {
   PI_TRY(check_pair(p, m));
   if (!x0 || !u_nom || !iter) return fail(PI_ERR_NULL, "x0, u_nom and iter must be non-NULL");
   const ModelArgs a = model_args(m);

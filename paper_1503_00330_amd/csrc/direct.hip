@@ -394,8 +394,11 @@ __global__ void __launch_bounds__(kUpdThreads) update_chunk_kernel(ProbDev<Real>
 template <typename Real>
 __global__ void update_apply_kernel(int T, int C, int n_u, double lambda,
                                     const double *__restrict__ part,
-                                    Real *__restrict__ u_nom, double *__restrict__ norm) {
+                                    Real *__restrict__ u_nom, double *__restrict__ norm,
+                                    uint32_t *__restrict__ iter) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // the iteration's draws have all been consumed: advance the iteration word
+  if (i == 0) *iter += 1u;
   if (i >= T) return;
   const double *pi_ = part + (int64_t)i * C * (2 + kMaxU);
   double mn = 1.0 / 0.0;
@@ -434,7 +437,7 @@ static hipError_t update_t(const ProbDev<Real> &p, const Real *cost, const uint3
   hipLaunchKernelGGL(update_chunk_kernel<Real>, dim3(C, T), dim3(kUpdThreads), 0, s, p, lambda,
                      weighting, iter, (const double *)S, part);
   hipLaunchKernelGGL(update_apply_kernel<Real>, dim3((T + 63) / 64), dim3(64), 0, s, T, C, p.n_u,
-                     lambda, (const double *)part, u_nom, norm);
+                     lambda, (const double *)part, u_nom, norm, const_cast<uint32_t *>(iter));
   if (W) {
     const int64_t n = (int64_t)K * T;
     hipLaunchKernelGGL(update_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K,
@@ -458,8 +461,8 @@ hipError_t launch_update(int dtype, const void *pargs, const void *cost, const u
 // (o, c) evaluates 64 local models of output o at z = [x0 ; u_nom[0]], one per
 // lane, and merges them into one partial statistic (fixed tree order).
 // Kernel 2 (one block): merges the partials of every output in order, samples
-// the accelerations, steps Euler, shifts the plan left by one step (last
-// control repeated) and advances iter.
+// the accelerations, steps Euler and shifts the plan left by one step (last
+// control repeated).  The iteration word is read, not advanced.
 constexpr int kShiftThreads = 64;
 
 size_t shift_partial_bytes(const ModelArgs &m, int dtype) {
@@ -505,14 +508,12 @@ template <typename Real, int DYN>
 __global__ void __launch_bounds__(256) plant_apply_kernel(ProbDev<Real> p, int C,
                                                           const MixStat<Real> *__restrict__ part,
                                                           Real *__restrict__ x0, Real *__restrict__ u_nom,
-                                                          uint32_t *__restrict__ iter) {
+                                                          const uint32_t *__restrict__ iter) {
   using DD = DynDims<DYN>;
   constexpr int NX = DD::NX, NU = DD::NU, NO = DD::NO;
   __shared__ Real xnew[kMaxX];
-  __shared__ uint32_t it_s;
   if (threadIdx.x == 0) {
     const uint32_t it = *iter;
-    it_s = it;
     Real xi[8], acc[NO], xs[NX], xn[NX];
     normals<Real, NO>(p.key0, p.key1, stream_word(kTagPlant, p.problem_id, it), 0u, 0u, 0u, xi);
     for (int o = 0; o < NO; ++o) {
@@ -540,12 +541,11 @@ __global__ void __launch_bounds__(256) plant_apply_kernel(ProbDev<Real> p, int C
     __syncthreads();
   }
   if (threadIdx.x < NX) x0[threadIdx.x] = xnew[threadIdx.x];
-  if (threadIdx.x == 0) *iter = it_s + 1u;
 }
 
 template <typename Real>
 static hipError_t rh_shift_t(const ProbDev<Real> &p, const ModelArgs &m, const void *rec, void *part,
-                             void *x0, void *u_nom, uint32_t *iter, hipStream_t s) {
+                             void *x0, void *u_nom, const uint32_t *iter, hipStream_t s) {
   int Lmax = 1;
   for (int o = 0; o < m.n_out; ++o) Lmax = max(Lmax, m.L_off[o + 1] - m.L_off[o]);
   const int C = (Lmax + kShiftThreads - 1) / kShiftThreads;
@@ -565,7 +565,7 @@ static hipError_t rh_shift_t(const ProbDev<Real> &p, const ModelArgs &m, const v
 }
 
 hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, const void *rec,
-                           void *part, void *x0, void *u_nom, uint32_t *iter, hipStream_t s) {
+                           void *part, void *x0, void *u_nom, const uint32_t *iter, hipStream_t s) {
   return dtype == PI_F64
              ? rh_shift_t<double>(*(const ProbDev<double> *)pargs, m, rec, part, x0, u_nom, iter, s)
              : rh_shift_t<float>(*(const ProbDev<float> *)pargs, m, rec, part, x0, u_nom, iter, s);

@@ -36,10 +36,12 @@ inline size_t direct_bytes(int dtype, int d, int Ltot) {
 // stored lane-major:  W[tile][kb4][lane][4],  kblock kb = 4*kb4 + component,
 // B[k][n] with k = 4*kb + lane/16 (feature), n = lane%16 (model of the tile).
 // Features: kblocks [0, KQB): quadratic-form features
-//   {z_a z_b (a<=b), z_a, 1} with coefficients alpha*{theta_ab, h_a, kappa},
-//   h = -(D + D^T) c, kappa = c^T D c, alpha = -log2(e)/2, so the product is
-//   the activation in base-2 units;  kblocks [KQB, KQB+KYB): {z_a, 1} with
-//   coefficients {b_a, beta0 - b.c} giving the local prediction y.
+//   {z_a z_b (a<=b), z_a, 1, shift} with coefficients
+//   {alpha theta_ab, alpha h_a, alpha kappa, 1}, h = -(D + D^T) c,
+//   kappa = c^T D c, alpha = -log2(e)/2, so the product is the activation in
+//   base-2 units minus a per-sample anchor (the A operand carries -anchor in
+//   the shift slot);  kblocks [KQB, KQB+KYB): {z_a, 1, shift} with
+//   coefficients {b_a, beta0 - b.c, 1} giving y minus a per-sample reference.
 // Padded model columns get activation -1e30 (zero weight) and y = 0.
 struct MfmaGeom {
   int D, NP, KQ, KQB, KY, KYB, KB, KB4;
@@ -47,9 +49,9 @@ struct MfmaGeom {
     MfmaGeom g;
     g.D = d;
     g.NP = d * (d + 1) / 2;
-    g.KQ = g.NP + d + 1;
+    g.KQ = g.NP + d + 2;
     g.KQB = (g.KQ + 3) / 4;
-    g.KY = d + 1;
+    g.KY = d + 2;
     g.KYB = (g.KY + 3) / 4;
     g.KB = g.KQB + g.KYB;
     g.KB4 = (g.KB + 3) / 4;
@@ -120,7 +122,7 @@ hipError_t launch_update(int dtype, const void *pargs, const void *cost, const u
 size_t update_ws_bytes(int K, int T);
 
 hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, const void *rec,
-                           void *part, void *x0, void *u_nom, uint32_t *iter, hipStream_t s);
+                           void *part, void *x0, void *u_nom, const uint32_t *iter, hipStream_t s);
 size_t shift_partial_bytes(const ModelArgs &m, int dtype);
 
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,

@@ -6,10 +6,21 @@
 // alpha = -log2(e)/2, and the local prediction is y_j = [z, 1] . [b_j, beta0_j - b_j.c_j].
 // A workgroup owns 16*MT samples (rows of the A operand, staged in LDS as
 // lane-major fragments); its NW waves split the model tiles (16 models = the
-// columns of one B operand, streamed from L2 as 1 KB coalesced loads).  Each
-// lane folds its 4 rows x 1 column results into running softmax/Welford
-// statistics (base-2 shift), which are merged across the 16 column lanes with
-// cross-lane shuffles and across waves in LDS, in a fixed order.
+// columns of one B operand, streamed from L2 as 1 KB coalesced loads).
+//
+// Anchored accumulation.  Every (sample, output) carries an anchor m (an
+// activation close to the largest one) and a reference mean r, both taken
+// from the previous step and fed through one extra feature of each
+// contraction, so the matrix core returns a' = a - m and d = y - r directly.
+// Per model a lane then only accumulates
+//   Z += 2^a', S1 += 2^a' d, S2 += 2^a' d^2, S3 += 2^a' sigma^2, mx = max(mx, a'),
+// and the normalised mixture of Eq. (1) is
+//   mu = r + S1/Z,  var = (S2 - S1^2/Z + S3)/Z.
+// Partial sums merge across lanes (DPP row rotations) and waves (LDS) as
+// plain sums in a fixed order.  If the largest shifted activation leaves
+// [-60, 64] (too far from the anchor for 2^a' in FP32) the step is evaluated
+// again with the anchor moved to the observed maximum; the first step always
+// takes this second pass so its reference mean is the first pass's mean.
 // (PI^2-RH with LWPR dynamics, arXiv:1503.00330.)
 #include "internal.hpp"
 
@@ -20,51 +31,63 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int D>
 struct Geo {
   static constexpr int NP = D * (D + 1) / 2;
-  static constexpr int KQ = NP + D + 1;
+  static constexpr int KQ = NP + D + 2;
   static constexpr int KQB = (KQ + 3) / 4;
-  static constexpr int KY = D + 1;
+  static constexpr int KY = D + 2;
   static constexpr int KYB = (KY + 3) / 4;
   static constexpr int KB = KQB + KYB;
   static constexpr int KB4 = (KB + 3) / 4;
+  static constexpr int FQS = NP + D + 1;         // activation anchor feature
+  static constexpr int FYS = 4 * KQB + D + 1;    // prediction reference feature
+  static constexpr int NE = KB4 * 256;           // fragment floats per row tile
 };
 
 // alpha = -log2(e) / 2
 constexpr double kAlpha = -0.72134752044448170368;
 constexpr float kPadAct = -1.0e30f;
+constexpr float kAnchorHi = 64.0f, kAnchorLo = -60.0f;
 
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
 // in double the derived vectors (h = -(D + D^T) c, kappa = c^T D c, the folded
 // PLS map b and y0 = beta0 - b.c) into LDS; phase 2: every lane writes whole
-// float4 fragments, coalesced.
+// fragments, coalesced.
 constexpr int kFoldThreads = 256;
 
 __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, MfmaLayout l,
                                                                  float *__restrict__ W,
                                                                  float *__restrict__ sig2) {
   __shared__ double hv[16][kMaxD], bv[16][kMaxD], kap[16], y0v[16];
+  __shared__ float Dl[16][kMaxD * kMaxD];
   __shared__ int jcol[16];
   const int tile = blockIdx.x, d = m.d, R = m.R;
   const MfmaGeom g = MfmaGeom::make(d);
   int o = 0;
   while (o + 1 < m.n_out && tile >= l.tile_off[o + 1]) ++o;
+  const int jfirst = m.L_off[o] + (tile - l.tile_off[o]) * 16;
+  const int nvalid = min(16, m.L_off[o + 1] - jfirst);
+  // stage the metrics of the tile's models (coalesced)
+  for (int e = threadIdx.x; e < nvalid * d * d; e += blockDim.x)
+    Dl[e / (d * d)][e % (d * d)] = ((const float *)m.metric)[(size_t)jfirst * d * d + e];
+  __syncthreads();
   if (threadIdx.x < 16) {
     const int col = threadIdx.x;
-    const int jloc = (tile - l.tile_off[o]) * 16 + col;
-    const int j = jloc < m.L_off[o + 1] - m.L_off[o] ? m.L_off[o] + jloc : -1;
+    const int j = col < nvalid ? jfirst + col : -1;
     jcol[col] = j;
     if (j >= 0) {
       const float *c = (const float *)m.centre + (size_t)j * d;
-      const float *D = (const float *)m.metric + (size_t)j * d * d;
+      const float *D = Dl[col];
       const float *U = (const float *)m.proj_u + (size_t)j * R * d;
       const float *P = m.proj_p ? (const float *)m.proj_p + (size_t)j * R * d : U;
       const float *B = (const float *)m.beta + (size_t)j * (R + 1);
+      double cc[kMaxD];
+      for (int a = 0; a < d; ++a) cc[a] = (double)c[a];
       double kappa = 0.0;
       for (int a = 0; a < d; ++a) {
         double h = 0.0;
         for (int b = 0; b < d; ++b) {
-          h += ((double)D[a * d + b] + (double)D[b * d + a]) * (double)c[b];
-          kappa += (double)c[a] * (double)D[a * d + b] * (double)c[b];
+          h += ((double)D[a * d + b] + (double)D[b * d + a]) * cc[b];
+          kappa += cc[a] * (double)D[a * d + b] * cc[b];
         }
         hv[col][a] = -h;
       }
@@ -81,7 +104,7 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
       double y0 = (double)B[0];
       for (int a = 0; a < d; ++a) {
         bv[col][a] = rb[a];
-        y0 -= rb[a] * (double)c[a];
+        y0 -= rb[a] * cc[a];
       }
       y0v[col] = y0;
       sig2[tile * 16 + col] = ((const float *)m.sigma2)[j];
@@ -91,13 +114,16 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
   }
   __syncthreads();
   const int NE = g.KB4 * 64 * 4;
+  const int fqs = g.NP + d + 1, fys = 4 * g.KQB + d + 1;
   float *dst = W + (size_t)tile * NE;
   for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
     const int f = 4 * (4 * kb4 + comp) + lane / 16, col = lane & 15;
     const int j = jcol[col];
     float v = 0.0f;
-    if (j < 0) {
+    if (f == fqs || f == fys) {
+      v = 1.0f;
+    } else if (j < 0) {
       v = (f == g.NP + d) ? kPadAct : 0.0f;
     } else if (f < g.NP) {
       int a = 0, rem = f;
@@ -106,7 +132,7 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
         ++a;
       }
       const int b = a + rem;
-      const float *D = (const float *)m.metric + (size_t)j * d * d;
+      const float *D = Dl[col];
       const double th = (a == b) ? (double)D[a * d + a] : (double)D[a * d + b] + (double)D[b * d + a];
       v = (float)(kAlpha * th);
     } else if (f < g.NP + d) {
@@ -140,72 +166,107 @@ static MfmaModel mfma_view(const MfmaLayout &l, const void *base) {
 }
 
 // ------------------------------------------------------ shared mixture
+// DPP row rotation (16-lane rows): v + v[lane +- n within the row].
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_f<0x128>(v);  // row_ror:8
+  v += dpp_f<0x124>(v);  // row_ror:4
+  v += dpp_f<0x122>(v);  // row_ror:2
+  v += dpp_f<0x121>(v);  // row_ror:1
+  return v;
+}
+__device__ __forceinline__ float row_max16(float v) {
+  v = fmaxf(v, dpp_f<0x128>(v));
+  v = fmaxf(v, dpp_f<0x124>(v));
+  v = fmaxf(v, dpp_f<0x122>(v));
+  v = fmaxf(v, dpp_f<0x121>(v));
+  return v;
+}
+
+// Partial sums of one (sample, output) over a subset of local models.
+struct Acc {
+  float Z, S1, S2, S3, mx;
+};
+
+__device__ __forceinline__ Acc acc_empty() { return Acc{0.f, 0.f, 0.f, 0.f, -3.0e38f}; }
+
 template <int D, int MT, int NW>
 struct MixSmem {
   static constexpr int ROWS = 16 * MT;
-  float4 A[MT][Geo<D>::KB4][64];                 // A fragments, lane-major
-  MixStat<float> part[NW][kMaxOut][ROWS];        // per-wave partial statistics
-  float z[ROWS][D];
+  float4 A[MT][Geo<D>::KB4][64];         // A fragments, lane-major (anchor slots 0)
+  Acc part[NW][kMaxOut][ROWS];           // per-wave partial sums
+  float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
+  float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
-  unsigned char pa[Geo<D>::NP], pb[Geo<D>::NP];  // feature -> (a, b)
+  unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
+  int redo;
 };
 
+// Fragment entry e = ((kb4 * 64 + lane) * 4 + comp) of row tile mt holds
+// feature f = 4 (4 kb4 + comp) + lane/16 of row 16 mt + lane%16; every feature
+// is a product z'[ia] z'[ib] of the extended input z' = [z, 1, 0].
 template <int D, int MT, int NW>
 __device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
-  if (threadIdx.x == 0) {
-    int f = 0;
-    for (int a = 0; a < D; ++a)
-      for (int b = a; b < D; ++b) {
-        sm.pa[f] = (unsigned char)a;
-        sm.pb[f] = (unsigned char)b;
-        ++f;
+  using G = Geo<D>;
+  for (int e = threadIdx.x; e < G::NE; e += NW * 64) {
+    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
+    const int f = 4 * (4 * kb4 + comp) + lane / 16;
+    int ia = D + 1, ib = D + 1;  // zero
+    if (f < G::NP) {
+      int a = 0, rem = f;
+      while (rem >= D - a) {
+        rem -= D - a;
+        ++a;
       }
+      ia = a;
+      ib = a + rem;
+    } else if (f < G::NP + D) {
+      ia = f - G::NP;
+      ib = D;
+    } else if (f == G::NP + D) {
+      ia = D;
+      ib = D;
+    } else if (f >= 4 * G::KQB && f < 4 * G::KQB + D) {
+      ia = f - 4 * G::KQB;
+      ib = D;
+    } else if (f == 4 * G::KQB + D) {
+      ia = D;
+      ib = D;
+    }
+    sm.fsrc[e] = (unsigned short)((ia << 8) | ib);
   }
+  if (threadIdx.x == 0) sm.redo = 0;
 }
 
-// Stage 1 (all lanes): A fragments from sm.z; resets the partial statistics.
+// Stage 1 (all lanes): A fragments from sm.z; resets the partial sums.
 template <int D, int MT, int NW>
 __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
   using G = Geo<D>;
-  constexpr int NE = MT * G::KB4 * 64 * 4;
   float *Af = (float *)&sm.A[0][0][0];
-  for (int e = threadIdx.x; e < NE; e += NW * 64) {
-    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = (e >> 8) % G::KB4, mt = (e >> 8) / G::KB4;
-    const int kb = 4 * kb4 + comp, f = 4 * kb + lane / 16, row = 16 * mt + (lane & 15);
-    float v = 0.0f;
-    if (f < G::NP) {
-      v = sm.z[row][sm.pa[f]] * sm.z[row][sm.pb[f]];
-    } else if (f < G::NP + D) {
-      v = sm.z[row][f - G::NP];
-    } else if (f == G::NP + D) {
-      v = 1.0f;
-    } else if (f >= 4 * G::KQB) {
-      const int g = f - 4 * G::KQB;
-      v = g < D ? sm.z[row][g] : (g == D ? 1.0f : 0.0f);
-    }
-    Af[e] = v;
+  for (int e = threadIdx.x; e < MT * G::NE; e += NW * 64) {
+    const int mt = e / G::NE, el = e - mt * G::NE;
+    const int row = 16 * mt + ((el >> 2) & 15);
+    const unsigned src = sm.fsrc[el];
+    Af[e] = sm.z[row][src >> 8] * sm.z[row][src & 0xFF];
   }
-  MixStat<float> *pp = &sm.part[0][0][0];
+  Acc *pp = &sm.part[0][0][0];
   for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW>::ROWS; i += NW * 64)
-    pp[i] = mix_empty<float>();
-}
-
-__device__ __forceinline__ MixStat<float> shfl_xor_stat(const MixStat<float> &s, int mask) {
-  MixStat<float> r;
-  r.m = __shfl_xor(s.m, mask);
-  r.Z = __shfl_xor(s.Z, mask);
-  r.mu = __shfl_xor(s.mu, mask);
-  r.M2 = __shfl_xor(s.M2, mask);
-  r.S2 = __shfl_xor(s.S2, mask);
-  return r;
+    pp[i] = acc_empty();
 }
 
 // Stage 2 (each wave): its contiguous range of model tiles, one MFMA chain per
-// tile; statistics flushed per output into sm.part[wave][o][row].
+// tile; partial sums flushed per output into sm.part[wave][o][row].
 template <int D, int MT, int NW>
 __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW> &sm) {
   using G = Geo<D>;
+  constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
+  constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t0 = (int)((int64_t)wave * md.n_tiles / NW), t1 = (int)((int64_t)(wave + 1) * md.n_tiles / NW);
+  if (t0 >= t1) return;
   f32x4 A[MT][G::KB4];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -214,34 +275,45 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       const float4 v = sm.A[mt][q][lane];
       A[mt][q] = f32x4{v.x, v.y, v.z, v.w};
     }
-  const int t0 = (int)((int64_t)wave * md.n_tiles / NW), t1 = (int)((int64_t)(wave + 1) * md.n_tiles / NW);
-  if (t0 >= t1) return;
   int o = 0;
   while (o + 1 < md.n_out && t0 >= md.tile_off[o + 1]) ++o;
-  MixStat<float> st[MT][4];
+  // anchors of output o go into the lanes of the shift features
+  auto set_anchor = [&](int oo) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = 16 * mt + (lane & 15);
+      if ((lane >> 4) == GQS) A[mt][KQS / 4][KQS % 4] = -sm.mref[row][oo];
+      if ((lane >> 4) == GYS) A[mt][KYS / 4][KYS % 4] = -sm.yref[row][oo];
+    }
+  };
+  set_anchor(o);
+  Acc st[MT][4];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) st[mt][r] = mix_empty<float>();
+    for (int r = 0; r < 4; ++r) st[mt][r] = acc_empty();
 
   auto flush = [&](int oo) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        MixStat<float> s = st[mt][r];
-#pragma unroll
-        for (int msk = 8; msk >= 1; msk >>= 1) s = mix_merge<true>(s, shfl_xor_stat(s, msk));
+        Acc s;
+        s.Z = row_sum16(st[mt][r].Z);
+        s.S1 = row_sum16(st[mt][r].S1);
+        s.S2 = row_sum16(st[mt][r].S2);
+        s.S3 = row_sum16(st[mt][r].S3);
+        s.mx = row_max16(st[mt][r].mx);
         if ((lane & 15) == 0) sm.part[wave][oo][16 * mt + 4 * (lane >> 4) + r] = s;
-        st[mt][r] = mix_empty<float>();
+        st[mt][r] = acc_empty();
       }
   };
 
   // Software pipeline over tiles with two B buffers: the loads of tile i+1
   // are issued before the MFMA chain of tile i, and scheduling barriers keep
-  // the compiler from sinking them next to their use.
-  // sigma^2 of the lane's model column travels with its tile (loads complete
-  // in order, so a later load would make the wait drain the prefetch too).
+  // the compiler from sinking them next to their use.  sigma^2 of the lane's
+  // model column travels with its tile (loads complete in order, so a later
+  // load would make the wait drain the prefetch too).
   f32x4 B0[G::KB4], B1[G::KB4];
   float s2_0, s2_1;
   auto load_tile = [&](f32x4 (&Bd)[G::KB4], float &s2d, int tile) {
@@ -254,6 +326,7 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
     if (tile >= md.tile_off[o + 1]) {
       flush(o);
       while (tile >= md.tile_off[o + 1]) ++o;
+      set_anchor(o);
     }
     f32x4 qa[MT], qb[MT], ya[MT];
 #pragma unroll
@@ -283,7 +356,16 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) mix_add<true>(st[mt][r], qa[mt][r] + qb[mt][r], ya[mt][r], s2);
+      for (int r = 0; r < 4; ++r) {
+        const float a = qa[mt][r] + qb[mt][r], dd = ya[mt][r];
+        const float e = exp2f(a);
+        const float te = e * dd;
+        st[mt][r].Z += e;
+        st[mt][r].S1 += te;
+        st[mt][r].S2 = fmaf(te, dd, st[mt][r].S2);
+        st[mt][r].S3 = fmaf(e, s2, st[mt][r].S3);
+        st[mt][r].mx = fmaxf(st[mt][r].mx, a);
+      }
   };
 
   load_tile(B0, s2_0, t0);
@@ -301,16 +383,58 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   flush(o);
 }
 
-// Stage 3 (lanes < ROWS * n_out): fixed-order merge over waves.
+// Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, Eq. (1)
+// moments, next anchors; flags a second pass when an anchor was too far.
 template <int D, int MT, int NW>
 __device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out) {
   constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
   for (int i = threadIdx.x; i < ROWS * n_out; i += NW * 64) {
     const int row = i % ROWS, o = i / ROWS;
-    MixStat<float> s = sm.part[0][o][row];
+    Acc s = sm.part[0][o][row];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) s = mix_merge<true>(s, sm.part[w][o][row]);
-    mix_finish(s, &sm.mean[row][o], &sm.var[row][o]);
+    for (int w = 1; w < NW; ++w) {
+      const Acc &b = sm.part[w][o][row];
+      s.Z += b.Z;
+      s.S1 += b.S1;
+      s.S2 += b.S2;
+      s.S3 += b.S3;
+      s.mx = fmaxf(s.mx, b.mx);
+    }
+    const float d1 = s.S1 / s.Z;
+    const float mu = sm.yref[row][o] + d1;
+    sm.mean[row][o] = mu;
+    sm.var[row][o] = (s.S2 - s.S1 * d1 + s.S3) / s.Z;
+    if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo = 1;
+    // anchors for the next evaluation: the observed maximum and mean
+    sm.mref[row][o] += s.mx;
+    if (isfinite(mu)) sm.yref[row][o] = mu;
+  }
+}
+
+// The whole mixture of one step for the rows in sm.z: one pass, a second
+// one if an anchor was out of range or `force_second`.  Block-synchronous.
+template <int D, int MT, int NW>
+__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW> &sm,
+                                             bool force_second) {
+  for (int pass = 0; pass < 2; ++pass) {
+    build_fragments(sm);
+    __syncthreads();
+    mixture_tiles(md, sm);
+    __syncthreads();
+    merge_waves(sm, md.n_out);
+    __syncthreads();
+    const bool again = pass == 0 && (force_second || sm.redo != 0);
+    __syncthreads();
+    if (threadIdx.x == 0) sm.redo = 0;
+    if (!again) break;
+  }
+}
+
+template <int D, int MT, int NW>
+__device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW> &sm) {
+  for (int i = threadIdx.x; i < MixSmem<D, MT, NW>::ROWS * kMaxOut; i += NW * 64) {
+    (&sm.mref[0][0])[i] = 0.0f;
+    (&sm.yref[0][0])[i] = 0.0f;
   }
 }
 
@@ -322,18 +446,14 @@ __global__ void __launch_bounds__(NW * 64) predict_mfma_kernel(MfmaModel md, con
   __shared__ MixSmem<D, MT, NW> sm;
   constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
   mix_setup(sm);
+  reset_anchors(sm);
   const int64_t n0 = (int64_t)blockIdx.x * ROWS;
-  for (int i = threadIdx.x; i < ROWS * D; i += NW * 64) {
-    const int row = i / D, a = i % D;
-    sm.z[row][a] = (n0 + row < N) ? Z[(n0 + row) * D + a] : 0.0f;
+  for (int i = threadIdx.x; i < ROWS * (D + 2); i += NW * 64) {
+    const int row = i / (D + 2), a = i % (D + 2);
+    sm.z[row][a] = a < D ? ((n0 + row < N) ? Z[(n0 + row) * D + a] : 0.0f) : (a == D ? 1.0f : 0.0f);
   }
   __syncthreads();
-  build_fragments(sm);
-  __syncthreads();
-  mixture_tiles(md, sm);
-  __syncthreads();
-  merge_waves(sm, md.n_out);
-  __syncthreads();
+  mixture_step(md, sm, true);
   for (int i = threadIdx.x; i < ROWS * md.n_out; i += NW * 64) {
     const int row = i / md.n_out, o = i % md.n_out;
     if (n0 + row < N) {
@@ -374,10 +494,13 @@ struct Dims<kDynQuad12> {
   static constexpr int NX = 12, NU = 4, NO = 6, D = 16;
 };
 
+constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
+
 // One workgroup owns `spw` (<= 16*MT) sub-rollouts for the whole horizon.
-// Per step: rows draw their noise and form z (A fragments), the waves run the
-// model tiles, statistics are merged, and each row samples its accelerations,
-// steps Euler and writes dt*q(x_{t+1}).
+// Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS.
+// Per step: rows form z, the waves run the model tiles, partial sums are
+// merged, and each row samples its accelerations, steps Euler and writes
+// dt*q(x_{t+1}).
 template <int DYN, int MT, int NW>
 __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
                                                                int spw) {
@@ -386,54 +509,78 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
   constexpr int ROWS = 16 * MT;
   __shared__ MixSmem<D, MT, NW> sm;
   __shared__ float xs[ROWS][NX];
-  __shared__ float xis[ROWS][8];
-  __shared__ float obs[3 * kMaxObs];
+  __shared__ float eps_s[kNoiseChunk][ROWS][4];
+  __shared__ float xi_s[kNoiseChunk][ROWS][8];
   const ProbDev<float> &p = ra.p;
   mix_setup(sm);
-  for (int i = threadIdx.x; i < 3 * p.n_obs; i += NW * 64) obs[i] = p.obs[i];
+  reset_anchors(sm);
   const int row = threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * spw + row;
-  const bool is_row = row < spw;
-  const bool active = is_row && s < (int64_t)p.K * p.Ms;
-  const uint32_t k = active ? (uint32_t)(s / p.Ms) : 0u, mm = active ? (uint32_t)(s % p.Ms) : 0u;
+  const int64_t s_base = (int64_t)blockIdx.x * spw;
+  const int64_t s = s_base + row;
+  const bool active = row < spw && s < (int64_t)p.K * p.Ms;
   const uint32_t it = *ra.iter;
   const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it);
   const uint32_t wd = stream_word(kTagDyn, p.problem_id, it);
-  if (row < ROWS)
+  if (row < ROWS) {
     for (int a = 0; a < NX; ++a) xs[row][a] = ra.x0[a];
+    sm.z[row][D] = 1.0f;
+    sm.z[row][D + 1] = 0.0f;
+  }
   for (int t = 0; t < p.T; ++t) {
+    const int tc = t % kNoiseChunk;
+    if (tc == 0) {
+      // draw the next chunk: one lane per (step, row, counter block)
+      constexpr int NB = 1 + (NO + 3) / 4;
+      for (int i = threadIdx.x; i < kNoiseChunk * ROWS * NB; i += NW * 64) {
+        const int blk = i % NB, rr = (i / NB) % ROWS, cc = i / (NB * ROWS);
+        const int64_t ss = s_base + rr;
+        const bool act = rr < spw && ss < (int64_t)p.K * p.Ms && t + cc < p.T;
+        if (!act) continue;
+        const uint32_t kk = (uint32_t)(ss / p.Ms), mm = (uint32_t)(ss % p.Ms);
+        if (blk == 0) {
+          normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), &eps_s[cc][rr][0]);
+        } else if (p.M > 0) {
+          // counter block blk-1 of the sub-rollout's draw: normals 4(blk-1) .. 4(blk-1)+3
+          const Philox4 r4 = philox4x32_10((uint32_t)(t + cc), kk, (mm << 4) | (uint32_t)(blk - 1), wd,
+                                           p.key0, p.key1);
+          float s0, c0, s1, c1;
+          const float rad0 = sqrtf(-2.0f * logf(unit_open<float>(r4.v[0])));
+          const float rad1 = sqrtf(-2.0f * logf(unit_open<float>(r4.v[2])));
+          sincos_2pi(unit_open<float>(r4.v[1]), &s0, &c0);
+          sincos_2pi(unit_open<float>(r4.v[3]), &s1, &c1);
+          float *dst = &xi_s[cc][rr][4 * (blk - 1)];
+          dst[0] = rad0 * c0;
+          dst[1] = rad0 * s0;
+          dst[2] = rad1 * c1;
+          dst[3] = rad1 * s1;
+        }
+      }
+      __syncthreads();
+    }
     if (row < ROWS) {
       if (active) {
-        float eps[4];
-        normals<float, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)t, eps);
 #pragma unroll
         for (int a = 0; a < NX; ++a) sm.z[row][a] = xs[row][a];
 #pragma unroll
-        for (int a = 0; a < NU; ++a) sm.z[row][NX + a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps[a];
-        if (p.M > 0) normals<float, NO>(p.key0, p.key1, wd, k, mm, (uint32_t)t, xis[row]);
+        for (int a = 0; a < NU; ++a) sm.z[row][NX + a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps_s[tc][row][a];
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) sm.z[row][a] = 0.0f;
       }
     }
     __syncthreads();
-    build_fragments(sm);
-    __syncthreads();
-    mixture_tiles(md, sm);
-    __syncthreads();
-    merge_waves(sm, NO);
-    __syncthreads();
+    mixture_step(md, sm, t == 0);
     if (active) {
       float acc[NO], xn[NX], x[NX];
 #pragma unroll
       for (int o = 0; o < NO; ++o)
-        acc[o] = p.M > 0 ? sm.mean[row][o] + sqrtf(sm.var[row][o]) * xis[row][o] : sm.mean[row][o];
+        acc[o] = p.M > 0 ? sm.mean[row][o] + sqrtf(sm.var[row][o]) * xi_s[tc][row][o] : sm.mean[row][o];
 #pragma unroll
       for (int a = 0; a < NX; ++a) x[a] = xs[row][a];
       euler_step<float>(DYN, p.dt, x, acc, xn);
 #pragma unroll
       for (int a = 0; a < NX; ++a) xs[row][a] = xn[a];
-      ra.cost[s * p.T + t] = p.dt * state_cost<float>(p, obs, xn);
+      ra.cost[s * p.T + t] = p.dt * state_cost<float>(p, p.obs, xn);
     }
   }
 }

@@ -397,10 +397,9 @@ def test_trajectory_weighting_uses_the_first_row():
     assert np.allclose(Wt, np.repeat(Wc[:1], prob.T, 0), rtol=1e-14)
 
 
-def test_rh_shift_moves_the_plan_and_advances_iter():
+def test_rh_shift_moves_the_plan():
     prob, model = synth.tiny_problem(8, K=2, T=5)
-    x, u, it = oracle.rh_shift(prob, model, prob.x0, prob.u_nom, 3)
-    assert it == 4
+    x, u = oracle.rh_shift(prob, model, prob.x0, prob.u_nom, 3)
     assert np.array_equal(u[:-1], prob.u_nom[1:]) and np.array_equal(u[-1], prob.u_nom[-1])
     # velocities change by dt * a, positions by dt * v (v0 = 0)
     assert np.allclose(x[:2], prob.x0[:2]) and not np.allclose(x[2:], prob.x0[2:])
