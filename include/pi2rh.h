@@ -162,23 +162,28 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
                              void *J, void *g_u_nom, void *g_centre, void *g_metric, void *ws,
                              size_t ws_bytes, void *stream);
 
-/* Batched rollouts of B independent problems in one persistent launch.
- * Step 1: pi_batched_plan fills a caller-owned HOST buffer (size from
- * pi_batched_plan_bytes) with per-problem descriptors and a work list of
- * (problem, sample tile) items ordered by decreasing cost.  Step 2: the
- * caller copies that buffer to device memory of the same size.  Step 3:
- * pi_rollout_cost_batched runs every item and writes each problem's
- * cost[b] (dev [K_b][T_b]) exactly as pi_rollout_cost would.  Per-problem
- * arrays are given as host arrays of B device pointers.  All problems must be
- * PI_F32.                                                                    */
+/* Batched rollouts of B independent problems in one persistent launch
+ * (problems may differ in K, T, M, models, obstacles and start states).
+ * Step 1: size the caller-owned workspace (pi_batched_workspace_bytes) and
+ * the HOST plan buffer (pi_batched_plan_bytes).  Step 2: pi_batched_plan
+ * fills the plan with per-problem descriptors and a work list of
+ * (problem, sample tile) items ordered by decreasing work; it records the
+ * workspace and every per-problem device pointer.  Step 3: the caller copies
+ * the plan to device memory of the same size.  Step 4:
+ * pi_rollout_cost_batched runs every item -- one workgroup per item, pulled
+ * from a queue by a persistent grid -- and writes each problem's cost[b]
+ * (dev [K_b][T_b]) exactly as pi_rollout_cost would.  Per-problem arrays are
+ * host arrays of B device pointers.  All problems must be PI_F32 and
+ * PI_DYN_QUAD12; tile_samples/tile_waves of problem 0 apply to the batch.
+ * The plan, workspace and every recorded pointer must stay valid while a
+ * launch that uses them is in flight.                                        */
+size_t pi_batched_workspace_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m);
 size_t pi_batched_plan_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m);
 pi_status pi_batched_plan(int32_t B, const pi_problem *p, const pi_lwpr *m,
                           const void *const *x0, const void *const *u_nom,
-                          const uint32_t *const *iter, void *const *cost, void *plan_host,
-                          size_t plan_bytes);
-size_t pi_batched_workspace_bytes(const void *plan_host);
-pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *ws,
-                                  size_t ws_bytes, void *stream);
+                          const uint32_t *const *iter, void *const *cost, void *ws,
+                          size_t ws_bytes, void *plan_host, size_t plan_bytes);
+pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *stream);
 
 /* Streams of the counter-based generator (see pi_noise). */
 enum { PI_TAG_CTRL = 0, PI_TAG_DYN = 1, PI_TAG_PLANT = 2 };

@@ -31,9 +31,9 @@ STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4:
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6)}
 EXPORTED = ["pi_workspace_bytes", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
-            "pi_rollout_adjoint", "pi_batched_plan_bytes", "pi_batched_plan",
-            "pi_batched_workspace_bytes", "pi_rollout_cost_batched", "pi_philox4x32_10",
-            "pi_noise", "pi_last_error", "pi_version"]
+            "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
+            "pi_batched_plan", "pi_rollout_cost_batched", "pi_philox4x32_10", "pi_noise",
+            "pi_last_error", "pi_version"]
 PI_TAG_CTRL, PI_TAG_DYN, PI_TAG_PLANT = 0, 1, 2
 
 
@@ -83,10 +83,10 @@ def load(path: str = LIB_PATH):
     lib.pi_rollout_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_batched_plan_bytes.argtypes = [i32, vp, vp]
     lib.pi_batched_plan_bytes.restype = sz
-    lib.pi_batched_plan.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz]
-    lib.pi_batched_workspace_bytes.argtypes = [vp]
+    lib.pi_batched_workspace_bytes.argtypes = [i32, vp, vp]
     lib.pi_batched_workspace_bytes.restype = sz
-    lib.pi_rollout_cost_batched.argtypes = [vp, vp, vp, sz, vp]
+    lib.pi_batched_plan.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz, vp, sz]
+    lib.pi_rollout_cost_batched.argtypes = [vp, vp, vp]
     lib.pi_philox4x32_10.argtypes = [vp, C.c_uint64, vp, i64, vp]
     lib.pi_noise.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.pi_last_error.restype = C.c_char_p
@@ -317,6 +317,41 @@ def iteration(prob: DeviceProblem, model: DeviceModel, cost=None):
     cost = rollout_cost(prob, model, out=cost)
     update(prob, cost)
     return cost
+
+
+class BatchedRollout:
+    """Rollouts of many independent problems in one persistent launch
+    (pi_rollout_cost_batched).  The plan records the device pointers of every
+    problem's x0, u_nom, iter and cost, so those tensors must stay alive."""
+
+    def __init__(self, problems, models, costs=None):
+        torch = _torch()
+        lib = load()
+        self.problems, self.models = list(problems), list(models)
+        B = len(self.problems)
+        self.ps = (pi_problem * B)(*[p.struct() for p in self.problems])
+        self.ms = (pi_lwpr * B)(*[m.struct() for m in self.models])
+        dev = self.problems[0].device
+        self.costs = costs if costs is not None else [
+            torch.empty((p.K, p.T), dtype=torch.float32, device=dev) for p in self.problems]
+        nws = lib.pi_batched_workspace_bytes(B, self.ps, self.ms)
+        npl = lib.pi_batched_plan_bytes(B, self.ps, self.ms)
+        if nws == C.c_size_t(-1).value or npl == C.c_size_t(-1).value:
+            raise PiError(2, last_error())
+        self.ws = torch.empty(max(int(nws), 256), dtype=torch.uint8, device=dev)
+        self.plan_host = np.zeros(int(npl), dtype=np.uint8)
+        arr = lambda xs: (C.c_void_p * B)(*[int(x) for x in xs])
+        _check(lib.pi_batched_plan(B, self.ps, self.ms, arr(p.x0.data_ptr() for p in self.problems),
+                                   arr(p.u_nom.data_ptr() for p in self.problems),
+                                   arr(p.iter.data_ptr() for p in self.problems),
+                                   arr(c.data_ptr() for c in self.costs), self.ws.data_ptr(),
+                                   self.ws.numel(), self.plan_host.ctypes.data, self.plan_host.size))
+        self.plan_dev = torch.from_numpy(self.plan_host).to(dev)
+
+    def run(self):
+        _check(load().pi_rollout_cost_batched(self.plan_host.ctypes.data, self.plan_dev.data_ptr(),
+                                              _stream()))
+        return self.costs
 
 
 def philox4x32_10(ctr, key: int):

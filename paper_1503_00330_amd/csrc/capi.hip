@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -214,6 +215,62 @@ pi_status check_ws(void *ws, size_t ws_bytes, size_t need) {
   return PI_OK;
 }
 
+// ---- batched plan layout ------------------------------------------------------
+constexpr uint32_t kPlanMagic = 0x50493252u;  // "PI2R"
+
+struct PlanHeader {
+  uint32_t magic;
+  int32_t B, n_items, spw, waves, pad;
+  size_t plan_bytes, probs_off, items_off, queue_off;
+  void *ws;
+};
+
+struct PlanProblemHost {
+  ModelArgs margs;
+  MfmaLayout layout;
+  size_t fold_off, sub_off;
+  int K, T, Ms;
+  void *cost;
+};
+
+struct BatchSizes {
+  int spw, waves, n_items;
+  size_t ws_bytes, plan_bytes, host_off, probs_off, items_off, queue_off;
+};
+
+pi_status batch_sizes(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchSizes *out) {
+  if (B < 1 || B > (1 << 20)) return fail(PI_ERR_SHAPE, "B=%d outside [1, 2^20]", B);
+  if (!p || !m) return fail(PI_ERR_NULL, "problem and model arrays must be non-NULL");
+  for (int b = 0; b < B; ++b) {
+    pi_status st = check_pair(&p[b], &m[b]);
+    if (st != PI_OK) return fail(st, "problem %d: %s", b, g_err);
+    if (p[b].dtype != PI_F32 || p[b].dyn != PI_DYN_QUAD12)
+      return fail(PI_ERR_UNSUPPORTED, "problem %d: batched rollouts need float32 quadrotor problems", b);
+  }
+  BatchSizes bs;
+  bs.spw = p[0].tile_samples > 0 ? p[0].tile_samples : 16;
+  bs.waves = p[0].tile_waves > 0 ? p[0].tile_waves : 4;
+  if (bs.waves == 8 && bs.spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
+  int64_t n = 0;
+  size_t ws = 0;
+  for (int b = 0; b < B; ++b) {
+    const int Ms = p[b].M > 0 ? p[b].M : 1;
+    n += ((int64_t)p[b].K * Ms + bs.spw - 1) / bs.spw;
+    ws += mfma_layout(m[b].d, m[b].n_out, m[b].L_off).bytes;
+    if (Ms > 1) ws += align_up((size_t)p[b].K * Ms * p[b].T * 4, 256);
+  }
+  if (n > INT32_MAX) return fail(PI_ERR_SHAPE, "too many work items");
+  bs.n_items = (int)n;
+  bs.queue_off = ws;
+  bs.ws_bytes = ws + 256;
+  bs.host_off = align_up(sizeof(PlanHeader), 64);
+  bs.probs_off = align_up(bs.host_off + (size_t)B * sizeof(PlanProblemHost), 256);
+  bs.items_off = align_up(bs.probs_off + (size_t)B * sizeof(BatchedProblem), 256);
+  bs.plan_bytes = align_up(bs.items_off + (size_t)n * sizeof(BatchedItem), 256);
+  *out = bs;
+  return PI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -382,21 +439,111 @@ pi_status pi_noise(const pi_problem *p, int32_t tag, const uint32_t *iter, int32
   return launched(e, "pi_noise");
 }
 
-size_t pi_batched_plan_bytes(int32_t, const pi_problem *, const pi_lwpr *) {
-  fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
-  return (size_t)-1;
+size_t pi_batched_workspace_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m) {
+  BatchSizes bs;
+  if (batch_sizes(B, p, m, &bs) != PI_OK) return (size_t)-1;
+  return bs.ws_bytes;
 }
 
-pi_status pi_batched_plan(int32_t, const pi_problem *, const pi_lwpr *, const void *const *,
-                          const void *const *, const uint32_t *const *, void *const *, void *,
-                          size_t) {
-  return fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
+size_t pi_batched_plan_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m) {
+  BatchSizes bs;
+  if (batch_sizes(B, p, m, &bs) != PI_OK) return (size_t)-1;
+  return bs.plan_bytes;
 }
 
-size_t pi_batched_workspace_bytes(const void *) { return (size_t)-1; }
+pi_status pi_batched_plan(int32_t B, const pi_problem *p, const pi_lwpr *m, const void *const *x0,
+                          const void *const *u_nom, const uint32_t *const *iter, void *const *cost,
+                          void *ws, size_t ws_bytes, void *plan_host, size_t plan_bytes) {
+  BatchSizes bs;
+  PI_TRY(batch_sizes(B, p, m, &bs));
+  if (!x0 || !u_nom || !iter || !cost || !plan_host) return fail(PI_ERR_NULL, "NULL array argument");
+  for (int b = 0; b < B; ++b)
+    if (!x0[b] || !u_nom[b] || !iter[b] || !cost[b]) return fail(PI_ERR_NULL, "problem %d: NULL pointer", b);
+  PI_TRY(check_ws(ws, ws_bytes, bs.ws_bytes));
+  if (plan_bytes < bs.plan_bytes) return fail(PI_ERR_WORKSPACE, "plan buffer of %zu bytes needed", bs.plan_bytes);
+  char *base = (char *)plan_host;
+  memset(base, 0, bs.plan_bytes);
+  PlanHeader *h = (PlanHeader *)base;
+  PlanProblemHost *ph = (PlanProblemHost *)(base + bs.host_off);
+  BatchedProblem *bp = (BatchedProblem *)(base + bs.probs_off);
+  BatchedItem *items = (BatchedItem *)(base + bs.items_off);
+  h->magic = kPlanMagic;
+  h->B = B;
+  h->n_items = bs.n_items;
+  h->spw = bs.spw;
+  h->waves = bs.waves;
+  h->plan_bytes = bs.plan_bytes;
+  h->probs_off = bs.probs_off;
+  h->items_off = bs.items_off;
+  h->ws = ws;
+  h->queue_off = bs.queue_off;
+  size_t off = 0;
+  for (int b = 0; b < B; ++b) {
+    const MfmaLayout l = mfma_layout(m[b].d, m[b].n_out, m[b].L_off);
+    const int Ms = p[b].M > 0 ? p[b].M : 1;
+    ph[b].margs = model_args(&m[b]);
+    ph[b].layout = l;
+    ph[b].fold_off = off;
+    off += l.bytes;
+    ph[b].sub_off = Ms > 1 ? off : (size_t)-1;
+    if (Ms > 1) off += align_up((size_t)p[b].K * Ms * p[b].T * 4, 256);
+    ph[b].K = p[b].K;
+    ph[b].T = p[b].T;
+    ph[b].Ms = Ms;
+    ph[b].cost = cost[b];
+    bp[b].p = prob_dev<float>(&p[b]);
+    bp[b].x0 = (const float *)x0[b];
+    bp[b].u_nom = (const float *)u_nom[b];
+    bp[b].iter = iter[b];
+    bp[b].cost = Ms > 1 ? (float *)((char *)ws + ph[b].sub_off) : (float *)cost[b];
+    bp[b].md = mfma_model_view(l, (char *)ws + ph[b].fold_off);
+  }
+  // work list: problems by decreasing per-tile work (T * model tiles), tiles in order
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return (int64_t)ph[a].T * ph[a].layout.n_tiles > (int64_t)ph[c].T * ph[c].layout.n_tiles;
+  });
+  int n = 0;
+  for (int b : order) {
+    const int64_t ns = (int64_t)ph[b].K * ph[b].Ms;
+    for (int64_t s0 = 0; s0 < ns; s0 += bs.spw) {
+      items[n].b = b;
+      items[n].s_base = s0;
+      ++n;
+    }
+  }
+  return ok();
+}
 
-pi_status pi_rollout_cost_batched(const void *, const void *, void *, size_t, void *) {
-  return fail(PI_ERR_UNSUPPORTED, "batched rollouts: not available in this build");
+pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *stream) {
+  if (!plan_host || !plan_dev) return fail(PI_ERR_NULL, "plan_host and plan_dev must be non-NULL");
+  const char *base = (const char *)plan_host;
+  const PlanHeader *h = (const PlanHeader *)base;
+  if (h->magic != kPlanMagic) return fail(PI_ERR_VALUE, "plan_host is not a batched plan");
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  const PlanProblemHost *ph = (const PlanProblemHost *)(base + align_up(sizeof(PlanHeader), 64));
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < h->B && e == hipSuccess; ++b)
+    e = launch_fold_mfma(PI_F32, ph[b].margs, ph[b].layout, (char *)h->ws + ph[b].fold_off, s);
+  int *queue = (int *)((char *)h->ws + h->queue_off);
+  if (e == hipSuccess) e = launch_zero_int(queue, s);
+  if (e == hipSuccess) {
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = h->waves == 8 ? 1 : 2;
+    const int grid = std::max(1, std::min(h->n_items, ncu * per_cu));
+    e = launch_rollout_batched((const BatchedProblem *)((const char *)plan_dev + h->probs_off),
+                               (const BatchedItem *)((const char *)plan_dev + h->items_off), h->n_items,
+                               h->spw, h->waves, grid, queue, s);
+  }
+  for (int b = 0; b < h->B && e == hipSuccess; ++b)
+    if (ph[b].Ms > 1)
+      e = launch_subcost_reduce(PI_F32, (char *)h->ws + ph[b].sub_off, ph[b].cost, ph[b].K, ph[b].Ms,
+                                ph[b].T, s);
+  return launched(e, "pi_rollout_cost_batched");
 }
 
 }  // extern "C"

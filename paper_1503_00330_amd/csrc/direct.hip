@@ -571,6 +571,13 @@ hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, con
              : rh_shift_t<float>(*(const ProbDev<float> *)pargs, m, rec, part, x0, u_nom, iter, s);
 }
 
+// Clears one counter with a kernel (graph-capture friendly, no memset node).
+__global__ void zero_int_kernel(int *p) { *p = 0; }
+hipError_t launch_zero_int(int *p, hipStream_t s) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, p);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ stream access
 __global__ void philox_kernel(const uint32_t *__restrict__ ctr, uint32_t k0, uint32_t k1,
                               uint32_t *__restrict__ out, int64_t N) {

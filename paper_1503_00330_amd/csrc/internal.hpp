@@ -125,6 +125,26 @@ hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, con
                            void *part, void *x0, void *u_nom, const uint32_t *iter, hipStream_t s);
 size_t shift_partial_bytes(const ModelArgs &m, int dtype);
 
+// ---- batched rollouts --------------------------------------------------------
+// Device descriptor of one problem of a batch and one work item (a tile of
+// `spw` consecutive sub-rollouts of problem b).
+struct BatchedProblem {
+  ProbDev<float> p;
+  const float *x0, *u_nom;
+  const uint32_t *iter;
+  float *cost;          // [K][T] (M <= 1) or the sub-rollout cost area in the workspace
+  MfmaModel md;         // folded model inside the workspace
+};
+struct BatchedItem {
+  int b;
+  int pad;
+  int64_t s_base;
+};
+MfmaModel mfma_model_view(const MfmaLayout &l, const void *base);
+hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
+                                  int spw, int waves, int grid, int *queue, hipStream_t s);
+hipError_t launch_zero_int(int *p, hipStream_t s);
+
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
                          hipStream_t s);
 hipError_t launch_noise(int dtype, const void *pargs, int tag, const uint32_t *iter, int k0, int nk,

@@ -496,33 +496,38 @@ struct Dims<kDynQuad12> {
 
 constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
 
-// One workgroup owns `spw` (<= 16*MT) sub-rollouts for the whole horizon.
+template <int DYN, int MT, int NW>
+struct RollSmem {
+  static constexpr int ROWS = 16 * MT;
+  MixSmem<Dims<DYN>::D, MT, NW> sm;
+  float xs[ROWS][Dims<DYN>::NX];
+  float eps_s[kNoiseChunk][ROWS][4];
+  float xi_s[kNoiseChunk][ROWS][8];
+};
+
+// Rollouts s_base .. s_base + spw - 1 of one problem for its whole horizon.
 // Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS.
 // Per step: rows form z, the waves run the model tiles, partial sums are
 // merged, and each row samples its accelerations, steps Euler and writes
-// dt*q(x_{t+1}).
+// dt*q(x_{t+1}).  Block-synchronous; rs.sm must have been set up.
 template <int DYN, int MT, int NW>
-__global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
-                                                               int spw) {
+__device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
+                             const float *__restrict__ x0, const float *__restrict__ u_nom,
+                             uint32_t it, float *__restrict__ cost, const MfmaModel &md,
+                             int64_t s_base, int spw) {
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
-  __shared__ MixSmem<D, MT, NW> sm;
-  __shared__ float xs[ROWS][NX];
-  __shared__ float eps_s[kNoiseChunk][ROWS][4];
-  __shared__ float xi_s[kNoiseChunk][ROWS][8];
-  const ProbDev<float> &p = ra.p;
-  mix_setup(sm);
+  MixSmem<D, MT, NW> &sm = rs.sm;
+  __syncthreads();  // the previous tile (persistent use) is done with LDS
   reset_anchors(sm);
   const int row = threadIdx.x;
-  const int64_t s_base = (int64_t)blockIdx.x * spw;
   const int64_t s = s_base + row;
   const bool active = row < spw && s < (int64_t)p.K * p.Ms;
-  const uint32_t it = *ra.iter;
   const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it);
   const uint32_t wd = stream_word(kTagDyn, p.problem_id, it);
   if (row < ROWS) {
-    for (int a = 0; a < NX; ++a) xs[row][a] = ra.x0[a];
+    for (int a = 0; a < NX; ++a) rs.xs[row][a] = x0[a];
     sm.z[row][D] = 1.0f;
     sm.z[row][D + 1] = 0.0f;
   }
@@ -538,7 +543,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
         if (!act) continue;
         const uint32_t kk = (uint32_t)(ss / p.Ms), mm = (uint32_t)(ss % p.Ms);
         if (blk == 0) {
-          normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), &eps_s[cc][rr][0]);
+          normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), &rs.eps_s[cc][rr][0]);
         } else if (p.M > 0) {
           // counter block blk-1 of the sub-rollout's draw: normals 4(blk-1) .. 4(blk-1)+3
           const Philox4 r4 = philox4x32_10((uint32_t)(t + cc), kk, (mm << 4) | (uint32_t)(blk - 1), wd,
@@ -548,7 +553,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
           const float rad1 = sqrtf(-2.0f * logf(unit_open<float>(r4.v[2])));
           sincos_2pi(unit_open<float>(r4.v[1]), &s0, &c0);
           sincos_2pi(unit_open<float>(r4.v[3]), &s1, &c1);
-          float *dst = &xi_s[cc][rr][4 * (blk - 1)];
+          float *dst = &rs.xi_s[cc][rr][4 * (blk - 1)];
           dst[0] = rad0 * c0;
           dst[1] = rad0 * s0;
           dst[2] = rad1 * c1;
@@ -560,9 +565,9 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
     if (row < ROWS) {
       if (active) {
 #pragma unroll
-        for (int a = 0; a < NX; ++a) sm.z[row][a] = xs[row][a];
+        for (int a = 0; a < NX; ++a) sm.z[row][a] = rs.xs[row][a];
 #pragma unroll
-        for (int a = 0; a < NU; ++a) sm.z[row][NX + a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps_s[tc][row][a];
+        for (int a = 0; a < NU; ++a) sm.z[row][NX + a] = u_nom[t * NU + a] + p.noise_std[a] * rs.eps_s[tc][row][a];
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) sm.z[row][a] = 0.0f;
@@ -574,14 +579,49 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
       float acc[NO], xn[NX], x[NX];
 #pragma unroll
       for (int o = 0; o < NO; ++o)
-        acc[o] = p.M > 0 ? sm.mean[row][o] + sqrtf(sm.var[row][o]) * xi_s[tc][row][o] : sm.mean[row][o];
+        acc[o] = p.M > 0 ? sm.mean[row][o] + sqrtf(sm.var[row][o]) * rs.xi_s[tc][row][o] : sm.mean[row][o];
 #pragma unroll
-      for (int a = 0; a < NX; ++a) x[a] = xs[row][a];
+      for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
       euler_step<float>(DYN, p.dt, x, acc, xn);
 #pragma unroll
-      for (int a = 0; a < NX; ++a) xs[row][a] = xn[a];
-      ra.cost[s * p.T + t] = p.dt * state_cost<float>(p, p.obs, xn);
+      for (int a = 0; a < NX; ++a) rs.xs[row][a] = xn[a];
+      cost[s * p.T + t] = p.dt * state_cost<float>(p, p.obs, xn);
     }
+  }
+}
+
+// One workgroup per tile of `spw` (<= 16*MT) sub-rollouts.
+template <int DYN, int MT, int NW>
+__global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
+                                                               int spw) {
+  __shared__ RollSmem<DYN, MT, NW> rs;
+  mix_setup(rs.sm);
+  rollout_tile<DYN, MT, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
+                            (int64_t)blockIdx.x * spw, spw);
+}
+
+// Persistent form for many independent problems: every workgroup pulls
+// (problem, tile) items from a queue (items are ordered by decreasing work)
+// until the queue is empty.  Each item is exactly a plain rollout tile.
+template <int DYN, int MT, int NW>
+__global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedProblem *__restrict__ probs,
+                                                                  const BatchedItem *__restrict__ items,
+                                                                  int n_items, int spw,
+                                                                  int *__restrict__ queue) {
+  __shared__ RollSmem<DYN, MT, NW> rs;
+  __shared__ int item_s;
+  mix_setup(rs.sm);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = atomicAdd(queue, 1);
+    __syncthreads();
+    const int item = item_s;
+    if (item >= n_items) break;
+    const BatchedItem it = items[item];
+    const BatchedProblem &bp = probs[it.b];
+    const ProbDev<float> p = bp.p;
+    const MfmaModel md = bp.md;
+    rollout_tile<DYN, MT, NW>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, spw);
   }
 }
 
@@ -610,5 +650,24 @@ hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
   if (spw <= 16) return rollout_mfma_t<kDynPointMass2D, 1, 4>(ra, md, spw, s);
   return rollout_mfma_t<kDynPointMass2D, 2, 4>(ra, md, spw, s);
 }
+
+hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
+                                  int spw, int waves, int grid, int *queue, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  if (spw <= 16) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8>), dim3(grid), dim3(512), 0, s, probs,
+                         items, n_items, spw, queue);
+    else
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4>), dim3(grid), dim3(256), 0, s, probs,
+                         items, n_items, spw, queue);
+  } else {
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4>), dim3(grid), dim3(256), 0, s, probs,
+                       items, n_items, spw, queue);
+  }
+  return hipGetLastError();
+}
+
+MfmaModel mfma_model_view(const MfmaLayout &l, const void *base) { return mfma_view(l, base); }
 
 }  // namespace pi2rh

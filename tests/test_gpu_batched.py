@@ -1,0 +1,63 @@
+"""Batched persistent rollouts: each problem of an uneven batch gives exactly
+(bitwise) the costs of its own plain launch, and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import DYN_QUAD12
+
+torch = pytest.importorskip("torch")
+pi = pytest.importorskip("paper_1503_00330_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    yield
+    torch.cuda.synchronize()
+
+
+def _batch(spw=0, waves=0):
+    specs = [(33, 9, [20, 17, 33, 16, 1, 40], 1), (70, 5, 16, 2), (17, 12, 7, 1),
+             (128, 3, [64, 3, 9, 12, 30, 2], 0), (5, 7, 48, 1)]
+    out = []
+    for b, (K, T, L, M) in enumerate(specs):
+        prob, model = synth.tiny_problem(40 + b, dyn=DYN_QUAD12, L=L, R=4, K=K, T=T, M=M,
+                                         dtype=np.float32, n_obs=4 + b)
+        prob.problem_id = b
+        out.append((prob, model))
+    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves) for p, _ in out]
+    dms = [pi.DeviceModel(m) for _, m in out]
+    return out, dps, dms
+
+
+@pytest.mark.parametrize("spw,waves", [(0, 0), (8, 4), (16, 8), (32, 4)])
+def test_batched_equals_plain_launches(spw, waves):
+    host, dps, dms = _batch(spw, waves)
+    for dp in dps:
+        dp.iter.fill_(3)
+    br = pi.BatchedRollout(dps, dms)
+    costs = [c.clone() for c in br.run()]
+    for b, (dp, dm) in enumerate(zip(dps, dms)):
+        plain = pi.rollout_cost(dp, dm)
+        assert torch.equal(plain, costs[b]), b
+    # and against the oracle
+    for b, (prob, model) in enumerate(host):
+        ref = oracle.rollout_cost(prob, model, it=3)
+        g = costs[b].cpu().numpy().astype(np.float64)
+        r = np.abs(g.sum(1) - ref.sum(1)) / np.abs(ref.sum(1))
+        flips = np.abs(g - ref).max(1) > 0.25 * prob.dt * prob.obs_penalty
+        assert flips.sum() <= 1 and r[~flips].max() <= 1e-4, (b, r.max())
+
+
+def test_batched_rerun_is_repeatable():
+    _, dps, dms = _batch()
+    br = pi.BatchedRollout(dps, dms)
+    a = [c.clone() for c in br.run()]
+    b = br.run()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
