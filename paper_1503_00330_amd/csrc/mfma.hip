@@ -275,8 +275,26 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       const float4 v = sm.A[mt][q][lane];
       A[mt][q] = f32x4{v.x, v.y, v.z, v.w};
     }
-  int o = 0;
-  while (o + 1 < md.n_out && t0 >= md.tile_off[o + 1]) ++o;
+  // Output of a tile and the next output boundary, from compile-time indexed
+  // scans of tile_off (scalar registers): a runtime-indexed read would be a
+  // vector memory load whose wait would also drain the B prefetch.
+  auto output_of = [&](int tile) {
+    int oo = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxOut; ++i) oo += (i < md.n_out && md.tile_off[i] <= tile) ? 1 : 0;
+    return oo;
+  };
+  auto next_boundary = [&](int tile) {
+    int nb = md.n_tiles;
+#pragma unroll
+    for (int i = 1; i <= kMaxOut; ++i) {
+      const int v = md.tile_off[i];
+      nb = (v > tile && v < nb) ? v : nb;
+    }
+    return nb;
+  };
+  int o = output_of(t0);
+  int nb = next_boundary(t0);
   // anchors of output o go into the lanes of the shift features
   auto set_anchor = [&](int oo) {
 #pragma unroll
@@ -323,9 +341,10 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
     s2d = md.sig2[tile * 16 + (lane & 15)];
   };
   auto compute_tile = [&](const f32x4 (&Bc)[G::KB4], float s2, int tile) {
-    if (tile >= md.tile_off[o + 1]) {
+    if (tile >= nb) {
       flush(o);
-      while (tile >= md.tile_off[o + 1]) ++o;
+      o = output_of(tile);
+      nb = next_boundary(tile);
       set_anchor(o);
     }
     f32x4 qa[MT], qb[MT], ya[MT];
@@ -368,14 +387,16 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       }
   };
 
+  // Prefetches are unconditional (a clamped index re-reads the last tile) so
+  // that every wait counts exactly the loads issued after the needed ones.
   load_tile(B0, s2_0, t0);
   for (int tile = t0; tile < t1; tile += 2) {
-    if (tile + 1 < t1) load_tile(B1, s2_1, tile + 1);
+    load_tile(B1, s2_1, min(tile + 1, t1 - 1));
     __builtin_amdgcn_sched_barrier(0);
     compute_tile(B0, s2_0, tile);
     __builtin_amdgcn_sched_barrier(0);
     if (tile + 1 >= t1) break;
-    if (tile + 2 < t1) load_tile(B0, s2_0, tile + 2);
+    load_tile(B0, s2_0, min(tile + 2, t1 - 1));
     __builtin_amdgcn_sched_barrier(0);
     compute_tile(B1, s2_1, tile + 1);
     __builtin_amdgcn_sched_barrier(0);
