@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--cpu-rollouts", type=int, default=256)
     ap.add_argument("--tile-samples", type=int, default=0)
     ap.add_argument("--tile-waves", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy a 512 MiB buffer once (a plain copy kernel of "
+                         "known size for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -148,6 +151,13 @@ def main():
                      "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
                      "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model)},
     }
+    if args.calibrate_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, model, args.cpu_rollouts)
     print(json.dumps(out))

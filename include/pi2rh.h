@@ -154,9 +154,11 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
  * writes J (dev, one double) and its gradients w.r.t. the nominal controls
  * g_u_nom dev [T][n_u], the centres g_centre dev [Ltot][d] and every entry of
  * the metrics g_metric dev [Ltot][d][d] (problem dtype).  States are
- * checkpointed every `ckpt_every` steps (0: library's choice, about sqrt(T))
- * and recomputed segment by segment in the reverse sweep.  The indicator
- * obstacle term has zero derivative almost everywhere.                      */
+ * checkpointed every `ckpt_every` steps (0: ceil(sqrt(T))) and recomputed
+ * segment by segment in the reverse sweep.  pi_workspace_bytes(PI_OP_ADJOINT)
+ * sizes the workspace for the default checkpoint interval; another interval
+ * may need more (PI_ERR_WORKSPACE says how much).  The indicator obstacle
+ * term has zero derivative almost everywhere.                               */
 pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0,
                              const void *u_nom, const uint32_t *iter, int32_t ckpt_every,
                              void *J, void *g_u_nom, void *g_centre, void *g_metric, void *ws,

@@ -354,6 +354,37 @@ class BatchedRollout:
         return self.costs
 
 
+def rollout_adjoint(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, iter=None,
+                    ckpt_every: int = 0):
+    """J and (dJ/du_nom, dJ/dc, dJ/dD) of the expected rollout cost with the noise
+    held fixed (pi_rollout_adjoint)."""
+    torch = _torch()
+    lib = load()
+    x0 = prob.x0 if x0 is None else x0
+    u_nom = (prob.u_nom if u_nom is None else u_nom).contiguous()
+    it = prob.iter if iter is None else iter
+    dev = x0.device
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    gu = torch.empty_like(u_nom)
+    gc = torch.empty_like(model.centre)
+    gD = torch.empty_like(model.metric)
+    ps, ms = prob.struct(), model.struct()
+    need = workspace_bytes(PI_OP_ADJOINT, prob, model)
+    ws = workspace(need, dev)
+    st = lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it), int(ckpt_every),
+                                _ptr(J), _ptr(gu), _ptr(gc), _ptr(gD), _ptr(ws), ws.numel(), _stream())
+    if st == 5:   # a non-default checkpoint interval may need a larger workspace
+        import re
+        m = re.search(r"of (\d+) bytes needed", last_error())
+        if m:
+            ws = workspace(int(m.group(1)), dev)
+            st = lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it),
+                                        int(ckpt_every), _ptr(J), _ptr(gu), _ptr(gc), _ptr(gD), _ptr(ws),
+                                        ws.numel(), _stream())
+    _check(st)
+    return J, gu, gc, gD
+
+
 def philox4x32_10(ctr, key: int):
     """Raw Philox4x32-10 blocks for uint32 counters ctr [N][4] (a device int32 tensor)."""
     torch = _torch()

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpi2rh.so")
-SOURCES = ["capi.hip", "direct.hip", "mfma.hip"]
+SOURCES = ["capi.hip", "direct.hip", "mfma.hip", "adjoint.hip"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled: the compiler must not emit v_pk_*_f32
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

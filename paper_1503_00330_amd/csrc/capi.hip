@@ -296,8 +296,8 @@ size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
       return fold_bytes(m, false) + shift_partial_bytes(model_args(m), m->dtype);
     case PI_OP_ADJOINT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
-      fail(PI_ERR_UNSUPPORTED, "adjoint workspace: not available in this build");
-      return (size_t)-1;
+      return adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
+                              adjoint_default_ckpt(p->T));
   }
   fail(PI_ERR_VALUE, "unknown op %d", op);
   return (size_t)-1;
@@ -403,11 +403,30 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
   return launched(e, "pi_rh_shift");
 }
 
-pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *, const void *,
-                             const uint32_t *, int32_t, void *, void *, void *, void *, void *,
-                             size_t, void *) {
+pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
+                             const uint32_t *iter, int32_t ckpt_every, void *J, void *g_u_nom, void *g_centre,
+                             void *g_metric, void *ws, size_t ws_bytes, void *stream) {
   PI_TRY(check_pair(p, m));
-  return fail(PI_ERR_UNSUPPORTED, "pi_rollout_adjoint: not available in this build");
+  if (!x0 || !u_nom || !iter || !J || !g_u_nom || !g_centre || !g_metric)
+    return fail(PI_ERR_NULL, "x0, u_nom, iter, J and the gradient outputs must be non-NULL");
+  if (ckpt_every < 0) return fail(PI_ERR_VALUE, "ckpt_every=%d must be >= 0", ckpt_every);
+  const int ckpt = ckpt_every == 0 ? adjoint_default_ckpt(p->T) : std::min<int>(ckpt_every, p->T);
+  if ((int64_t)p->K * (p->M > 0 ? p->M : 1) * p->T > ((int64_t)1 << 36))
+    return fail(PI_ERR_SHAPE, "K*max(M,1)*T too large for the adjoint records");
+  PI_TRY(check_ws(ws, ws_bytes, adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
+                                                 ckpt)));
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  const ModelArgs a = model_args(m);
+  hipError_t e;
+  if (p->dtype == PI_F64) {
+    const ProbDev<double> d = prob_dev<double>(p);
+    e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws, s);
+  } else {
+    const ProbDev<float> d = prob_dev<float>(p);
+    e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws, s);
+  }
+  return launched(e, "pi_rollout_adjoint");
 }
 
 pi_status pi_philox4x32_10(const uint32_t *ctr, uint64_t key, uint32_t *out, int64_t N,

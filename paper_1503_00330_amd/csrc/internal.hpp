@@ -145,6 +145,13 @@ hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem
                                   int spw, int waves, int grid, int *queue, hipStream_t s);
 hipError_t launch_zero_int(int *p, hipStream_t s);
 
+// ---- adjoint -------------------------------------------------------------------
+int adjoint_default_ckpt(int T);
+size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt);
+hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
+                          const uint32_t *iter, int ckpt, double *J, void *gu, void *gc, void *gD, void *ws,
+                          hipStream_t s);
+
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
                          hipStream_t s);
 hipError_t launch_noise(int dtype, const void *pargs, int tag, const uint32_t *iter, int k0, int nk,
