@@ -1,0 +1,211 @@
+"""Measurements of the other workloads of the PI^2-RH hot path (one JSON line each).
+
+  --workload cfg0      point mass, FP64, K=256, T=20: per-iteration latency p50/p99
+                       (eager and HIP-graph replay)
+  --workload rh-graph  quadrotor, 6 x 1024 local models, K=65536, T=200: receding-
+                       horizon loop, one control step per HIP-graph replay;
+                       per-iteration latency p50/p99 and pi_update alone
+  --workload batched   64 quadrotor problems with uneven K, L, T and obstacles in one
+                       persistent launch vs 64 sequential plain launches
+  --workload adjoint   quadrotor, K=8192, T=400, checkpoints every 20: fused forward +
+                       adjoint (pi_rollout_adjoint) vs the forward rollout alone
+  --workload paper     the paper's GPU timing shapes (1000 rollouts x 50 steps, M sub-
+                       rollouts, 15/15/24 local models per output group)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12
+PEAK_FP64 = 78.6e12
+
+
+def flops_per_sample_step(model):
+    d = model.d
+    return model.Ltot * (d * d + 5 * d + 8)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def timed(fn, n, stream):
+    import torch
+    out = []
+    for _ in range(n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        out.append((a, b))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in out]
+
+
+def w_cfg0(args):
+    import torch
+    import paper_1503_00330_amd as pi
+    from paper_1503_00330_amd.rh import RHController
+    import synth
+    prob, model, _ = synth.config(0)
+    res = {}
+    for graph in (False, True):
+        dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+        c = RHController(dp, dm, iterations=1, graph=graph)
+        for _ in range(5):
+            c.step()
+        torch.cuda.synchronize()
+        ms = timed(c.step, args.steps, torch.cuda.current_stream())
+        res["graph" if graph else "eager"] = {"p50_us": pct(ms, 50) * 1e3, "p99_us": pct(ms, 99) * 1e3}
+    ss = prob.K * prob.T
+    return {"workload": "point mass FP64 PI2-RH iteration K=256 T=20 d=6 2x16 models",
+            "latency": res, "rollout_steps_per_s_graph": ss / (res["graph"]["p50_us"] * 1e-6),
+            "dtype": "f64"}
+
+
+def w_rh_graph(args):
+    import torch
+    import paper_1503_00330_amd as pi
+    from paper_1503_00330_amd.rh import RHController
+    import synth
+    prob, model, extra = synth.config(2)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    c = RHController(dp, dm, iterations=1, graph=True)
+    c.capture()
+    steps = args.steps or extra["rh_steps"]
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        c.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = timed(c.step, steps, stream)
+    wall = time.perf_counter() - t0
+    cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
+    pi.rollout_cost(dp, dm, out=cost)
+    upd = timed(lambda: pi.update(dp, cost), 10, stream)
+    roll = timed(lambda: pi.rollout_cost(dp, dm, out=cost), 2, stream)
+    ss = prob.K * prob.T
+    flop = flops_per_sample_step(model) * ss
+    return {"workload": "quadrotor RH loop, HIP graph per control step: K=65536 T=200 d=16 "
+                        "6x1024 models R=4 M=1",
+            "steps": steps, "iteration_ms_p50": pct(ms, 50), "iteration_ms_p99": pct(ms, 99),
+            "update_ms_p50": pct(upd, 50), "update_ms_p99": pct(upd, 99),
+            "rollout_ms": float(np.mean(roll)), "rollout_steps_per_s": ss / (float(np.mean(roll)) * 1e-3),
+            "rollout_tflops": flop / (float(np.mean(roll)) * 1e-3) / 1e12,
+            "rollout_frac_fp32_peak": flop / (float(np.mean(roll)) * 1e-3) / PEAK_FP32,
+            "wall_s": wall, "dtype": "f32"}
+
+
+def w_batched(args):
+    import torch
+    import paper_1503_00330_amd as pi
+    import synth
+    batch = synth.batched_config()
+    dps = [pi.DeviceProblem(p, tile_samples=args.tile_samples) for p, _ in batch]
+    dms = [pi.DeviceModel(m) for _, m in batch]
+    br = pi.BatchedRollout(dps, dms)
+    stream = torch.cuda.current_stream()
+    br.run()
+    costs = [torch.empty((p.K, p.T), dtype=torch.float32, device="cuda") for p in dps]
+
+    def seq():
+        for dp, dm, c in zip(dps, dms, costs):
+            pi.rollout_cost(dp, dm, out=c)
+    seq()
+    torch.cuda.synchronize()
+    tb = timed(br.run, args.steps or 3, stream)
+    ts = timed(seq, args.steps or 3, stream)
+    flop = sum(flops_per_sample_step(m) * p.K * p.T for p, m in batch)
+    ss = sum(p.K * p.T for p, _ in batch)
+    same = all(torch.equal(a, b) for a, b in zip(br.costs, costs))
+    return {"workload": "64 quadrotor problems, K in 512..16384, L in 64..1024 per output, "
+                        "T in 50..200, 10..40 obstacles",
+            "batched_ms": float(np.median(tb)), "sequential_ms": float(np.median(ts)),
+            "speedup": float(np.median(ts) / np.median(tb)),
+            "batched_rollout_steps_per_s": ss / (float(np.median(tb)) * 1e-3),
+            "batched_tflops": flop / (float(np.median(tb)) * 1e-3) / 1e12,
+            "batched_frac_fp32_peak": flop / (float(np.median(tb)) * 1e-3) / PEAK_FP32,
+            "bitwise_equal_to_plain": bool(same), "dtype": "f32"}
+
+
+def w_adjoint(args):
+    import torch
+    import paper_1503_00330_amd as pi
+    import synth
+    prob, model, extra = synth.config(4, obs_kind=synth.OBS_SMOOTH)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    stream = torch.cuda.current_stream()
+    cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
+    pi.rollout_cost(dp, dm, out=cost)
+    pi.rollout_adjoint(dp, dm, ckpt_every=extra["ckpt"])
+    torch.cuda.synchronize()
+    tf = timed(lambda: pi.rollout_cost(dp, dm, out=cost), args.steps or 3, stream)
+    ta = timed(lambda: pi.rollout_adjoint(dp, dm, ckpt_every=extra["ckpt"]), args.steps or 3, stream)
+    ss = prob.K * prob.T
+    d = model.d
+    f_fwd = flops_per_sample_step(model) * ss
+    f_adj = model.Ltot * (3 * d * d + 9 * d + 15) * ss
+    return {"workload": "quadrotor adjoint K=8192 T=400 d=16 6x256 models, checkpoints every 20, "
+                        "smooth obstacles",
+            "forward_ms": float(np.median(tf)), "fused_forward_adjoint_ms": float(np.median(ta)),
+            "ratio": float(np.median(ta) / np.median(tf)),
+            "forward_rollout_steps_per_s": ss / (float(np.median(tf)) * 1e-3),
+            "fused_rollout_steps_per_s": ss / (float(np.median(ta)) * 1e-3),
+            "forward_tflops": f_fwd / (float(np.median(tf)) * 1e-3) / 1e12,
+            "fused_algorithmic_tflops": (f_fwd + f_adj) / (float(np.median(ta)) * 1e-3) / 1e12,
+            "dtype": "f32"}
+
+
+def w_paper(args):
+    import torch
+    import paper_1503_00330_amd as pi
+    import synth
+    rows = []
+    stream = torch.cuda.current_stream()
+    for M in (0, 1, 4, 8, 16, 32):
+        prob, model = synth.paper_shape(M=M)
+        dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+        cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
+
+        def it():
+            pi.rollout_cost(dp, dm, out=cost)
+            pi.update(dp, cost)
+        it()
+        torch.cuda.synchronize()
+        ms = timed(it, args.steps or 10, stream)
+        rows.append({"M": M, "iteration_ms_p50": pct(ms, 50),
+                     "sub_rollout_steps_per_s": prob.K * max(M, 1) * prob.T / (pct(ms, 50) * 1e-3)})
+    return {"workload": "paper timing shapes: 1000 rollouts x 50 steps, M sub-rollouts "
+                        "(M = 0: mean prediction only), 15/15/24 local models per output group, d=16",
+            "rows": rows, "dtype": "f32"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", required=True,
+                    choices=["cfg0", "rh-graph", "batched", "adjoint", "paper"])
+    ap.add_argument("--steps", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tile-samples", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    fn = {"cfg0": w_cfg0, "rh-graph": w_rh_graph, "batched": w_batched, "adjoint": w_adjoint,
+          "paper": w_paper}[args.workload]
+    if args.workload == "cfg0" and not args.steps:
+        args.steps = 200
+    out = fn(args)
+    out["bench"] = args.workload
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
