@@ -105,6 +105,17 @@ typedef struct {
   int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
   int32_t tile_samples;            /* samples per workgroup, <= 32 (0 = library's choice) */
   int32_t tile_waves;              /* waves per workgroup, 4 or 8 (0 = library's choice) */
+  int32_t tile_split;              /* workgroups per tile of 16 samples: 1 (one
+                                    * workgroup runs every local model) or 2 (a
+                                    * pair of workgroups, on two compute units,
+                                    * each runs half and they exchange partial
+                                    * sums every step); 0 = library's choice:
+                                    * 2 when the problem has fewer tiles than
+                                    * the device has compute units and the
+                                    * pairs fit on the device at once.  Float32
+                                    * matrix-core rollouts with tile_samples
+                                    * <= 16 (4 waves, or 8 for the quadrotor)
+                                    * only; otherwise 1.                       */
 } pi_problem;
 
 /* Bytes of workspace `op` needs for this problem/model (0 is a valid answer;
@@ -127,7 +138,9 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
  * explicit Euler; the step cost is dt * q(x_{t+1}).  Writes
  *   cost dev [K][T]: cbar_{k,t} = mean over sub-rollouts of the step cost,
  * so S_k = sum_t cost[k][t].  `iter` (dev, one uint32) is the iteration
- * counter of the random stream.                                              */
+ * counter of the random stream.  With paired workgroups (tile_split) every
+ * wait of a workgroup on its partner is bounded; should one run out (the
+ * pair was not resident at once), the affected costs are written as NaN.   */
 pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
                           const void *u_nom, const uint32_t *iter, void *cost, void *ws,
                           size_t ws_bytes, void *stream);

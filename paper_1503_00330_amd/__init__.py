@@ -58,7 +58,8 @@ class pi_problem(C.Structure):
                 ("obs_kind", C.c_int32), ("n_obs", C.c_int32), ("obs", C.c_void_p),
                 ("obs_penalty", C.c_double), ("obs_decay", C.c_double),
                 ("weighting", C.c_int32), ("problem_id", C.c_uint32), ("seed", C.c_uint64),
-                ("variant", C.c_int32), ("tile_samples", C.c_int32), ("tile_waves", C.c_int32)]
+                ("variant", C.c_int32), ("tile_samples", C.c_int32), ("tile_waves", C.c_int32),
+                ("tile_split", C.c_int32)]
 
 
 _lib = None
@@ -202,7 +203,7 @@ class DeviceProblem:
     counter `iter` (the random stream's iteration word)."""
 
     def __init__(self, prob, device="cuda", dtype=None, variant: int = PI_VARIANT_AUTO,
-                 tile_samples: int = 0, tile_waves: int = 0):
+                 tile_samples: int = 0, tile_waves: int = 0, tile_split: int = 0):
         torch = _torch()
         dtype = dtype or (torch.float32 if np.asarray(prob.x0).dtype == np.float32
                           else torch.float64)
@@ -216,6 +217,7 @@ class DeviceProblem:
         self.u_nom = torch.as_tensor(np.asarray(prob.u_nom), dtype=dtype, device=device).clone()
         self.iter = torch.zeros(1, dtype=torch.int32, device=device)
         self.variant, self.tile_samples, self.tile_waves = variant, tile_samples, tile_waves
+        self.tile_split = tile_split
 
     def struct(self) -> pi_problem:
         p, s = self.prob, pi_problem()
@@ -236,6 +238,7 @@ class DeviceProblem:
         s.seed = int(p.seed) & 0xFFFFFFFFFFFFFFFF
         s.variant, s.tile_samples = int(self.variant), int(self.tile_samples)
         s.tile_waves = int(self.tile_waves)
+        s.tile_split = int(self.tile_split)
         return s
 
 

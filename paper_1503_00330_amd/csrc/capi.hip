@@ -84,6 +84,8 @@ pi_status check_problem(const pi_problem *p) {
     return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,32]", p->tile_samples);
   if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8)
     return fail(PI_ERR_VALUE, "tile_waves=%d must be 0, 4 or 8", p->tile_waves);
+  if (p->tile_split < 0 || p->tile_split > 2)
+    return fail(PI_ERR_VALUE, "tile_split=%d must be 0, 1 or 2", p->tile_split);
   return PI_OK;
 }
 
@@ -99,6 +101,8 @@ pi_status check_pair(const pi_problem *p, const pi_lwpr *m) {
 }
 
 // Device check: a gfx950 device must be current.  Cached per device id.
+constexpr int kMaxDevices = 64;
+
 pi_status check_device() {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
@@ -108,8 +112,8 @@ pi_status check_device() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(PI_ERR_DEVICE, "hipGetDevice failed");
   static std::mutex mu;
-  static int known[64] = {0};  // 0 unknown, 1 ok, 2 wrong arch
-  if (dev < 0 || dev >= 64) return fail(PI_ERR_DEVICE, "device id out of range");
+  static int known[kMaxDevices] = {0};  // 0 unknown, 1 ok, 2 wrong arch
+  if (dev < 0 || dev >= kMaxDevices) return fail(PI_ERR_DEVICE, "device id out of range");
   std::lock_guard<std::mutex> lk(mu);
   if (known[dev] == 0) {
     hipDeviceProp_t prop;
@@ -175,24 +179,59 @@ ProbDev<Real> prob_dev(const pi_problem *p) {
 
 bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6); }
 
-// Rollout variant and samples per workgroup.
+// Rollout variant, samples per workgroup and whether tiles may be split over
+// a pair of workgroups (pair_ok; the launch decides with the device's
+// compute-unit count and residency).  The workspace never depends on the
+// device: a pair-capable plan always reserves the exchange slots.
 struct RolloutPlan {
-  bool mfma;
+  bool mfma, pair_ok;
   int spw, waves;
+  int64_t groups;
 };
+
+constexpr int64_t kMaxPairGroups = 2048;
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   RolloutPlan r;
   r.mfma = p->variant == PI_VARIANT_MFMA || (p->variant == PI_VARIANT_AUTO && mfma_ok(p->dtype, m->d));
+  const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
+  r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
+  const bool split_allowed = r.mfma && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
+                             p->tile_split != 1 && p->dtype == PI_F32;
   if (p->tile_samples > 0) {
     r.spw = p->tile_samples;
+  } else if (split_allowed) {
+    r.spw = 16;   // full 16-row tiles; small problems are spread by pairing
   } else {
     // enough workgroups to cover the 256 compute units, at most 32 rows each
-    const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
     r.spw = n >= 256 * 16 ? 16 : 8;
   }
-  r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
+  r.groups = (n + r.spw - 1) / r.spw;
+  r.pair_ok = split_allowed && r.spw <= 16 && r.groups <= kMaxPairGroups;
   return r;
+}
+
+// Pairing at launch: requested (tile_split 2) or, by default, when the tiles
+// leave compute units idle; in both cases only if the whole grid is resident.
+bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
+  if (!pl.pair_ok) return false;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return false;
+  static std::mutex mu;
+  static int per_cu[kMaxDevices][3];  // resident pair workgroups per compute unit, +1 (0 = unknown)
+  if (dev < 0 || dev >= kMaxDevices) return false;
+  const int di = p->dyn != PI_DYN_QUAD12 ? 0 : (pl.waves == 8 ? 2 : 1);
+  int cap;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (per_cu[dev][di] == 0) per_cu[dev][di] = pair_blocks_per_cu(p->dyn, pl.waves) + 1;
+    cap = per_cu[dev][di] - 1;
+  }
+  const bool resident = (int64_t)pair_grid(pl.groups) <= (int64_t)cap * n_cu;
+  if (!resident) return false;
+  return p->tile_split == 2 || pl.groups < n_cu;
 }
 
 size_t fold_bytes(const pi_lwpr *m, bool mfma) {
@@ -200,11 +239,15 @@ size_t fold_bytes(const pi_lwpr *m, bool mfma) {
   return direct_bytes(m->dtype, m->d, m->L_off[m->n_out]);
 }
 
+size_t sub_bytes(const pi_problem *p) {
+  const int Ms = p->M > 0 ? p->M : 1;
+  return Ms > 1 ? align_up((size_t)p->K * Ms * p->T * (p->dtype == PI_F64 ? 8 : 4), 256) : 0;
+}
+
 size_t rollout_ws(const pi_problem *p, const pi_lwpr *m) {
   const RolloutPlan pl = rollout_plan(p, m);
-  size_t b = fold_bytes(m, pl.mfma);
-  const int Ms = p->M > 0 ? p->M : 1;
-  if (Ms > 1) b += align_up((size_t)p->K * Ms * p->T * (p->dtype == PI_F64 ? 8 : 4), 256);
+  size_t b = fold_bytes(m, pl.mfma) + sub_bytes(p);
+  if (pl.pair_ok) b += pair_ws_bytes(pl.groups);
   return b;
 }
 
@@ -352,7 +395,12 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
     if (pl.mfma) {
       const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
       e = launch_fold_mfma(PI_F32, a, l, ws, s);
-      if (e == hipSuccess) e = launch_rollout_mfma(ra, a, l, ws, pl.spw, pl.waves, s);
+      if (e == hipSuccess) {
+        if (use_pair(p, pl))
+          e = launch_rollout_pair(ra, l, ws, pl.spw, pl.waves, (char *)ws + fb + sub_bytes(p), s);
+        else
+          e = launch_rollout_mfma(ra, a, l, ws, pl.spw, pl.waves, s);
+      }
     } else {
       e = launch_fold_direct(PI_F32, a, ws, s);
       if (e == hipSuccess) e = launch_rollout_direct(PI_F32, &ra, a, ws, s);

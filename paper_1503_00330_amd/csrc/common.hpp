@@ -256,10 +256,14 @@ __device__ __forceinline__ void mix_add(MixStat<Real> &s, Real act, Real y, Real
   s.mu = mun;
 }
 
+// M2 (the spread of the local predictions) is non-negative in exact
+// arithmetic; when a new leading model takes over, e/Z can round to just above
+// one and leave a negative M2 of order eps * (y - mu)^2, which in float can
+// exceed the noise term, so it is clamped at zero.
 template <typename Real>
 __device__ __forceinline__ void mix_finish(const MixStat<Real> &s, Real *mean, Real *var) {
   *mean = s.mu;
-  *var = (s.M2 + s.S2) / s.Z;
+  *var = ((s.M2 > (Real)0 ? s.M2 : (Real)0) + s.S2) / s.Z;
 }
 
 }  // namespace pi2rh

@@ -3,6 +3,8 @@
 // update and the receding-horizon shift.  One lane evaluates one input
 // against every local model; model records are staged through LDS tiles and
 // read as broadcasts.  (PI^2-RH with LWPR dynamics, arXiv:1503.00330.)
+#include <algorithm>
+
 #include "direct.hpp"
 
 namespace pi2rh {
@@ -499,6 +501,16 @@ hipError_t launch_rh_shift(int dtype, const void *pargs, const ModelArgs &m, con
 
 // Clears one counter with a kernel (graph-capture friendly, no memset node).
 __global__ void zero_int_kernel(int *p) { *p = 0; }
+__global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)nb), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 hipError_t launch_zero_int(int *p, hipStream_t s) {
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, p);
   return hipGetLastError();

@@ -144,6 +144,13 @@ MfmaModel mfma_model_view(const MfmaLayout &l, const void *base);
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
                                   int spw, int waves, int grid, int *queue, hipStream_t s);
 hipError_t launch_zero_int(int *p, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+// Paired-workgroup rollout (MFMA, 16 rows per pair of workgroups).
+size_t pair_ws_bytes(int64_t n_groups);
+int pair_grid(int64_t n_groups);
+int pair_blocks_per_cu(int dyn, int waves);
+hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
+                               int waves, void *pair_ws, hipStream_t s);
 
 // ---- adjoint -------------------------------------------------------------------
 int adjoint_default_ckpt(int T);

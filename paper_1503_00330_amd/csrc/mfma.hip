@@ -15,7 +15,10 @@
 // Per model a lane then only accumulates
 //   Z += 2^a', S1 += 2^a' d, S2 += 2^a' d^2, S3 += 2^a' sigma^2, mx = max(mx, a'),
 // and the normalised mixture of Eq. (1) is
-//   mu = r + S1/Z,  var = (S2 - S1^2/Z + S3)/Z.
+//   mu = r + S1/Z,  var = (max(S2 - S1^2/Z, 0) + S3)/Z;
+// the spread term is non-negative in exact arithmetic, and the clamp keeps its
+// rounding (FP32 cancellation when the models' predictions differ widely) from
+// turning the variance negative.
 // Partial sums merge across lanes (DPP row rotations) and waves (LDS) as
 // plain sums in a fixed order.  If the largest shifted activation leaves
 // [-60, 64] (too far from the anchor for 2^a' in FP32) the step is evaluated
@@ -203,6 +206,7 @@ struct MixSmem {
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
   unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
   int redo;
+  int pair_fail;                         // a partner wait ran out (results invalid)
 };
 
 // Fragment entry e = ((kb4 * 64 + lane) * 4 + comp) of row tile mt holds
@@ -238,7 +242,10 @@ __device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
     }
     sm.fsrc[e] = (unsigned short)((ia << 8) | ib);
   }
-  if (threadIdx.x == 0) sm.redo = 0;
+  if (threadIdx.x == 0) {
+    sm.redo = 0;
+    sm.pair_fail = 0;
+  }
 }
 
 // Stage 1 (all lanes): A fragments from sm.z; resets the partial sums.
@@ -260,12 +267,12 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
 // Stage 2 (each wave): its contiguous range of model tiles, one MFMA chain per
 // tile; partial sums flushed per output into sm.part[wave][o][row].
 template <int D, int MT, int NW>
-__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW> &sm) {
+__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW> &sm, int T0, int T1) {
   using G = Geo<D>;
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t0 = (int)((int64_t)wave * md.n_tiles / NW), t1 = (int)((int64_t)(wave + 1) * md.n_tiles / NW);
+  const int t0 = T0 + (int)((int64_t)wave * (T1 - T0) / NW), t1 = T0 + (int)((int64_t)(wave + 1) * (T1 - T0) / NW);
   if (t0 >= t1) return;
   f32x4 A[MT][G::KB4];
 #pragma unroll
@@ -377,7 +384,9 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float a = qa[mt][r] + qb[mt][r], dd = ya[mt][r];
-        const float e = exp2f(a);
+        // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+        // largest term of at least 2^-60) need none of exp2f's denormal scaling
+        const float e = __builtin_amdgcn_exp2f(a);
         const float te = e * dd;
         st[mt][r].Z += e;
         st[mt][r].S1 += te;
@@ -404,45 +413,132 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   flush(o);
 }
 
-// Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, Eq. (1)
-// moments, next anchors; flags a second pass when an anchor was too far.
+// Eq. (1) moments of one (row, output) from its complete sums, the anchors of
+// the next evaluation (observed maximum and mean), and the redo flag when the
+// maximum left the anchor window.
+template <int D, int MT, int NW>
+__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int o, const Acc &s) {
+  const float d1 = s.S1 / s.Z;
+  const float mu = sm.yref[row][o] + d1;
+  sm.mean[row][o] = mu;
+  sm.var[row][o] = (fmaxf(s.S2 - s.S1 * d1, 0.f) + s.S3) / s.Z;
+  if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo = 1;
+  sm.mref[row][o] += s.mx;
+  if (isfinite(mu)) sm.yref[row][o] = mu;
+}
+
+__device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
+  return Acc{a.Z + b.Z, a.S1 + b.S1, a.S2 + b.S2, a.S3 + b.S3, fmaxf(a.mx, b.mx)};
+}
+
+template <int D, int MT, int NW>
+__device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW> &sm, int row, int o) {
+  Acc s = sm.part[0][o][row];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) s = acc_sum(s, sm.part[w][o][row]);
+  return s;
+}
+
+// Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, then the
+// moments.
 template <int D, int MT, int NW>
 __device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out) {
   constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
   for (int i = threadIdx.x; i < ROWS * n_out; i += NW * 64) {
     const int row = i % ROWS, o = i / ROWS;
-    Acc s = sm.part[0][o][row];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const Acc &b = sm.part[w][o][row];
-      s.Z += b.Z;
-      s.S1 += b.S1;
-      s.S2 += b.S2;
-      s.S3 += b.S3;
-      s.mx = fmaxf(s.mx, b.mx);
-    }
-    const float d1 = s.S1 / s.Z;
-    const float mu = sm.yref[row][o] + d1;
-    sm.mean[row][o] = mu;
-    sm.var[row][o] = (s.S2 - s.S1 * d1 + s.S3) / s.Z;
-    if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo = 1;
-    // anchors for the next evaluation: the observed maximum and mean
-    sm.mref[row][o] += s.mx;
-    if (isfinite(mu)) sm.yref[row][o] = mu;
+    finish_sums(sm, row, o, sum_waves(sm, row, o));
   }
 }
 
-// The whole mixture of one step for the rows in sm.z: one pass, a second
-// one if an anchor was out of range or `force_second`.  Block-synchronous.
+// Paired workgroups: two workgroups (on two compute units) hold the same rows
+// and each runs half of the model tiles.  After its own wave sums, each
+// publishes them, waits for the partner's, and both add the two halves in
+// the same order (half 0 + half 1), so both hold bit-identical moments and
+// take the same redo decision.
+//
+// Protocol per evaluation (sequence number seq, slots double-buffered by
+// parity): data go out as agent-scope relaxed atomic stores; every wave waits
+// for its stores to complete before the barrier, then one lane publishes seq
+// in the half's flag; the partner's flag is polled (agent-scope loads) until
+// it reaches seq and its data are read with agent-scope loads.  A slot is
+// rewritten only two evaluations later, after the partner has published the
+// next seq, which it does only once it has read this one.  Every wait is
+// bounded: on running out, pair_fail is set, no further waits are made and
+// the rollout's costs are written as NaN.
+struct PairCtx {
+  float *xbuf;       // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
+  uint32_t *flags;   // [2]: last sequence number published by each half
+  int half;          // 0 or 1; -1 when not paired
+};
+constexpr int kXSlots = 16 * kMaxOut;
+constexpr int kPairFloats = 2 * 2 * kXSlots * 5;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
 template <int D, int MT, int NW>
-__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW> &sm,
-                                             bool force_second) {
+__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, const PairCtx &pc, uint32_t seq) {
+  static_assert(MT == 1, "paired workgroups hold one 16-row tile");
+  constexpr int ROWS = 16;
+  const int i = threadIdx.x;
+  const bool mine = i < ROWS * n_out;
+  const int row = i % ROWS, o = i / ROWS;
+  Acc loc = acc_empty();
+  if (mine) {
+    loc = sum_waves(sm, row, o);
+    // one sum per store instruction: consecutive lanes write consecutive words
+    float *dst = pc.xbuf + (size_t)(pc.half * 2 + (seq & 1)) * 5 * kXSlots + i;
+    __hip_atomic_store(dst + 0 * kXSlots, loc.Z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 1 * kXSlots, loc.S1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 2 * kXSlots, loc.S2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 3 * kXSlots, loc.S3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 4 * kXSlots, loc.mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0 && !sm.pair_fail) {
+    __hip_atomic_store(pc.flags + pc.half, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t n = 0;
+    while (__hip_atomic_load(pc.flags + (1 - pc.half), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < seq) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++n >= kSpinLimit) {
+        sm.pair_fail = 1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (mine) {
+    const float *src = pc.xbuf + (size_t)((1 - pc.half) * 2 + (seq & 1)) * 5 * kXSlots + i;
+    Acc rem;
+    rem.Z = __hip_atomic_load(src + 0 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rem.S1 = __hip_atomic_load(src + 1 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rem.S2 = __hip_atomic_load(src + 2 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rem.S3 = __hip_atomic_load(src + 3 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rem.mx = __hip_atomic_load(src + 4 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    finish_sums(sm, row, o, pc.half == 0 ? acc_sum(loc, rem) : acc_sum(rem, loc));
+  }
+}
+
+// The whole mixture of one step for the rows in sm.z over model tiles
+// [T0, T1): one pass, a second one if an anchor was out of range or
+// `force_second`.  Block-synchronous.  With a pair context the two halves'
+// sums are exchanged every pass (seq counts the exchanges).
+template <int D, int MT, int NW>
+__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW> &sm, bool force_second,
+                                             int T0, int T1, const PairCtx *pc, uint32_t &seq) {
   for (int pass = 0; pass < 2; ++pass) {
     build_fragments(sm);
     __syncthreads();
-    mixture_tiles(md, sm);
+    mixture_tiles(md, sm, T0, T1);
     __syncthreads();
-    merge_waves(sm, md.n_out);
+    if constexpr (MT == 1) {
+      if (pc != nullptr) {
+        merge_pair(sm, md.n_out, *pc, ++seq);
+      } else {
+        merge_waves(sm, md.n_out);
+      }
+    } else {
+      merge_waves(sm, md.n_out);
+    }
     __syncthreads();
     const bool again = pass == 0 && (force_second || sm.redo != 0);
     __syncthreads();
@@ -474,7 +570,8 @@ __global__ void __launch_bounds__(NW * 64) predict_mfma_kernel(MfmaModel md, con
     sm.z[row][a] = a < D ? ((n0 + row < N) ? Z[(n0 + row) * D + a] : 0.0f) : (a == D ? 1.0f : 0.0f);
   }
   __syncthreads();
-  mixture_step(md, sm, true);
+  uint32_t seq = 0;
+  mixture_step(md, sm, true, 0, md.n_tiles, (const PairCtx *)nullptr, seq);
   for (int i = threadIdx.x; i < ROWS * md.n_out; i += NW * 64) {
     const int row = i / md.n_out, o = i % md.n_out;
     if (n0 + row < N) {
@@ -530,16 +627,22 @@ struct RollSmem {
 // Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS.
 // Per step: rows form z, the waves run the model tiles, partial sums are
 // merged, and each row samples its accelerations, steps Euler and writes
-// dt*q(x_{t+1}).  Block-synchronous; rs.sm must have been set up.
+// dt*q(x_{t+1}).  Block-synchronous; rs.sm must have been set up.  With a
+// pair context (pc->half = 0 or 1) the workgroup runs its half of the model
+// tiles, exchanges sums with its partner, and only half 0 writes costs.
 template <int DYN, int MT, int NW>
 __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
                              uint32_t it, float *__restrict__ cost, const MfmaModel &md,
-                             int64_t s_base, int spw) {
+                             int64_t s_base, int spw, const PairCtx *pc = nullptr) {
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
   MixSmem<D, MT, NW> &sm = rs.sm;
+  const int T0 = pc == nullptr || pc->half == 0 ? 0 : md.n_tiles / 2;
+  const int T1 = pc == nullptr || pc->half == 1 ? md.n_tiles : md.n_tiles / 2;
+  const bool writer = pc == nullptr || pc->half == 0;
+  uint32_t seq = 0;
   __syncthreads();  // the previous tile (persistent use) is done with LDS
   reset_anchors(sm);
   const int row = threadIdx.x;
@@ -595,7 +698,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
     }
     __syncthreads();
-    mixture_step(md, sm, t == 0);
+    mixture_step(md, sm, t == 0, T0, T1, pc, seq);
     if (active) {
       float acc[NO], xn[NX], x[NX];
 #pragma unroll
@@ -606,7 +709,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       euler_step<float>(DYN, p.dt, x, acc, xn);
 #pragma unroll
       for (int a = 0; a < NX; ++a) rs.xs[row][a] = xn[a];
-      cost[s * p.T + t] = p.dt * state_cost<float>(p, p.obs, xn);
+      if (writer) cost[s * p.T + t] = sm.pair_fail ? __builtin_nanf("") : p.dt * state_cost<float>(p, p.obs, xn);
     }
   }
 }
@@ -619,6 +722,23 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
   mix_setup(rs.sm);
   rollout_tile<DYN, MT, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
                             (int64_t)blockIdx.x * spw, spw);
+}
+
+// Paired form (one 16-row tile per pair of workgroups, for problems with
+// fewer tiles than compute units): partners are blocks b and b + 8 of each
+// 16-block group, which the round-robin dispatch places on the same XCD, so
+// their exchange stays inside one L2.  The grid must be resident at once.
+template <int DYN, int NW>
+__global__ void __launch_bounds__(NW * 64) rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
+                                                               int n_groups, float *__restrict__ xbuf,
+                                                               uint32_t *__restrict__ flags) {
+  __shared__ RollSmem<DYN, 1, NW> rs;
+  const int blk = blockIdx.x;
+  const int g = (blk / 16) * 8 + (blk % 8);
+  if (g >= n_groups) return;  // both halves of an unused pair leave
+  const PairCtx pc{xbuf + (size_t)g * kPairFloats, flags + 2 * g, (blk / 8) & 1};
+  mix_setup(rs.sm);
+  rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc);
 }
 
 // Persistent form for many independent problems: every workgroup pulls
@@ -670,6 +790,49 @@ hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
   }
   if (spw <= 16) return rollout_mfma_t<kDynPointMass2D, 1, 4>(ra, md, spw, s);
   return rollout_mfma_t<kDynPointMass2D, 2, 4>(ra, md, spw, s);
+}
+
+size_t pair_ws_bytes(int64_t n_groups) {
+  return align_up((size_t)n_groups * kPairFloats * sizeof(float), 256) +
+         align_up((size_t)n_groups * 2 * sizeof(uint32_t), 256);
+}
+
+int pair_grid(int64_t n_groups) { return (int)(16 * ((n_groups + 7) / 8)); }
+
+int pair_blocks_per_cu(int dyn, int waves) {
+  int nb = 0;
+  hipError_t e;
+  if (dyn == kDynQuad12 && waves == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8>, 512, 0);
+  else if (dyn == kDynQuad12)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4>, 256, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
+                               int waves, void *pair_ws, hipStream_t s) {
+  const MfmaModel md = mfma_view(l, base);
+  const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
+  const int64_t n_groups = (n + spw - 1) / spw;
+  float *xbuf = (float *)pair_ws;
+  uint32_t *flags = (uint32_t *)((char *)pair_ws + align_up((size_t)n_groups * kPairFloats * sizeof(float), 256));
+  hipError_t e = launch_zero_u32(flags, 2 * n_groups, s);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)pair_grid(n_groups));
+  if (ra.p.dyn == kDynQuad12) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8>), grid, dim3(512), 0, s, ra, md, spw, (int)n_groups,
+                         xbuf, flags);
+    else
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4>), grid, dim3(256), 0, s, ra, md, spw, (int)n_groups,
+                         xbuf, flags);
+  } else {
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4>), grid, dim3(256), 0, s, ra, md, spw,
+                       (int)n_groups, xbuf, flags);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,

@@ -89,7 +89,8 @@ class TestValidation:
     @pytest.mark.parametrize("field,value,code", [
         ("K", 0, 2), ("T", 0, 2), ("M", -1, 2), ("dt", 0.0, 3), ("lambda_", -1.0, 3),
         ("dyn", 7, 3), ("obs_kind", 5, 3), ("n_obs", 65, 2), ("weighting", 3, 3),
-        ("variant", 9, 3), ("tile_samples", 100, 3), ("dtype", 5, 4)])
+        ("variant", 9, 3), ("tile_samples", 100, 3), ("tile_waves", 5, 3), ("tile_split", 3, 3),
+        ("tile_split", -1, 3), ("dtype", 5, 4)])
     def test_bad_problem_fields(self, field, value, code):
         ps, ms = _structs()
         setattr(ps, field, value)
@@ -153,3 +154,9 @@ def test_workspace_sizes_scale_with_problem():
     r3 = lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
     ps.M = 1
     assert r3 > lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
+    # pair-capable float32 plans reserve the exchange slots whatever the device
+    ps.dtype, ms.dtype = pi.PI_F32, pi.PI_F32
+    paired = lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
+    ps.tile_split = 1
+    single = lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))
+    assert paired > single > 0

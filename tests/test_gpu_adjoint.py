@@ -23,6 +23,11 @@ def _device():
     torch.cuda.synchronize()
 
 
+# FP32 against FP64 for the mean cost at the 400-step adjoint workload, where
+# rounding differences grow chaotically (2.8e-3 measured)
+FP32_LONG_J_TOL = 1e-2
+
+
 def nrel(g, o):
     g, o = np.asarray(g, np.float64).ravel(), np.asarray(o, np.float64).ravel()
     return float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-300))
@@ -93,25 +98,56 @@ def test_adjoint_repeatable():
 
 
 def test_adjoint_full_size_directional_derivative():
-    # the adjoint workload (K = 8192, T = 400, checkpoints every 20 steps) with
-    # the smooth obstacle cost: g_u . v against central differences of J from
-    # the forward rollout kernel
+    # The adjoint workload (K = 8192, T = 400, checkpoints every 20 steps,
+    # smooth obstacle cost).  Over 400 steps many sampled trajectories leave
+    # the models' support; far from every centre the mixture weights switch
+    # between local models over distances of ~1e-5 (activation gaps of 1e4 and
+    # more), and derivatives with respect to early controls grow like
+    # exp(lambda (T - t)) (mean directional derivatives of 1e17 for t < 40),
+    # beyond what any finite-difference step resolves in FP64.  Controls of
+    # the last 40 steps act through at most 40 steps of dynamics, and there
+    # central differences converge once h is below the switching width (the
+    # oracle on 16 rollouts: 15 % at h = 1e-3, 2e-4 at 1e-6, 5e-6 at 1e-7):
+    # FP64, h = 1e-7, g_u . v against (J(u + h v) - J(u - h v)) / 2h, with J
+    # from the adjoint's own forward sweep: the forward kernel sums in another
+    # order, and over 360 chaotic steps the two FP64 trajectories of some
+    # rollouts part (mean J agrees to ~1e-5, checked separately).
     prob, model, _ = synth.config(4, obs_kind=OBS_SMOOTH)
-    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    dp = pi.DeviceProblem(prob, dtype=torch.float64)
+    dm = pi.DeviceModel(model, dtype=torch.float64)
     J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=20)
-    assert np.all(np.isfinite(gu.cpu().numpy())) and np.all(np.isfinite(gD.cpu().numpy()))
-    cost = pi.rollout_cost(dp, dm)
-    Jf = cost.double().sum(1).mean().item()
-    assert abs(J.item() - Jf) <= 2e-4 * abs(Jf)
+    for g in (gu, gc, gD):
+        assert torch.isfinite(g).all()
+    # J of the adjoint's own forward sweep against the forward kernel: two FP64
+    # evaluation orders, whose rounding the chaotic rollouts amplify to ~1e-5
+    Jf = pi.rollout_cost(dp, dm).sum(1).mean().item()
+    assert abs(J.item() - Jf) <= 1e-4 * abs(Jf)
     v = torch.zeros_like(dp.u_nom)
-    v[:40] = torch.randn(40, 4, generator=torch.Generator().manual_seed(0)).to(v)
-    h = 2e-2
+    v[-40:] = torch.randn(40, 4, generator=torch.Generator().manual_seed(0)).to(v)
+    h = 1e-7
     u0 = dp.u_nom.clone()
     Js = []
     for sgn in (1.0, -1.0):
         dp.u_nom.copy_(u0 + sgn * h * v)
-        Js.append(pi.rollout_cost(dp, dm).double().sum(1).mean().item())
+        Js.append(pi.rollout_adjoint(dp, dm, ckpt_every=20)[0].item())
     dp.u_nom.copy_(u0)
     fd = (Js[0] - Js[1]) / (2 * h)
-    an = float((gu.double() * v.double()).sum().item())
-    assert abs(fd - an) <= 0.05 * abs(an) + 1e-3 * abs(Jf), (fd, an)
+    an = float((gu * v).sum().item())
+    print("full-size FP64 directional derivative: fd %.8e adjoint %.8e" % (fd, an))
+    assert abs(fd - an) <= 1e-3 * abs(an), (fd, an)
+
+
+def test_adjoint_full_size_fp32():
+    # the same workload in FP32: every gradient finite (the variance of
+    # Eq. (1) is clamped against rounding), and J consistent with the FP64
+    # forward kernel to the spread FP32 trajectories reach over 400 chaotic
+    # steps (per-rollout cost differences: median 3e-5, 99th percentile 0.12;
+    # mean cost 2.8e-3 measured)
+    prob, model, _ = synth.config(4, obs_kind=OBS_SMOOTH)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=20)
+    for g in (gu, gc, gD):
+        assert torch.isfinite(g).all()
+    d64 = pi.DeviceProblem(prob, dtype=torch.float64)
+    J64 = pi.rollout_cost(d64, pi.DeviceModel(model, dtype=torch.float64)).sum(1).mean().item()
+    assert abs(J.item() - J64) <= FP32_LONG_J_TOL * abs(J64)

@@ -1,5 +1,6 @@
 """Batched persistent rollouts: each problem of an uneven batch gives exactly
-(bitwise) the costs of its own plain launch, and matches the oracle."""
+(bitwise) the costs of its own plain launch with one workgroup per tile, and
+matches the oracle."""
 import numpy as np
 import pytest
 
@@ -30,7 +31,9 @@ def _batch(spw=0, waves=0):
                                          dtype=np.float32, n_obs=4 + b)
         prob.problem_id = b
         out.append((prob, model))
-    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves) for p, _ in out]
+    # plain launches of the same problems keep one workgroup per tile (a pair of
+    # workgroups sums the model halves in another order)
+    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves, tile_split=1) for p, _ in out]
     dms = [pi.DeviceModel(m) for _, m in out]
     return out, dps, dms
 

@@ -125,6 +125,30 @@ def test_lwpr_predict_far_inputs_reported():
     assert np.all(np.isfinite(mean.cpu().numpy())) and e < 1e-3
 
 
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_DIRECT, pi.PI_VARIANT_MFMA])
+def test_lwpr_predict_variance_lower_bound(variant):
+    # Eq. (1): var = sum w (y - mu)^2 + sum w sigma^2 >= min_j sigma_j^2 of the
+    # output, at any input; far from the centres the local predictions differ
+    # by hundreds, which in FP32 cancels the spread term to rounding noise
+    model = MODELS["cfg1"].astype(F32)
+    Z = np.random.default_rng(16).uniform(-40, 40, (301, 16)).astype(F32)
+    mean, var = pi.lwpr_predict(pi.DeviceModel(model), torch.from_numpy(Z).cuda(), variant=variant)
+    v = var.cpu().numpy()
+    lo = np.array([model.sigma2[model.L_off[o]:model.L_off[o + 1]].min() for o in range(model.n_out)])
+    assert np.all(np.isfinite(v)) and np.all(np.isfinite(mean.cpu().numpy()))
+    assert np.all(v >= lo[None, :] * (1 - 1e-4))
+
+
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_DIRECT, pi.PI_VARIANT_MFMA])
+def test_long_horizon_fp32_rollout_stays_finite(variant):
+    # the adjoint workload's horizon (T = 400): trajectories leave the models'
+    # support, where FP32 rounding once made the sampled variance negative
+    prob, model, _ = synth.config(4, obs_kind=synth.OBS_SMOOTH, K=64)
+    dp, dm = pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model)
+    c = pi.rollout_cost(dp, dm).cpu().numpy()
+    assert np.all(np.isfinite(c))
+
+
 def test_lwpr_predict_empty_and_single():
     model = MODELS["pm6"].astype(F32)
     dm = pi.DeviceModel(model)
@@ -148,26 +172,31 @@ def test_rollout_fp64_config0_strict():
     assert np.max(np.abs(cost - ref)) <= 1e-10 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", [pi.PI_VARIANT_MFMA, pi.PI_VARIANT_DIRECT])
+# (variant, samples per workgroup, split): MFMA tiles of 16 rows on a pair of
+# workgroups (split 0 = library's choice, which pairs these small problems, or
+# 2 = forced) or on one (split 1), 8 rows, 32 rows; and the direct kernel
+ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2), (pi.PI_VARIANT_MFMA, 16, 1),
+                  (pi.PI_VARIANT_MFMA, 8, 1), (pi.PI_VARIANT_MFMA, 32, 0), (pi.PI_VARIANT_DIRECT, 0, 0)]
+
+
+@pytest.mark.parametrize("shape", ROLLOUT_SHAPES)
 @pytest.mark.parametrize("M", [0, 1, 3])
-@pytest.mark.parametrize("spw", [0, 16, 32])
-def test_rollout_fp32_ragged(variant, M, spw):
-    if variant == pi.PI_VARIANT_DIRECT and spw:
-        pytest.skip("tile size applies to the MFMA kernel")
+def test_rollout_fp32_ragged(shape, M):
+    variant, spw, split = shape
     prob, model = synth.tiny_problem(11, dyn=DYN_QUAD12, L=[20, 17, 33, 16, 1, 40], R=4, K=37, T=9,
                                      M=M, dtype=F32, n_obs=6)
-    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split)
     cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     cost_check(cost, ref, prob, 1e-4)
     assert nrel(cost, ref) <= 1e-4
 
 
-@pytest.mark.parametrize("dtype", [F32, F64])
-def test_rollout_pointmass(dtype):
+@pytest.mark.parametrize("dtype,split", [(F32, 1), (F32, 2), (F64, 0)])
+def test_rollout_pointmass(dtype, split):
     prob, model = synth.tiny_problem(12, dyn=DYN_POINTMASS2D, L=[9, 23], R=2, K=70, T=15, M=2,
                                      dtype=dtype, n_obs=3, obs_kind=OBS_SMOOTH)
-    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    cost = pi.rollout_cost(pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     cost_check(cost, ref, prob, 1e-10 if dtype == F64 else 1e-4)
 
@@ -181,9 +210,12 @@ def test_rollout_edge_sizes():
         cost_check(cost, ref, prob, 1e-4)
 
 
-def test_rollout_config1_full_launch_sampled_rows():
+@pytest.mark.parametrize("split", [0, 1])
+def test_rollout_config1_full_launch_sampled_rows(split):
+    # the benchmarked launch (split 0: 128 tiles of 16 rollouts on 256 paired
+    # workgroups) and the one-workgroup-per-tile form
     prob, model, _ = synth.config(1)
-    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    cost = pi.rollout_cost(pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)).cpu().numpy()
     assert cost.shape == (2048, 100) and np.all(np.isfinite(cost))
     rows = list(range(0, 16)) + list(range(1016, 1032)) + list(range(2032, 2048))
     ref = np.concatenate([oracle.rollout_cost(prob, model, k_range=(a, a + 16))
@@ -192,12 +224,13 @@ def test_rollout_config1_full_launch_sampled_rows():
     print("config 1 sampled rows: max S rel %.2e, flips %d" % (r, flips))
 
 
-def test_rollout_bitwise_repeatable():
+@pytest.mark.parametrize("split", [1, 2])
+def test_rollout_bitwise_repeatable(split):
     prob, model, _ = synth.config(1, K=512, T=20)
-    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    dp, dm = pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)
     a = pi.rollout_cost(dp, dm).clone()
-    b = pi.rollout_cost(dp, dm).clone()
-    assert torch.equal(a, b)
+    for _ in range(3):
+        assert torch.equal(a, pi.rollout_cost(dp, dm))
 
 
 # ------------------------------------------------------------------- update
