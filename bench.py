@@ -10,8 +10,9 @@ inputs with R = 4 PLS projections, 20 cylinder obstacles, FP32.
 
 Prints one JSON line: whole-job rollout-steps/s, per-iteration and update
 latency percentiles, the roofline of the rollout kernel (algorithmic FLOP per
-launch over its mean HIP-event duration) and the FP64 oracle's rate on a
-bounded sample of the same workload on the host cores.
+launch over its mean HIP-event duration; HBM bytes per launch from the
+committed rocprofv3 counter summary while the kernel sources are unchanged)
+and the FP64 oracle's rate on the same workload on the host cores.
 """
 import argparse
 import json
@@ -28,6 +29,7 @@ if ROOT not in sys.path:
 METRIC = "LWPR rollout steps/s + PI^2 update p50/p99 latency; fwd+adjoint & batched vs plain"
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rollout_pair_kernel.quad_k2048_t100.traffic.txt")
 
 
 def flops_per_sample_step(model):
@@ -42,15 +44,19 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(prob, model, n_rollouts=256):
+def cpu_baseline(prob, model, n_rollouts=0):
+    """The FP64 oracle's rollout rate on rollouts 0..n-1 of the workload (all of
+    them by default: the whole rollout stage, a few seconds on 16 cores)."""
     import oracle
+    n_rollouts = n_rollouts or prob.K
     t0 = time.perf_counter()
     oracle.rollout_cost(prob, model, k_range=(0, n_rollouts))
     dt = time.perf_counter() - t0
+    what = ("all %d rollouts" % prob.K) if n_rollouts == prob.K else ("rollouts k=0..%d" % (n_rollouts - 1))
     return {"value": n_rollouts * max(prob.M, 1) * prob.T / dt, "unit": "rollout-steps/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "FP64 oracle rollouts k=0..%d of the same workload (all %d steps), %.1f s wall"
-                      % (n_rollouts - 1, prob.T, dt)}
+            "sample": "FP64 oracle, %s of the workload x %d steps (the rollout stage), %.1f s wall"
+                      % (what, prob.T, dt)}
 
 
 def main():
@@ -59,7 +65,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rollouts", type=int, default=256)
+    ap.add_argument("--cpu-rollouts", type=int, default=0, help="oracle sample (0 = all K rollouts)")
     ap.add_argument("--tile-samples", type=int, default=0)
     ap.add_argument("--tile-waves", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -125,6 +131,9 @@ def main():
     flop = flops_per_sample_step(model) * ssteps
     roll_mean_s = float(np.mean(roll_ms)) * 1e-3
     achieved = flop / roll_mean_s
+    plan = pi.rollout_describe(dp, dm)
+    from paper_1503_00330_amd.profiling import traffic_from_summary
+    traffic = traffic_from_summary(TRAFFIC_SUMMARY) if plan["kernel"] == "rollout_pair_kernel" else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -146,10 +155,11 @@ def main():
         "latency_ms": {"iteration_p50": percentile(it_ms, 50), "iteration_p99": percentile(it_ms, 99),
                        "update_p50": percentile(upd_ms, 50), "update_p99": percentile(upd_ms, 99),
                        "rollout_mean": float(np.mean(roll_ms))},
-        "roofline": {"bound": "mfma", "kernel": "rollout_mfma_kernel",
+        "roofline": {"bound": "mfma", "kernel": plan["kernel"],
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model)},
+                     "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
+                     "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model),
+                     "launch": {k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")}},
     }
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")

@@ -124,6 +124,13 @@ typedef struct {
  * query count is taken as p ? p->K : 0 (prediction needs no per-query space). */
 size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m);
 
+/* The launch pi_rollout_cost would make for this problem and model on the
+ * current device (no work is done): out[0] = PI_VARIANT_DIRECT or
+ * PI_VARIANT_MFMA, out[1] = samples per tile, out[2] = waves per workgroup,
+ * out[3] = workgroups per tile (1 or 2, see tile_split).  out is a host array
+ * of 4.  Returns PI_ERR_* for invalid arguments as pi_rollout_cost would.   */
+pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out);
+
 /* Eq. (1): for N inputs Z (dev [N][d]) writes the mixture mean and variance
  * of every output: mean, var dev [N][n_out] in the model's dtype.
  * `variant` selects the kernel (PI_VARIANT_*).                               */

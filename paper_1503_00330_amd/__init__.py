@@ -30,7 +30,7 @@ PI_MAX_OUT, PI_MAX_U = 8, 4
 STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4: "PI_ERR_DTYPE",
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6)}
-EXPORTED = ["pi_workspace_bytes", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
+EXPORTED = ["pi_workspace_bytes", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
             "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
             "pi_batched_plan", "pi_rollout_cost_batched", "pi_philox4x32_10", "pi_noise",
             "pi_last_error", "pi_version"]
@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH):
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.pi_workspace_bytes.argtypes = [i32, vp, vp]
     lib.pi_workspace_bytes.restype = sz
+    lib.pi_rollout_describe.argtypes = [vp, vp, vp]
+    lib.pi_rollout_describe.restype = i32
     lib.lwpr_predict.argtypes = [vp, vp, i64, vp, vp, i32, vp, sz, vp]
     lib.pi_rollout_cost.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_update.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
@@ -269,6 +271,17 @@ def lwpr_predict(model: DeviceModel, Z, variant: int = PI_VARIANT_AUTO, out=None
     _check(lib.lwpr_predict(C.byref(ms), _ptr(Z), N, _ptr(mean), _ptr(var), variant, _ptr(ws),
                             ws.numel(), _stream()))
     return mean, var
+
+
+def rollout_describe(prob: DeviceProblem, model: DeviceModel) -> dict:
+    """The launch pi_rollout_cost makes for this problem on the current device."""
+    out = (C.c_int32 * 4)()
+    ps, ms = prob.struct(), model.struct()
+    _check(load().pi_rollout_describe(C.byref(ps), C.byref(ms), out))
+    return {"variant": "mfma" if out[0] == PI_VARIANT_MFMA else "direct", "tile_samples": out[1],
+            "tile_waves": out[2], "tile_split": out[3],
+            "kernel": ("rollout_pair_kernel" if out[3] == 2 else "rollout_mfma_kernel")
+            if out[0] == PI_VARIANT_MFMA else "rollout_direct_kernel"}
 
 
 def rollout_cost(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, iter=None,

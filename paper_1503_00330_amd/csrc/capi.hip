@@ -322,6 +322,19 @@ const char *pi_last_error(void) { return g_err; }
 
 const char *pi_version(void) { return "pi2rh 0.1 (gfx950)"; }
 
+pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out) {
+  PI_TRY(check_pair(p, m));
+  if (!out) return fail(PI_ERR_NULL, "out must be non-NULL");
+  const RolloutPlan pl = rollout_plan(p, m);
+  if (pl.mfma && !mfma_ok(p->dtype, m->d)) return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  PI_TRY(check_device());
+  out[0] = pl.mfma ? PI_VARIANT_MFMA : PI_VARIANT_DIRECT;
+  out[1] = pl.mfma ? pl.spw : 1;
+  out[2] = pl.mfma ? pl.waves : 1;
+  out[3] = use_pair(p, pl) ? 2 : 1;
+  return ok();
+}
+
 size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
   switch (op) {
     case PI_OP_PREDICT:

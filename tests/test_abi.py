@@ -96,6 +96,15 @@ class TestValidation:
         setattr(ps, field, value)
         assert _rollout(ps, ms) == code, pi.last_error()
 
+    def test_describe_validates(self):
+        ps, ms = _structs()
+        lib = pi.load()
+        out = (C.c_int32 * 4)()
+        assert lib.pi_rollout_describe(C.byref(ps), C.byref(ms), None) == 1
+        assert lib.pi_rollout_describe(None, C.byref(ms), out) == 1
+        ps.tile_split = 7
+        assert lib.pi_rollout_describe(C.byref(ps), C.byref(ms), out) == 3
+
     def test_bad_model(self):
         ps, ms = _structs()
         ms.d = 17

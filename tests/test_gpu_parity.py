@@ -224,6 +224,21 @@ def test_rollout_config1_full_launch_sampled_rows(split):
     print("config 1 sampled rows: max S rel %.2e, flips %d" % (r, flips))
 
 
+def test_rollout_describe_reports_the_launch():
+    prob, model, _ = synth.config(1)
+    dm = pi.DeviceModel(model)
+    d = pi.rollout_describe(pi.DeviceProblem(prob), dm)
+    # 128 tiles of 16 rollouts leave compute units idle: pairs of workgroups
+    assert d == {"variant": "mfma", "tile_samples": 16, "tile_waves": 4, "tile_split": 2,
+                 "kernel": "rollout_pair_kernel"}
+    assert pi.rollout_describe(pi.DeviceProblem(prob, tile_split=1), dm)["tile_split"] == 1
+    big, _, _ = synth.config(1, K=65536, T=2)
+    assert pi.rollout_describe(pi.DeviceProblem(big), dm)["tile_split"] == 1
+    p64 = pi.DeviceProblem(prob, dtype=torch.float64)
+    assert pi.rollout_describe(p64, pi.DeviceModel(model, dtype=torch.float64))["kernel"] == \
+        "rollout_direct_kernel"
+
+
 @pytest.mark.parametrize("split", [1, 2])
 def test_rollout_bitwise_repeatable(split):
     prob, model, _ = synth.config(1, K=512, T=20)
