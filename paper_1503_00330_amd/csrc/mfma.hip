@@ -621,15 +621,19 @@ struct RollSmem {
   float xs[ROWS][Dims<DYN>::NX];
   float eps_s[kNoiseChunk][ROWS][4];
   float xi_s[kNoiseChunk][ROWS][8];
+  float xc[kNoiseChunk][ROWS][Dims<DYN>::NX];   // x_{t+1} of the chunk's steps, for the costs
+  float obs_s[kMaxObs * 3];
 };
 
 // Rollouts s_base .. s_base + spw - 1 of one problem for its whole horizon.
-// Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS.
-// Per step: rows form z, the waves run the model tiles, partial sums are
-// merged, and each row samples its accelerations, steps Euler and writes
-// dt*q(x_{t+1}).  Block-synchronous; rs.sm must have been set up.  With a
-// pair context (pc->half = 0 or 1) the workgroup runs its half of the model
-// tiles, exchanges sums with its partner, and only half 0 writes costs.
+// Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS and
+// evaluate the previous chunk's step costs dt*q(x_{t+1}) from the states kept
+// in LDS (the cost feeds nothing on the path, so it leaves the per-step
+// critical section).  Per step: rows form z, the waves run the model tiles,
+// partial sums are merged, and each row samples its accelerations and steps
+// Euler.  Block-synchronous; rs.sm must have been set up.  With a pair
+// context (pc->half = 0 or 1) the workgroup runs its half of the model tiles,
+// exchanges sums with its partner, and only half 0 writes costs.
 template <int DYN, int MT, int NW>
 __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
@@ -655,9 +659,26 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
     sm.z[row][D] = 1.0f;
     sm.z[row][D + 1] = 0.0f;
   }
+  for (int i = threadIdx.x; i < 3 * p.n_obs; i += NW * 64) rs.obs_s[i] = p.obs[i];
+  // costs of steps t0 .. t0+n-1 from rs.xc, one (row, step) per lane, runs of
+  // consecutive steps per row so the stores coalesce
+  auto flush_costs = [&](int t0, int n) {
+    if (!writer) return;
+    const bool failed = sm.pair_fail != 0;
+    for (int i = threadIdx.x; i < ROWS * n; i += NW * 64) {
+      const int rr = i / n, cc = i - rr * n;
+      const int64_t ss = s_base + rr;
+      if (rr >= spw || ss >= (int64_t)p.K * p.Ms) continue;
+      cost[ss * p.T + t0 + cc] = failed ? __builtin_nanf("") : p.dt * state_cost<float>(p, rs.obs_s, rs.xc[cc][rr]);
+    }
+  };
   for (int t = 0; t < p.T; ++t) {
     const int tc = t % kNoiseChunk;
     if (tc == 0) {
+      if (t > 0) {
+        __syncthreads();  // the chunk's states are in rs.xc
+        flush_costs(t - kNoiseChunk, kNoiseChunk);
+      }
       // draw the next chunk: one lane per (step, row, counter block)
       constexpr int NB = 1 + (NO + 3) / 4;
       for (int i = threadIdx.x; i < kNoiseChunk * ROWS * NB; i += NW * 64) {
@@ -708,10 +729,15 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
       euler_step<float>(DYN, p.dt, x, acc, xn);
 #pragma unroll
-      for (int a = 0; a < NX; ++a) rs.xs[row][a] = xn[a];
-      if (writer) cost[s * p.T + t] = sm.pair_fail ? __builtin_nanf("") : p.dt * state_cost<float>(p, p.obs, xn);
+      for (int a = 0; a < NX; ++a) {
+        rs.xs[row][a] = xn[a];
+        rs.xc[tc][row][a] = xn[a];
+      }
     }
   }
+  __syncthreads();
+  const int tl = p.T > 0 ? ((p.T - 1) / kNoiseChunk) * kNoiseChunk : 0;
+  flush_costs(tl, p.T - tl);
 }
 
 // One workgroup per tile of `spw` (<= 16*MT) sub-rollouts.
