@@ -456,66 +456,70 @@ __device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out) {
 // the same order (half 0 + half 1), so both hold bit-identical moments and
 // take the same redo decision.
 //
-// Protocol per evaluation (sequence number seq, slots double-buffered by
-// parity): data go out as agent-scope relaxed atomic stores; every wave waits
-// for its stores to complete before the barrier, then one lane publishes seq
-// in the half's flag; the partner's flag is polled (agent-scope loads) until
-// it reaches seq and its data are read with agent-scope loads.  A slot is
-// rewritten only two evaluations later, after the partner has published the
-// next seq, which it does only once it has read this one.  Every wait is
-// bounded: on running out, pair_fail is set, no further waits are made and
-// the rollout's costs are written as NaN.
+// Protocol per evaluation (sequence number seq >= 1, slots double-buffered by
+// parity): every published sum travels in a 64-bit word (sequence number in
+// the high half, the float's bits in the low half) written with an
+// agent-scope relaxed atomic store; the lane that needs the partner's word
+// polls it with agent-scope loads until its sequence number is seq.  Aligned
+// 64-bit accesses are single-copy atomic, so a word carrying seq carries
+// this evaluation's value: no flag, fence or barrier orders the data.  A slot
+// is rewritten two evaluations later, which the partner can only reach after
+// every one of our lanes has read it (it needs our next evaluation's words,
+// published after a barrier that follows the reads).  The slots are zeroed
+// before each launch.  Every wait is bounded: on running out, pair_fail is
+// set, no further waits are made and the rollout's costs are written as NaN.
 struct PairCtx {
-  float *xbuf;       // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
-  uint32_t *flags;   // [2]: last sequence number published by each half
+  uint64_t *xbuf;    // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
   int half;          // 0 or 1; -1 when not paired
 };
 constexpr int kXSlots = 16 * kMaxOut;
-constexpr int kPairFloats = 2 * 2 * kXSlots * 5;
+constexpr int kPairWords = 2 * 2 * kXSlots * 5;
 constexpr uint32_t kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ void put_word(uint64_t *p, float v, uint32_t seq) {
+  __hip_atomic_store(p, ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int D, int MT, int NW>
 __device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, const PairCtx &pc, uint32_t seq) {
   static_assert(MT == 1, "paired workgroups hold one 16-row tile");
   constexpr int ROWS = 16;
   const int i = threadIdx.x;
-  const bool mine = i < ROWS * n_out;
+  if (i >= ROWS * n_out) return;
   const int row = i % ROWS, o = i / ROWS;
-  Acc loc = acc_empty();
-  if (mine) {
-    loc = sum_waves(sm, row, o);
-    // one sum per store instruction: consecutive lanes write consecutive words
-    float *dst = pc.xbuf + (size_t)(pc.half * 2 + (seq & 1)) * 5 * kXSlots + i;
-    __hip_atomic_store(dst + 0 * kXSlots, loc.Z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(dst + 1 * kXSlots, loc.S1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(dst + 2 * kXSlots, loc.S2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(dst + 3 * kXSlots, loc.S3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(dst + 4 * kXSlots, loc.mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have completed
-  __syncthreads();
-  if (threadIdx.x == 0 && !sm.pair_fail) {
-    __hip_atomic_store(pc.flags + pc.half, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t n = 0;
-    while (__hip_atomic_load(pc.flags + (1 - pc.half), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < seq) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++n >= kSpinLimit) {
-        sm.pair_fail = 1;
-        break;
-      }
+  const Acc loc = sum_waves(sm, row, o);
+  // consecutive lanes write consecutive words of each sum
+  uint64_t *dst = pc.xbuf + (size_t)(pc.half * 2 + (seq & 1)) * 5 * kXSlots + i;
+  put_word(dst + 0 * kXSlots, loc.Z, seq);
+  put_word(dst + 1 * kXSlots, loc.S1, seq);
+  put_word(dst + 2 * kXSlots, loc.S2, seq);
+  put_word(dst + 3 * kXSlots, loc.S3, seq);
+  put_word(dst + 4 * kXSlots, loc.mx, seq);
+  const uint64_t *src = pc.xbuf + (size_t)((1 - pc.half) * 2 + (seq & 1)) * 5 * kXSlots + i;
+  uint64_t w[5];
+  uint32_t n = 0;
+  for (;;) {
+    bool ready = true;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      w[k] = __hip_atomic_load(src + k * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ready = ready && (uint32_t)(w[k] >> 32) == seq;
     }
+    if (ready) break;
+    if (sm.pair_fail || ++n >= kSpinLimit) {
+      sm.pair_fail = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
-  __syncthreads();
-  if (mine) {
-    const float *src = pc.xbuf + (size_t)((1 - pc.half) * 2 + (seq & 1)) * 5 * kXSlots + i;
-    Acc rem;
-    rem.Z = __hip_atomic_load(src + 0 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    rem.S1 = __hip_atomic_load(src + 1 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    rem.S2 = __hip_atomic_load(src + 2 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    rem.S3 = __hip_atomic_load(src + 3 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    rem.mx = __hip_atomic_load(src + 4 * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    finish_sums(sm, row, o, pc.half == 0 ? acc_sum(loc, rem) : acc_sum(rem, loc));
-  }
+  Acc rem;
+  rem.Z = __uint_as_float((uint32_t)w[0]);
+  rem.S1 = __uint_as_float((uint32_t)w[1]);
+  rem.S2 = __uint_as_float((uint32_t)w[2]);
+  rem.S3 = __uint_as_float((uint32_t)w[3]);
+  rem.mx = __uint_as_float((uint32_t)w[4]);
+  finish_sums(sm, row, o, pc.half == 0 ? acc_sum(loc, rem) : acc_sum(rem, loc));
 }
 
 // The whole mixture of one step for the rows in sm.z over model tiles
@@ -756,13 +760,12 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
 // their exchange stays inside one L2.  The grid must be resident at once.
 template <int DYN, int NW>
 __global__ void __launch_bounds__(NW * 64) rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
-                                                               int n_groups, float *__restrict__ xbuf,
-                                                               uint32_t *__restrict__ flags) {
+                                                               int n_groups, uint64_t *__restrict__ xbuf) {
   __shared__ RollSmem<DYN, 1, NW> rs;
   const int blk = blockIdx.x;
   const int g = (blk / 16) * 8 + (blk % 8);
   if (g >= n_groups) return;  // both halves of an unused pair leave
-  const PairCtx pc{xbuf + (size_t)g * kPairFloats, flags + 2 * g, (blk / 8) & 1};
+  const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1};
   mix_setup(rs.sm);
   rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc);
 }
@@ -818,10 +821,7 @@ hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
   return rollout_mfma_t<kDynPointMass2D, 2, 4>(ra, md, spw, s);
 }
 
-size_t pair_ws_bytes(int64_t n_groups) {
-  return align_up((size_t)n_groups * kPairFloats * sizeof(float), 256) +
-         align_up((size_t)n_groups * 2 * sizeof(uint32_t), 256);
-}
+size_t pair_ws_bytes(int64_t n_groups) { return align_up((size_t)n_groups * kPairWords * sizeof(uint64_t), 256); }
 
 int pair_grid(int64_t n_groups) { return (int)(16 * ((n_groups + 7) / 8)); }
 
@@ -842,21 +842,21 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
   const MfmaModel md = mfma_view(l, base);
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
   const int64_t n_groups = (n + spw - 1) / spw;
-  float *xbuf = (float *)pair_ws;
-  uint32_t *flags = (uint32_t *)((char *)pair_ws + align_up((size_t)n_groups * kPairFloats * sizeof(float), 256));
-  hipError_t e = launch_zero_u32(flags, 2 * n_groups, s);
+  uint64_t *xbuf = (uint64_t *)pair_ws;
+  // sequence numbers restart at 1 every launch: clear the previous launch's
+  hipError_t e = launch_zero_u32((uint32_t *)xbuf, 2 * n_groups * kPairWords, s);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)pair_grid(n_groups));
   if (ra.p.dyn == kDynQuad12) {
     if (waves == 8)
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8>), grid, dim3(512), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf, flags);
+                         xbuf);
     else
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4>), grid, dim3(256), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf, flags);
+                         xbuf);
   } else {
     hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4>), grid, dim3(256), 0, s, ra, md, spw,
-                       (int)n_groups, xbuf, flags);
+                       (int)n_groups, xbuf);
   }
   return hipGetLastError();
 }
