@@ -204,8 +204,9 @@ struct MixSmem {
   float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
+  float acc[ROWS][kMaxOut];              // sampled accelerations (rollouts)
   unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
-  int redo;
+  int redo[2];                           // second-pass requests, by evaluation parity
   int pair_fail;                         // a partner wait ran out (results invalid)
 };
 
@@ -243,7 +244,7 @@ __device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
     sm.fsrc[e] = (unsigned short)((ia << 8) | ib);
   }
   if (threadIdx.x == 0) {
-    sm.redo = 0;
+    sm.redo[0] = sm.redo[1] = 0;
     sm.pair_fail = 0;
   }
 }
@@ -413,16 +414,26 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   flush(o);
 }
 
-// Eq. (1) moments of one (row, output) from its complete sums, the anchors of
-// the next evaluation (observed maximum and mean), and the redo flag when the
-// maximum left the anchor window.
+// Sampling of the next-state draw inside the mixture's last stage: with xi
+// set, acc = mu + sqrt(var) xi[row][o] (a draw from N(mu, var)); without, mu.
+struct SampleArgs {
+  const float *xi;   // [rows][8] standard normals of this step, or null
+};
+
+// Eq. (1) moments of one (row, output) from its complete sums, the sampled
+// acceleration, the anchors of the next evaluation (observed maximum and
+// mean), and the redo flag of evaluation `ev` when the maximum left the
+// anchor window.
 template <int D, int MT, int NW>
-__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int o, const Acc &s) {
+__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int o, const Acc &s, uint32_t ev,
+                                            const SampleArgs &sa) {
   const float d1 = s.S1 / s.Z;
   const float mu = sm.yref[row][o] + d1;
+  const float var = (fmaxf(s.S2 - s.S1 * d1, 0.f) + s.S3) / s.Z;
   sm.mean[row][o] = mu;
-  sm.var[row][o] = (fmaxf(s.S2 - s.S1 * d1, 0.f) + s.S3) / s.Z;
-  if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo = 1;
+  sm.var[row][o] = var;
+  sm.acc[row][o] = sa.xi ? mu + sqrtf(var) * sa.xi[row * 8 + o] : mu;
+  if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo[ev & 1] = 1;
   sm.mref[row][o] += s.mx;
   if (isfinite(mu)) sm.yref[row][o] = mu;
 }
@@ -442,11 +453,11 @@ __device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW> &sm, int row, 
 // Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, then the
 // moments.
 template <int D, int MT, int NW>
-__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out) {
+__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out, uint32_t ev, const SampleArgs &sa) {
   constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
   for (int i = threadIdx.x; i < ROWS * n_out; i += NW * 64) {
     const int row = i % ROWS, o = i / ROWS;
-    finish_sums(sm, row, o, sum_waves(sm, row, o));
+    finish_sums(sm, row, o, sum_waves(sm, row, o), ev, sa);
   }
 }
 
@@ -482,7 +493,8 @@ __device__ __forceinline__ void put_word(uint64_t *p, float v, uint32_t seq) {
 }
 
 template <int D, int MT, int NW>
-__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, const PairCtx &pc, uint32_t seq) {
+__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, const PairCtx &pc, uint32_t seq,
+                                           const SampleArgs &sa) {
   static_assert(MT == 1, "paired workgroups hold one 16-row tile");
   constexpr int ROWS = 16;
   const int i = threadIdx.x;
@@ -519,34 +531,38 @@ __device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, co
   rem.S2 = __uint_as_float((uint32_t)w[2]);
   rem.S3 = __uint_as_float((uint32_t)w[3]);
   rem.mx = __uint_as_float((uint32_t)w[4]);
-  finish_sums(sm, row, o, pc.half == 0 ? acc_sum(loc, rem) : acc_sum(rem, loc));
+  finish_sums(sm, row, o, pc.half == 0 ? acc_sum(loc, rem) : acc_sum(rem, loc), seq, sa);
 }
 
 // The whole mixture of one step for the rows in sm.z over model tiles
 // [T0, T1): one pass, a second one if an anchor was out of range or
-// `force_second`.  Block-synchronous.  With a pair context the two halves'
-// sums are exchanged every pass (seq counts the exchanges).
+// `force_second`.  Block-synchronous.  seq counts the evaluations (it numbers
+// the pair exchanges and selects the redo flag, double-buffered so that one
+// barrier per evaluation suffices); with a pair context the two halves' sums
+// are exchanged every pass.
 template <int D, int MT, int NW>
 __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW> &sm, bool force_second,
-                                             int T0, int T1, const PairCtx *pc, uint32_t &seq) {
+                                             int T0, int T1, const PairCtx *pc, uint32_t &seq,
+                                             const SampleArgs &sa = SampleArgs{nullptr}) {
   for (int pass = 0; pass < 2; ++pass) {
     build_fragments(sm);
     __syncthreads();
     mixture_tiles(md, sm, T0, T1);
     __syncthreads();
+    const uint32_t ev = ++seq;
     if constexpr (MT == 1) {
       if (pc != nullptr) {
-        merge_pair(sm, md.n_out, *pc, ++seq);
+        merge_pair(sm, md.n_out, *pc, ev, sa);
       } else {
-        merge_waves(sm, md.n_out);
+        merge_waves(sm, md.n_out, ev, sa);
       }
     } else {
-      merge_waves(sm, md.n_out);
+      merge_waves(sm, md.n_out, ev, sa);
     }
     __syncthreads();
-    const bool again = pass == 0 && (force_second || sm.redo != 0);
-    __syncthreads();
-    if (threadIdx.x == 0) sm.redo = 0;
+    const bool again = pass == 0 && (force_second || sm.redo[ev & 1] != 0);
+    // the next evaluation's flag: last read before this evaluation's barriers
+    if (threadIdx.x == 0) sm.redo[(ev + 1) & 1] = 0;
     if (!again) break;
   }
 }
@@ -723,12 +739,11 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
     }
     __syncthreads();
-    mixture_step(md, sm, t == 0, T0, T1, pc, seq);
+    mixture_step(md, sm, t == 0, T0, T1, pc, seq, SampleArgs{p.M > 0 ? &rs.xi_s[tc][0][0] : nullptr});
     if (active) {
       float acc[NO], xn[NX], x[NX];
 #pragma unroll
-      for (int o = 0; o < NO; ++o)
-        acc[o] = p.M > 0 ? sm.mean[row][o] + sqrtf(sm.var[row][o]) * rs.xi_s[tc][row][o] : sm.mean[row][o];
+      for (int o = 0; o < NO; ++o) acc[o] = sm.acc[row][o];
 #pragma unroll
       for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
       euler_step<float>(DYN, p.dt, x, acc, xn);
