@@ -84,7 +84,8 @@ def main():
     torch.cuda.set_device(0)
     prob, model, _ = synth.config(1)
     dp = pi.DeviceProblem(prob, tile_samples=args.tile_samples, tile_waves=args.tile_waves)
-    dm = pi.DeviceModel(model)
+    # the model is fixed over the receding-horizon loop: fold it once
+    dm = pi.DeviceModel(model).fold()
     cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
     x0_init, u_init = dp.x0.clone(), dp.u_nom.clone()
     # reserve every workspace before timing

@@ -84,6 +84,13 @@ typedef struct {
   const void *proj_p;              /* dev [Ltot][R][d], or NULL for p = u    */
   const void *beta;                /* dev [Ltot][R+1]                        */
   const void *sigma2;              /* dev [Ltot], >= 0                       */
+  const void *folded;              /* dev, optional: this model's folded forms as
+                                    * written by pi_model_fold.  When non-NULL,
+                                    * prediction, rollouts and the RH shift read
+                                    * them instead of folding the model into their
+                                    * workspace on every call; the caller re-folds
+                                    * after changing any model array.           */
+  size_t folded_bytes;             /* size of `folded` (>= pi_model_fold_bytes) */
 } pi_lwpr;
 
 /* One PI^2-RH instance (Sec. 3.1, 3.2, 5). */
@@ -123,6 +130,17 @@ typedef struct {
  * if the arguments are invalid.  For PI_OP_PREDICT, `p` may be NULL and the
  * query count is taken as p ? p->K : 0 (prediction needs no per-query space). */
 size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m);
+
+/* Model folding (Sec. 2 local models, Eq. 1): the PLS chain of every local
+ * model reduces to an affine map y = beta0 + b.(z - c); the kernels read the
+ * model in folded forms -- per-model records (c, D + D^T packed, b, beta0,
+ * sigma^2) and, for float32 with d in {6, 16}, the matrix-core tiles.
+ * pi_model_fold_bytes gives the size of both (or (size_t)-1 on an invalid
+ * model); pi_model_fold writes them to `folded` (dev, caller-owned, at least
+ * that many bytes), stream-ordered.  Pass the buffer in pi_lwpr.folded to skip
+ * the per-call fold.                                                          */
+size_t pi_model_fold_bytes(const pi_lwpr *m);
+pi_status pi_model_fold(const pi_lwpr *m, void *folded, size_t folded_bytes, void *stream);
 
 /* The launch pi_rollout_cost would make for this problem and model on the
  * current device (no work is done): out[0] = PI_VARIANT_DIRECT or

@@ -30,7 +30,7 @@ PI_MAX_OUT, PI_MAX_U = 8, 4
 STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4: "PI_ERR_DTYPE",
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6)}
-EXPORTED = ["pi_workspace_bytes", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
+EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
             "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
             "pi_batched_plan", "pi_rollout_cost_batched", "pi_philox4x32_10", "pi_noise",
             "pi_last_error", "pi_version"]
@@ -47,7 +47,8 @@ class pi_lwpr(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("d", C.c_int32), ("n_out", C.c_int32), ("R", C.c_int32),
                 ("L_off", C.c_int32 * (PI_MAX_OUT + 1)), ("centre", C.c_void_p),
                 ("metric", C.c_void_p), ("proj_u", C.c_void_p), ("proj_p", C.c_void_p),
-                ("beta", C.c_void_p), ("sigma2", C.c_void_p)]
+                ("beta", C.c_void_p), ("sigma2", C.c_void_p), ("folded", C.c_void_p),
+                ("folded_bytes", C.c_size_t)]
 
 
 class pi_problem(C.Structure):
@@ -79,6 +80,10 @@ def load(path: str = LIB_PATH):
     lib.pi_workspace_bytes.restype = sz
     lib.pi_rollout_describe.argtypes = [vp, vp, vp]
     lib.pi_rollout_describe.restype = i32
+    lib.pi_model_fold_bytes.argtypes = [vp]
+    lib.pi_model_fold_bytes.restype = sz
+    lib.pi_model_fold.argtypes = [vp, vp, sz, vp]
+    lib.pi_model_fold.restype = i32
     lib.lwpr_predict.argtypes = [vp, vp, i64, vp, vp, i32, vp, sz, vp]
     lib.pi_rollout_cost.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_update.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
@@ -182,12 +187,32 @@ class DeviceModel:
         self.beta, self.sigma2 = tt(model.beta), tt(model.sigma2)
         self.dtype = dtype
         self.device = torch.device(device)
+        self.folded = None
 
     @property
     def Ltot(self):
         return self.L_off[-1]
 
-    def struct(self) -> pi_lwpr:
+    def fold(self):
+        """Folds the model once (pi_model_fold) so that prediction, rollouts and
+        the RH shift stop re-folding it on every call.  Call again after
+        changing any of the model tensors; unfold() returns to per-call folds."""
+        torch = _torch()
+        s = self.struct(folded=False)
+        lib = load()
+        n = lib.pi_model_fold_bytes(C.byref(s))
+        if n == C.c_size_t(-1).value:
+            raise PiError(PI_ERR_VALUE, last_error())
+        if self.folded is None or self.folded.numel() < n:
+            self.folded = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib.pi_model_fold(C.byref(s), _ptr(self.folded), self.folded.numel(), _stream()))
+        return self
+
+    def unfold(self):
+        self.folded = None
+        return self
+
+    def struct(self, folded: bool = True) -> pi_lwpr:
         s = pi_lwpr()
         s.dtype = _dt(self.dtype)
         s.d, s.n_out, s.R = self.d, self.n_out, self.R
@@ -196,6 +221,8 @@ class DeviceModel:
         s.centre, s.metric = _ptr(self.centre), _ptr(self.metric)
         s.proj_u, s.proj_p = _ptr(self.proj_u), _ptr(self.proj_p)
         s.beta, s.sigma2 = _ptr(self.beta), _ptr(self.sigma2)
+        if folded and self.folded is not None:
+            s.folded, s.folded_bytes = _ptr(self.folded), self.folded.numel()
         return s
 
 

@@ -234,6 +234,44 @@ bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
   return p->tile_split == 2 || pl.groups < n_cu;
 }
 
+// Layout of a pi_model_fold buffer: direct records, then (float32, d in
+// {6, 16}) the matrix-core tiles.
+struct FoldedLayout {
+  size_t direct_off, mfma_off, bytes;
+  bool has_mfma;
+};
+FoldedLayout folded_layout(const pi_lwpr *m) {
+  FoldedLayout f;
+  f.direct_off = 0;
+  f.has_mfma = mfma_ok(m->dtype, m->d);
+  f.mfma_off = align_up(direct_bytes(m->dtype, m->d, m->L_off[m->n_out]), 256);
+  f.bytes = f.mfma_off + (f.has_mfma ? align_up(mfma_layout(m->d, m->n_out, m->L_off).bytes, 256) : 0);
+  return f;
+}
+
+// Where the kernels read the folded model from: the caller's pi_model_fold
+// buffer, or the start of the workspace after folding into it on `s`.
+hipError_t folded_base(const pi_lwpr *m, bool mfma, void *ws, hipStream_t s, const void **base) {
+  if (m->folded) {
+    const FoldedLayout f = folded_layout(m);
+    *base = (const char *)m->folded + (mfma ? f.mfma_off : f.direct_off);
+    return hipSuccess;
+  }
+  *base = ws;
+  const ModelArgs a = model_args(m);
+  if (mfma) return launch_fold_mfma(m->dtype, a, mfma_layout(m->d, m->n_out, m->L_off), ws, s);
+  return launch_fold_direct(m->dtype, a, ws, s);
+}
+
+pi_status check_folded(const pi_lwpr *m, bool mfma) {
+  if (!m->folded) return PI_OK;
+  const FoldedLayout f = folded_layout(m);
+  if (m->folded_bytes < f.bytes)
+    return fail(PI_ERR_WORKSPACE, "folded model of %zu bytes needed, %zu given", f.bytes, m->folded_bytes);
+  if (mfma && !f.has_mfma) return fail(PI_ERR_UNSUPPORTED, "folded model has no matrix-core form");
+  return PI_OK;
+}
+
 size_t fold_bytes(const pi_lwpr *m, bool mfma) {
   if (mfma) return mfma_layout(m->d, m->n_out, m->L_off).bytes;
   return direct_bytes(m->dtype, m->d, m->L_off[m->n_out]);
@@ -322,6 +360,26 @@ const char *pi_last_error(void) { return g_err; }
 
 const char *pi_version(void) { return "pi2rh 0.1 (gfx950)"; }
 
+size_t pi_model_fold_bytes(const pi_lwpr *m) {
+  if (check_model(m) != PI_OK) return (size_t)-1;
+  return folded_layout(m).bytes;
+}
+
+pi_status pi_model_fold(const pi_lwpr *m, void *folded, size_t folded_bytes, void *stream) {
+  PI_TRY(check_model(m));
+  const FoldedLayout f = folded_layout(m);
+  if (!folded) return fail(PI_ERR_NULL, "folded must be non-NULL");
+  if (folded_bytes < f.bytes) return fail(PI_ERR_WORKSPACE, "folded model of %zu bytes needed, %zu given", f.bytes,
+                                          folded_bytes);
+  PI_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  const ModelArgs a = model_args(m);
+  hipError_t e = launch_fold_direct(m->dtype, a, (char *)folded + f.direct_off, s);
+  if (e == hipSuccess && f.has_mfma)
+    e = launch_fold_mfma(m->dtype, a, mfma_layout(m->d, m->n_out, m->L_off), (char *)folded + f.mfma_off, s);
+  return launched(e, "pi_model_fold");
+}
+
 pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out) {
   PI_TRY(check_pair(p, m));
   if (!out) return fail(PI_ERR_NULL, "out must be non-NULL");
@@ -368,19 +426,19 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
   const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_ok(m->dtype, m->d));
   if (use_mfma && !mfma_ok(m->dtype, m->d))
     return fail(PI_ERR_UNSUPPORTED, "MFMA prediction needs float32 and d in {6,16}");
-  PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, use_mfma)));
+  PI_TRY(check_folded(m, use_mfma));
+  if (!m->folded) PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, use_mfma)));
   PI_TRY(check_device());
   if (N == 0) return ok();
   hipStream_t s = (hipStream_t)stream;
   const ModelArgs a = model_args(m);
-  hipError_t e;
-  if (use_mfma) {
-    const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
-    e = launch_fold_mfma(m->dtype, a, l, ws, s);
-    if (e == hipSuccess) e = launch_predict_mfma(a, l, ws, Z, N, mean, var, s);
-  } else {
-    e = launch_fold_direct(m->dtype, a, ws, s);
-    if (e == hipSuccess) e = launch_predict_direct(m->dtype, a, ws, Z, N, mean, var, s);
+  const void *base = nullptr;
+  hipError_t e = folded_base(m, use_mfma, ws, s, &base);
+  if (e == hipSuccess) {
+    if (use_mfma)
+      e = launch_predict_mfma(a, mfma_layout(m->d, m->n_out, m->L_off), base, Z, N, mean, var, s);
+    else
+      e = launch_predict_direct(m->dtype, a, base, Z, N, mean, var, s);
   }
   return launched(e, "lwpr_predict");
 }
@@ -391,6 +449,7 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
   if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost must be non-NULL");
   const RolloutPlan pl = rollout_plan(p, m);
   if (pl.mfma && !mfma_ok(p->dtype, m->d)) return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  PI_TRY(check_folded(m, pl.mfma));
   PI_TRY(check_ws(ws, ws_bytes, rollout_ws(p, m)));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
@@ -398,25 +457,23 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
   const int Ms = p->M > 0 ? p->M : 1;
   const size_t fb = fold_bytes(m, pl.mfma);
   void *sub = Ms > 1 ? (void *)((char *)ws + fb) : cost;
-  hipError_t e;
-  if (p->dtype == PI_F64) {
-    RolloutArgs<double> ra{prob_dev<double>(p), (const double *)x0, (const double *)u_nom, iter, (double *)sub};
-    e = launch_fold_direct(PI_F64, a, ws, s);
-    if (e == hipSuccess) e = launch_rollout_direct(PI_F64, &ra, a, ws, s);
-  } else {
-    RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
-    if (pl.mfma) {
-      const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
-      e = launch_fold_mfma(PI_F32, a, l, ws, s);
-      if (e == hipSuccess) {
-        if (use_pair(p, pl))
-          e = launch_rollout_pair(ra, l, ws, pl.spw, pl.waves, (char *)ws + fb + sub_bytes(p), s);
-        else
-          e = launch_rollout_mfma(ra, a, l, ws, pl.spw, pl.waves, s);
-      }
+  const void *base = nullptr;
+  hipError_t e = folded_base(m, pl.mfma, ws, s, &base);
+  if (e == hipSuccess) {
+    if (p->dtype == PI_F64) {
+      RolloutArgs<double> ra{prob_dev<double>(p), (const double *)x0, (const double *)u_nom, iter, (double *)sub};
+      e = launch_rollout_direct(PI_F64, &ra, a, base, s);
     } else {
-      e = launch_fold_direct(PI_F32, a, ws, s);
-      if (e == hipSuccess) e = launch_rollout_direct(PI_F32, &ra, a, ws, s);
+      RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
+      if (pl.mfma) {
+        const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+        if (use_pair(p, pl))
+          e = launch_rollout_pair(ra, l, base, pl.spw, pl.waves, (char *)ws + fb + sub_bytes(p), s);
+        else
+          e = launch_rollout_mfma(ra, a, l, base, pl.spw, pl.waves, s);
+      } else {
+        e = launch_rollout_direct(PI_F32, &ra, a, base, s);
+      }
     }
   }
   if (e == hipSuccess && Ms > 1) e = launch_subcost_reduce(p->dtype, sub, cost, p->K, Ms, p->T, s);
@@ -447,18 +504,20 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
   if (!x0 || !u_nom || !iter) return fail(PI_ERR_NULL, "x0, u_nom and iter must be non-NULL");
   const ModelArgs a = model_args(m);
   const size_t fb = fold_bytes(m, false);
+  PI_TRY(check_folded(m, false));
   PI_TRY(check_ws(ws, ws_bytes, fb + shift_partial_bytes(a, m->dtype)));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
   void *part = (char *)ws + fb;
-  hipError_t e = launch_fold_direct(p->dtype, a, ws, s);
+  const void *base = nullptr;
+  hipError_t e = folded_base(m, false, ws, s, &base);
   if (e == hipSuccess) {
     if (p->dtype == PI_F64) {
       const ProbDev<double> d = prob_dev<double>(p);
-      e = launch_rh_shift(PI_F64, &d, a, ws, part, x0, u_nom, iter, s);
+      e = launch_rh_shift(PI_F64, &d, a, base, part, x0, u_nom, iter, s);
     } else {
       const ProbDev<float> d = prob_dev<float>(p);
-      e = launch_rh_shift(PI_F32, &d, a, ws, part, x0, u_nom, iter, s);
+      e = launch_rh_shift(PI_F32, &d, a, base, part, x0, u_nom, iter, s);
     }
   }
   return launched(e, "pi_rh_shift");

@@ -245,29 +245,30 @@ size_t update_ws_bytes(int K, int T) {
          align_up((size_t)T * 2 * 8, 256);
 }
 
-// Suffix sums through an LDS transpose: a block of 256 rollouts walks the
-// horizon backwards in chunks of 16 steps; chunk loads read 64-byte row
-// segments and every S row write is coalesced over k.
+// Suffix sums S[t][k] = sum_{t' >= t} cost[k][t'] in double.  A block holds 64
+// rollouts and splits the horizon into 4 segments, one wave each: every lane
+// sums its (rollout, segment), the segment totals meet in LDS, and each lane
+// walks its segment backwards from the total of the later segments; the S
+// stores of a wave cover 64 consecutive rollouts.
+constexpr int kSufK = 64, kSufSeg = 4;
 template <typename Real>
-__global__ void __launch_bounds__(256) suffix_kernel(const Real *__restrict__ cost, int K, int T,
-                                                     double *__restrict__ S) {
-  __shared__ double tile[256][17];
-  const int k0 = blockIdx.x * 256, k = k0 + threadIdx.x;
-  const int nk = min(256, K - k0);
+__global__ void __launch_bounds__(kSufK * kSufSeg) suffix_kernel(const Real *__restrict__ cost, int K, int T,
+                                                                 double *__restrict__ S) {
+  __shared__ double tot[kSufSeg][kSufK];
+  const int kl = threadIdx.x % kSufK, seg = threadIdx.x / kSufK;
+  const int k = blockIdx.x * kSufK + kl;
+  const int lo = (int)((int64_t)seg * T / kSufSeg), hi = (int)((int64_t)(seg + 1) * T / kSufSeg);
+  const Real *row = cost + (int64_t)min(k, K - 1) * T;
+  double sum = 0.0;
+  for (int t = lo; t < hi; ++t) sum += (double)row[t];
+  tot[seg][kl] = sum;
+  __syncthreads();
   double acc = 0.0;
-  for (int hi = T; hi > 0; hi -= 16) {
-    const int lo = max(0, hi - 16), w = hi - lo;
-    __syncthreads();
-    for (int e = threadIdx.x; e < 256 * 16; e += 256) {
-      const int r = e / 16, c = e % 16;
-      if (r < nk && c < w) tile[r][c] = (double)cost[(int64_t)(k0 + r) * T + lo + c];
-    }
-    __syncthreads();
-    if (k < K)
-      for (int c = w - 1; c >= 0; --c) {
-        acc += tile[threadIdx.x][c];
-        S[(int64_t)(lo + c) * K + k] = acc;
-      }
+  for (int j = kSufSeg - 1; j > seg; --j) acc += tot[j][kl];
+  if (k >= K) return;
+  for (int t = hi - 1; t >= lo; --t) {
+    acc += (double)row[t];
+    S[(int64_t)t * K + k] = acc;
   }
 }
 
@@ -361,7 +362,8 @@ static hipError_t update_t(const ProbDev<Real> &p, const Real *cost, const uint3
   double *S = (double *)ws;
   double *part = (double *)((char *)ws + align_up((size_t)K * T * 8, 256));
   double *norm = (double *)((char *)part + align_up((size_t)T * C * (2 + kMaxU) * 8, 256));
-  hipLaunchKernelGGL(suffix_kernel<Real>, dim3((K + 255) / 256), dim3(256), 0, s, cost, K, T, S);
+  hipLaunchKernelGGL(suffix_kernel<Real>, dim3((K + kSufK - 1) / kSufK), dim3(kSufK * kSufSeg), 0, s, cost, K, T,
+                     S);
   hipLaunchKernelGGL(update_chunk_kernel<Real>, dim3(C, T), dim3(kUpdThreads), 0, s, p, lambda,
                      weighting, iter, (const double *)S, part);
   hipLaunchKernelGGL(update_apply_kernel<Real>, dim3((T + 63) / 64), dim3(64), 0, s, T, C, p.n_u,

@@ -19,9 +19,15 @@ from . import (DeviceModel, DeviceProblem, PI_OP_ROLLOUT, PI_OP_RH_SHIFT, PI_OP_
 
 
 class RHController:
+    """The model is folded once here (DeviceModel.fold) unless fold_model is
+    False: it stays fixed over the loop; call model.fold() again after changing
+    its tensors."""
+
     def __init__(self, prob: DeviceProblem, model: DeviceModel, iterations: int = 1,
-                 graph: bool = True):
+                 graph: bool = True, fold_model: bool = True):
         self.prob, self.model = prob, model
+        if fold_model:
+            model.fold()
         self.iterations = int(iterations)
         self.cost = torch.empty((prob.K, prob.T), dtype=prob.dtype, device=prob.device)
         need = max(workspace_bytes(PI_OP_ROLLOUT, prob, model),

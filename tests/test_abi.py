@@ -105,6 +105,18 @@ class TestValidation:
         ps.tile_split = 7
         assert lib.pi_rollout_describe(C.byref(ps), C.byref(ms), out) == 3
 
+    def test_model_fold_validates(self):
+        ps, ms = _structs()
+        lib = pi.load()
+        n = lib.pi_model_fold_bytes(C.byref(ms))
+        assert 0 < n < (1 << 40)
+        assert lib.pi_model_fold(C.byref(ms), None, n, None) == 1
+        assert lib.pi_model_fold(C.byref(ms), FAKE, n - 1, None) == 5
+        ms.folded, ms.folded_bytes = FAKE, n - 1      # too small a folded buffer
+        assert _rollout(ps, ms) == 5
+        ms.d = 0
+        assert lib.pi_model_fold_bytes(C.byref(ms)) == C.c_size_t(-1).value
+
     def test_bad_model(self):
         ps, ms = _structs()
         ms.d = 17

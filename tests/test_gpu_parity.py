@@ -224,6 +224,29 @@ def test_rollout_config1_full_launch_sampled_rows(split):
     print("config 1 sampled rows: max S rel %.2e, flips %d" % (r, flips))
 
 
+def test_prefolded_model_gives_identical_results():
+    # pi_model_fold once, then every entry point reads the folded buffer: the
+    # same kernels on the same folded values, so results are bitwise equal
+    prob, model, _ = synth.config(1, K=300, T=12)
+    dm, df = pi.DeviceModel(model), pi.DeviceModel(model).fold()
+    Z = torch.from_numpy(np.random.default_rng(8).uniform(-1, 1, (77, 16)).astype(F32)).cuda()
+    for variant in (pi.PI_VARIANT_DIRECT, pi.PI_VARIANT_MFMA):
+        a, b = pi.lwpr_predict(dm, Z, variant=variant), pi.lwpr_predict(df, Z, variant=variant)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for split in (1, 2):
+        dp = pi.DeviceProblem(prob, tile_split=split)
+        assert torch.equal(pi.rollout_cost(dp, dm), pi.rollout_cost(dp, df))
+    d1, d2 = pi.DeviceProblem(prob), pi.DeviceProblem(prob)
+    pi.rh_shift(d1, dm)
+    pi.rh_shift(d2, df)
+    assert torch.equal(d1.x0, d2.x0) and torch.equal(d1.u_nom, d2.u_nom)
+    p64, _, _ = synth.config(0)
+    m64 = synth.config(0)[1]
+    a = pi.rollout_cost(pi.DeviceProblem(p64), pi.DeviceModel(m64))
+    b = pi.rollout_cost(pi.DeviceProblem(p64), pi.DeviceModel(m64).fold())
+    assert torch.equal(a, b)
+
+
 def test_rollout_describe_reports_the_launch():
     prob, model, _ = synth.config(1)
     dm = pi.DeviceModel(model)
