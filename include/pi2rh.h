@@ -47,12 +47,19 @@ typedef enum {
 
 typedef enum { PI_F32 = 0, PI_F64 = 1 } pi_dtype;
 
-/* Dynamics families.  LWPR input is z = [state ; control] (d = n_x + n_u);
- * outputs are accelerations integrated by explicit Euler.
- *   POINTMASS2D: state [px,py,vx,vy], control 2, outputs [ax,ay]
+/* Dynamics families; every step is explicit Euler with the LWPR outputs as
+ * accelerations.
+ *   POINTMASS2D: state [px,py,vx,vy], control 2, z = [state ; control] (d = 6),
+ *                outputs [ax,ay]
  *   QUAD12:      state [p(3), v(3), euler(3), rates(3)], control 4,
- *                outputs [linear acc(3), angular acc(3)]                    */
-enum { PI_DYN_POINTMASS2D = 0, PI_DYN_QUAD12 = 1 };
+ *                z = [state ; control] (d = 16),
+ *                outputs [linear acc(3), angular acc(3)]
+ *   QUAD_HYBRID: the paper's quadrotor model (Sec. 4.1): state [p(3), v(3),
+ *                euler(3)], control [commanded euler rates(3), thrust F];
+ *                the angles follow d(euler)/dt = 25 (commanded - euler), and
+ *                three LWPR models of z = [euler(3), F] (d = 4) give the
+ *                linear accelerations (outputs 3)                            */
+enum { PI_DYN_POINTMASS2D = 0, PI_DYN_QUAD12 = 1, PI_DYN_QUAD_HYBRID = 2 };
 /* Obstacle term of the state cost q(x) (Sec. 5): an indicator with a fixed
  * penalty for being strictly inside any disc/vertical cylinder, or the smooth
  * form penalty * sum_i exp(-decay * (dx_i^2 + dy_i^2)).                     */
@@ -197,6 +204,7 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
  * sizes the workspace for the default checkpoint interval; another interval
  * may need more (PI_ERR_WORKSPACE says how much).  The indicator obstacle
  * term has zero derivative almost everywhere.                               */
+/* (PI_DYN_POINTMASS2D and PI_DYN_QUAD12; PI_ERR_UNSUPPORTED otherwise.)     */
 pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0,
                              const void *u_nom, const uint32_t *iter, int32_t ckpt_every,
                              void *J, void *g_u_nom, void *g_centre, void *g_metric, void *ws,

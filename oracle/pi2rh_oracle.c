@@ -42,6 +42,11 @@
  *       precision), Box-Muller pairs (u0,u1), (u2,u3).
  *   R8  adjoint: J = (1/(K max(M,1))) sum_{k,m,t} c_{k,m,t} with all noise
  *       held fixed; derivatives w.r.t. u_nom, c_j and every entry of D_j.
+ *   R9  the paper's own quadrotor model (Sec. 4.1, "hybrid"): controls are
+ *       commanded euler rates and the total thrust F; the angles follow the
+ *       first-order response dr/dt = 25 (r_commanded - r); three LWPR models
+ *       with inputs (phi, theta, psi, F) give the cartesian accelerations.
+ *       State [p, v, r] (9), integrated by explicit Euler like the others.
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,6 +58,8 @@
 
 #define ORC_POINTMASS2D 0
 #define ORC_QUAD12 1
+#define ORC_QUAD_HYBRID 2
+#define ORC_RATE_GAIN 25.0
 #define ORC_OBS_INDICATOR 0
 #define ORC_OBS_SMOOTH 1
 #define ORC_W_COST_TO_GO 0
@@ -228,15 +235,32 @@ void orc_lwpr_predict(const orc_model *md, const double *Z, int64_t N, double *m
 
 /* ---------------------------------------------------------------- dynamics */
 
-static int n_state(int dyn) { return dyn == ORC_POINTMASS2D ? 4 : 12; }
+static int n_state(int dyn) { return dyn == ORC_POINTMASS2D ? 4 : (dyn == ORC_QUAD_HYBRID ? 9 : 12); }
 static int n_control(int dyn) { return dyn == ORC_POINTMASS2D ? 2 : 4; }
 static int n_pos(int dyn) { return dyn == ORC_POINTMASS2D ? 2 : 3; }
 
+/* The LWPR input for state x and applied control u (readings R3, R9). */
+static void model_input(int dyn, const double *x, const double *u, double *z) {
+  if (dyn == ORC_QUAD_HYBRID) {
+    /* euler angles phi, theta, psi and the thrust F */
+    z[0] = x[6];
+    z[1] = x[7];
+    z[2] = x[8];
+    z[3] = u[3];
+    return;
+  }
+  const int nx = n_state(dyn), nu = n_control(dyn);
+  for (int a = 0; a < nx; ++a) z[a] = x[a];
+  for (int a = 0; a < nu; ++a) z[nx + a] = u[a];
+}
+
 /* Explicit Euler (Table 1 caption): positions integrate velocities, velocities
- * integrate the sampled linear accelerations; for the quadrotor the Euler
- * angles integrate the body rates and the rates integrate the angular
- * accelerations.  All right-hand sides use the old state. */
-static void euler_step(int dyn, double dt, const double *x, const double *acc, double *xn) {
+ * integrate the sampled linear accelerations; for the 12-state quadrotor the
+ * Euler angles integrate the body rates and the rates integrate the angular
+ * accelerations; for the hybrid model the angles relax towards the commanded
+ * rates u[0..2] (reading R9).  All right-hand sides use the old state. */
+static void euler_step(int dyn, double dt, const double *x, const double *acc, const double *u,
+                       double *xn) {
   const int np = n_pos(dyn);
   for (int a = 0; a < np; ++a) {
     xn[a] = x[a] + dt * x[np + a];
@@ -246,6 +270,11 @@ static void euler_step(int dyn, double dt, const double *x, const double *acc, d
     for (int a = 0; a < 3; ++a) {
       xn[6 + a] = x[6 + a] + dt * x[9 + a];
       xn[9 + a] = x[9 + a] + dt * acc[3 + a];
+    }
+  } else if (dyn == ORC_QUAD_HYBRID) {
+    for (int a = 0; a < 3; ++a) {
+      double rate = ORC_RATE_GAIN * (u[a] - x[6 + a]);
+      xn[6 + a] = x[6 + a] + dt * rate;
     }
   }
 }
@@ -261,7 +290,7 @@ static double state_cost(const orc_problem *p, const double *x) {
     c += p->w_pos[a] * e * e;
   }
   for (int a = 0; a < np; ++a) c += p->w_vel * x[np + a] * x[np + a];
-  if (p->dyn == ORC_QUAD12)
+  if (p->dyn != ORC_POINTMASS2D) /* the three euler angles */
     for (int a = 0; a < 3; ++a) c += p->w_ang * x[6 + a] * x[6 + a];
   if (p->obs_kind == ORC_OBS_INDICATOR) {
     int inside = 0;
@@ -285,7 +314,7 @@ static void state_cost_grad(const orc_problem *p, const double *x, double *g) {
   for (int a = 0; a < nx; ++a) g[a] = 0.0;
   for (int a = 0; a < np; ++a) g[a] += 2.0 * p->w_pos[a] * (x[a] - p->goal[a]);
   for (int a = 0; a < np; ++a) g[np + a] += 2.0 * p->w_vel * x[np + a];
-  if (p->dyn == ORC_QUAD12)
+  if (p->dyn != ORC_POINTMASS2D)
     for (int a = 0; a < 3; ++a) g[6 + a] += 2.0 * p->w_ang * x[6 + a];
   if (p->obs_kind == ORC_OBS_SMOOTH) {
     for (int i = 0; i < p->n_obs; ++i) {
@@ -307,13 +336,14 @@ static void rollout_step(const orc_problem *p, const orc_model *md, const double
                          const double *u_nom_t, uint32_t iter, int64_t k, int m, int t,
                          step_scratch *s, double *xn, double *mean_out, double *var_out) {
   const int nx = n_state(p->dyn), nu = n_control(p->dyn), no = md->n_out;
-  double eps[4], xi[8], z[32], acc[8];
+  double eps[4], xi[8], z[32], acc[8], u[4];
+  (void)nx;
   orc_normals(p->seed, ORC_TAG_CTRL, p->problem_id, iter, (uint32_t)k, 0u, (uint32_t)t, nu, eps);
   if (p->M > 0)
     orc_normals(p->seed, ORC_TAG_DYN, p->problem_id, iter, (uint32_t)k, (uint32_t)m,
                 (uint32_t)t, no, xi);
-  for (int a = 0; a < nx; ++a) z[a] = x[a];
-  for (int a = 0; a < nu; ++a) z[nx + a] = u_nom_t[a] + p->noise_std[a] * eps[a];
+  for (int a = 0; a < nu; ++a) u[a] = u_nom_t[a] + p->noise_std[a] * eps[a];
+  model_input(p->dyn, x, u, z);
   for (int o = 0; o < no; ++o) {
     double mu, v;
     mixture(md, o, z, s->w, s->y, &mu, &v, s->work);
@@ -321,7 +351,7 @@ static void rollout_step(const orc_problem *p, const orc_model *md, const double
     if (mean_out) mean_out[o] = mu;
     if (var_out) var_out[o] = v;
   }
-  euler_step(p->dyn, p->dt, x, acc, xn);
+  euler_step(p->dyn, p->dt, x, acc, u, xn);
 }
 
 /* cost: [(k1-k0)][T] = cbar_{k,t}; states (nullable): [(k1-k0)][max(M,1)][T+1][n_x]. */
@@ -418,14 +448,13 @@ void orc_rh_shift(const orc_problem *p, const orc_model *md, double *x0, double 
   double *work = malloc(sizeof(double) * 2 * md->d);
   double z[32], acc[8], xi[8], xn[16];
   orc_normals(p->seed, ORC_TAG_PLANT, p->problem_id, *iter, 0u, 0u, 0u, no, xi);
-  for (int a = 0; a < nx; ++a) z[a] = x0[a];
-  for (int a = 0; a < nu; ++a) z[nx + a] = u_nom[a];
+  model_input(p->dyn, x0, u_nom, z);
   for (int o = 0; o < no; ++o) {
     double mu, v;
     mixture(md, o, z, w, y, &mu, &v, work);
     acc[o] = mu + sqrt(v) * xi[o];
   }
-  euler_step(p->dyn, p->dt, x0, acc, xn);
+  euler_step(p->dyn, p->dt, x0, acc, u_nom, xn);
   for (int a = 0; a < nx; ++a) x0[a] = xn[a];
   for (int t = 0; t + 1 < T; ++t)
     for (int a = 0; a < nu; ++a) u_nom[t * nu + a] = u_nom[(t + 1) * nu + a];
@@ -442,6 +471,7 @@ void orc_rh_shift(const orc_problem *p, const orc_model *md, double *x0, double 
 double orc_adjoint(const orc_problem *p, const orc_model *md, const double *x0,
                    const double *u_nom, uint32_t iter, double *g_u, double *g_c, double *g_D,
                    int32_t nthreads) {
+  if (p->dyn == ORC_QUAD_HYBRID) return NAN; /* the adjoint covers the other two families */
   const int nx = n_state(p->dyn), nu = n_control(p->dyn), no = md->n_out, T = p->T;
   const int d = md->d, R = md->R;
   const int Ms = p->M > 0 ? p->M : 1;

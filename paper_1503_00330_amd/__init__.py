@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpi2rh.so")
 
 PI_F32, PI_F64 = 0, 1
-PI_DYN_POINTMASS2D, PI_DYN_QUAD12 = 0, 1
+PI_DYN_POINTMASS2D, PI_DYN_QUAD12, PI_DYN_QUAD_HYBRID = 0, 1, 2
 PI_OBS_INDICATOR, PI_OBS_SMOOTH = 0, 1
 PI_W_COST_TO_GO, PI_W_TRAJECTORY = 0, 1
 PI_VARIANT_AUTO, PI_VARIANT_DIRECT, PI_VARIANT_MFMA = 0, 1, 2
@@ -29,7 +29,7 @@ PI_OP_PREDICT, PI_OP_ROLLOUT, PI_OP_UPDATE, PI_OP_ADJOINT, PI_OP_RH_SHIFT = 0, 1
 PI_MAX_OUT, PI_MAX_U = 8, 4
 STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4: "PI_ERR_DTYPE",
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
-DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6)}
+DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6), PI_DYN_QUAD_HYBRID: (9, 4, 3)}
 EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
             "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
             "pi_batched_plan", "pi_rollout_cost_batched", "pi_philox4x32_10", "pi_noise",

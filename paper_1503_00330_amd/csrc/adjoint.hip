@@ -159,7 +159,7 @@ __device__ Real adj_step(const AdjArgs<Real> &a, const ModelArgs &m, AdjSmem<Rea
       acc[o] = p.M > 0 ? sm.mu[g][o] + sqrt_(sm.var[g][o]) * sm.xi[g][o] : sm.mu[g][o];
 #pragma unroll
     for (int i = 0; i < G::NX; ++i) xs[i] = sm.x[g][i];
-    euler_step<Real>(DYN, p.dt, xs, acc, xn);
+    euler_step<Real>(DYN, p.dt, xs, acc, &sm.z[g][G::NX], xn);  // controls sit after the state in z
 #pragma unroll
     for (int i = 0; i < G::NX; ++i) sm.x[g][i] = xn[i];
     c = p.dt * state_cost<Real>(p, p.obs, xn);

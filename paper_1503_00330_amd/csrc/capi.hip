@@ -37,9 +37,11 @@ pi_status ok() {
     if (_st != PI_OK) return _st;     \
   } while (0)
 
-int dyn_nx(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 4 : 12; }
+int dyn_nx(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 4 : dyn == PI_DYN_QUAD_HYBRID ? 9 : 12; }
 int dyn_nu(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 2 : 4; }
-int dyn_no(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 2 : 6; }
+int dyn_no(int dyn) { return dyn == PI_DYN_POINTMASS2D ? 2 : dyn == PI_DYN_QUAD_HYBRID ? 3 : 6; }
+// LWPR input size: [state ; control], or [euler angles ; thrust] for the hybrid model
+int dyn_d(int dyn) { return dyn == PI_DYN_QUAD_HYBRID ? 4 : dyn_nx(dyn) + dyn_nu(dyn); }
 
 pi_status check_model(const pi_lwpr *m) {
   if (!m) return fail(PI_ERR_NULL, "model is NULL");
@@ -61,7 +63,8 @@ pi_status check_model(const pi_lwpr *m) {
 pi_status check_problem(const pi_problem *p) {
   if (!p) return fail(PI_ERR_NULL, "problem is NULL");
   if (p->dtype != PI_F32 && p->dtype != PI_F64) return fail(PI_ERR_DTYPE, "unknown problem dtype %d", p->dtype);
-  if (p->dyn != PI_DYN_POINTMASS2D && p->dyn != PI_DYN_QUAD12) return fail(PI_ERR_VALUE, "unknown dyn %d", p->dyn);
+  if (p->dyn != PI_DYN_POINTMASS2D && p->dyn != PI_DYN_QUAD12 && p->dyn != PI_DYN_QUAD_HYBRID)
+    return fail(PI_ERR_VALUE, "unknown dyn %d", p->dyn);
   if (p->K < 1) return fail(PI_ERR_SHAPE, "K=%d must be >= 1", p->K);
   if (p->T < 1) return fail(PI_ERR_SHAPE, "T=%d must be >= 1", p->T);
   if (p->M < 0 || p->M > (1 << 27)) return fail(PI_ERR_SHAPE, "M=%d outside [0, 2^27]", p->M);
@@ -93,8 +96,8 @@ pi_status check_pair(const pi_problem *p, const pi_lwpr *m) {
   PI_TRY(check_problem(p));
   PI_TRY(check_model(m));
   if (p->dtype != m->dtype) return fail(PI_ERR_DTYPE, "problem dtype %d != model dtype %d", p->dtype, m->dtype);
-  if (m->d != dyn_nx(p->dyn) + dyn_nu(p->dyn))
-    return fail(PI_ERR_SHAPE, "model input d=%d != n_x+n_u=%d", m->d, dyn_nx(p->dyn) + dyn_nu(p->dyn));
+  if (m->d != dyn_d(p->dyn))
+    return fail(PI_ERR_SHAPE, "model input d=%d != %d for this dynamics family", m->d, dyn_d(p->dyn));
   if (m->n_out != dyn_no(p->dyn))
     return fail(PI_ERR_SHAPE, "model n_out=%d != %d accelerations", m->n_out, dyn_no(p->dyn));
   return PI_OK;
@@ -157,7 +160,7 @@ ProbDev<Real> prob_dev(const pi_problem *p) {
   d.n_x = dyn_nx(p->dyn);
   d.n_u = dyn_nu(p->dyn);
   d.n_out = dyn_no(p->dyn);
-  d.d = d.n_x + d.n_u;
+  d.d = dyn_d(p->dyn);
   d.dt = (Real)p->dt;
   for (int a = 0; a < kMaxU; ++a) d.noise_std[a] = (Real)p->noise_std[a];
   for (int a = 0; a < 3; ++a) {
@@ -177,7 +180,7 @@ ProbDev<Real> prob_dev(const pi_problem *p) {
   return d;
 }
 
-bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6); }
+bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6 || d == 4); }
 
 // Rollout variant, samples per workgroup and whether tiles may be split over
 // a pair of workgroups (pair_ok; the launch decides with the device's
@@ -220,9 +223,9 @@ bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return false;
   static std::mutex mu;
-  static int per_cu[kMaxDevices][3];  // resident pair workgroups per compute unit, +1 (0 = unknown)
+  static int per_cu[kMaxDevices][4];  // resident pair workgroups per compute unit, +1 (0 = unknown)
   if (dev < 0 || dev >= kMaxDevices) return false;
-  const int di = p->dyn != PI_DYN_QUAD12 ? 0 : (pl.waves == 8 ? 2 : 1);
+  const int di = p->dyn == PI_DYN_QUAD12 ? (pl.waves == 8 ? 2 : 1) : (p->dyn == PI_DYN_QUAD_HYBRID ? 3 : 0);
   int cap;
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -527,6 +530,7 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
                              const uint32_t *iter, int32_t ckpt_every, void *J, void *g_u_nom, void *g_centre,
                              void *g_metric, void *ws, size_t ws_bytes, void *stream) {
   PI_TRY(check_pair(p, m));
+  if (p->dyn == PI_DYN_QUAD_HYBRID) return fail(PI_ERR_UNSUPPORTED, "the adjoint covers POINTMASS2D and QUAD12");
   if (!x0 || !u_nom || !iter || !J || !g_u_nom || !g_centre || !g_metric)
     return fail(PI_ERR_NULL, "x0, u_nom, iter, J and the gradient outputs must be non-NULL");
   if (ckpt_every < 0) return fail(PI_ERR_VALUE, "ckpt_every=%d must be >= 0", ckpt_every);

@@ -15,7 +15,10 @@ constexpr int kMaxX = 12;
 constexpr int kMaxObs = 64;
 constexpr int kMaxR = 16;
 
-enum { kDynPointMass2D = 0, kDynQuad12 = 1 };
+enum { kDynPointMass2D = 0, kDynQuad12 = 1, kDynQuadHybrid = 2 };
+// First-order response of the attitude rates to their commands (Sec. 4.1):
+// d(angles)/dt = kRateGain (commanded - actual).
+constexpr double kRateGain = 25.0;
 enum { kObsIndicator = 0, kObsSmooth = 1 };
 enum { kTagCtrl = 0u, kTagDyn = 1u, kTagPlant = 2u };
 
@@ -115,17 +118,47 @@ __device__ __forceinline__ void normals_n(int n, uint32_t key0, uint32_t key1, u
 }
 
 // ---------------------------------------------------------------- dynamics
+// The LWPR input of a state and an applied control: z = [x ; u] for the point
+// mass and the 12-state quadrotor; for the hybrid quadrotor (Sec. 4.1: the
+// learned models take the three euler angles and the total thrust) z =
+// [phi, theta, psi, F] = [x_6, x_7, x_8, u_3].
+template <int DYN, typename Real>
+__device__ __forceinline__ void lwpr_input(const Real *x, const Real *u, Real *z) {
+  if constexpr (DYN == kDynQuadHybrid) {
+    z[0] = x[6];
+    z[1] = x[7];
+    z[2] = x[8];
+    z[3] = u[3];
+  } else {
+    constexpr int NX = DYN == kDynPointMass2D ? 4 : 12, NU = DYN == kDynPointMass2D ? 2 : 4;
+#pragma unroll
+    for (int a = 0; a < NX; ++a) z[a] = x[a];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) z[NX + a] = u[a];
+  }
+}
+
 // Explicit Euler: positions integrate velocities, velocities the linear
-// accelerations; for the quadrotor euler angles integrate the body rates and
-// rates integrate the angular accelerations.  Right-hand sides use x_t.
+// accelerations; for the 12-state quadrotor euler angles integrate the body
+// rates and rates integrate the angular accelerations; for the hybrid
+// quadrotor the angles follow their commanded rates u_0..2 through the
+// first-order response (Sec. 4.1) and the learned models give the linear
+// accelerations.  Right-hand sides use x_t and the applied control u.
 template <typename Real>
-__device__ __forceinline__ void euler_step(int dyn, Real dt, const Real *x, const Real *acc,
+__device__ __forceinline__ void euler_step(int dyn, Real dt, const Real *x, const Real *acc, const Real *u,
                                            Real *xn) {
   if (dyn == kDynPointMass2D) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       xn[a] = x[a] + dt * x[2 + a];
       xn[2 + a] = x[2 + a] + dt * acc[a];
+    }
+  } else if (dyn == kDynQuadHybrid) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xn[a] = x[a] + dt * x[3 + a];
+      xn[3 + a] = x[3 + a] + dt * acc[a];
+      xn[6 + a] = x[6 + a] + dt * ((Real)kRateGain * (u[a] - x[6 + a]));
     }
   } else {
 #pragma unroll
@@ -149,7 +182,7 @@ __device__ __forceinline__ Real state_cost(const ProbDev<Real> &p, const Real *o
     c += p.w_pos[a] * e * e;
   }
   for (int a = 0; a < np; ++a) c += p.w_vel * x[np + a] * x[np + a];
-  if (p.dyn == kDynQuad12)
+  if (p.dyn != kDynPointMass2D)
     for (int a = 0; a < 3; ++a) c += p.w_ang * x[6 + a] * x[6 + a];
   if (p.obs_kind == kObsIndicator) {
     bool inside = false;
@@ -175,7 +208,7 @@ __device__ __forceinline__ void state_cost_grad(const ProbDev<Real> &p, const Re
   for (int a = 0; a < p.n_x; ++a) g[a] = 0;
   for (int a = 0; a < np; ++a) g[a] = 2 * p.w_pos[a] * (x[a] - p.goal[a]);
   for (int a = 0; a < np; ++a) g[np + a] = 2 * p.w_vel * x[np + a];
-  if (p.dyn == kDynQuad12)
+  if (p.dyn != kDynPointMass2D)
     for (int a = 0; a < 3; ++a) g[6 + a] = 2 * p.w_ang * x[6 + a];
   if (p.obs_kind == kObsSmooth) {
     for (int i = 0; i < p.n_obs; ++i) {

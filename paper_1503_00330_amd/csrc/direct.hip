@@ -149,13 +149,12 @@ __global__ void __launch_bounds__(128) rollout_direct_kernel(RolloutArgs<Real> r
   for (int a = 0; a < NX; ++a) x[a] = ra.x0[a];
   __syncthreads();
   for (int t = 0; t < p.T; ++t) {
-    Real eps[4];
+    Real eps[4], u[NU];
     normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)t, eps);
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u[a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps[a];
     Real z[D];
-#pragma unroll
-    for (int a = 0; a < NX; ++a) z[a] = x[a];
-#pragma unroll
-    for (int a = 0; a < NU; ++a) z[NX + a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps[a];
+    lwpr_input<DYN>(x, u, z);
     direct_mixture<Real, D>(m, rec, z, tile, out);
     Real acc[NO];
     if (p.M > 0) {
@@ -168,7 +167,7 @@ __global__ void __launch_bounds__(128) rollout_direct_kernel(RolloutArgs<Real> r
       for (int o = 0; o < NO; ++o) acc[o] = out[o];
     }
     Real xn[NX];
-    euler_step<Real>(DYN, p.dt, x, acc, xn);
+    euler_step<Real>(DYN, p.dt, x, acc, u, xn);
 #pragma unroll
     for (int a = 0; a < NX; ++a) x[a] = xn[a];
     const Real c = p.dt * state_cost<Real>(p, obs, x);
@@ -186,6 +185,12 @@ static hipError_t rollout_direct_t(const RolloutArgs<Real> &ra, const ModelArgs 
     const size_t sh = (size_t)(tile_models<Real, D>() * rec_stride<Real, D>() + 128 * 2 * kMaxOut +
                                3 * kMaxObs) * sizeof(Real);
     hipLaunchKernelGGL((rollout_direct_kernel<Real, kDynPointMass2D>), dim3(nb), dim3(128), sh, s,
+                       ra, m, (const Real *)rec);
+  } else if (ra.p.dyn == kDynQuadHybrid) {
+    constexpr int D = 4;
+    const size_t sh = (size_t)(tile_models<Real, D>() * rec_stride<Real, D>() + 128 * 2 * kMaxOut +
+                               3 * kMaxObs) * sizeof(Real);
+    hipLaunchKernelGGL((rollout_direct_kernel<Real, kDynQuadHybrid>), dim3(nb), dim3(128), sh, s,
                        ra, m, (const Real *)rec);
   } else {
     constexpr int D = 16;
@@ -413,11 +418,12 @@ __global__ void __launch_bounds__(kShiftThreads) plant_partial_kernel(ModelArgs 
   constexpr int RS = rec_stride<Real, D>();
   __shared__ MixStat<Real> red[kShiftThreads];
   const int o = blockIdx.y, c = blockIdx.x, C = gridDim.x;
-  Real z[D];
+  Real z[D], x[NX], u[NU];
 #pragma unroll
-  for (int a = 0; a < NX; ++a) z[a] = x0[a];
+  for (int a = 0; a < NX; ++a) x[a] = x0[a];
 #pragma unroll
-  for (int a = 0; a < NU; ++a) z[NX + a] = u_nom[a];
+  for (int a = 0; a < NU; ++a) u[a] = u_nom[a];
+  lwpr_input<DYN>(x, u, z);
   MixStat<Real> st = mix_empty<Real>();
   const int j = m.L_off[o] + c * kShiftThreads + threadIdx.x;
   if (j < m.L_off[o + 1]) {
@@ -453,8 +459,10 @@ __global__ void __launch_bounds__(256) plant_apply_kernel(ProbDev<Real> p, int C
       mix_finish(st, &mu, &v);
       acc[o] = mu + sqrt_(v) * xi[o];
     }
+    Real u0[NU];
     for (int a = 0; a < NX; ++a) xs[a] = x0[a];
-    euler_step<Real>(DYN, p.dt, xs, acc, xn);
+    for (int a = 0; a < NU; ++a) u0[a] = u_nom[a];
+    euler_step<Real>(DYN, p.dt, xs, acc, u0, xn);
     for (int a = 0; a < NX; ++a) xnew[a] = xn[a];
   }
   __syncthreads();
@@ -484,6 +492,11 @@ static hipError_t rh_shift_t(const ProbDev<Real> &p, const ModelArgs &m, const v
     hipLaunchKernelGGL((plant_partial_kernel<Real, kDynPointMass2D>), grid, dim3(kShiftThreads), 0, s, m,
                        (const Real *)rec, (const Real *)x0, (const Real *)u_nom, (MixStat<Real> *)part);
     hipLaunchKernelGGL((plant_apply_kernel<Real, kDynPointMass2D>), dim3(1), dim3(256), 0, s, p, C,
+                       (const MixStat<Real> *)part, (Real *)x0, (Real *)u_nom, iter);
+  } else if (p.dyn == kDynQuadHybrid) {
+    hipLaunchKernelGGL((plant_partial_kernel<Real, kDynQuadHybrid>), grid, dim3(kShiftThreads), 0, s, m,
+                       (const Real *)rec, (const Real *)x0, (const Real *)u_nom, (MixStat<Real> *)part);
+    hipLaunchKernelGGL((plant_apply_kernel<Real, kDynQuadHybrid>), dim3(1), dim3(256), 0, s, p, C,
                        (const MixStat<Real> *)part, (Real *)x0, (Real *)u_nom, iter);
   } else {
     hipLaunchKernelGGL((plant_partial_kernel<Real, kDynQuad12>), grid, dim3(kShiftThreads), 0, s, m,

@@ -79,6 +79,10 @@ template <>
 struct DynDims<kDynQuad12> {
   static constexpr int NX = 12, NU = 4, NO = 6, D = 16;
 };
+template <>
+struct DynDims<kDynQuadHybrid> {
+  static constexpr int NX = 9, NU = 4, NO = 3, D = 4;
+};
 
 
 }  // namespace pi2rh

@@ -617,6 +617,7 @@ hipError_t launch_predict_mfma(const ModelArgs &m, const MfmaLayout &l, const vo
   const MfmaModel md = mfma_view(l, base);
   if (m.d == 16) return predict_mfma_d<16>(md, (const float *)Z, N, (float *)mean, (float *)var, s);
   if (m.d == 6) return predict_mfma_d<6>(md, (const float *)Z, N, (float *)mean, (float *)var, s);
+  if (m.d == 4) return predict_mfma_d<4>(md, (const float *)Z, N, (float *)mean, (float *)var, s);
   return hipErrorInvalidValue;
 }
 
@@ -630,6 +631,10 @@ struct Dims<kDynPointMass2D> {
 template <>
 struct Dims<kDynQuad12> {
   static constexpr int NX = 12, NU = 4, NO = 6, D = 16;
+};
+template <>
+struct Dims<kDynQuadHybrid> {
+  static constexpr int NX = 9, NU = 4, NO = 3, D = 4;
 };
 
 constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
@@ -727,12 +732,20 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
       __syncthreads();
     }
+    // the applied controls u_nom + eps of the row at step t
+    auto applied = [&](float (&u)[NU]) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) u[a] = u_nom[t * NU + a] + p.noise_std[a] * rs.eps_s[tc][row][a];
+    };
     if (row < ROWS) {
       if (active) {
+        float u[NU], x[NX], z[D];
+        applied(u);
 #pragma unroll
-        for (int a = 0; a < NX; ++a) sm.z[row][a] = rs.xs[row][a];
+        for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
+        lwpr_input<DYN>(x, u, z);
 #pragma unroll
-        for (int a = 0; a < NU; ++a) sm.z[row][NX + a] = u_nom[t * NU + a] + p.noise_std[a] * rs.eps_s[tc][row][a];
+        for (int a = 0; a < D; ++a) sm.z[row][a] = z[a];
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) sm.z[row][a] = 0.0f;
@@ -741,12 +754,13 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
     __syncthreads();
     mixture_step(md, sm, t == 0, T0, T1, pc, seq, SampleArgs{p.M > 0 ? &rs.xi_s[tc][0][0] : nullptr});
     if (active) {
-      float acc[NO], xn[NX], x[NX];
+      float acc[NO], xn[NX], x[NX], u[NU];
 #pragma unroll
       for (int o = 0; o < NO; ++o) acc[o] = sm.acc[row][o];
 #pragma unroll
       for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
-      euler_step<float>(DYN, p.dt, x, acc, xn);
+      applied(u);
+      euler_step<float>(DYN, p.dt, x, acc, u, xn);
 #pragma unroll
       for (int a = 0; a < NX; ++a) {
         rs.xs[row][a] = xn[a];
@@ -832,6 +846,10 @@ hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
     if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4>(ra, md, spw, s);
     return rollout_mfma_t<kDynQuad12, 2, 4>(ra, md, spw, s);
   }
+  if (ra.p.dyn == kDynQuadHybrid) {
+    if (spw <= 16) return rollout_mfma_t<kDynQuadHybrid, 1, 4>(ra, md, spw, s);
+    return rollout_mfma_t<kDynQuadHybrid, 2, 4>(ra, md, spw, s);
+  }
   if (spw <= 16) return rollout_mfma_t<kDynPointMass2D, 1, 4>(ra, md, spw, s);
   return rollout_mfma_t<kDynPointMass2D, 2, 4>(ra, md, spw, s);
 }
@@ -847,6 +865,8 @@ int pair_blocks_per_cu(int dyn, int waves) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8>, 512, 0);
   else if (dyn == kDynQuad12)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4>, 256, 0);
+  else if (dyn == kDynQuadHybrid)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuadHybrid, 4>, 256, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4>, 256, 0);
   return e == hipSuccess ? nb : 0;
@@ -869,6 +889,9 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
     else
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4>), grid, dim3(256), 0, s, ra, md, spw, (int)n_groups,
                          xbuf);
+  } else if (ra.p.dyn == kDynQuadHybrid) {
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4>), grid, dim3(256), 0, s, ra, md, spw,
+                       (int)n_groups, xbuf);
   } else {
     hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4>), grid, dim3(256), 0, s, ra, md, spw,
                        (int)n_groups, xbuf);

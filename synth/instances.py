@@ -13,8 +13,10 @@ bit-identical parameter values.  Distributions follow the workload recipe:
   rates zero; obstacle centres ~ U[-1, 1]^2 with radius 0.2, redrawn when the
   start or the goal lies inside.
 
-LWPR input is z = [state ; control] (Sec. 4.1 feeds the model attitude and
-thrust, i.e. state and control features).
+LWPR input is z = [state ; control] for the point mass and the 12-state
+quadrotor; the hybrid quadrotor follows Sec. 4.1 (three models of the euler
+angles and the thrust give the cartesian accelerations, the angles follow
+their commanded rates).
 """
 from __future__ import annotations
 
@@ -26,8 +28,11 @@ import numpy as np
 
 DYN_POINTMASS2D = 0   # state [px, py, vx, vy], control [ax, ay]
 DYN_QUAD12 = 1        # state [p(3), v(3), euler(3), rates(3)], control [thrust, 3 torques]
+DYN_QUAD_HYBRID = 2   # state [p(3), v(3), euler(3)], control [commanded rates(3), thrust]
 # dyn -> (n_x, n_u, n_out)
-DYN_DIMS = {DYN_POINTMASS2D: (4, 2, 2), DYN_QUAD12: (12, 4, 6)}
+DYN_DIMS = {DYN_POINTMASS2D: (4, 2, 2), DYN_QUAD12: (12, 4, 6), DYN_QUAD_HYBRID: (9, 4, 3)}
+# dyn -> LWPR input size d
+DYN_D = {DYN_POINTMASS2D: 6, DYN_QUAD12: 16, DYN_QUAD_HYBRID: 4}
 
 OBS_INDICATOR = 0
 OBS_SMOOTH = 1
@@ -253,17 +258,15 @@ def batched_config(dtype=np.float32, B: int = 64, K_range=(512, 16384), L_range=
     return out
 
 
-def paper_shape(M: int = 1, K: int = 1000, T: int = 50, dtype=np.float32, seed: int = 7):
-    """Workload at the paper's own GPU timing shapes (Sec. 4): three outputs with
-    15/15/24 local models, a 1000 x 50-step rollout set and M sub-rollouts.
-
-    The paper's LWPR inputs are 4 attitude/thrust features; here the synthetic
-    point-mass-like quadrotor keeps the full 16-dim input of the quadrotor family,
-    so this shape is the paper's (K, T, M, L) only.
-    """
+def paper_shape(M: int = 1, K: int = 1000, T: int = 50, dtype=np.float32, seed: int = 7,
+                R: int = 2):
+    """The paper's own model and GPU timing shapes (Sec. 4, 4.1): the hybrid
+    quadrotor whose three LWPR models (15, 15 and 24 local models) map the euler
+    angles and the thrust (d = 4) to the cartesian accelerations, 1000 rollouts
+    of 50 steps and M sub-rollouts (M = 0: mean prediction only)."""
     rng = np.random.Generator(np.random.PCG64(2000 + seed))
-    model = make_lwpr(rng, 16, [15, 15, 24, 15, 15, 24], 4)
-    prob = make_problem(rng, DYN_QUAD12, K, T, M=M, n_obs=3, obs_kind=OBS_SMOOTH,
+    model = make_lwpr(rng, DYN_D[DYN_QUAD_HYBRID], [15, 15, 24], R)
+    prob = make_problem(rng, DYN_QUAD_HYBRID, K, T, M=M, n_obs=3, obs_kind=OBS_SMOOTH,
                         seed=0xC0FFEE10 + seed)
     return prob.astype(dtype), model.astype(dtype)
 
@@ -273,7 +276,7 @@ def tiny_problem(seed: int = 0, dyn: int = DYN_POINTMASS2D, L=3, R: int = 2, K: 
     """Small instance for pins and quick parity checks."""
     rng = np.random.Generator(np.random.PCG64(5000 + seed))
     n_x, n_u, n_out = DYN_DIMS[dyn]
-    model = make_lwpr(rng, n_x + n_u, L, R, n_out=n_out)
+    model = make_lwpr(rng, DYN_D[dyn], L, R, n_out=n_out)
     prob = make_problem(rng, dyn, K, T, M=M, seed=0xC0FFEE00 + 97 * seed, **kw)
     prob.u_nom = rng.normal(0.0, 0.3, (T, n_u))
     return prob.astype(dtype), model.astype(dtype)

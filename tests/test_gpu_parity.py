@@ -88,6 +88,7 @@ def _models():
         "ragged16": synth.make_lwpr(rng, 16, [1, 17, 33, 5, 16, 40], 4),
         "pm6": synth.make_lwpr(rng, 6, [16, 16], 2),
         "d3": synth.make_lwpr(rng, 3, [7, 2], 2, loadings_equal_u=False),
+        "paper4": synth.paper_shape()[1].astype(F64),     # d = 4, 15/15/24 models
     }
 
 
@@ -96,7 +97,8 @@ PRED_CASES = [("cfg1", pi.PI_VARIANT_MFMA, F32), ("cfg1", pi.PI_VARIANT_DIRECT, 
               ("cfg1", pi.PI_VARIANT_DIRECT, F64), ("ragged16", pi.PI_VARIANT_MFMA, F32),
               ("ragged16", pi.PI_VARIANT_DIRECT, F64), ("pm6", pi.PI_VARIANT_MFMA, F32),
               ("pm6", pi.PI_VARIANT_DIRECT, F64), ("d3", pi.PI_VARIANT_DIRECT, F32),
-              ("d3", pi.PI_VARIANT_DIRECT, F64)]
+              ("d3", pi.PI_VARIANT_DIRECT, F64), ("paper4", pi.PI_VARIANT_MFMA, F32),
+              ("paper4", pi.PI_VARIANT_DIRECT, F32), ("paper4", pi.PI_VARIANT_DIRECT, F64)]
 
 
 @pytest.mark.parametrize("name,variant,dtype", PRED_CASES)
@@ -199,6 +201,45 @@ def test_rollout_pointmass(dtype, split):
     cost = pi.rollout_cost(pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     cost_check(cost, ref, prob, 1e-10 if dtype == F64 else 1e-4)
+
+
+# (variant, samples per workgroup, split) for the paper's hybrid quadrotor
+HYBRID_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0), (pi.PI_VARIANT_MFMA, 16, 1), (pi.PI_VARIANT_MFMA, 32, 0),
+                 (pi.PI_VARIANT_DIRECT, 0, 0)]
+
+
+@pytest.mark.parametrize("shape", HYBRID_SHAPES)
+@pytest.mark.parametrize("M", [0, 1, 4])
+def test_rollout_hybrid_quadrotor(shape, M):
+    # the paper's model (Sec. 4.1): angles follow commanded rates, three
+    # LWPR models of (angles, thrust) give the accelerations
+    variant, spw, split = shape
+    prob, model = synth.paper_shape(M=M, K=150, T=21)
+    prob.u_nom = np.random.default_rng(M).normal(0.0, 0.3, prob.u_nom.shape).astype(F32)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    cost_check(cost, ref, prob, 1e-4)
+    assert nrel(cost, ref) <= 1e-4
+
+
+def test_hybrid_fp64_iteration_and_shift():
+    prob, model = synth.paper_shape(M=2, K=64, T=15, dtype=F64)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    cost = pi.rollout_cost(dp, dm).cpu().numpy()
+    assert np.max(np.abs(cost - oracle.rollout_cost(prob, model))) <= 1e-10 * np.abs(cost).max()
+    pi.iteration(dp, dm)
+    pi.rh_shift(dp, dm)
+    x, u, it = oracle.rh_loop(prob, model, steps=1, iterations=1)
+    assert int(dp.iter.item()) == it
+    assert np.max(np.abs(dp.u_nom.cpu().numpy() - u)) <= 1e-10
+    assert np.max(np.abs(dp.x0.cpu().numpy() - x)) <= 1e-10
+
+
+def test_hybrid_adjoint_is_refused():
+    prob, model = synth.paper_shape(K=4, T=3)
+    with pytest.raises(pi.PiError):
+        pi.rollout_adjoint(pi.DeviceProblem(prob), pi.DeviceModel(model))
 
 
 def test_rollout_edge_sizes():

@@ -16,7 +16,7 @@ from scipy import stats
 
 import oracle
 import synth
-from synth import DYN_POINTMASS2D, DYN_QUAD12, OBS_SMOOTH, W_TRAJECTORY
+from synth import DYN_POINTMASS2D, DYN_QUAD12, DYN_QUAD_HYBRID, OBS_SMOOTH, W_TRAJECTORY
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -275,6 +275,48 @@ def test_single_model_zero_noise_is_hand_stepped_linear_dynamics(dyn):
         assert np.allclose(X[k, 0], xs, rtol=1e-12, atol=1e-13)
         expect = [prob.dt * _goal_cost(prob, xs[t + 1]) for t in range(prob.T)]
         assert np.allclose(cost[k], expect, rtol=1e-12, atol=1e-15)
+
+
+def test_hybrid_angles_follow_commanded_rates_closed_form():
+    # Sec. 4.1: the angles obey dr/dt = 25 (r_commanded - r), independent of the
+    # learned models; explicit Euler with a constant command c gives the
+    # geometric approach r_n = c + (r_0 - c)(1 - 25 dt)^n
+    prob, model = synth.tiny_problem(21, dyn=DYN_QUAD_HYBRID, L=[2, 3, 1], R=2, K=2, T=9, M=0, n_obs=0)
+    prob.noise_std[:] = 0.0
+    cmd = np.array([0.3, -0.2, 0.05])
+    prob.u_nom[:, :3] = cmd
+    prob.x0[6:9] = [-0.1, 0.4, 0.0]
+    _, X = oracle.rollout_cost(prob, model, states=True)
+    n = np.arange(prob.T + 1)[:, None]
+    expect = cmd + (prob.x0[6:9] - cmd) * (1.0 - 25.0 * prob.dt) ** n
+    assert np.allclose(X[0, 0, :, 6:9], expect, rtol=1e-12, atol=1e-14)
+
+
+def test_hybrid_single_model_is_hand_stepped():
+    # one local model per output: the accelerations are affine in the model
+    # input (phi, theta, psi, F) = (x_6, x_7, x_8, u_3); positions and
+    # velocities integrate them, the angles follow the commanded rates
+    prob, model = synth.tiny_problem(22, dyn=DYN_QUAD_HYBRID, L=1, R=3, K=2, T=8, M=0, n_obs=0)
+    prob.noise_std[:] = 0.0
+    prob.x0[6:9] = [0.2, -0.3, 0.1]
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    bs, offs = _affine_system(prob, model)
+    x = np.asarray(prob.x0, np.float64).copy()
+    xs, cs = [x.copy()], []
+    for t in range(prob.T):
+        u = prob.u_nom[t]
+        acc = bs @ np.array([x[6], x[7], x[8], u[3]]) + offs
+        xn = x.copy()
+        xn[0:3] = x[0:3] + prob.dt * x[3:6]
+        xn[3:6] = x[3:6] + prob.dt * acc
+        xn[6:9] = x[6:9] + prob.dt * 25.0 * (u[0:3] - x[6:9])
+        x = xn
+        xs.append(x.copy())
+        c = sum(prob.w_pos[a] * (x[a] - prob.goal[a]) ** 2 for a in range(3))
+        c += prob.w_vel * np.sum(x[3:6] ** 2) + prob.w_ang * np.sum(x[6:9] ** 2)
+        cs.append(prob.dt * c)
+    assert np.allclose(X[0, 0], np.array(xs), rtol=1e-12, atol=1e-13)
+    assert np.allclose(cost[0], cs, rtol=1e-12, atol=1e-15)
 
 
 def test_single_model_with_noise_follows_its_perturbations():
