@@ -20,10 +20,13 @@
 // rounding (FP32 cancellation when the models' predictions differ widely) from
 // turning the variance negative.
 // Partial sums merge across lanes (DPP row rotations) and waves (LDS) as
-// plain sums in a fixed order.  If the largest shifted activation leaves
-// [-60, 64] (too far from the anchor for 2^a' in FP32) the step is evaluated
-// again with the anchor moved to the observed maximum; the first step always
-// takes this second pass so its reference mean is the first pass's mean.
+// plain sums in a fixed order.  The sums are exact up to rounding whatever
+// the anchor, as long as none of them overflowed and the largest term kept
+// full precision; so the step is evaluated again, with the anchor moved to the
+// observed maximum, only if a sum is not finite or the largest shifted
+// activation fell below -100 (its term near the denormal range).  The first
+// step always takes this second pass so its reference mean is the first
+// pass's mean.
 // (PI^2-RH with LWPR dynamics, arXiv:1503.00330.)
 #include "internal.hpp"
 
@@ -48,7 +51,7 @@ struct Geo {
 // alpha = -log2(e) / 2
 constexpr double kAlpha = -0.72134752044448170368;
 constexpr float kPadAct = -1.0e30f;
-constexpr float kAnchorHi = 64.0f, kAnchorLo = -60.0f;
+constexpr float kAnchorLo = -100.0f;
 
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
@@ -203,6 +206,7 @@ struct MixSmem {
   Acc part[NW][kMaxOut][ROWS];           // per-wave partial sums
   float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
+  float mprev[ROWS][kMaxOut];            // previous step's largest activation
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
   float acc[ROWS][kMaxOut];              // sampled accelerations (rollouts)
   unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
@@ -386,7 +390,7 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       for (int r = 0; r < 4; ++r) {
         const float a = qa[mt][r] + qb[mt][r], dd = ya[mt][r];
         // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
-        // largest term of at least 2^-60) need none of exp2f's denormal scaling
+        // largest term of at least 2^-100) need none of exp2f's denormal scaling
         const float e = __builtin_amdgcn_exp2f(a);
         const float te = e * dd;
         st[mt][r].Z += e;
@@ -422,8 +426,8 @@ struct SampleArgs {
 
 // Eq. (1) moments of one (row, output) from its complete sums, the sampled
 // acceleration, the anchors of the next evaluation (observed maximum and
-// mean), and the redo flag of evaluation `ev` when the maximum left the
-// anchor window.
+// mean), and the redo flag of evaluation `ev` when the sums are not usable
+// (one overflowed, or the largest term came near the denormal range).
 template <int D, int MT, int NW>
 __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int o, const Acc &s, uint32_t ev,
                                             const SampleArgs &sa) {
@@ -433,7 +437,8 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int
   sm.mean[row][o] = mu;
   sm.var[row][o] = var;
   sm.acc[row][o] = sa.xi ? mu + sqrtf(var) * sa.xi[row * 8 + o] : mu;
-  if (!(s.mx <= kAnchorHi && s.mx >= kAnchorLo)) sm.redo[ev & 1] = 1;
+  const bool valid = isfinite(s.Z) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.S3) && s.mx >= kAnchorLo;
+  if (!valid) sm.redo[ev & 1] = 1;
   sm.mref[row][o] += s.mx;
   if (isfinite(mu)) sm.yref[row][o] = mu;
 }
@@ -563,7 +568,21 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
     const bool again = pass == 0 && (force_second || sm.redo[ev & 1] != 0);
     // the next evaluation's flag: last read before this evaluation's barriers
     if (threadIdx.x == 0) sm.redo[(ev + 1) & 1] = 0;
-    if (!again) break;
+    if (!again) {
+      // Anchor of the next step: the largest activation moves smoothly along a
+      // trajectory (it drifts steadily once the state leaves the models'
+      // support), so extrapolate it linearly from the last two steps; the
+      // lanes that merged each (row, output) own its entries.
+      constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
+      for (int i = threadIdx.x; i < ROWS * md.n_out; i += NW * 64) {
+        const int row = i % ROWS, o = i / ROWS;
+        const float M = sm.mref[row][o];
+        const float d = force_second ? 0.f : M - sm.mprev[row][o];
+        sm.mprev[row][o] = M;
+        if (isfinite(d)) sm.mref[row][o] = M + d;
+      }
+      break;
+    }
   }
 }
 
@@ -572,6 +591,7 @@ __device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW> &sm) {
   for (int i = threadIdx.x; i < MixSmem<D, MT, NW>::ROWS * kMaxOut; i += NW * 64) {
     (&sm.mref[0][0])[i] = 0.0f;
     (&sm.yref[0][0])[i] = 0.0f;
+    (&sm.mprev[0][0])[i] = 0.0f;
   }
 }
 
