@@ -254,26 +254,62 @@ size_t update_ws_bytes(int K, int T) {
 // rollouts and splits the horizon into 4 segments, one wave each: every lane
 // sums its (rollout, segment), the segment totals meet in LDS, and each lane
 // walks its segment backwards from the total of the later segments; the S
-// stores of a wave cover 64 consecutive rollouts.
-constexpr int kSufK = 64, kSufSeg = 4;
-template <typename Real>
+// stores of a wave cover 64 consecutive rollouts.  Two ways to read the costs:
+// each lane straight along its own row (every load of a wave touches 64 rows,
+// but all of a lane's loads are in flight at once: best when the grid is
+// small), or through a per-wave LDS tile in chunks of 16 steps (each load
+// covers 16 consecutive steps of 4 rollouts: best when bandwidth matters).
+constexpr int kSufK = 64, kSufSeg = 4, kSufChunk = 16;
+template <typename Real, bool kStaged>
 __global__ void __launch_bounds__(kSufK * kSufSeg) suffix_kernel(const Real *__restrict__ cost, int K, int T,
                                                                  double *__restrict__ S) {
+  __shared__ double tile[kStaged ? kSufSeg : 1][kSufK][kSufChunk + 1];
   __shared__ double tot[kSufSeg][kSufK];
-  const int kl = threadIdx.x % kSufK, seg = threadIdx.x / kSufK;
-  const int k = blockIdx.x * kSufK + kl;
+  const int lane = threadIdx.x % kSufK, seg = threadIdx.x / kSufK;
+  const int k0 = blockIdx.x * kSufK, k = k0 + lane;
   const int lo = (int)((int64_t)seg * T / kSufSeg), hi = (int)((int64_t)(seg + 1) * T / kSufSeg);
   const Real *row = cost + (int64_t)min(k, K - 1) * T;
+  double (*tl)[kSufChunk + 1] = tile[kStaged ? seg : 0];
+  // chunk [c0, c0 + w) of the segment into this wave's tile (rows past K read row K-1)
+  auto load = [&](int c0, int w) {
+    for (int e = lane; e < kSufK * kSufChunk; e += kSufK) {
+      const int r = e / kSufChunk, c = e % kSufChunk;
+      if (c < w) tl[r][c] = (double)cost[(int64_t)min(k0 + r, K - 1) * T + c0 + c];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  };
   double sum = 0.0;
-  for (int t = lo; t < hi; ++t) sum += (double)row[t];
-  tot[seg][kl] = sum;
+  if constexpr (kStaged) {
+    for (int c0 = lo; c0 < hi; c0 += kSufChunk) {
+      const int w = min(kSufChunk, hi - c0);
+      load(c0, w);
+      for (int c = 0; c < w; ++c) sum += tl[lane][c];
+      __builtin_amdgcn_wave_barrier();
+    }
+  } else {
+    for (int t = lo; t < hi; ++t) sum += (double)row[t];
+  }
+  tot[seg][lane] = sum;
   __syncthreads();
   double acc = 0.0;
-  for (int j = kSufSeg - 1; j > seg; --j) acc += tot[j][kl];
-  if (k >= K) return;
-  for (int t = hi - 1; t >= lo; --t) {
-    acc += (double)row[t];
-    S[(int64_t)t * K + k] = acc;
+  for (int j = kSufSeg - 1; j > seg; --j) acc += tot[j][lane];
+  if constexpr (kStaged) {
+    for (int c1 = hi; c1 > lo; c1 -= kSufChunk) {
+      const int c0 = max(lo, c1 - kSufChunk), w = c1 - c0;
+      load(c0, w);
+      for (int c = w - 1; c >= 0; --c) {
+        acc += tl[lane][c];
+        if (k < K) S[(int64_t)(c0 + c) * K + k] = acc;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  } else {
+    if (k >= K) return;
+    for (int t = hi - 1; t >= lo; --t) {
+      acc += (double)row[t];
+      S[(int64_t)t * K + k] = acc;
+    }
   }
 }
 
@@ -367,8 +403,11 @@ static hipError_t update_t(const ProbDev<Real> &p, const Real *cost, const uint3
   double *S = (double *)ws;
   double *part = (double *)((char *)ws + align_up((size_t)K * T * 8, 256));
   double *norm = (double *)((char *)part + align_up((size_t)T * C * (2 + kMaxU) * 8, 256));
-  hipLaunchKernelGGL(suffix_kernel<Real>, dim3((K + kSufK - 1) / kSufK), dim3(kSufK * kSufSeg), 0, s, cost, K, T,
-                     S);
+  const unsigned nsb = (unsigned)((K + kSufK - 1) / kSufK);
+  if (nsb >= 256)   // enough blocks to cover the compute units: read through LDS
+    hipLaunchKernelGGL((suffix_kernel<Real, true>), dim3(nsb), dim3(kSufK * kSufSeg), 0, s, cost, K, T, S);
+  else
+    hipLaunchKernelGGL((suffix_kernel<Real, false>), dim3(nsb), dim3(kSufK * kSufSeg), 0, s, cost, K, T, S);
   hipLaunchKernelGGL(update_chunk_kernel<Real>, dim3(C, T), dim3(kUpdThreads), 0, s, p, lambda,
                      weighting, iter, (const double *)S, part);
   hipLaunchKernelGGL(update_apply_kernel<Real>, dim3((T + 63) / 64), dim3(64), 0, s, T, C, p.n_u,
