@@ -200,10 +200,14 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
  * g_u_nom dev [T][n_u], the centres g_centre dev [Ltot][d] and every entry of
  * the metrics g_metric dev [Ltot][d][d] (problem dtype).  States are
  * checkpointed every `ckpt_every` steps (0: ceil(sqrt(T))) and recomputed
- * segment by segment in the reverse sweep.  pi_workspace_bytes(PI_OP_ADJOINT)
- * sizes the workspace for the default checkpoint interval; another interval
- * may need more (PI_ERR_WORKSPACE says how much).  The indicator obstacle
- * term has zero derivative almost everywhere.                               */
+ * segment by segment in the reverse sweep.  Float32 problems whose model has
+ * a matrix-core form (d in {6, 16}, variant not PI_VARIANT_DIRECT) instead run
+ * the forward on the matrix cores and keep every step's state and mixture
+ * moments (no recompute; ckpt_every is then unused).
+ * pi_workspace_bytes(PI_OP_ADJOINT) sizes the workspace for the default
+ * checkpoint interval; another interval may need more (PI_ERR_WORKSPACE says
+ * how much).  The indicator obstacle term has zero derivative almost
+ * everywhere.                                                                */
 /* (PI_DYN_POINTMASS2D and PI_DYN_QUAD12; PI_ERR_UNSUPPORTED otherwise.)     */
 pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0,
                              const void *u_nom, const uint32_t *iter, int32_t ckpt_every,

@@ -60,6 +60,7 @@ struct AdjArgs {
   Real *seg;            // [S][ckpt+1][SEGW]
   Real *recs;           // [S][T][RW]
   double *jsum;         // [S]
+  int recompute;        // 0: seg already holds every step ([S][T+1][SEGW], ckpt = T)
 };
 
 template <typename Real, int DYN>
@@ -242,21 +243,24 @@ __global__ void __launch_bounds__(kAThreads) adj_backward_kernel(AdjArgs<Real> a
   for (int ci = a.ncp - 1; ci >= 0; --ci) {
     const int t0 = ci * a.ckpt, t1 = min(p.T, t0 + a.ckpt);
     // recompute the segment's states and mixture moments from its checkpoint
-    if (l == 0)
-      for (int i = 0; i < NX; ++i) sm.x[g][i] = active ? a.ckpt_buf[(s * a.ncp + ci) * NX + i] : (Real)0;
-    for (int t = t0; t < t1; ++t) {
+    // (a traced forward has already stored every step)
+    if (a.recompute) {
+      if (l == 0)
+        for (int i = 0; i < NX; ++i) sm.x[g][i] = active ? a.ckpt_buf[(s * a.ncp + ci) * NX + i] : (Real)0;
+      for (int t = t0; t < t1; ++t) {
+        if (l == 0 && active)
+          for (int i = 0; i < NX; ++i) segs[(t - t0) * G::SEGW + i] = sm.x[g][i];
+        adj_step(a, m, sm, g, l, active, k, mm, t, wc, wd);
+        if (l == 0 && active)
+          for (int o = 0; o < NO; ++o) {
+            segs[(t - t0) * G::SEGW + NX + 3 * o] = sm.mu[g][o];
+            segs[(t - t0) * G::SEGW + NX + 3 * o + 1] = sm.var[g][o];
+            segs[(t - t0) * G::SEGW + NX + 3 * o + 2] = sm.lse[g][o];
+          }
+      }
       if (l == 0 && active)
-        for (int i = 0; i < NX; ++i) segs[(t - t0) * G::SEGW + i] = sm.x[g][i];
-      adj_step(a, m, sm, g, l, active, k, mm, t, wc, wd);
-      if (l == 0 && active)
-        for (int o = 0; o < NO; ++o) {
-          segs[(t - t0) * G::SEGW + NX + 3 * o] = sm.mu[g][o];
-          segs[(t - t0) * G::SEGW + NX + 3 * o + 1] = sm.var[g][o];
-          segs[(t - t0) * G::SEGW + NX + 3 * o + 2] = sm.lse[g][o];
-        }
+        for (int i = 0; i < NX; ++i) segs[(t1 - t0) * G::SEGW + i] = sm.x[g][i];
     }
-    if (l == 0 && active)
-      for (int i = 0; i < NX; ++i) segs[(t1 - t0) * G::SEGW + i] = sm.x[g][i];
     // reverse sweep over the segment
     for (int t = t1 - 1; t >= t0; --t) {
       if (l == 0) {
@@ -478,6 +482,15 @@ __global__ void __launch_bounds__(256) adj_u_kernel(int64_t S, int T, const Real
   if (threadIdx.x < G::NU) gu[t * G::NU + threadIdx.x] = (Real)(scale * red[0][threadIdx.x]);
 }
 
+// Traced forward: jsum[s] = sum_t cost[s][t] in double, one lane per sub-rollout.
+__global__ void adj_jsum_kernel(int64_t S, int T, const float *__restrict__ cost, double *__restrict__ jsum) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double acc = 0.0;
+  for (int t = 0; t < T; ++t) acc += (double)cost[s * T + t];
+  jsum[s] = acc;
+}
+
 // Stage 4c: J = scale * sum_s jsum[s] (one block, fixed tree).
 __global__ void __launch_bounds__(256) adj_j_kernel(int64_t S, const double *__restrict__ jsum, double scale,
                                                     double *__restrict__ J) {
@@ -502,26 +515,32 @@ int adjoint_default_ckpt(int T) {
 
 int adjoint_param_chunks(int64_t R) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, R / 2048)); }
 
-size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt) {
+size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes) {
   const int Ms = M > 0 ? M : 1;
   const int64_t S = (int64_t)K * Ms;
   const int nx = dyn == kDynPointMass2D ? 4 : 12, nu = dyn == kDynPointMass2D ? 2 : 4,
             no = dyn == kDynPointMass2D ? 2 : 6;
   const size_t rb = dtype == PI_F64 ? 8 : 4;
+  const bool traced = mfma_bytes > 0;
+  if (traced) ckpt = T;
   const int ncp = (T + ckpt - 1) / ckpt;
   const int segw = nx + 3 * no, rw = d + 5 * no + nu, pw = d * (d + 1) / 2 + d + 1;
   const int nch = adjoint_param_chunks(S * T);
-  return direct_bytes(dtype, d, Ltot) + align_up((size_t)S * ncp * nx * rb, 256) +
-         align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * T * rw * rb, 256) +
-         align_up((size_t)S * 8, 256) + align_up((size_t)nch * Ltot * pw * rb, 256);
+  size_t b = direct_bytes(dtype, d, Ltot) + align_up((size_t)S * ncp * nx * rb, 256) +
+             align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * T * rw * rb, 256) +
+             align_up((size_t)S * 8, 256) + align_up((size_t)nch * Ltot * pw * rb, 256);
+  if (traced) b += align_up(mfma_bytes, 256) + align_up((size_t)S * T * 4, 256);
+  return b;
 }
 
 template <typename Real, int DYN>
 static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Real *x0, const Real *u_nom,
                             const uint32_t *iter, int ckpt, double *J, Real *gu, Real *gc, Real *gD, void *ws,
-                            hipStream_t s) {
+                            const MfmaLayout *ml, hipStream_t s) {
   using G = AdjGeo<Real, DYN>;
   const int64_t S = (int64_t)p.K * p.Ms;
+  const bool traced = ml != nullptr;
+  if (traced) ckpt = p.T;
   const int ncp = (p.T + ckpt - 1) / ckpt;
   const int64_t R = S * p.T;
   const int nch = adjoint_param_chunks(R);
@@ -544,10 +563,28 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   a.jsum = (double *)w;
   w += align_up((size_t)S * 8, 256);
   Real *gpart = (Real *)w;
+  w += align_up((size_t)nch * m.Ltot * G::PW * sizeof(Real), 256);
+  a.recompute = traced ? 0 : 1;
   hipError_t e = launch_fold_direct(sizeof(Real) == 8 ? PI_F64 : PI_F32, m, (void *)a.model, s);
   if (e != hipSuccess) return e;
   const unsigned nb = (unsigned)((S + kAS - 1) / kAS);
-  hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
+  if constexpr (sizeof(Real) == 4) {
+    if (traced) {
+      // forward on the matrix cores, storing every step's state and moments
+      void *mbase = w;
+      w += align_up(ml->bytes, 256);
+      float *cost = (float *)w;
+      e = launch_fold_mfma(PI_F32, m, *ml, mbase, s);
+      if (e != hipSuccess) return e;
+      RolloutArgs<float> ra{p, x0, u_nom, iter, cost};
+      ra.trace = a.seg;
+      e = launch_rollout_mfma(ra, m, *ml, mbase, S >= 4096 ? 16 : 8, 4, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(adj_jsum_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, p.T,
+                         (const float *)cost, a.jsum);
+    }
+  }
+  if (!traced) hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
   hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
   hipLaunchKernelGGL((adj_param_kernel<Real, DYN>), dim3((m.Ltot + kParamThreads - 1) / kParamThreads, nch),
                      dim3(kParamThreads), 0, s, m, a.model, (const Real *)a.recs, R, nch, gpart);
@@ -562,21 +599,21 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
 
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
                           const uint32_t *iter, int ckpt, double *J, void *gu, void *gc, void *gD, void *ws,
-                          hipStream_t s) {
+                          const MfmaLayout *ml, hipStream_t s) {
   if (dtype == PI_F64) {
     const ProbDev<double> &p = *(const ProbDev<double> *)pargs;
     if (p.dyn == kDynPointMass2D)
       return adjoint_t<double, kDynPointMass2D>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, J,
-                                                (double *)gu, (double *)gc, (double *)gD, ws, s);
+                                                (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
     return adjoint_t<double, kDynQuad12>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, J,
-                                         (double *)gu, (double *)gc, (double *)gD, ws, s);
+                                         (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
   }
   const ProbDev<float> &p = *(const ProbDev<float> *)pargs;
   if (p.dyn == kDynPointMass2D)
     return adjoint_t<float, kDynPointMass2D>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, J,
-                                             (float *)gu, (float *)gc, (float *)gD, ws, s);
+                                             (float *)gu, (float *)gc, (float *)gD, ws, ml, s);
   return adjoint_t<float, kDynQuad12>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, J, (float *)gu,
-                                      (float *)gc, (float *)gD, ws, s);
+                                      (float *)gc, (float *)gD, ws, ml, s);
 }
 
 }  // namespace pi2rh

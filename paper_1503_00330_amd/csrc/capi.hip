@@ -275,6 +275,15 @@ pi_status check_folded(const pi_lwpr *m, bool mfma) {
   return PI_OK;
 }
 
+// The float32 adjoint runs its forward on the matrix cores and keeps every
+// step (state and moments) when the model has a matrix-core form: bytes of
+// that form, or 0 for the checkpointed direct forward.
+size_t adjoint_traced_bytes(const pi_problem *p, const pi_lwpr *m) {
+  if (p->dtype != PI_F32 || !mfma_ok(m->dtype, m->d) || p->dyn == PI_DYN_QUAD_HYBRID) return 0;
+  if (p->variant == PI_VARIANT_DIRECT) return 0;
+  return mfma_layout(m->d, m->n_out, m->L_off).bytes;
+}
+
 size_t fold_bytes(const pi_lwpr *m, bool mfma) {
   if (mfma) return mfma_layout(m->d, m->n_out, m->L_off).bytes;
   return direct_bytes(m->dtype, m->d, m->L_off[m->n_out]);
@@ -414,7 +423,7 @@ size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
     case PI_OP_ADJOINT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
       return adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
-                              adjoint_default_ckpt(p->T));
+                              adjoint_default_ckpt(p->T), adjoint_traced_bytes(p, m));
   }
   fail(PI_ERR_VALUE, "unknown op %d", op);
   return (size_t)-1;
@@ -537,18 +546,22 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
   const int ckpt = ckpt_every == 0 ? adjoint_default_ckpt(p->T) : std::min<int>(ckpt_every, p->T);
   if ((int64_t)p->K * (p->M > 0 ? p->M : 1) * p->T > ((int64_t)1 << 36))
     return fail(PI_ERR_SHAPE, "K*max(M,1)*T too large for the adjoint records");
+  const size_t traced = adjoint_traced_bytes(p, m);
   PI_TRY(check_ws(ws, ws_bytes, adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
-                                                 ckpt)));
+                                                 ckpt, traced)));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
   const ModelArgs a = model_args(m);
   hipError_t e;
   if (p->dtype == PI_F64) {
     const ProbDev<double> d = prob_dev<double>(p);
-    e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws, s);
+    e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws,
+                       nullptr, s);
   } else {
     const ProbDev<float> d = prob_dev<float>(p);
-    e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws, s);
+    const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+    e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws,
+                       traced ? &l : nullptr, s);
   }
   return launched(e, "pi_rollout_adjoint");
 }

@@ -106,6 +106,8 @@ struct RolloutArgs {
   const Real *x0, *u_nom;
   const uint32_t *iter;
   Real *cost;       // [K][T] (Ms == 1) or sub-rollout costs [K][Ms][T]
+  Real *trace = nullptr;  // optional [K*Ms][T+1][n_x + 3 n_out]: x_t, then (mu, var, lse)
+                          // of every output at step t (matrix-core kernels only)
 };
 
 hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
@@ -154,9 +156,12 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
 
 // ---- adjoint -------------------------------------------------------------------
 int adjoint_default_ckpt(int T);
-size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt);
+// mfma_bytes > 0: float32 forward on the matrix cores with every step traced
+// (no checkpoints, no recompute); 0: direct forward with checkpoints.
+size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes);
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
                           const uint32_t *iter, int ckpt, double *J, void *gu, void *gc, void *gD, void *ws,
+                          const MfmaLayout *ml,
                           hipStream_t s);
 
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,

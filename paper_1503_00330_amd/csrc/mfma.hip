@@ -208,6 +208,7 @@ struct MixSmem {
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mprev[ROWS][kMaxOut];            // previous step's largest activation
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
+  float lse[ROWS][kMaxOut];              // log sum_j exp(-q_j / 2)
   float acc[ROWS][kMaxOut];              // sampled accelerations (rollouts)
   unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
   int redo[2];                           // second-pass requests, by evaluation parity
@@ -422,6 +423,11 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // set, acc = mu + sqrt(var) xi[row][o] (a draw from N(mu, var)); without, mu.
 struct SampleArgs {
   const float *xi;   // [rows][8] standard normals of this step, or null
+  // optional per-step trace: (mu, var, lse) of output o for row r go to
+  // trace[r * trace_stride + trace_off + 3 o + {0, 1, 2}] for r < trace_rows
+  float *trace = nullptr;
+  int64_t trace_stride = 0;
+  int trace_off = 0, trace_rows = 0;
 };
 
 // Eq. (1) moments of one (row, output) from its complete sums, the sampled
@@ -436,6 +442,8 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int
   const float var = (fmaxf(s.S2 - s.S1 * d1, 0.f) + s.S3) / s.Z;
   sm.mean[row][o] = mu;
   sm.var[row][o] = var;
+  // the anchor in use is m (base-2 units): sum_j exp(-q_j/2) = 2^m Z
+  sm.lse[row][o] = 0.69314718055994531f * (sm.mref[row][o] + log2f(s.Z));
   sm.acc[row][o] = sa.xi ? mu + sqrtf(var) * sa.xi[row * 8 + o] : mu;
   const bool valid = isfinite(s.Z) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.S3) && s.mx >= kAnchorLo;
   if (!valid) sm.redo[ev & 1] = 1;
@@ -488,6 +496,7 @@ struct PairCtx {
   uint64_t *xbuf;    // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
   int half;          // 0 or 1; -1 when not paired
 };
+__device__ __forceinline__ bool writer_of(const PairCtx *pc) { return pc == nullptr || pc->half == 0; }
 constexpr int kXSlots = 16 * kMaxOut;
 constexpr int kPairWords = 2 * 2 * kXSlots * 5;
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -580,6 +589,12 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
         const float d = force_second ? 0.f : M - sm.mprev[row][o];
         sm.mprev[row][o] = M;
         if (isfinite(d)) sm.mref[row][o] = M + d;
+        if (sa.trace && row < sa.trace_rows) {
+          float *dst = sa.trace + row * sa.trace_stride + sa.trace_off + 3 * o;
+          dst[0] = sm.mean[row][o];
+          dst[1] = sm.var[row][o];
+          dst[2] = sm.lse[row][o];
+        }
       }
       break;
     }
@@ -683,14 +698,18 @@ template <int DYN, int MT, int NW>
 __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
                              uint32_t it, float *__restrict__ cost, const MfmaModel &md,
-                             int64_t s_base, int spw, const PairCtx *pc = nullptr) {
+                             int64_t s_base, int spw, const PairCtx *pc = nullptr, float *tr = nullptr) {
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
   MixSmem<D, MT, NW> &sm = rs.sm;
+  constexpr int SEGW = NX + 3 * NO;
+  const int64_t tstride = (int64_t)(p.T + 1) * SEGW;
+  float *trace = writer_of(pc) && tr ? tr + s_base * tstride : nullptr;
+  const int trows = (int)min<int64_t>(spw, (int64_t)p.K * p.Ms - s_base);
   const int T0 = pc == nullptr || pc->half == 0 ? 0 : md.n_tiles / 2;
   const int T1 = pc == nullptr || pc->half == 1 ? md.n_tiles : md.n_tiles / 2;
-  const bool writer = pc == nullptr || pc->half == 0;
+  const bool writer = writer_of(pc);
   uint32_t seq = 0;
   __syncthreads();  // the previous tile (persistent use) is done with LDS
   reset_anchors(sm);
@@ -763,6 +782,10 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
         applied(u);
 #pragma unroll
         for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
+        if (trace) {
+#pragma unroll
+          for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)t * SEGW + a] = x[a];
+        }
         lwpr_input<DYN>(x, u, z);
 #pragma unroll
         for (int a = 0; a < D; ++a) sm.z[row][a] = z[a];
@@ -772,7 +795,14 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
     }
     __syncthreads();
-    mixture_step(md, sm, t == 0, T0, T1, pc, seq, SampleArgs{p.M > 0 ? &rs.xi_s[tc][0][0] : nullptr});
+    SampleArgs sa{p.M > 0 ? &rs.xi_s[tc][0][0] : nullptr};
+    if (trace) {
+      sa.trace = trace + (int64_t)t * SEGW;
+      sa.trace_stride = tstride;
+      sa.trace_off = NX;
+      sa.trace_rows = trows;
+    }
+    mixture_step(md, sm, t == 0, T0, T1, pc, seq, sa);
     if (active) {
       float acc[NO], xn[NX], x[NX], u[NU];
 #pragma unroll
@@ -788,6 +818,10 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
     }
   }
+  if (trace && active) {
+#pragma unroll
+    for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)p.T * SEGW + a] = rs.xs[row][a];
+  }
   __syncthreads();
   const int tl = p.T > 0 ? ((p.T - 1) / kNoiseChunk) * kNoiseChunk : 0;
   flush_costs(tl, p.T - tl);
@@ -800,7 +834,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
   __shared__ RollSmem<DYN, MT, NW> rs;
   mix_setup(rs.sm);
   rollout_tile<DYN, MT, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
-                            (int64_t)blockIdx.x * spw, spw);
+                            (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace);
 }
 
 // Paired form (one 16-row tile per pair of workgroups, for problems with
@@ -816,7 +850,8 @@ __global__ void __launch_bounds__(NW * 64) rollout_pair_kernel(RolloutArgs<float
   if (g >= n_groups) return;  // both halves of an unused pair leave
   const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1};
   mix_setup(rs.sm);
-  rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc);
+  rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
+                           ra.trace);
 }
 
 // Persistent form for many independent problems: every workgroup pulls

@@ -54,10 +54,14 @@ def test_adjoint_fp64_matches_oracle(dyn, M, ckpt):
         assert nrel(g.cpu().numpy(), o) <= 1e-10
 
 
+# float32: the matrix-core forward that keeps every step (variant AUTO) and the
+# checkpointed direct forward (variant DIRECT)
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_AUTO, pi.PI_VARIANT_DIRECT])
+@pytest.mark.parametrize("M", [0, 1, 3])
 @pytest.mark.parametrize("dyn", [DYN_POINTMASS2D, DYN_QUAD12])
-def test_adjoint_fp32_matches_oracle(dyn):
-    prob, model = _case(dyn, 1, np.float32, K=40, T=16)
-    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+def test_adjoint_fp32_matches_oracle(dyn, M, variant):
+    prob, model = _case(dyn, M, np.float32, K=40, T=16)
+    dp, dm = pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model)
     J, gu, gc, gD = pi.rollout_adjoint(dp, dm)
     oJ, ogu, ogc, ogD = oracle.adjoint(prob, model)
     assert abs(J.item() - oJ) <= 1e-5 * abs(oJ)
