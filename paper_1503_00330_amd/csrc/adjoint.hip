@@ -422,6 +422,34 @@ __global__ void __launch_bounds__(kParamThreads) adj_param_kernel(ModelArgs m, c
     for (int i = 0; i < PW; ++i) gpart[((size_t)ch * m.Ltot + j) * PW + i] = acc[i];
 }
 
+// dJ/dD_j and dJ/dc_j of one model from its centred sums (sum[0..NP) =
+// sum qbar dl dl^T packed, sum[NP..NP+D) = sum qbar dl, sum[NP+D] = sum ybar,
+// dl = z - c_j) and its direct record r.
+template <typename Real, int D>
+__device__ void param_grads_from_sums(int j, const Real *r, const double *sum, double scale, Real *gc, Real *gD) {
+  constexpr int NP = D * (D + 1) / 2;
+  int idx = 0;
+  for (int a = 0; a < D; ++a)
+    for (int b = a; b < D; ++b) {
+      const double v = sum[idx++] * scale;
+      gD[((size_t)j * D + a) * D + b] = (Real)v;
+      gD[((size_t)j * D + b) * D + a] = (Real)v;
+    }
+  // (D + D^T) from the packed record: diagonal 2 theta_aa, off-diagonal theta_ab
+  const Real *th = r + D;
+  const Real *bb = th + NP;
+  for (int a = 0; a < D; ++a) {
+    double v = 0.0;
+    for (int b = 0; b < D; ++b) {
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      const int pidx = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+      const double t = (double)th[pidx] * (a == b ? 2.0 : 1.0);
+      v += t * sum[NP + b];
+    }
+    gc[(size_t)j * D + a] = (Real)(scale * (-v - (double)bb[a] * sum[NP + D]));
+  }
+}
+
 // Stage 4a: per model, chunk partials summed in order and turned into
 // dJ/dD_j and dJ/dc_j.
 template <typename Real, int DYN>
@@ -436,29 +464,42 @@ __global__ void adj_param_finish_kernel(ModelArgs m, const Real *__restrict__ mo
   for (int i = 0; i < PW; ++i) sum[i] = 0.0;
   for (int ch = 0; ch < nch; ++ch)
     for (int i = 0; i < PW; ++i) sum[i] += (double)gpart[((size_t)ch * m.Ltot + j) * PW + i];
-  const Real *r = model + (size_t)j * RS;
+  param_grads_from_sums<Real, D>(j, model + (size_t)j * RS, sum, scale, gc, gD);
+}
+
+// Stage 4a, matrix-core sums: G_j = sum qbar [z z^T, z, 1] and sum ybar per
+// chunk, added in chunk order in double, then centred at c_j:
+//   sum qbar dl dl^T = G_zz - G_z c^T - c G_z^T + G_1 c c^T,  sum qbar dl = G_z - G_1 c.
+template <int DYN>
+__global__ void adj_param_mfma_finish_kernel(ModelArgs m, MfmaLayout l, const float *__restrict__ model, int nch,
+                                             const float *__restrict__ gpart, int width, double scale,
+                                             float *__restrict__ gc, float *__restrict__ gD) {
+  using G = AdjGeo<float, DYN>;
+  constexpr int D = G::D, RS = G::RS, NP = G::NP, PW = G::PW;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.Ltot) return;
+  int o = 0;
+  while (o + 1 < m.n_out && j >= m.L_off[o + 1]) ++o;
+  const int slot = (l.tile_off[o] + (j - m.L_off[o]) / 16) * 16 + (j - m.L_off[o]) % 16;
+  double g[NP + D + 1], y = 0.0;
+  for (int i = 0; i < NP + D + 1; ++i) g[i] = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const float *src = gpart + ((size_t)ch * l.n_tiles * 16 + slot) * width;
+    for (int i = 0; i < NP + D + 1; ++i) g[i] += (double)src[i];
+    y += (double)src[width - 1];
+  }
+  const float *r = model + (size_t)j * RS;
+  double c[D], gz[D];
+  for (int a = 0; a < D; ++a) c[a] = (double)r[a];
+  const double g1 = g[NP + D];
+  for (int a = 0; a < D; ++a) gz[a] = g[NP + a];
+  double sum[PW];
   int idx = 0;
   for (int a = 0; a < D; ++a)
-    for (int b = a; b < D; ++b) {
-      const double v = sum[idx++] * scale;
-      gD[((size_t)j * D + a) * D + b] = (Real)v;
-      gD[((size_t)j * D + b) * D + a] = (Real)v;
-    }
-  // (D + D^T) from the packed record: diagonal 2 theta_aa, off-diagonal theta_ab
-  const Real *th = r + D;
-  const Real *bb = th + G::NP;
-  double g1[D];
-  for (int a = 0; a < D; ++a) g1[a] = sum[G::NP + a];
-  for (int a = 0; a < D; ++a) {
-    double v = 0.0;
-    for (int b = 0; b < D; ++b) {
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      const int pidx = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-      const double t = (double)th[pidx] * (a == b ? 2.0 : 1.0);
-      v += t * g1[b];
-    }
-    gc[(size_t)j * D + a] = (Real)(scale * (-v - (double)bb[a] * sum[G::NP + D]));
-  }
+    for (int b = a; b < D; ++b, ++idx) sum[idx] = g[idx] - gz[a] * c[b] - c[a] * gz[b] + g1 * c[a] * c[b];
+  for (int a = 0; a < D; ++a) sum[NP + a] = gz[a] - g1 * c[a];
+  sum[NP + D] = y;
+  param_grads_from_sums<float, D>(j, r, sum, scale, gc, gD);
 }
 
 // Stage 4b: dJ/du_nom[t] = scale * sum_s ubar[s][t] (block per step, fixed tree).
@@ -514,6 +555,22 @@ int adjoint_default_ckpt(int T) {
 }
 
 int adjoint_param_chunks(int64_t R) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, R / 2048)); }
+// record chunks of the matrix-core parameter pass (each workgroup holds 8 model tiles)
+static int adjoint_param_chunks_mfma(int64_t R) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, R / 16384));
+}
+
+// Partial sums of the parameter pass: per chunk and model, PW values (direct)
+// or adj_param_mfma_width(d) values per model slot (matrix cores; the padded
+// tiles of n_out outputs add at most 16 n_out slots).
+static size_t adj_gpart_bytes(int dtype, int d, int n_out, int Ltot, int64_t R, bool traced) {
+  const size_t rb = dtype == PI_F64 ? 8 : 4;
+  const int pw = d * (d + 1) / 2 + d + 1;
+  size_t b = (size_t)adjoint_param_chunks(R) * Ltot * pw * rb;
+  if (traced)
+    b = std::max(b, (size_t)adjoint_param_chunks_mfma(R) * (size_t)(Ltot + 16 * n_out) * adj_param_mfma_width(d) * 4);
+  return align_up(b, 256);
+}
 
 size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes) {
   const int Ms = M > 0 ? M : 1;
@@ -525,10 +582,10 @@ size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d
   if (traced) ckpt = T;
   const int ncp = (T + ckpt - 1) / ckpt;
   const int segw = nx + 3 * no, rw = d + 5 * no + nu, pw = d * (d + 1) / 2 + d + 1;
-  const int nch = adjoint_param_chunks(S * T);
+  (void)pw;
   size_t b = direct_bytes(dtype, d, Ltot) + align_up((size_t)S * ncp * nx * rb, 256) +
              align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * T * rw * rb, 256) +
-             align_up((size_t)S * 8, 256) + align_up((size_t)nch * Ltot * pw * rb, 256);
+             align_up((size_t)S * 8, 256) + adj_gpart_bytes(dtype, d, no, Ltot, S * T, traced);
   if (traced) b += align_up(mfma_bytes, 256) + align_up((size_t)S * T * 4, 256);
   return b;
 }
@@ -563,7 +620,8 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   a.jsum = (double *)w;
   w += align_up((size_t)S * 8, 256);
   Real *gpart = (Real *)w;
-  w += align_up((size_t)nch * m.Ltot * G::PW * sizeof(Real), 256);
+  w += adj_gpart_bytes(sizeof(Real) == 8 ? PI_F64 : PI_F32, m.d, m.n_out, m.Ltot, R, traced);
+  void *mbase = nullptr;
   a.recompute = traced ? 0 : 1;
   hipError_t e = launch_fold_direct(sizeof(Real) == 8 ? PI_F64 : PI_F32, m, (void *)a.model, s);
   if (e != hipSuccess) return e;
@@ -571,7 +629,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   if constexpr (sizeof(Real) == 4) {
     if (traced) {
       // forward on the matrix cores, storing every step's state and moments
-      void *mbase = w;
+      mbase = w;
       w += align_up(ml->bytes, 256);
       float *cost = (float *)w;
       e = launch_fold_mfma(PI_F32, m, *ml, mbase, s);
@@ -586,11 +644,26 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   }
   if (!traced) hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
   hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
-  hipLaunchKernelGGL((adj_param_kernel<Real, DYN>), dim3((m.Ltot + kParamThreads - 1) / kParamThreads, nch),
-                     dim3(kParamThreads), 0, s, m, a.model, (const Real *)a.recs, R, nch, gpart);
   const double scale = 1.0 / (double)S;
-  hipLaunchKernelGGL((adj_param_finish_kernel<Real, DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m,
-                     a.model, nch, (const Real *)gpart, scale, gc, gD);
+  bool done = false;
+  if constexpr (sizeof(Real) == 4) {
+    if (traced) {
+      // parameter sums on the matrix cores from the folded tiles
+      const int nchm = adjoint_param_chunks_mfma(R);
+      const int width = adj_param_mfma_width(m.d);
+      e = launch_adj_param_mfma(*ml, mbase, (const float *)a.recs, G::RW, R, nchm, (float *)gpart, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((adj_param_mfma_finish_kernel<DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m, *ml,
+                         (const float *)a.model, nchm, (const float *)gpart, width, scale, (float *)gc, (float *)gD);
+      done = true;
+    }
+  }
+  if (!done) {
+    hipLaunchKernelGGL((adj_param_kernel<Real, DYN>), dim3((m.Ltot + kParamThreads - 1) / kParamThreads, nch),
+                       dim3(kParamThreads), 0, s, m, a.model, (const Real *)a.recs, R, nch, gpart);
+    hipLaunchKernelGGL((adj_param_finish_kernel<Real, DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m,
+                       a.model, nch, (const Real *)gpart, scale, gc, gD);
+  }
   hipLaunchKernelGGL((adj_u_kernel<Real, DYN>), dim3(p.T), dim3(256), 0, s, S, p.T, (const Real *)a.recs,
                      scale, gu);
   hipLaunchKernelGGL(adj_j_kernel, dim3(1), dim3(256), 0, s, S, (const double *)a.jsum, scale, J);

@@ -156,6 +156,13 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
 
 // ---- adjoint -------------------------------------------------------------------
 int adjoint_default_ckpt(int T);
+// Adjoint parameter sums on the matrix cores (float32, d in {6, 16}): per
+// record chunk and model, G = sum_r qbar Phi(z_r) (Phi = [z_a z_b, z, 1],
+// padded to a multiple of 16) and sum_r ybar; adj_param_mfma_width(d) floats
+// per (chunk, model slot), gpart [nch][n_tiles * 16][width].
+int adj_param_mfma_width(int d);
+hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const float *recs, int RW, int64_t R,
+                                 int nch, float *gpart, hipStream_t s);
 // mfma_bytes > 0: float32 forward on the matrix cores with every step traced
 // (no checkpoints, no recompute); 0: direct forward with checkpoints.
 size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes);

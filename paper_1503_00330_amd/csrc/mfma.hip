@@ -973,4 +973,165 @@ hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem
 
 MfmaModel mfma_model_view(const MfmaLayout &l, const void *base) { return mfma_view(l, base); }
 
+// ------------------------------------------------------ adjoint parameters
+// Parameter gradients of the adjoint on the matrix cores.  For a tile of 16
+// records (sub-rollout steps of the reverse sweep) and a tile of 16 local
+// models of output o:
+//  (1) the forward contraction, with the activation anchor at lse_{r,o} and
+//      the prediction reference at mu_{r,o}, returns log2 w_{rj} and
+//      e_{rj} = y_j - mu directly;
+//  (2) each lane turns its four (record, model) elements into
+//      ybar = w (mubar + 2 vbar e) and qbar = -w (mubar e + vbar (e^2 + sigma_j^2 - var)) / 2;
+//  (3) G_j += sum_r qbar_{rj} Phi(z_r), Phi = [z_a z_b (a <= b), z, 1]: the C
+//      fragments of (1) serve unchanged as the A operand (rows = models,
+//      k = records) of a second contraction against the records' features,
+//      which the fragments built for (1) already hold.
+// Every workgroup holds a record chunk and 8 model tiles (2 per wave) and
+// writes per-chunk sums G_j (NF features) and sum_r ybar_{rj}; the finish pass
+// adds the chunks in double and centres them at c_j.
+constexpr int kPrmTilesPerWave = 2;
+
+template <int D>
+__global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const float *__restrict__ recs, int RW,
+                                                              int64_t R, int nch, float *__restrict__ gpart) {
+  using G = Geo<D>;
+  constexpr int NF = G::NP + D + 1;           // features of Phi
+  constexpr int NFB = (NF + 15) / 16;
+  constexpr int PWM = NFB * 16 + 1;           // per-model partial: G (padded), sum ybar
+  constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;
+  constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
+  __shared__ MixSmem<D, 1, 4> sm;
+  __shared__ float st[16][kMaxOut][5];        // lse, mu, var, mubar, vbar per record and output
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ch = blockIdx.y;
+  const int64_t r0 = R * ch / nch, r1 = R * (ch + 1) / nch;
+  const int n_out = md.n_out;
+  mix_setup(sm);
+  for (int i = threadIdx.x; i < 16; i += 256) {
+    sm.z[i][D] = 1.0f;
+    sm.z[i][D + 1] = 0.0f;
+  }
+  int tile[kPrmTilesPerWave], tout[kPrmTilesPerWave];
+#pragma unroll
+  for (int q = 0; q < kPrmTilesPerWave; ++q) {
+    tile[q] = (blockIdx.x * 4 + wave) * kPrmTilesPerWave + q;
+    int oo = 0;
+    for (int i = 1; i < n_out; ++i) oo += (md.tile_off[i] <= tile[q]) ? 1 : 0;
+    tout[q] = oo;
+  }
+  f32x4 acc[kPrmTilesPerWave][NFB];
+  float ysum[kPrmTilesPerWave];
+#pragma unroll
+  for (int q = 0; q < kPrmTilesPerWave; ++q) {
+    ysum[q] = 0.f;
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) acc[q][fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const float *Af = (const float *)&sm.A[0][0][0];
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+    const int nr = (int)min((int64_t)16, r1 - rb);
+    __syncthreads();  // the previous records' fragments and statistics are no longer read
+    for (int i = threadIdx.x; i < 16 * D; i += 256) {
+      const int row = i / D, a = i - row * D;
+      sm.z[row][a] = row < nr ? recs[(rb + row) * RW + a] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < 16 * n_out * 5; i += 256) {
+      const int row = i / (n_out * 5), rem = i - row * (n_out * 5);
+      const int o = rem / 5, c = rem - o * 5;
+      // rows past the chunk carry mubar = vbar = 0, so they add nothing
+      st[row][o][c] = row < nr ? recs[(rb + row) * RW + D + 5 * o + c] : 0.0f;
+    }
+    __syncthreads();
+    build_fragments(sm);
+    __syncthreads();
+    f32x4 A[G::KB4];
+#pragma unroll
+    for (int q = 0; q < G::KB4; ++q) {
+      const float4 v = sm.A[0][q][lane];
+      A[q] = f32x4{v.x, v.y, v.z, v.w};
+    }
+#pragma unroll
+    for (int q = 0; q < kPrmTilesPerWave; ++q) {
+      if (tile[q] >= md.n_tiles) continue;   // uniform over the wave
+      const int o = tout[q];
+      const int row = lane & 15;
+      if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = -st[row][o][0] * 1.4426950408889634f;
+      if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = -st[row][o][1];
+      f32x4 B[G::KB4];
+      const f32x4 *src = (const f32x4 *)md.W + (size_t)tile[q] * G::KB4 * 64 + lane;
+#pragma unroll
+      for (int k = 0; k < G::KB4; ++k) B[k] = src[k * 64];
+      const float s2 = md.sig2[tile[q] * 16 + (lane & 15)];
+      f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
+#pragma unroll
+      for (int kb = 0; kb < G::KQB; ++kb) {
+        if (kb & 1)
+          qb = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb / 4][kb % 4], B[kb / 4][kb % 4], qb, 0, 0, 0);
+        else
+          qa = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb / 4][kb % 4], B[kb / 4][kb % 4], qa, 0, 0, 0);
+      }
+#pragma unroll
+      for (int kb = G::KQB; kb < G::KB; ++kb)
+        ya = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb / 4][kb % 4], B[kb / 4][kb % 4], ya, 0, 0, 0);
+      float qbar[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = 4 * (lane >> 4) + i;
+        const float w = exp2f(qa[i] + qb[i]), e = ya[i];
+        const float var = st[rr][o][2], mub = st[rr][o][3], vb = st[rr][o][4];
+        ysum[q] += w * (mub + 2.0f * vb * e);
+        qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
+      }
+      // G[model][feature] += sum_r qbar[r][model] Phi(z_r)[feature]: instance i
+      // takes records 4k + i at k = lane/16; lane reads Phi of its record and
+      // feature from the (anchor-free) fragments in LDS
+#pragma unroll
+      for (int fb = 0; fb < NFB; ++fb) {
+        const int f = 16 * fb + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 4 * (lane >> 4) + i;
+          const float b = f < NF ? Af[((f >> 4) * 64 + 16 * (f & 3) + r) * 4 + ((f & 15) >> 2)] : 0.0f;
+          acc[q][fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qbar[i], b, acc[q][fb], 0, 0, 0);
+        }
+      }
+      // restore the anchor slots for the next tile (they were set for output o)
+      if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = 0.0f;
+      if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = 0.0f;
+    }
+  }
+  // per-chunk partials: acc[q][fb][j] = G[model 4 (lane/16) + j][feature 16 fb + lane%16]
+#pragma unroll
+  for (int q = 0; q < kPrmTilesPerWave; ++q) {
+    if (tile[q] >= md.n_tiles) continue;
+    float *dst = gpart + ((size_t)ch * md.n_tiles + tile[q]) * 16 * PWM;
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[(4 * (lane >> 4) + j) * PWM + 16 * fb + (lane & 15)] = acc[q][fb][j];
+    float y = ysum[q];
+    y += __shfl_xor(y, 16);
+    y += __shfl_xor(y, 32);
+    if (lane < 16) dst[lane * PWM + NFB * 16] = y;
+  }
+}
+
+int adj_param_mfma_width(int d) {
+  const int nf = d * (d + 1) / 2 + d + 1;
+  return ((nf + 15) / 16) * 16 + 1;
+}
+
+hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const float *recs, int RW, int64_t R,
+                                 int nch, float *gpart, hipStream_t s) {
+  const MfmaModel md = mfma_view(l, base);
+  const dim3 grid((unsigned)((md.n_tiles + 4 * kPrmTilesPerWave - 1) / (4 * kPrmTilesPerWave)), (unsigned)nch);
+  if (l.d == 16)
+    hipLaunchKernelGGL(adj_param_mfma_kernel<16>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart);
+  else if (l.d == 6)
+    hipLaunchKernelGGL(adj_param_mfma_kernel<6>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace pi2rh
