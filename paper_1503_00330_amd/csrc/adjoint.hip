@@ -621,7 +621,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   w += align_up((size_t)S * 8, 256);
   Real *gpart = (Real *)w;
   w += adj_gpart_bytes(sizeof(Real) == 8 ? PI_F64 : PI_F32, m.d, m.n_out, m.Ltot, R, traced);
-  void *mbase = nullptr;
+  void *mbase = nullptr, *rfold = nullptr;
   a.recompute = traced ? 0 : 1;
   hipError_t e = launch_fold_direct(sizeof(Real) == 8 ? PI_F64 : PI_F32, m, (void *)a.model, s);
   if (e != hipSuccess) return e;
@@ -631,6 +631,8 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
       // forward on the matrix cores, storing every step's state and moments
       mbase = w;
       w += align_up(ml->bytes, 256);
+      rfold = w;
+      w += adj_rfold_bytes(*ml);
       float *cost = (float *)w;
       e = launch_fold_mfma(PI_F32, m, *ml, mbase, s);
       if (e != hipSuccess) return e;
@@ -642,8 +644,17 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
                          (const float *)cost, a.jsum);
     }
   }
+  bool swept = false;
+  if constexpr (sizeof(Real) == 4) {
+    if (traced) {
+      // reverse sweep on the matrix cores, reading the trace
+      e = launch_adj_reverse_mfma(p, u_nom, iter, m, *ml, mbase, a.model, G::RS, rfold, a.seg, a.recs, s);
+      if (e != hipSuccess) return e;
+      swept = true;
+    }
+  }
   if (!traced) hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
-  hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
+  if (!swept) hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
   const double scale = 1.0 / (double)S;
   bool done = false;
   if constexpr (sizeof(Real) == 4) {

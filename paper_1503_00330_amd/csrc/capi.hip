@@ -281,7 +281,8 @@ pi_status check_folded(const pi_lwpr *m, bool mfma) {
 size_t adjoint_traced_bytes(const pi_problem *p, const pi_lwpr *m) {
   if (p->dtype != PI_F32 || !mfma_ok(m->dtype, m->d) || p->dyn == PI_DYN_QUAD_HYBRID) return 0;
   if (p->variant == PI_VARIANT_DIRECT) return 0;
-  return mfma_layout(m->d, m->n_out, m->L_off).bytes;
+  const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+  return align_up(l.bytes, 256) + adj_rfold_bytes(l);   // forward tiles + reverse-sweep parameters
 }
 
 size_t fold_bytes(const pi_lwpr *m, bool mfma) {

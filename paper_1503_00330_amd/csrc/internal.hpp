@@ -161,6 +161,14 @@ int adjoint_default_ckpt(int T);
 // padded to a multiple of 16) and sum_r ybar; adj_param_mfma_width(d) floats
 // per (chunk, model slot), gpart [nch][n_tiles * 16][width].
 int adj_param_mfma_width(int d);
+// Adjoint reverse sweep on the matrix cores (float32, traced forward): the
+// per-model parameters of the second contraction go to `rfold`
+// (adj_rfold_bytes), then one workgroup per 16 sub-rollouts sweeps t = T-1..0
+// writing the records [S][T][d + 5 n_out + n_u].
+size_t adj_rfold_bytes(const MfmaLayout &l);
+hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, const uint32_t *iter,
+                                   const ModelArgs &m, const MfmaLayout &l, const void *base, const void *rec,
+                                   int RS, void *rfold, const float *trace, float *recs, hipStream_t s);
 hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const float *recs, int RW, int64_t R,
                                  int nch, float *gpart, hipStream_t s);
 // mfma_bytes > 0: float32 forward on the matrix cores with every step traced

@@ -1116,6 +1116,289 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
   }
 }
 
+// ------------------------------------------------------ adjoint reverse sweep
+// The reverse sweep needs, per (sample, step),
+//   zbar = sum_j qbar_j ((D_j + D_j^T) z + h_j) + ybar_j b_j,   h_j = -(D_j + D_j^T) c_j,
+// with qbar, ybar from the weights and residuals of Eq. (1) as in the
+// parameter pass.  On the matrix cores: the forward contraction with the
+// operands swapped (the model tile as the A operand, the samples' features as
+// B: the folded tiles and the built fragments have exactly those register
+// layouts) leaves, per lane, four models of one sample -- which is the A
+// operand layout of the second contraction over models (rows = samples,
+// k = models) against per-model parameters P = [packed D + D^T, h] (for qbar)
+// and b (for ybar), stored by adj_rfold_kernel in B operand order:
+//   [tile][block fb][lane][i] = param(model 4 (lane/16) + i)[16 fb + lane%16].
+template <int D>
+struct RevGeo {
+  static constexpr int NP = D * (D + 1) / 2;
+  static constexpr int NQ = NP + D;              // packed D + D^T, then h
+  static constexpr int NFBQ = (NQ + 15) / 16;
+  static constexpr int NFB = NFBQ + 1;           // + the b block
+};
+
+__global__ void __launch_bounds__(256) adj_rfold_kernel(ModelArgs m, MfmaLayout l, const float *__restrict__ rec,
+                                                        int RS, int nfbq, float *__restrict__ dst) {
+  const int tile = blockIdx.x, d = m.d, np = d * (d + 1) / 2;
+  int o = 0;
+  while (o + 1 < m.n_out && tile >= l.tile_off[o + 1]) ++o;
+  const int jfirst = m.L_off[o] + (tile - l.tile_off[o]) * 16;
+  const int n = (nfbq + 1) * 64 * 4;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int i = e & 3, lane = (e >> 2) & 63, fb = e >> 8;
+    const int j = jfirst + 4 * (lane >> 4) + i;
+    const int f = 16 * fb + (lane & 15);
+    float v = 0.0f;
+    if (j < m.L_off[o + 1]) {
+      const float *r = rec + (size_t)j * RS;   // [c | packed theta | b | beta0 | sigma^2]
+      // entry (a, b) of D + D^T from the packed theta (theta_aa = D_aa)
+      auto P = [&](int a, int b) {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const float t = r[d + lo * d - lo * (lo - 1) / 2 + (hi - lo)];
+        return a == b ? 2.0f * t : t;
+      };
+      if (fb < nfbq) {
+        if (f < np) {
+          int a = 0, rem = f;
+          while (rem >= d - a) {
+            rem -= d - a;
+            ++a;
+          }
+          v = P(a, a + rem);
+        } else if (f < np + d) {
+          const int a = f - np;
+          double h = 0.0;
+          for (int b = 0; b < d; ++b) h -= (double)P(a, b) * (double)r[b];
+          v = (float)h;
+        }
+      } else if ((lane & 15) < d) {
+        v = r[d + np + (lane & 15)];
+      }
+    }
+    dst[(size_t)tile * n + e] = v;
+  }
+}
+
+struct RevArgs {
+  ProbDev<float> p;
+  const float *u_nom;
+  const uint32_t *iter;
+  MfmaModel md;
+  const float4 *P;        // adj_rfold_kernel output
+  const float *trace;     // [S][T+1][NX + 3 NO]
+  float *recs;            // [S][T][D + 5 NO + NU]
+};
+
+template <int DYN>
+__global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
+  using DD = Dims<DYN>;
+  constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
+  using G = Geo<D>;
+  using RG = RevGeo<D>;
+  constexpr int SEGW = NX + 3 * NO, RW = D + 5 * NO + NU;
+  constexpr int NPOS = DYN == kDynPointMass2D ? 2 : 3;
+  constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;
+  constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
+  constexpr int PSTR = RG::NFB * 16;
+  __shared__ MixSmem<D, 1, 4> sm;
+  __shared__ float xbar[16][NX];
+  __shared__ float stt[16][kMaxOut][5];          // mu, var, lse, mubar, vbar
+  __shared__ float part[4][16][PSTR];            // per-wave sums of the second contraction
+  __shared__ float zb[16][D];
+  __shared__ float obs_s[kMaxObs * 3];
+  const ProbDev<float> &p = ra.p;
+  const MfmaModel &md = ra.md;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = threadIdx.x;
+  const int64_t S = (int64_t)p.K * p.Ms, s = (int64_t)blockIdx.x * 16 + row;
+  const bool active = row < 16 && s < S;
+  const uint32_t k = active ? (uint32_t)(s / p.Ms) : 0u, mm = active ? (uint32_t)(s % p.Ms) : 0u;
+  const uint32_t it = *ra.iter;
+  const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it), wd = stream_word(kTagDyn, p.problem_id, it);
+  mix_setup(sm);
+  for (int i = threadIdx.x; i < 3 * p.n_obs; i += 256) obs_s[i] = p.obs[i];
+  if (row < 16) {
+    for (int i = 0; i < NX; ++i) xbar[row][i] = 0.0f;
+    sm.z[row][D] = 1.0f;
+    sm.z[row][D + 1] = 0.0f;
+  }
+  const int t0w = (int)((int64_t)wave * md.n_tiles / 4), t1w = (int)((int64_t)(wave + 1) * md.n_tiles / 4);
+  const float *tr = ra.trace + (active ? s : 0) * (int64_t)(p.T + 1) * SEGW;
+  __syncthreads();
+  for (int t = p.T - 1; t >= 0; --t) {
+    // (1) per sample: cost gradient at x_{t+1}, the draws of step t, z_t and the
+    //     adjoints of the sampled accelerations
+    if (row < 16) {
+      if (active) {
+        float x1[NX], gq[NX], x[NX], u[NU], z[D], eps[4], xi[8];
+        for (int i = 0; i < NX; ++i) x1[i] = tr[(int64_t)(t + 1) * SEGW + i];
+        state_cost_grad<float>(p, obs_s, x1, gq);
+        for (int i = 0; i < NX; ++i) xbar[row][i] += p.dt * gq[i];
+        float ab[NO];
+        for (int o = 0; o < NPOS; ++o) ab[o] = p.dt * xbar[row][NPOS + o];
+        if (DYN == kDynQuad12)
+          for (int o = 0; o < 3; ++o) ab[3 + o] = p.dt * xbar[row][9 + o];
+        normals<float, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)t, eps);
+        if (p.M > 0) normals<float, NO>(p.key0, p.key1, wd, k, mm, (uint32_t)t, xi);
+        for (int i = 0; i < NX; ++i) x[i] = tr[(int64_t)t * SEGW + i];
+        for (int i = 0; i < NU; ++i) u[i] = ra.u_nom[t * NU + i] + p.noise_std[i] * eps[i];
+        lwpr_input<DYN>(x, u, z);
+        for (int i = 0; i < D; ++i) sm.z[row][i] = z[i];
+        for (int o = 0; o < NO; ++o) {
+          const float mu = tr[(int64_t)t * SEGW + NX + 3 * o], v = tr[(int64_t)t * SEGW + NX + 3 * o + 1];
+          stt[row][o][0] = mu;
+          stt[row][o][1] = v;
+          stt[row][o][2] = tr[(int64_t)t * SEGW + NX + 3 * o + 2];
+          stt[row][o][3] = ab[o];
+          stt[row][o][4] = (p.M > 0 && v > 0.f) ? ab[o] * xi[o] / (2.0f * sqrtf(v)) : 0.0f;
+        }
+      } else {
+        for (int i = 0; i < D; ++i) sm.z[row][i] = 0.0f;
+        for (int o = 0; o < NO; ++o) {
+          stt[row][o][0] = 0.f;
+          stt[row][o][1] = 1.f;
+          stt[row][o][2] = 0.f;
+          stt[row][o][3] = 0.f;
+          stt[row][o][4] = 0.f;
+        }
+      }
+    }
+    __syncthreads();
+    build_fragments(sm);
+    __syncthreads();
+    // (2) this wave's model tiles: both contractions
+    f32x4 Z[G::KB4];
+#pragma unroll
+    for (int q = 0; q < G::KB4; ++q) {
+      const float4 v = sm.A[0][q][lane];
+      Z[q] = f32x4{v.x, v.y, v.z, v.w};
+    }
+    f32x4 accq[RG::NFBQ], accy = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int fb = 0; fb < RG::NFBQ; ++fb) accq[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int smp = lane & 15;   // this lane's sample in the swapped contraction
+    int ocur = -1;
+    for (int tile = t0w; tile < t1w; ++tile) {
+      int o = 0;
+#pragma unroll
+      for (int i = 1; i < kMaxOut; ++i) o += (i < md.n_out && md.tile_off[i] <= tile) ? 1 : 0;
+      if (o != ocur) {
+        ocur = o;
+        if ((lane >> 4) == GQS) Z[KQS / 4][KQS % 4] = -stt[smp][o][2] * 1.4426950408889634f;
+        if ((lane >> 4) == GYS) Z[KYS / 4][KYS % 4] = -stt[smp][o][0];
+      }
+      const f32x4 *wsrc = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
+      f32x4 W[G::KB4];
+#pragma unroll
+      for (int q = 0; q < G::KB4; ++q) W[q] = wsrc[q * 64];
+      const f32x4 *psrc = (const f32x4 *)ra.P + (size_t)tile * RG::NFB * 64 + lane;
+      f32x4 P[RG::NFB];
+#pragma unroll
+      for (int fb = 0; fb < RG::NFB; ++fb) P[fb] = psrc[fb * 64];
+      f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
+#pragma unroll
+      for (int kb = 0; kb < G::KQB; ++kb) {
+        if (kb & 1)
+          qb = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kb / 4][kb % 4], Z[kb / 4][kb % 4], qb, 0, 0, 0);
+        else
+          qa = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kb / 4][kb % 4], Z[kb / 4][kb % 4], qa, 0, 0, 0);
+      }
+#pragma unroll
+      for (int kb = G::KQB; kb < G::KB; ++kb)
+        ya = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kb / 4][kb % 4], Z[kb / 4][kb % 4], ya, 0, 0, 0);
+      const float var = stt[smp][o][1], mub = stt[smp][o][3], vb = stt[smp][o][4];
+      float qbar[4], ybar[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float s2 = md.sig2[tile * 16 + 4 * (lane >> 4) + i];
+        const float w = exp2f(qa[i] + qb[i]), e = ya[i];
+        ybar[i] = w * (mub + 2.0f * vb * e);
+        qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
+      }
+#pragma unroll
+      for (int fb = 0; fb < RG::NFBQ; ++fb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) accq[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qbar[i], P[fb][i], accq[fb], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) accy = __builtin_amdgcn_mfma_f32_16x16x4f32(ybar[i], P[RG::NFBQ][i], accy, 0, 0, 0);
+    }
+    // (3) per-wave sums to LDS: acc[fb][j] = sum[sample 4 (lane/16) + j][16 fb + lane%16]
+#pragma unroll
+    for (int fb = 0; fb < RG::NFBQ; ++fb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[wave][4 * (lane >> 4) + j][16 * fb + (lane & 15)] = accq[fb][j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[wave][4 * (lane >> 4) + j][16 * RG::NFBQ + (lane & 15)] = accy[j];
+    __syncthreads();
+    // (4) zbar[s][a] = sum_b M[a][b] z_b + h part + b part (waves added in order)
+    {
+      const int sr = threadIdx.x >> 4, a = threadIdx.x & 15;
+      if (a < D) {
+        float acc = 0.f;
+        for (int b = 0; b < D; ++b) {
+          const int lo = a < b ? a : b, hi = a < b ? b : a;
+          const int pk = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+          const float M = ((part[0][sr][pk] + part[1][sr][pk]) + part[2][sr][pk]) + part[3][sr][pk];
+          acc = fmaf(M, sm.z[sr][b], acc);
+        }
+        const int ih = RG::NP + a, iy = 16 * RG::NFBQ + a;
+        acc += ((part[0][sr][ih] + part[1][sr][ih]) + part[2][sr][ih]) + part[3][sr][ih];
+        acc += ((part[0][sr][iy] + part[1][sr][iy]) + part[2][sr][iy]) + part[3][sr][iy];
+        zb[sr][a] = acc;
+      }
+    }
+    __syncthreads();
+    // (5) per sample: Euler transpose, the record of (s, t)
+    if (active) {
+      float xp[NX];
+      for (int i = 0; i < NX; ++i) xp[i] = xbar[row][i];
+      for (int i = 0; i < NPOS; ++i) xp[NPOS + i] += p.dt * xbar[row][i];
+      if (DYN == kDynQuad12)
+        for (int i = 0; i < 3; ++i) xp[9 + i] += p.dt * xbar[row][6 + i];
+      for (int i = 0; i < NX; ++i) xbar[row][i] = xp[i] + zb[row][i];
+      float *rec = ra.recs + (s * p.T + t) * RW;
+      for (int i = 0; i < D; ++i) rec[i] = sm.z[row][i];
+      for (int o = 0; o < NO; ++o) {
+        rec[D + 5 * o] = stt[row][o][2];
+        rec[D + 5 * o + 1] = stt[row][o][0];
+        rec[D + 5 * o + 2] = stt[row][o][1];
+        rec[D + 5 * o + 3] = stt[row][o][3];
+        rec[D + 5 * o + 4] = stt[row][o][4];
+      }
+      for (int i = 0; i < NU; ++i) rec[D + 5 * NO + i] = zb[row][NX + i];
+    }
+    __syncthreads();
+  }
+}
+
+size_t adj_rfold_bytes(const MfmaLayout &l) {
+  const int np = l.d * (l.d + 1) / 2, nfbq = (np + l.d + 15) / 16;
+  return align_up((size_t)l.n_tiles * (nfbq + 1) * 64 * 4 * sizeof(float), 256);
+}
+
+hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, const uint32_t *iter,
+                                   const ModelArgs &m, const MfmaLayout &l, const void *base, const void *rec,
+                                   int RS, void *rfold, const float *trace, float *recs, hipStream_t s) {
+  const int np = l.d * (l.d + 1) / 2, nfbq = (np + l.d + 15) / 16;
+  hipLaunchKernelGGL(adj_rfold_kernel, dim3(l.n_tiles), dim3(256), 0, s, m, l, (const float *)rec, RS, nfbq,
+                     (float *)rfold);
+  RevArgs ra;
+  ra.p = p;
+  ra.u_nom = u_nom;
+  ra.iter = iter;
+  ra.md = mfma_view(l, base);
+  ra.P = (const float4 *)rfold;
+  ra.trace = trace;
+  ra.recs = recs;
+  const int64_t S = (int64_t)p.K * p.Ms;
+  const dim3 grid((unsigned)((S + 15) / 16));
+  if (p.dyn == kDynQuad12)
+    hipLaunchKernelGGL(adj_reverse_mfma_kernel<kDynQuad12>, grid, dim3(256), 0, s, ra);
+  else if (p.dyn == kDynPointMass2D)
+    hipLaunchKernelGGL(adj_reverse_mfma_kernel<kDynPointMass2D>, grid, dim3(256), 0, s, ra);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 int adj_param_mfma_width(int d) {
   const int nf = d * (d + 1) / 2 + d + 1;
   return ((nf + 15) / 16) * 16 + 1;
