@@ -1028,6 +1028,16 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
     for (int fb = 0; fb < NFB; ++fb) acc[q][fb] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   const float *Af = (const float *)&sm.A[0][0][0];
+  // the wave's model tiles are fixed: W of the first one is requested ahead of
+  // each record tile, the second one's right after the first contraction
+  auto loadW = [&](f32x4 (&Wd)[G::KB4], int q) {
+    const int tq = min(tile[q], md.n_tiles - 1);
+    const f32x4 *src = (const f32x4 *)md.W + (size_t)tq * G::KB4 * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < G::KB4; ++k) Wd[k] = src[k * 64];
+  };
+  f32x4 B[G::KB4];
+  loadW(B, 0);
   for (int64_t rb = r0; rb < r1; rb += 16) {
     const int nr = (int)min((int64_t)16, r1 - rb);
     __syncthreads();  // the previous records' fragments and statistics are no longer read
@@ -1050,6 +1060,19 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
       const float4 v = sm.A[0][q][lane];
       A[q] = f32x4{v.x, v.y, v.z, v.w};
     }
+    // Phi(record 4k + i)[16 fb + lane%16] for the second contraction's B
+    // operand (k = lane/16), read once per record tile from the anchor-free
+    // fragments in LDS
+    float phi[NFB][4];
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) {
+      const int f = 16 * fb + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * (lane >> 4) + i;
+        phi[fb][i] = f < NF ? Af[((f >> 4) * 64 + 16 * (f & 3) + r) * 4 + ((f & 15) >> 2)] : 0.0f;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < kPrmTilesPerWave; ++q) {
       if (tile[q] >= md.n_tiles) continue;   // uniform over the wave
@@ -1057,11 +1080,8 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
       const int row = lane & 15;
       if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = -st[row][o][0] * 1.4426950408889634f;
       if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = -st[row][o][1];
-      f32x4 B[G::KB4];
-      const f32x4 *src = (const f32x4 *)md.W + (size_t)tile[q] * G::KB4 * 64 + lane;
-#pragma unroll
-      for (int k = 0; k < G::KB4; ++k) B[k] = src[k * 64];
       const float s2 = md.sig2[tile[q] * 16 + (lane & 15)];
+      __builtin_amdgcn_sched_barrier(0);
       f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
 #pragma unroll
       for (int kb = 0; kb < G::KQB; ++kb) {
@@ -1073,6 +1093,11 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
       for (int kb = G::KQB; kb < G::KB; ++kb)
         ya = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb / 4][kb % 4], B[kb / 4][kb % 4], ya, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      // the next tile this wave contracts: its second tile, else (next record
+      // tile) its first
+      loadW(B, (q + 1 < kPrmTilesPerWave && tile[q + 1] < md.n_tiles) ? q + 1 : 0);
+      __builtin_amdgcn_sched_barrier(0);
       float qbar[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -1083,18 +1108,12 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
       }
       // G[model][feature] += sum_r qbar[r][model] Phi(z_r)[feature]: instance i
-      // takes records 4k + i at k = lane/16; lane reads Phi of its record and
-      // feature from the (anchor-free) fragments in LDS
+      // takes records 4k + i at k = lane/16
 #pragma unroll
-      for (int fb = 0; fb < NFB; ++fb) {
-        const int f = 16 * fb + (lane & 15);
+      for (int fb = 0; fb < NFB; ++fb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = 4 * (lane >> 4) + i;
-          const float b = f < NF ? Af[((f >> 4) * 64 + 16 * (f & 3) + r) * 4 + ((f & 15) >> 2)] : 0.0f;
-          acc[q][fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qbar[i], b, acc[q][fb], 0, 0, 0);
-        }
-      }
+        for (int i = 0; i < 4; ++i)
+          acc[q][fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qbar[i], phi[fb][i], acc[q][fb], 0, 0, 0);
       // restore the anchor slots for the next tile (they were set for output o)
       if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = 0.0f;
       if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = 0.0f;
@@ -1276,6 +1295,22 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
     for (int fb = 0; fb < RG::NFBQ; ++fb) accq[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int smp = lane & 15;   // this lane's sample in the swapped contraction
     int ocur = -1;
+    // Loads run one stage ahead: the parameters P of a tile are requested
+    // before its first contraction, the next tile's W right after it, so both
+    // arrive while the matrix cores work (indices are clamped, not skipped,
+    // so every wait counts a fixed number of loads).
+    auto loadW = [&](f32x4 (&Wd)[G::KB4], int tile) {
+      const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < G::KB4; ++q) Wd[q] = src[q * 64];
+    };
+    auto loadP = [&](f32x4 (&Pd)[RG::NFB], int tile) {
+      const f32x4 *src = (const f32x4 *)ra.P + (size_t)tile * RG::NFB * 64 + lane;
+#pragma unroll
+      for (int fb = 0; fb < RG::NFB; ++fb) Pd[fb] = src[fb * 64];
+    };
+    f32x4 W[G::KB4], P[RG::NFB];
+    if (t0w < t1w) loadW(W, t0w);
     for (int tile = t0w; tile < t1w; ++tile) {
       int o = 0;
 #pragma unroll
@@ -1285,14 +1320,12 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
         if ((lane >> 4) == GQS) Z[KQS / 4][KQS % 4] = -stt[smp][o][2] * 1.4426950408889634f;
         if ((lane >> 4) == GYS) Z[KYS / 4][KYS % 4] = -stt[smp][o][0];
       }
-      const f32x4 *wsrc = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
-      f32x4 W[G::KB4];
+      const float var = stt[smp][o][1], mub = stt[smp][o][3], vb = stt[smp][o][4];
+      float s2v[4];
 #pragma unroll
-      for (int q = 0; q < G::KB4; ++q) W[q] = wsrc[q * 64];
-      const f32x4 *psrc = (const f32x4 *)ra.P + (size_t)tile * RG::NFB * 64 + lane;
-      f32x4 P[RG::NFB];
-#pragma unroll
-      for (int fb = 0; fb < RG::NFB; ++fb) P[fb] = psrc[fb * 64];
+      for (int i = 0; i < 4; ++i) s2v[i] = md.sig2[tile * 16 + 4 * (lane >> 4) + i];
+      loadP(P, tile);
+      __builtin_amdgcn_sched_barrier(0);
       f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
 #pragma unroll
       for (int kb = 0; kb < G::KQB; ++kb) {
@@ -1304,11 +1337,13 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
 #pragma unroll
       for (int kb = G::KQB; kb < G::KB; ++kb)
         ya = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kb / 4][kb % 4], Z[kb / 4][kb % 4], ya, 0, 0, 0);
-      const float var = stt[smp][o][1], mub = stt[smp][o][3], vb = stt[smp][o][4];
+      __builtin_amdgcn_sched_barrier(0);
+      loadW(W, min(tile + 1, t1w - 1));
+      __builtin_amdgcn_sched_barrier(0);
       float qbar[4], ybar[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float s2 = md.sig2[tile * 16 + 4 * (lane >> 4) + i];
+        const float s2 = s2v[i];
         const float w = exp2f(qa[i] + qb[i]), e = ya[i];
         ybar[i] = w * (mub + 2.0f * vb * e);
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));

@@ -69,6 +69,18 @@ def test_adjoint_fp32_matches_oracle(dyn, M, variant):
         assert nrel(g.cpu().numpy(), o) <= 1e-4
 
 
+def test_adjoint_fp32_odd_tile_count():
+    # 7 model tiles: in the matrix-core parameter pass one wave holds a valid
+    # and an absent tile (its prefetch must return to the valid one)
+    prob, model = _case(DYN_QUAD12, 1, np.float32, K=37, T=13, L=[5, 3, 7, 2, 6, 20])
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    J, gu, gc, gD = pi.rollout_adjoint(dp, dm)
+    oJ, ogu, ogc, ogD = oracle.adjoint(prob, model)
+    assert abs(J.item() - oJ) <= 1e-5 * abs(oJ)
+    for g, o in ((gu, ogu), (gc, ogc), (gD, ogD)):
+        assert nrel(g.cpu().numpy(), o) <= 1e-4
+
+
 def test_adjoint_J_matches_forward_rollout():
     prob, model = _case(DYN_QUAD12, 1, np.float64, K=20, T=9)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
