@@ -75,17 +75,6 @@ struct AdjSmem {
   Real mub[kAS][G::NO], vb[kAS][G::NO];
 };
 
-template <typename Real>
-__device__ __forceinline__ MixStat<Real> shfl_stat(const MixStat<Real> &s, int mask) {
-  MixStat<Real> r;
-  r.m = __shfl_xor(s.m, mask);
-  r.Z = __shfl_xor(s.Z, mask);
-  r.mu = __shfl_xor(s.mu, mask);
-  r.M2 = __shfl_xor(s.M2, mask);
-  r.S2 = __shfl_xor(s.S2, mask);
-  return r;
-}
-
 // Stages models j0 .. j0+nj-1 of the folded records into sm.tile.
 template <typename Real, int DYN>
 __device__ __forceinline__ void stage_tile(AdjSmem<Real, DYN> &sm, const Real *__restrict__ rec, int j0,

@@ -175,10 +175,122 @@ __global__ void __launch_bounds__(128) rollout_direct_kernel(RolloutArgs<Real> r
   }
 }
 
+// Small problems: 16 lanes per sub-rollout split the local models of every
+// output (merged by xor shuffles in a fixed order), 16 sub-rollouts per block;
+// lane 0 of each sub-rollout samples, steps Euler and writes the cost.  The
+// lanes draw the noise of the next 16 steps together (lane l: step t + l), and
+// a model that fits in LDS is staged once, so a step has a single barrier.
+// Sixteen times the threads of the lane-per-sub-rollout kernel, for grids
+// that would otherwise leave most of the chip idle.
+constexpr int kGroupLanes = 16, kGroupRows = 16, kGroupChunk = 16;
+template <typename Real, int DYN>
+__global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(RolloutArgs<Real> ra, ModelArgs m,
+                                                                              const Real *__restrict__ rec) {
+  using DD = DynDims<DYN>;
+  constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
+  constexpr int RS = rec_stride<Real, D>(), TM = tile_models<Real, D>();
+  __shared__ Real tile[TM * RS];
+  __shared__ Real zs[kGroupRows][D];
+  __shared__ Real eps_s[kGroupChunk][kGroupRows][4], xi_s[kGroupChunk][kGroupRows][8];
+  __shared__ Real obs[kMaxObs * 3];
+  const ProbDev<Real> &p = ra.p;
+  for (int i = threadIdx.x; i < 3 * p.n_obs; i += blockDim.x) obs[i] = p.obs[i];
+  const bool resident = m.Ltot <= TM;   // the whole model in LDS for the whole rollout
+  if (resident)
+    for (int i = threadIdx.x; i < m.Ltot * RS; i += blockDim.x) tile[i] = rec[i];
+  const int g = threadIdx.x / kGroupLanes, l = threadIdx.x % kGroupLanes;
+  const int64_t s = (int64_t)blockIdx.x * kGroupRows + g;
+  const bool active = s < (int64_t)p.K * p.Ms;
+  const uint32_t k = active ? (uint32_t)(s / p.Ms) : 0u, mm = active ? (uint32_t)(s % p.Ms) : 0u;
+  const uint32_t it = *ra.iter;
+  const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it);
+  const uint32_t wd = stream_word(kTagDyn, p.problem_id, it);
+  Real x[NX], u[NU];
+#pragma unroll
+  for (int a = 0; a < NX; ++a) x[a] = ra.x0[a];
+  for (int t = 0; t < p.T; ++t) {
+    const int tc = t % kGroupChunk;
+    if (tc == 0) {
+      __syncthreads();   // lane 0 of every row is done with the previous chunk
+      if (active && t + l < p.T) {
+        normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)(t + l), eps_s[l][g]);
+        if (p.M > 0) normals<Real, NO>(p.key0, p.key1, wd, k, mm, (uint32_t)(t + l), xi_s[l][g]);
+      }
+    }
+    if (l == 0) {
+      Real z[D];
+      if (active) {
+#pragma unroll
+        for (int a = 0; a < NU; ++a) u[a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps_s[tc][g][a];
+        lwpr_input<DYN>(x, u, z);
+      } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) z[a] = 0;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) zs[g][a] = z[a];
+    }
+    __syncthreads();
+    Real zz[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) zz[a] = zs[g][a];
+    Real acc[NO];
+    for (int o = 0; o < NO; ++o) {
+      MixStat<Real> st = mix_empty<Real>();
+      for (int j0 = m.L_off[o]; j0 < m.L_off[o + 1]; j0 += TM) {
+        const int nj = min(TM, m.L_off[o + 1] - j0);
+        const Real *base = tile;
+        if (resident) {
+          base = tile + (size_t)j0 * RS;
+        } else {
+          __syncthreads();
+          for (int i = threadIdx.x; i < nj * RS; i += blockDim.x) tile[i] = rec[(size_t)j0 * RS + i];
+          __syncthreads();
+        }
+        for (int jj = l; jj < nj; jj += kGroupLanes) {
+          Real q, y;
+          eval_record<Real, D>(base + jj * RS, zz, q, y);
+          mix_add<false>(st, (Real)-0.5 * q, y, base[jj * RS + RS - 1]);
+        }
+      }
+#pragma unroll
+      for (int msk = 8; msk >= 1; msk >>= 1) st = mix_merge<false>(st, shfl_stat(st, msk));
+      if (l == 0) {   // every lane holds the merged statistics; lane 0 owns the draws
+        Real mu, v;
+        mix_finish(st, &mu, &v);
+        acc[o] = p.M > 0 ? mu + sqrt_(v) * xi_s[tc][g][o] : mu;
+      }
+    }
+    if (l == 0 && active) {
+      Real xn[NX];
+      euler_step<Real>(DYN, p.dt, x, acc, u, xn);
+#pragma unroll
+      for (int a = 0; a < NX; ++a) x[a] = xn[a];
+      ra.cost[s * p.T + t] = p.dt * state_cost<Real>(p, obs, x);
+    }
+  }
+}
+
+template <typename Real>
+static hipError_t rollout_group_t(const RolloutArgs<Real> &ra, const ModelArgs &m, const void *rec,
+                                  hipStream_t s) {
+  const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
+  const dim3 grid((unsigned)((n + kGroupRows - 1) / kGroupRows)), block(kGroupLanes * kGroupRows);
+  if (ra.p.dyn == kDynPointMass2D)
+    hipLaunchKernelGGL((rollout_group_kernel<Real, kDynPointMass2D>), grid, block, 0, s, ra, m, (const Real *)rec);
+  else if (ra.p.dyn == kDynQuadHybrid)
+    hipLaunchKernelGGL((rollout_group_kernel<Real, kDynQuadHybrid>), grid, block, 0, s, ra, m, (const Real *)rec);
+  else
+    hipLaunchKernelGGL((rollout_group_kernel<Real, kDynQuad12>), grid, block, 0, s, ra, m, (const Real *)rec);
+  return hipGetLastError();
+}
+
 template <typename Real>
 static hipError_t rollout_direct_t(const RolloutArgs<Real> &ra, const ModelArgs &m, const void *rec,
                                    hipStream_t s) {
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
+  // fewer sub-rollouts than 32 lanes per compute unit: split the models over lanes
+  if (n < 256 * 32) return rollout_group_t(ra, m, rec, s);
   const unsigned nb = (unsigned)((n + 127) / 128);
   if (ra.p.dyn == kDynPointMass2D) {
     constexpr int D = 6;

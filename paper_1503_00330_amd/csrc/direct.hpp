@@ -69,6 +69,18 @@ __device__ void direct_mixture(const ModelArgs &m, const Real *__restrict__ rec,
   }
 }
 
+// Mixture statistics of the lane `mask` away (xor) in the wave.
+template <typename Real>
+__device__ __forceinline__ MixStat<Real> shfl_stat(const MixStat<Real> &s, int mask) {
+  MixStat<Real> r;
+  r.m = __shfl_xor(s.m, mask);
+  r.Z = __shfl_xor(s.Z, mask);
+  r.mu = __shfl_xor(s.mu, mask);
+  r.M2 = __shfl_xor(s.M2, mask);
+  r.S2 = __shfl_xor(s.S2, mask);
+  return r;
+}
+
 template <int DYN>
 struct DynDims;
 template <>

@@ -242,6 +242,22 @@ def test_hybrid_adjoint_is_refused():
         pi.rollout_adjoint(pi.DeviceProblem(prob), pi.DeviceModel(model))
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_rollout_direct_both_grids(dtype):
+    # the direct kernels: 16 lanes per sub-rollout below 8192 sub-rollouts, one
+    # lane each above; both against the oracle on sampled rollouts
+    for K in (300, 9000):
+        prob, model = synth.tiny_problem(17, dyn=DYN_QUAD12, L=[9, 3, 40, 2, 17, 5], R=3, K=K, T=5,
+                                         M=1, dtype=dtype, n_obs=4, obs_kind=OBS_SMOOTH)
+        dp = pi.DeviceProblem(prob, variant=pi.PI_VARIANT_DIRECT)
+        cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
+        rows = list(range(0, 40)) + list(range(K - 40, K))
+        ref = np.concatenate([oracle.rollout_cost(prob, model, k_range=(0, 40)),
+                              oracle.rollout_cost(prob, model, k_range=(K - 40, K))])
+        tol = 1e-10 if dtype == F64 else 1e-4
+        assert nrel(cost[rows], ref) <= tol
+
+
 def test_rollout_edge_sizes():
     for K, T in ((1, 1), (1, 5), (17, 1)):
         prob, model = synth.tiny_problem(13, dyn=DYN_QUAD12, L=3, R=2, K=K, T=T, M=1, dtype=F32)
