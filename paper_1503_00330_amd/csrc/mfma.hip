@@ -827,9 +827,19 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   flush_costs(tl, p.T - tl);
 }
 
+// Waves per SIMD the rollout kernels are compiled for: the small-model
+// dynamics fit four 4-wave workgroups per compute unit in LDS, so their
+// register budget is held to 128 to keep all four resident; the 12-state
+// quadrotor's fragments need twice that (two waves per SIMD).
+template <int DYN, int MT, int NW>
+constexpr int rollout_waves_per_eu() {
+  return (DYN != kDynQuad12 && MT == 1 && NW == 4) ? 4 : 1;
+}
+
 // One workgroup per tile of `spw` (<= 16*MT) sub-rollouts.
 template <int DYN, int MT, int NW>
-__global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, MT, NW>())))
+rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
                                                                int spw) {
   __shared__ RollSmem<DYN, MT, NW> rs;
   mix_setup(rs.sm);
@@ -842,7 +852,8 @@ __global__ void __launch_bounds__(NW * 64) rollout_mfma_kernel(RolloutArgs<float
 // 16-block group, which the round-robin dispatch places on the same XCD, so
 // their exchange stays inside one L2.  The grid must be resident at once.
 template <int DYN, int NW>
-__global__ void __launch_bounds__(NW * 64) rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, 1, NW>())))
+rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
                                                                int n_groups, uint64_t *__restrict__ xbuf) {
   __shared__ RollSmem<DYN, 1, NW> rs;
   const int blk = blockIdx.x;
