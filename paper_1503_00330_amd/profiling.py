@@ -2,13 +2,16 @@
 
   python -m paper_1503_00330_amd.profiling stats <kernel_stats.csv> [--top N]
       per-kernel call count and mean/min/max duration (``--kernel-trace --stats``)
+  python -m paper_1503_00330_amd.profiling counters <pmc_dir> [<pmc_dir> ...] --kernel NAME
+      mean per dispatch of every counter collected for one kernel (``--pmc``,
+      csv output), over one or more runs
   python -m paper_1503_00330_amd.profiling traffic <fetch_dir> <write_dir>
           --kernel NAME --copy-bytes B
       HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
       run (``--pmc``, csv output), each counter scaled by what it reads for the
       largest ``copyBuffer`` dispatch of the same run, a plain copy of B bytes
 
-Both print ``key: value`` lines (plus a table for ``stats``).  The traffic
+``stats`` and ``counters`` print markdown tables, ``traffic`` ``key: value`` lines.  The traffic
 summary records a digest of the rollout kernel sources, so a reader can tell
 whether the counters still describe the current kernel.
 """
@@ -62,6 +65,18 @@ def _counter(path: str, counter: str) -> Dict[str, List[float]]:
     return vals
 
 
+def counters(dirs: List[str], kernel: str) -> Dict[str, float]:
+    """Mean per dispatch of each counter of `kernel` over the runs in `dirs`."""
+    vals: Dict[str, List[float]] = defaultdict(list)
+    for d in dirs:
+        for r in csv.DictReader(open(_csv(d, "counter_collection.csv"))):
+            if kernel in r["Kernel_Name"]:
+                vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    if not vals:
+        raise ValueError("no dispatches of %r" % kernel)
+    return {k: sum(v) / len(v) for k, v in sorted(vals.items())}
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dict:
     """Bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch) averaged over its dispatches, each scaled by copy_bytes over what
@@ -113,6 +128,9 @@ def main(argv=None):
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("--top", type=int, default=12)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel", required=True)
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -125,6 +143,11 @@ def main(argv=None):
         for r in kernel_stats(args.csv, args.top):
             print("| %s | %d | %.1f | %.1f | %.1f | %.2f |" % (r["name"][:110], r["calls"], r["avg_us"],
                                                              r["min_us"], r["max_us"], r["pct"]))
+    elif args.cmd == "counters":
+        print("| counter | mean per dispatch |")
+        print("|---|---|")
+        for k, v in counters(args.dirs, args.kernel).items():
+            print("| %s | %.4g |" % (k, v))
     else:
         r = traffic(args.fetch_dir, args.write_dir, args.kernel, args.copy_bytes)
         print("kernel: %s" % args.kernel)
