@@ -12,9 +12,14 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpi2rh.so")
 SOURCES = ["capi.hip", "direct.hip", "mfma.hip", "adjoint.hip"]
 ARCH = "gfx950"
-# packed FP32 instructions are disabled: the compiler must not emit v_pk_*_f32
+# Packed FP32 instructions are disabled: the compiler must not emit v_pk_*_f32.
+# MFMA results go to VGPRs rather than AGPRs: the rollout kernels read every
+# accumulator with vector ALU instructions right after its chain, and AGPR
+# accumulators would cost a v_accvgpr_read per value (12 per model tile) on
+# that path.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def hipcc() -> str:

@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(
   constexpr int RS = rec_stride<Real, D>(), TM = tile_models<Real, D>();
   __shared__ Real tile[TM * RS];
   __shared__ Real zs[kGroupRows][D];
-  __shared__ Real eps_s[kGroupChunk][kGroupRows][4], xi_s[kGroupChunk][kGroupRows][8];
+  // applied controls u_nom + sigma eps and next-state draws of the chunk's steps
+  __shared__ Real us_s[kGroupChunk][kGroupRows][4], xi_s[kGroupChunk][kGroupRows][8];
   __shared__ Real obs[kMaxObs * 3];
   const ProbDev<Real> &p = ra.p;
   for (int i = threadIdx.x; i < 3 * p.n_obs; i += blockDim.x) obs[i] = p.obs[i];
@@ -213,7 +214,10 @@ __global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(
     if (tc == 0) {
       __syncthreads();   // lane 0 of every row is done with the previous chunk
       if (active && t + l < p.T) {
-        normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)(t + l), eps_s[l][g]);
+        Real e[NU];
+        normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)(t + l), e);
+#pragma unroll
+        for (int a = 0; a < NU; ++a) us_s[l][g][a] = ra.u_nom[(t + l) * NU + a] + p.noise_std[a] * e[a];
         if (p.M > 0) normals<Real, NO>(p.key0, p.key1, wd, k, mm, (uint32_t)(t + l), xi_s[l][g]);
       }
     }
@@ -221,7 +225,7 @@ __global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(
       Real z[D];
       if (active) {
 #pragma unroll
-        for (int a = 0; a < NU; ++a) u[a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps_s[tc][g][a];
+        for (int a = 0; a < NU; ++a) u[a] = us_s[tc][g][a];
         lwpr_input<DYN>(x, u, z);
       } else {
 #pragma unroll

@@ -679,17 +679,18 @@ struct RollSmem {
   static constexpr int ROWS = 16 * MT;
   MixSmem<Dims<DYN>::D, MT, NW> sm;
   float xs[ROWS][Dims<DYN>::NX];
-  float eps_s[kNoiseChunk][ROWS][4];
+  float us_s[kNoiseChunk][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
   float xi_s[kNoiseChunk][ROWS][8];
   float xc[kNoiseChunk][ROWS][Dims<DYN>::NX];   // x_{t+1} of the chunk's steps, for the costs
   float obs_s[kMaxObs * 3];
 };
 
 // Rollouts s_base .. s_base + spw - 1 of one problem for its whole horizon.
-// Every kNoiseChunk steps all lanes draw the chunk's eps and xi into LDS and
-// evaluate the previous chunk's step costs dt*q(x_{t+1}) from the states kept
-// in LDS (the cost feeds nothing on the path, so it leaves the per-step
-// critical section).  Per step: rows form z, the waves run the model tiles,
+// Every kNoiseChunk steps all lanes draw the chunk's eps and xi, store the
+// applied controls u_nom + sigma eps in LDS (no global read is left on the
+// per-step critical section) and evaluate the previous chunk's step costs
+// dt*q(x_{t+1}) from the states kept in LDS (the cost feeds nothing on the
+// path, so it leaves the per-step critical section too).  Per step: rows form z, the waves run the model tiles,
 // partial sums are merged, and each row samples its accelerations and steps
 // Euler.  Block-synchronous; rs.sm must have been set up.  With a pair
 // context (pc->half = 0 or 1) the workgroup runs its half of the model tiles,
@@ -752,7 +753,11 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
         if (!act) continue;
         const uint32_t kk = (uint32_t)(ss / p.Ms), mm = (uint32_t)(ss % p.Ms);
         if (blk == 0) {
-          normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), &rs.eps_s[cc][rr][0]);
+          float e4[4];
+          normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), e4);
+#pragma unroll
+          for (int a = 0; a < NU; ++a)
+            rs.us_s[cc][rr][a] = u_nom[(t + cc) * NU + a] + p.noise_std[a] * e4[a];
         } else if (p.M > 0) {
           // counter block blk-1 of the sub-rollout's draw: normals 4(blk-1) .. 4(blk-1)+3
           const Philox4 r4 = philox4x32_10((uint32_t)(t + cc), kk, (mm << 4) | (uint32_t)(blk - 1), wd,
@@ -771,10 +776,10 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       }
       __syncthreads();
     }
-    // the applied controls u_nom + eps of the row at step t
+    // the applied controls of the row at step t
     auto applied = [&](float (&u)[NU]) {
 #pragma unroll
-      for (int a = 0; a < NU; ++a) u[a] = u_nom[t * NU + a] + p.noise_std[a] * rs.eps_s[tc][row][a];
+      for (int a = 0; a < NU; ++a) u[a] = rs.us_s[tc][row][a];
     };
     if (row < ROWS) {
       if (active) {

@@ -26,11 +26,12 @@ from collections import defaultdict
 from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/mfma.hip", "csrc/common.hpp", "csrc/internal.hpp")
+KERNEL_SOURCES = ("csrc/mfma.hip", "csrc/common.hpp", "csrc/internal.hpp", "build.py")
 
 
 def source_digest() -> str:
-    """sha256 over the sources the matrix-core rollout kernels are built from."""
+    """sha256 over the sources the matrix-core rollout kernels are built from
+    and the build script that holds their compiler flags."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
