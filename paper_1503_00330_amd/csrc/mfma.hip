@@ -52,6 +52,8 @@ struct Geo {
 constexpr double kAlpha = -0.72134752044448170368;
 constexpr float kPadAct = -1.0e30f;
 constexpr float kAnchorLo = -100.0f;
+// Word 3 of a raw (untyped) buffer descriptor: 32-bit data format, no swizzle.
+constexpr int kBufferWord3 = 0x00020000;
 
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
@@ -278,7 +280,11 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t0 = T0 + (int)((int64_t)wave * (T1 - T0) / NW), t1 = T0 + (int)((int64_t)(wave + 1) * (T1 - T0) / NW);
+  // the wave's tile range is uniform across its lanes: held in scalar
+  // registers, the tile loop's control and the model addresses stay off the
+  // vector ALU
+  const int t0 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)wave * (T1 - T0) / NW));
+  const int t1 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)(wave + 1) * (T1 - T0) / NW));
   if (t0 >= t1) return;
   f32x4 A[MT][G::KB4];
 #pragma unroll
@@ -347,11 +353,31 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   // load would make the wait drain the prefetch too).
   f32x4 B0[G::KB4], B1[G::KB4];
   float s2_0, s2_1;
+  // Tile loads (large feature sets) through buffer descriptors bounded by the
+  // model's size: the tile's offset is a scalar, the lane's a fixed register,
+  // so no vector instruction goes into addressing (and a read past the end
+  // returns 0).
+  constexpr int kTileBytes = G::KB4 * 64 * 16;
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)md.W, (short)0, md.n_tiles * kTileBytes, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t srs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)md.sig2, (short)0, md.n_tiles * 16 * 4, kBufferWord3);
+  const int lane_off = lane * 16, col_off = (lane & 15) * 4;
   auto load_tile = [&](f32x4 (&Bd)[G::KB4], float &s2d, int tile) {
-    const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
+    if constexpr (G::KB4 >= 4) {
+      const int base = tile * kTileBytes;
 #pragma unroll
-    for (int q = 0; q < G::KB4; ++q) Bd[q] = src[q * 64];
-    s2d = md.sig2[tile * 16 + (lane & 15)];
+      for (int q = 0; q < G::KB4; ++q)
+        Bd[q] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, lane_off, base + q * 1024, 0));
+      s2d = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srs, col_off, tile * 64, 0));
+    } else {
+      // small feature sets (two or three fragments per lane) measured faster
+      // with plain global loads
+      const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < G::KB4; ++q) Bd[q] = src[q * 64];
+      s2d = md.sig2[tile * 16 + (lane & 15)];
+    }
   };
   auto compute_tile = [&](const f32x4 (&Bc)[G::KB4], float s2, int tile) {
     if (tile >= nb) {
@@ -885,7 +911,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedP
     __syncthreads();
     if (threadIdx.x == 0) item_s = atomicAdd(queue, 1);
     __syncthreads();
-    const int item = item_s;
+    const int item = __builtin_amdgcn_readfirstlane(item_s);   // uniform: the item's descriptors stay scalar
     if (item >= n_items) break;
     const BatchedItem it = items[item];
     const BatchedProblem &bp = probs[it.b];
