@@ -55,6 +55,19 @@ constexpr float kAnchorLo = -100.0f;
 // Word 3 of a raw (untyped) buffer descriptor: 32-bit data format, no swizzle.
 constexpr int kBufferWord3 = 0x00020000;
 
+// Model-tile reads through buffer descriptors bounded by the array's size: the
+// tile's offset is a scalar and the lane's a fixed register, so no vector
+// instruction goes into addressing, and a read past the end returns 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, bytes, kBufferWord3);
+}
+__device__ __forceinline__ f32x4 buffer_f32x4(__amdgpu_buffer_rsrc_t r, int lane_off, int tile_off) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, tile_off, 0));
+}
+__device__ __forceinline__ float buffer_f32(__amdgpu_buffer_rsrc_t r, int lane_off, int tile_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, tile_off, 0));
+}
+
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
 // in double the derived vectors (h = -(D + D^T) c, kappa = c^T D c, the folded
@@ -353,23 +366,17 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   // load would make the wait drain the prefetch too).
   f32x4 B0[G::KB4], B1[G::KB4];
   float s2_0, s2_1;
-  // Tile loads (large feature sets) through buffer descriptors bounded by the
-  // model's size: the tile's offset is a scalar, the lane's a fixed register,
-  // so no vector instruction goes into addressing (and a read past the end
-  // returns 0).
+  // Tile loads of the large feature set through buffer descriptors.
   constexpr int kTileBytes = G::KB4 * 64 * 16;
-  const __amdgpu_buffer_rsrc_t wrs =
-      __builtin_amdgcn_make_buffer_rsrc((void *)md.W, (short)0, md.n_tiles * kTileBytes, kBufferWord3);
-  const __amdgpu_buffer_rsrc_t srs =
-      __builtin_amdgcn_make_buffer_rsrc((void *)md.sig2, (short)0, md.n_tiles * 16 * 4, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.W, md.n_tiles * kTileBytes);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
   const int lane_off = lane * 16, col_off = (lane & 15) * 4;
   auto load_tile = [&](f32x4 (&Bd)[G::KB4], float &s2d, int tile) {
     if constexpr (G::KB4 >= 4) {
       const int base = tile * kTileBytes;
 #pragma unroll
-      for (int q = 0; q < G::KB4; ++q)
-        Bd[q] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, lane_off, base + q * 1024, 0));
-      s2d = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srs, col_off, tile * 64, 0));
+      for (int q = 0; q < G::KB4; ++q) Bd[q] = buffer_f32x4(wrs, lane_off, base + q * 1024);
+      s2d = buffer_f32(srs, col_off, tile * 64);
     } else {
       // small feature sets (two or three fragments per lane) measured faster
       // with plain global loads
@@ -1044,7 +1051,8 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   __shared__ MixSmem<D, 1, 4> sm;
   __shared__ float st[16][kMaxOut][5];        // lse, mu, var, mubar, vbar per record and output
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is uniform: its tiles' indices and offsets stay scalar
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ch = blockIdx.y;
   const int64_t r0 = R * ch / nch, r1 = R * (ch + 1) / nch;
   const int n_out = md.n_out;
@@ -1072,11 +1080,12 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
   const float *Af = (const float *)&sm.A[0][0][0];
   // the wave's model tiles are fixed: W of the first one is requested ahead of
   // each record tile, the second one's right after the first contraction
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.W, md.n_tiles * G::KB4 * 1024);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
   auto loadW = [&](f32x4 (&Wd)[G::KB4], int q) {
     const int tq = min(tile[q], md.n_tiles - 1);
-    const f32x4 *src = (const f32x4 *)md.W + (size_t)tq * G::KB4 * 64 + lane;
 #pragma unroll
-    for (int k = 0; k < G::KB4; ++k) Wd[k] = src[k * 64];
+    for (int k = 0; k < G::KB4; ++k) Wd[k] = buffer_f32x4(wrs, lane * 16, (tq * G::KB4 + k) * 1024);
   };
   f32x4 B[G::KB4];
   loadW(B, 0);
@@ -1122,7 +1131,7 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
       const int row = lane & 15;
       if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = -st[row][o][0] * 1.4426950408889634f;
       if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = -st[row][o][1];
-      const float s2 = md.sig2[tile[q] * 16 + (lane & 15)];
+      const float s2 = buffer_f32(srs, (lane & 15) * 4, tile[q] * 64);
       __builtin_amdgcn_sched_barrier(0);
       f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
 #pragma unroll
@@ -1268,7 +1277,8 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
   __shared__ float obs_s[kMaxObs * 3];
   const ProbDev<float> &p = ra.p;
   const MfmaModel &md = ra.md;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = threadIdx.x;
+  // the wave index is uniform: its tile range and offsets stay scalar
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), row = threadIdx.x;
   const int64_t S = (int64_t)p.K * p.Ms, s = (int64_t)blockIdx.x * 16 + row;
   const bool active = row < 16 && s < S;
   const uint32_t k = active ? (uint32_t)(s / p.Ms) : 0u, mm = active ? (uint32_t)(s % p.Ms) : 0u;
@@ -1341,15 +1351,16 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
     // before its first contraction, the next tile's W right after it, so both
     // arrive while the matrix cores work (indices are clamped, not skipped,
     // so every wait counts a fixed number of loads).
+    const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.W, md.n_tiles * G::KB4 * 1024);
+    const __amdgpu_buffer_rsrc_t prs = buffer_rsrc(ra.P, md.n_tiles * RG::NFB * 1024);
+    const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
     auto loadW = [&](f32x4 (&Wd)[G::KB4], int tile) {
-      const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
 #pragma unroll
-      for (int q = 0; q < G::KB4; ++q) Wd[q] = src[q * 64];
+      for (int q = 0; q < G::KB4; ++q) Wd[q] = buffer_f32x4(wrs, lane * 16, (tile * G::KB4 + q) * 1024);
     };
     auto loadP = [&](f32x4 (&Pd)[RG::NFB], int tile) {
-      const f32x4 *src = (const f32x4 *)ra.P + (size_t)tile * RG::NFB * 64 + lane;
 #pragma unroll
-      for (int fb = 0; fb < RG::NFB; ++fb) Pd[fb] = src[fb * 64];
+      for (int fb = 0; fb < RG::NFB; ++fb) Pd[fb] = buffer_f32x4(prs, lane * 16, (tile * RG::NFB + fb) * 1024);
     };
     f32x4 W[G::KB4], P[RG::NFB];
     if (t0w < t1w) loadW(W, t0w);
@@ -1363,9 +1374,8 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
         if ((lane >> 4) == GYS) Z[KYS / 4][KYS % 4] = -stt[smp][o][0];
       }
       const float var = stt[smp][o][1], mub = stt[smp][o][3], vb = stt[smp][o][4];
-      float s2v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s2v[i] = md.sig2[tile * 16 + 4 * (lane >> 4) + i];
+      // sigma^2 of the lane's four models 4 (lane/16) + i, one 16-byte read
+      const f32x4 s2v = buffer_f32x4(srs, 16 * (lane >> 4), tile * 64);
       loadP(P, tile);
       __builtin_amdgcn_sched_barrier(0);
       f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
