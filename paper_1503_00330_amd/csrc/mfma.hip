@@ -4,9 +4,11 @@
 // Phi(z) = [z_a z_b (a <= b), z, 1] the activation of model j is
 //   alpha * q_j = Phi(z) . w_j,   w_j = alpha [theta_j, -(D_j + D_j^T) c_j, c_j^T D_j c_j],
 // alpha = -log2(e)/2, and the local prediction is y_j = [z, 1] . [b_j, beta0_j - b_j.c_j].
-// A workgroup owns 16*MT samples (rows of the A operand, staged in LDS as
-// lane-major fragments); its NW waves split the model tiles (16 models = the
-// columns of one B operand, streamed from L2 as 1 KB coalesced loads).
+// A workgroup owns 16*MT samples (staged in LDS as lane-major fragments); its
+// NW waves split the model tiles (16 models, streamed from L2 as 1 KB
+// coalesced loads).  In the rollout contraction the model tile is the A
+// operand and the samples' features the B operand (both have the same
+// register layout), so each lane ends with four models of one sample.
 //
 // Anchored accumulation.  Every (sample, output) carries an anchor m (an
 // activation close to the largest one) and a reference mean r, both taken
@@ -19,8 +21,9 @@
 // the spread term is non-negative in exact arithmetic, and the clamp keeps its
 // rounding (FP32 cancellation when the models' predictions differ widely) from
 // turning the variance negative.
-// Partial sums merge across lanes (DPP row rotations) and waves (LDS) as
-// plain sums in a fixed order.  The sums are exact up to rounding whatever
+// Partial sums merge within a lane (its four models), across the four lane
+// groups (two cross-lane shuffles) and across waves (LDS) as plain sums in a
+// fixed order.  The sums are exact up to rounding whatever
 // the anchor, as long as none of them overflowed and the largest term kept
 // full precision; so the step is evaluated again, with the anchor moved to the
 // observed maximum, only if a sum is not finite or the largest shifted
@@ -187,25 +190,6 @@ static MfmaModel mfma_view(const MfmaLayout &l, const void *base) {
 }
 
 // ------------------------------------------------------ shared mixture
-// DPP row rotation (16-lane rows): v + v[lane +- n within the row].
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float row_sum16(float v) {
-  v += dpp_f<0x128>(v);  // row_ror:8
-  v += dpp_f<0x124>(v);  // row_ror:4
-  v += dpp_f<0x122>(v);  // row_ror:2
-  v += dpp_f<0x121>(v);  // row_ror:1
-  return v;
-}
-__device__ __forceinline__ float row_max16(float v) {
-  v = fmaxf(v, dpp_f<0x128>(v));
-  v = fmaxf(v, dpp_f<0x124>(v));
-  v = fmaxf(v, dpp_f<0x122>(v));
-  v = fmaxf(v, dpp_f<0x121>(v));
-  return v;
-}
 
 // Partial sums of one (sample, output) over a subset of local models.
 struct Acc {
@@ -213,6 +197,9 @@ struct Acc {
 };
 
 __device__ __forceinline__ Acc acc_empty() { return Acc{0.f, 0.f, 0.f, 0.f, -3.0e38f}; }
+__device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
+  return Acc{a.Z + b.Z, a.S1 + b.S1, a.S2 + b.S2, a.S3 + b.S3, fmaxf(a.mx, b.mx)};
+}
 
 template <int D, int MT, int NW>
 struct MixSmem {
@@ -286,7 +273,9 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
 }
 
 // Stage 2 (each wave): its contiguous range of model tiles, one MFMA chain per
-// tile; partial sums flushed per output into sm.part[wave][o][row].
+// tile with the model tile as the A operand: lane l holds models 4(l/16) + i
+// (i < 4) of sample l%16.  Partial sums are flushed per output into
+// sm.part[wave][o][row].
 template <int D, int MT, int NW>
 __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW> &sm, int T0, int T1) {
   using G = Geo<D>;
@@ -337,56 +326,62 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
     }
   };
   set_anchor(o);
+  // st[mt][i]: sums over this lane's model 4(lane/16) + i of every tile so
+  // far, for sample 16 mt + lane%16
   Acc st[MT][4];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) st[mt][r] = acc_empty();
+    for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
 
+  // the four models of the lane, then the four lane groups holding the same
+  // sample (lanes l, l^16, l^32, l^48); every lane ends with the same sums
   auto flush = [&](int oo) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+      Acc s = acc_sum(acc_sum(st[mt][0], st[mt][1]), acc_sum(st[mt][2], st[mt][3]));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        Acc s;
-        s.Z = row_sum16(st[mt][r].Z);
-        s.S1 = row_sum16(st[mt][r].S1);
-        s.S2 = row_sum16(st[mt][r].S2);
-        s.S3 = row_sum16(st[mt][r].S3);
-        s.mx = row_max16(st[mt][r].mx);
-        if ((lane & 15) == 0) sm.part[wave][oo][16 * mt + 4 * (lane >> 4) + r] = s;
-        st[mt][r] = acc_empty();
+      for (int m = 16; m <= 32; m <<= 1) {
+        s.Z += __shfl_xor(s.Z, m);
+        s.S1 += __shfl_xor(s.S1, m);
+        s.S2 += __shfl_xor(s.S2, m);
+        s.S3 += __shfl_xor(s.S3, m);
+        s.mx = fmaxf(s.mx, __shfl_xor(s.mx, m));
       }
+      if (lane < 16) sm.part[wave][oo][16 * mt + lane] = s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
+    }
   };
 
-  // Software pipeline over tiles with two B buffers: the loads of tile i+1
-  // are issued before the MFMA chain of tile i, and scheduling barriers keep
-  // the compiler from sinking them next to their use.  sigma^2 of the lane's
-  // model column travels with its tile (loads complete in order, so a later
-  // load would make the wait drain the prefetch too).
+  // Software pipeline over tiles with two buffers: the loads of tile i+1 are
+  // issued before the MFMA chain of tile i, and scheduling barriers keep the
+  // compiler from sinking them next to their use.  sigma^2 of the lane's four
+  // models travels with its tile (loads complete in order, so a later load
+  // would make the wait drain the prefetch too).
   f32x4 B0[G::KB4], B1[G::KB4];
-  float s2_0, s2_1;
+  f32x4 s2_0, s2_1;
   // Tile loads of the large feature set through buffer descriptors.
   constexpr int kTileBytes = G::KB4 * 64 * 16;
   const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.W, md.n_tiles * kTileBytes);
   const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
-  const int lane_off = lane * 16, col_off = (lane & 15) * 4;
-  auto load_tile = [&](f32x4 (&Bd)[G::KB4], float &s2d, int tile) {
+  const int lane_off = lane * 16, grp_off = 16 * (lane >> 4);
+  auto load_tile = [&](f32x4 (&Bd)[G::KB4], f32x4 &s2d, int tile) {
     if constexpr (G::KB4 >= 4) {
       const int base = tile * kTileBytes;
 #pragma unroll
       for (int q = 0; q < G::KB4; ++q) Bd[q] = buffer_f32x4(wrs, lane_off, base + q * 1024);
-      s2d = buffer_f32(srs, col_off, tile * 64);
+      s2d = buffer_f32x4(srs, grp_off, tile * 64);
     } else {
       // small feature sets (two or three fragments per lane) measured faster
       // with plain global loads
       const f32x4 *src = (const f32x4 *)md.W + (size_t)tile * G::KB4 * 64 + lane;
 #pragma unroll
       for (int q = 0; q < G::KB4; ++q) Bd[q] = src[q * 64];
-      s2d = md.sig2[tile * 16 + (lane & 15)];
+      s2d = *(const f32x4 *)(md.sig2 + tile * 16 + 4 * (lane >> 4));
     }
   };
-  auto compute_tile = [&](const f32x4 (&Bc)[G::KB4], float s2, int tile) {
+  auto compute_tile = [&](const f32x4 (&Bc)[G::KB4], const f32x4 &s2, int tile) {
     if (tile >= nb) {
       flush(o);
       o = output_of(tile);
@@ -400,38 +395,39 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
       qb[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       ya[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // two interleaved accumulators per row tile shorten the dependency chain
+    // two interleaved accumulators per row tile shorten the dependency chain;
+    // the model tile is the A operand, the samples' fragments the B operand
 #pragma unroll
     for (int kb = 0; kb < G::KQB; ++kb)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         if (kb & 1)
-          qb[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
+          qb[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Bc[kb / 4][kb % 4], A[mt][kb / 4][kb % 4],
                                                         qb[mt], 0, 0, 0);
         else
-          qa[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
+          qa[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Bc[kb / 4][kb % 4], A[mt][kb / 4][kb % 4],
                                                         qa[mt], 0, 0, 0);
       }
 #pragma unroll
     for (int kb = G::KQB; kb < G::KB; ++kb)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        ya[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][kb / 4][kb % 4], Bc[kb / 4][kb % 4],
+        ya[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Bc[kb / 4][kb % 4], A[mt][kb / 4][kb % 4],
                                                       ya[mt], 0, 0, 0);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float a = qa[mt][r] + qb[mt][r], dd = ya[mt][r];
+      for (int i = 0; i < 4; ++i) {
+        const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i];
         // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
         // largest term of at least 2^-100) need none of exp2f's denormal scaling
         const float e = __builtin_amdgcn_exp2f(a);
         const float te = e * dd;
-        st[mt][r].Z += e;
-        st[mt][r].S1 += te;
-        st[mt][r].S2 = fmaf(te, dd, st[mt][r].S2);
-        st[mt][r].S3 = fmaf(e, s2, st[mt][r].S3);
-        st[mt][r].mx = fmaxf(st[mt][r].mx, a);
+        st[mt][i].Z += e;
+        st[mt][i].S1 += te;
+        st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+        st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+        st[mt][i].mx = fmaxf(st[mt][i].mx, a);
       }
   };
 
@@ -484,9 +480,6 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int
   if (isfinite(mu)) sm.yref[row][o] = mu;
 }
 
-__device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
-  return Acc{a.Z + b.Z, a.S1 + b.S1, a.S2 + b.S2, a.S3 + b.S3, fmaxf(a.mx, b.mx)};
-}
 
 template <int D, int MT, int NW>
 __device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW> &sm, int row, int o) {
