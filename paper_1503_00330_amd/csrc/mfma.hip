@@ -58,9 +58,11 @@ constexpr float kAnchorLo = -100.0f;
 // Word 3 of a raw (untyped) buffer descriptor: 32-bit data format, no swizzle.
 constexpr int kBufferWord3 = 0x00020000;
 
-// Model-tile reads through buffer descriptors bounded by the array's size: the
-// tile's offset is a scalar and the lane's a fixed register, so no vector
-// instruction goes into addressing, and a read past the end returns 0.
+// Model-tile reads through buffer descriptors over the whole array: the tile's
+// offset is a scalar and the lane's a fixed register, so no vector
+// instruction goes into addressing.  The hardware range check covers only the
+// lane's offset, so callers keep tile indices in range themselves (the
+// prefetches clamp them).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, bytes, kBufferWord3);
 }
