@@ -263,11 +263,22 @@ template <int D, int MT, int NW>
 __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
   using G = Geo<D>;
   float *Af = (float *)&sm.A[0][0][0];
-  for (int e = threadIdx.x; e < MT * G::NE; e += NW * 64) {
-    const int mt = e / G::NE, el = e - mt * G::NE;
-    const int row = 16 * mt + ((el >> 2) & 15);
-    const unsigned src = sm.fsrc[el];
-    Af[e] = sm.z[row][src >> 8] * sm.z[row][src & 0xFF];
+  // fixed trip count, fully unrolled: every thread's reads go out together
+  // (a rolled loop waits for two dependent LDS round trips per element)
+  constexpr int NIT = (MT * G::NE + NW * 64 - 1) / (NW * 64);
+  unsigned src[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = threadIdx.x + it * NW * 64;
+    src[it] = e < MT * G::NE ? sm.fsrc[e % G::NE] : 0u;
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = threadIdx.x + it * NW * 64;
+    if (e < MT * G::NE) {
+      const int row = 16 * (e / G::NE) + (((e % G::NE) >> 2) & 15);
+      Af[e] = sm.z[row][src[it] >> 8] * sm.z[row][src[it] & 0xFF];
+    }
   }
   Acc *pp = &sm.part[0][0][0];
   for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW>::ROWS; i += NW * 64)
