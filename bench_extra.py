@@ -126,9 +126,10 @@ def w_batched(args):
     ts = timed(seq, args.steps or 3, stream)
     flop = sum(flops_per_sample_step(m) * p.K * p.T for p, m in batch)
     ss = sum(p.K * p.T for p, _ in batch)
-    # the persistent form runs one workgroup per tile: bitwise equal to plain
-    # launches of that form (the timed plain launches may pair workgroups)
-    one = [pi.DeviceProblem(p, tile_samples=args.tile_samples, tile_split=1) for p, _ in batch]
+    # the persistent form runs one 4-wave workgroup per tile: bitwise equal to
+    # plain launches of that form (the timed plain launches may pair
+    # workgroups or run 8 waves)
+    one = [pi.DeviceProblem(p, tile_samples=args.tile_samples, tile_split=1, tile_waves=4) for p, _ in batch]
     same = all(torch.equal(a, pi.rollout_cost(d, m)) for a, d, m in zip(br.costs, one, dms))
     return {"workload": "64 quadrotor problems, K in 512..16384, L in 64..1024 per output, "
                         "T in 50..200, 10..40 obstacles",

@@ -118,7 +118,11 @@ typedef struct {
   uint64_t seed;                   /* Philox key                             */
   int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
   int32_t tile_samples;            /* samples per workgroup, <= 32 (0 = library's choice) */
-  int32_t tile_waves;              /* waves per workgroup, 4 or 8 (0 = library's choice) */
+  int32_t tile_waves;              /* waves per workgroup, 4 or 8 (8: 12-state
+                                    * quadrotor only); 0 = library's choice:
+                                    * 8 for the quadrotor when the launch has
+                                    * at most one workgroup per compute unit,
+                                    * else 4                                  */
   int32_t tile_split;              /* workgroups per tile of 16 samples: 1 (one
                                     * workgroup runs every local model) or 2 (a
                                     * pair of workgroups, on two compute units,

@@ -214,14 +214,23 @@ RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   return r;
 }
 
+// Compute units of the current device (0 if the query fails).
+int device_cus(int *dev_out = nullptr) {
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (dev_out) *dev_out = dev;
+  return n_cu;
+}
+
 // Pairing at launch: requested (tile_split 2) or, by default, when the tiles
 // leave compute units idle; in both cases only if the whole grid is resident.
 bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
   if (!pl.pair_ok) return false;
-  int dev = 0, n_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return false;
+  int dev = 0;
+  const int n_cu = device_cus(&dev);
+  if (n_cu == 0) return false;
   static std::mutex mu;
   static int per_cu[kMaxDevices][4];  // resident pair workgroups per compute unit, +1 (0 = unknown)
   if (dev < 0 || dev >= kMaxDevices) return false;
@@ -235,6 +244,33 @@ bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
   const bool resident = (int64_t)pair_grid(pl.groups) <= (int64_t)cap * n_cu;
   if (!resident) return false;
   return p->tile_split == 2 || pl.groups < n_cu;
+}
+
+// The rollout launch on the current device: the plan, whether its tiles are
+// paired, and the waves per workgroup when the caller leaves them to the
+// library.  With at most one workgroup per compute unit, eight waves (two per
+// SIMD) keep the matrix cores busier than four; once workgroups share a unit
+// they already do, and four waves are faster (12-state quadrotor, 16-row
+// tiles; the other families have 4-wave kernels only).
+struct RolloutLaunch {
+  RolloutPlan pl;
+  bool pair;
+};
+
+RolloutLaunch rollout_launch(const pi_problem *p, const pi_lwpr *m) {
+  RolloutLaunch r{rollout_plan(p, m), false};
+  r.pair = use_pair(p, r.pl);
+  if (p->tile_waves == 0 && r.pl.mfma && p->dyn == PI_DYN_QUAD12 && r.pl.spw <= 16) {
+    const int n_cu = device_cus();
+    const int64_t wgs = r.pair ? 2 * r.pl.groups : r.pl.groups;
+    if (n_cu > 0 && wgs <= n_cu) {
+      RolloutPlan p8 = r.pl;
+      p8.waves = 8;
+      // a pair keeps four waves if its 8-wave grid would not be resident
+      if (!r.pair || use_pair(p, p8)) r.pl = p8;
+    }
+  }
+  return r;
 }
 
 // Layout of a pi_model_fold buffer: direct records, then (float32, d in
@@ -396,13 +432,15 @@ pi_status pi_model_fold(const pi_lwpr *m, void *folded, size_t folded_bytes, voi
 pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out) {
   PI_TRY(check_pair(p, m));
   if (!out) return fail(PI_ERR_NULL, "out must be non-NULL");
-  const RolloutPlan pl = rollout_plan(p, m);
-  if (pl.mfma && !mfma_ok(p->dtype, m->d)) return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  if (rollout_plan(p, m).mfma && !mfma_ok(p->dtype, m->d))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
   PI_TRY(check_device());
+  const RolloutLaunch rl = rollout_launch(p, m);
+  const RolloutPlan &pl = rl.pl;
   out[0] = pl.mfma ? PI_VARIANT_MFMA : PI_VARIANT_DIRECT;
   out[1] = pl.mfma ? pl.spw : 1;
   out[2] = pl.mfma ? pl.waves : 1;
-  out[3] = use_pair(p, pl) ? 2 : 1;
+  out[3] = rl.pair ? 2 : 1;
   return ok();
 }
 
@@ -480,10 +518,11 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
       RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
       if (pl.mfma) {
         const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
-        if (use_pair(p, pl))
-          e = launch_rollout_pair(ra, l, base, pl.spw, pl.waves, (char *)ws + fb + sub_bytes(p), s);
+        const RolloutLaunch rl = rollout_launch(p, m);
+        if (rl.pair)
+          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, (char *)ws + fb + sub_bytes(p), s);
         else
-          e = launch_rollout_mfma(ra, a, l, base, pl.spw, pl.waves, s);
+          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, s);
       } else {
         e = launch_rollout_direct(PI_F32, &ra, a, base, s);
       }

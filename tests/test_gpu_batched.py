@@ -32,8 +32,10 @@ def _batch(spw=0, waves=0):
         prob.problem_id = b
         out.append((prob, model))
     # plain launches of the same problems keep one workgroup per tile (a pair of
-    # workgroups sums the model halves in another order)
-    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves, tile_split=1) for p, _ in out]
+    # workgroups sums the model halves in another order) and the persistent
+    # launch's waves per workgroup (4 unless given; the waves' partial sums are
+    # added in order, so another wave count groups them differently)
+    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves or 4, tile_split=1) for p, _ in out]
     dms = [pi.DeviceModel(m) for _, m in out]
     return out, dps, dms
 

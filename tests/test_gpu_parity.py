@@ -177,17 +177,19 @@ def test_rollout_fp64_config0_strict():
 # (variant, samples per workgroup, split): MFMA tiles of 16 rows on a pair of
 # workgroups (split 0 = library's choice, which pairs these small problems, or
 # 2 = forced) or on one (split 1), 8 rows, 32 rows; and the direct kernel
-ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2), (pi.PI_VARIANT_MFMA, 16, 1),
-                  (pi.PI_VARIANT_MFMA, 8, 1), (pi.PI_VARIANT_MFMA, 32, 0), (pi.PI_VARIANT_DIRECT, 0, 0)]
+# (variant, samples per workgroup, workgroups per tile, waves per workgroup); 0 = library's choice
+ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2, 4), (pi.PI_VARIANT_MFMA, 16, 2, 8),
+                  (pi.PI_VARIANT_MFMA, 16, 1, 4), (pi.PI_VARIANT_MFMA, 16, 1, 8), (pi.PI_VARIANT_MFMA, 8, 1, 0),
+                  (pi.PI_VARIANT_MFMA, 32, 0, 0), (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("shape", ROLLOUT_SHAPES)
 @pytest.mark.parametrize("M", [0, 1, 3])
 def test_rollout_fp32_ragged(shape, M):
-    variant, spw, split = shape
+    variant, spw, split, waves = shape
     prob, model = synth.tiny_problem(11, dyn=DYN_QUAD12, L=[20, 17, 33, 16, 1, 40], R=4, K=37, T=9,
                                      M=M, dtype=F32, n_obs=6)
-    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split, tile_waves=waves)
     cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     cost_check(cost, ref, prob, 1e-4)
@@ -308,12 +310,16 @@ def test_rollout_describe_reports_the_launch():
     prob, model, _ = synth.config(1)
     dm = pi.DeviceModel(model)
     d = pi.rollout_describe(pi.DeviceProblem(prob), dm)
-    # 128 tiles of 16 rollouts leave compute units idle: pairs of workgroups
-    assert d == {"variant": "mfma", "tile_samples": 16, "tile_waves": 4, "tile_split": 2,
-                 "kernel": "rollout_pair_kernel"}
+    # 128 tiles of 16 rollouts leave compute units idle: pairs of workgroups,
+    # with 8 waves when the 256 workgroups fit one per compute unit
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert d == {"variant": "mfma", "tile_samples": 16, "tile_waves": 8 if n_cu >= 256 else 4,
+                 "tile_split": 2, "kernel": "rollout_pair_kernel"}
+    assert pi.rollout_describe(pi.DeviceProblem(prob, tile_waves=4), dm)["tile_waves"] == 4
     assert pi.rollout_describe(pi.DeviceProblem(prob, tile_split=1), dm)["tile_split"] == 1
     big, _, _ = synth.config(1, K=65536, T=2)
-    assert pi.rollout_describe(pi.DeviceProblem(big), dm)["tile_split"] == 1
+    db = pi.rollout_describe(pi.DeviceProblem(big), dm)
+    assert db["tile_split"] == 1 and db["tile_waves"] == 4
     p64 = pi.DeviceProblem(prob, dtype=torch.float64)
     assert pi.rollout_describe(p64, pi.DeviceModel(model, dtype=torch.float64))["kernel"] == \
         "rollout_direct_kernel"
