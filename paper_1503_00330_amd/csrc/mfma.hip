@@ -1093,21 +1093,47 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
     for (int k = 0; k < G::KB4; ++k) Wd[k] = buffer_f32x4(wrs, lane * 16, (tq * G::KB4 + k) * 1024);
   };
-  f32x4 B[G::KB4];
-  loadW(B, 0);
-  for (int64_t rb = r0; rb < r1; rb += 16) {
+  // A record tile's inputs (z and the five statistics per output of 16
+  // records) pass through registers: the next tile's are requested while the
+  // current one is contracted, so their memory latency is hidden.
+  constexpr int NZI = (16 * D + 255) / 256, NSI = (16 * kMaxOut * 5 + 255) / 256;
+  float zr[NZI], sr[NSI];
+  auto fetch = [&](int64_t rb) {
     const int nr = (int)min((int64_t)16, r1 - rb);
-    __syncthreads();  // the previous records' fragments and statistics are no longer read
-    for (int i = threadIdx.x; i < 16 * D; i += 256) {
+#pragma unroll
+    for (int k = 0; k < NZI; ++k) {
+      const int i = threadIdx.x + 256 * k;
       const int row = i / D, a = i - row * D;
-      sm.z[row][a] = row < nr ? recs[(rb + row) * RW + a] : 0.0f;
+      zr[k] = (i < 16 * D && row < nr) ? recs[(rb + row) * RW + a] : 0.0f;
     }
-    for (int i = threadIdx.x; i < 16 * n_out * 5; i += 256) {
+#pragma unroll
+    for (int k = 0; k < NSI; ++k) {
+      const int i = threadIdx.x + 256 * k;
       const int row = i / (n_out * 5), rem = i - row * (n_out * 5);
       const int o = rem / 5, c = rem - o * 5;
       // rows past the chunk carry mubar = vbar = 0, so they add nothing
-      st[row][o][c] = row < nr ? recs[(rb + row) * RW + D + 5 * o + c] : 0.0f;
+      sr[k] = (i < 16 * n_out * 5 && row < nr) ? recs[(rb + row) * RW + D + 5 * o + c] : 0.0f;
     }
+  };
+  f32x4 B[G::KB4];
+  loadW(B, 0);
+  if (r0 < r1) fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+    __syncthreads();  // the previous records' fragments and statistics are no longer read
+#pragma unroll
+    for (int k = 0; k < NZI; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < 16 * D) sm.z[i / D][i % D] = zr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NSI; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < 16 * n_out * 5) {
+        const int row = i / (n_out * 5), rem = i - row * (n_out * 5);
+        st[row][rem / 5][rem % 5] = sr[k];
+      }
+    }
+    if (rb + 16 < r1) fetch(rb + 16);
     __syncthreads();
     build_fragments(sm);
     __syncthreads();
