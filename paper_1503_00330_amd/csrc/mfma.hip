@@ -1185,7 +1185,9 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = 4 * (lane >> 4) + i;
-        const float w = exp2f(qa[i] + qb[i]), e = ya[i];
+        // normalised weight (anchor = log-sum-exp, so w <= 1): the bare
+        // v_exp_f32, whose results below 2^-126 flush to 0, loses nothing
+        const float w = __builtin_amdgcn_exp2f(qa[i] + qb[i]), e = ya[i];
         const float var = st[rr][o][2], mub = st[rr][o][3], vb = st[rr][o][4];
         ysum[q] += w * (mub + 2.0f * vb * e);
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
@@ -1428,7 +1430,9 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float s2 = s2v[i];
-        const float w = exp2f(qa[i] + qb[i]), e = ya[i];
+        // normalised weight (anchor = log-sum-exp, so w <= 1): the bare
+        // v_exp_f32, whose results below 2^-126 flush to 0, loses nothing
+        const float w = __builtin_amdgcn_exp2f(qa[i] + qb[i]), e = ya[i];
         ybar[i] = w * (mub + 2.0f * vb * e);
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
       }
