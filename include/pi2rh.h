@@ -176,7 +176,11 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
  * so S_k = sum_t cost[k][t].  `iter` (dev, one uint32) is the iteration
  * counter of the random stream.  With paired workgroups (tile_split) every
  * wait of a workgroup on its partner is bounded; should one run out (the
- * pair was not resident at once), the affected costs are written as NaN.   */
+ * pair was not resident at once), the affected costs are written as NaN.
+ * The library pairs only grids that fit the device's compute units at once;
+ * the 8-wave paired grid of the library's choice can fill them exactly (one
+ * workgroup per unit), so a caller that runs other kernels concurrently on
+ * the same device passes tile_waves 4 (or tile_split 1).                   */
 pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
                           const void *u_nom, const uint32_t *iter, void *cost, void *ws,
                           size_t ws_bytes, void *stream);
