@@ -280,6 +280,12 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
       Af[e] = sm.z[row][src[it] >> 8] * sm.z[row][src[it] & 0xFF];
     }
   }
+}
+
+// Empty per-wave partial sums: a wave flushes only the outputs its tiles
+// meet, and the merge adds every wave's slot in order.
+template <int D, int MT, int NW>
+__device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW> &sm) {
   Acc *pp = &sm.part[0][0][0];
   for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW>::ROWS; i += NW * 64)
     pp[i] = acc_empty();
@@ -599,6 +605,7 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
                                              const SampleArgs &sa = SampleArgs{nullptr}) {
   for (int pass = 0; pass < 2; ++pass) {
     build_fragments(sm);
+    clear_parts(sm);
     __syncthreads();
     mixture_tiles(md, sm, T0, T1);
     __syncthreads();
