@@ -182,6 +182,12 @@ ProbDev<Real> prob_dev(const pi_problem *p) {
 
 bool mfma_ok(int dtype, int d) { return dtype == PI_F32 && (d == 16 || d == 6 || d == 4); }
 
+// The matrix-core kernels address a model's folded tiles with 32-bit byte
+// offsets: a model whose tiles would reach 2 GiB keeps the direct form.
+bool mfma_model_ok(const pi_lwpr *m) {
+  return mfma_ok(m->dtype, m->d) && mfma_layout(m->d, m->n_out, m->L_off).w_floats * 4 < ((size_t)1 << 31);
+}
+
 // Rollout variant, samples per workgroup and whether tiles may be split over
 // a pair of workgroups (pair_ok; the launch decides with the device's
 // compute-unit count and residency).  The workspace never depends on the
@@ -196,7 +202,7 @@ constexpr int64_t kMaxPairGroups = 2048;
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   RolloutPlan r;
-  r.mfma = p->variant == PI_VARIANT_MFMA || (p->variant == PI_VARIANT_AUTO && mfma_ok(p->dtype, m->d));
+  r.mfma = p->variant == PI_VARIANT_MFMA || (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
   const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
   r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
   const bool split_allowed = r.mfma && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
@@ -282,7 +288,7 @@ struct FoldedLayout {
 FoldedLayout folded_layout(const pi_lwpr *m) {
   FoldedLayout f;
   f.direct_off = 0;
-  f.has_mfma = mfma_ok(m->dtype, m->d);
+  f.has_mfma = mfma_model_ok(m);
   f.mfma_off = align_up(direct_bytes(m->dtype, m->d, m->L_off[m->n_out]), 256);
   f.bytes = f.mfma_off + (f.has_mfma ? align_up(mfma_layout(m->d, m->n_out, m->L_off).bytes, 256) : 0);
   return f;
@@ -315,7 +321,7 @@ pi_status check_folded(const pi_lwpr *m, bool mfma) {
 // step (state and moments) when the model has a matrix-core form: bytes of
 // that form, or 0 for the checkpointed direct forward.
 size_t adjoint_traced_bytes(const pi_problem *p, const pi_lwpr *m) {
-  if (p->dtype != PI_F32 || !mfma_ok(m->dtype, m->d) || p->dyn == PI_DYN_QUAD_HYBRID) return 0;
+  if (p->dtype != PI_F32 || !mfma_model_ok(m) || p->dyn == PI_DYN_QUAD_HYBRID) return 0;
   if (p->variant == PI_VARIANT_DIRECT) return 0;
   const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
   return align_up(l.bytes, 256) + adj_rfold_bytes(l);   // forward tiles + reverse-sweep parameters
@@ -376,6 +382,8 @@ pi_status batch_sizes(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchSiz
     if (st != PI_OK) return fail(st, "problem %d: %s", b, g_err);
     if (p[b].dtype != PI_F32 || p[b].dyn != PI_DYN_QUAD12)
       return fail(PI_ERR_UNSUPPORTED, "problem %d: batched rollouts need float32 quadrotor problems", b);
+    if (!mfma_model_ok(&m[b]))
+      return fail(PI_ERR_UNSUPPORTED, "problem %d: the model's matrix-core tiles must stay under 2 GiB", b);
   }
   BatchSizes bs;
   bs.spw = p[0].tile_samples > 0 ? p[0].tile_samples : 16;
@@ -432,8 +440,8 @@ pi_status pi_model_fold(const pi_lwpr *m, void *folded, size_t folded_bytes, voi
 pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out) {
   PI_TRY(check_pair(p, m));
   if (!out) return fail(PI_ERR_NULL, "out must be non-NULL");
-  if (rollout_plan(p, m).mfma && !mfma_ok(p->dtype, m->d))
-    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  if (rollout_plan(p, m).mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
   PI_TRY(check_device());
   const RolloutLaunch rl = rollout_launch(p, m);
   const RolloutPlan &pl = rl.pl;
@@ -448,7 +456,7 @@ size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
   switch (op) {
     case PI_OP_PREDICT:
       if (check_model(m) != PI_OK) return (size_t)-1;
-      return mfma_ok(m->dtype, m->d) ? std::max(fold_bytes(m, true), fold_bytes(m, false))
+      return mfma_model_ok(m) ? std::max(fold_bytes(m, true), fold_bytes(m, false))
                                      : fold_bytes(m, false);
     case PI_OP_ROLLOUT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
@@ -474,9 +482,9 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
   if (N < 0) return fail(PI_ERR_SHAPE, "N=%lld must be >= 0", (long long)N);
   if (N > 0 && (!Z || !mean || !var)) return fail(PI_ERR_NULL, "Z, mean and var must be non-NULL");
   if (variant < PI_VARIANT_AUTO || variant > PI_VARIANT_MFMA) return fail(PI_ERR_VALUE, "unknown variant %d", variant);
-  const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_ok(m->dtype, m->d));
-  if (use_mfma && !mfma_ok(m->dtype, m->d))
-    return fail(PI_ERR_UNSUPPORTED, "MFMA prediction needs float32 and d in {6,16}");
+  const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_model_ok(m));
+  if (use_mfma && !mfma_model_ok(m))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA prediction needs float32, d in {4,6,16} and folded tiles under 2 GiB");
   PI_TRY(check_folded(m, use_mfma));
   if (!m->folded) PI_TRY(check_ws(ws, ws_bytes, fold_bytes(m, use_mfma)));
   PI_TRY(check_device());
@@ -499,7 +507,8 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
   PI_TRY(check_pair(p, m));
   if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost must be non-NULL");
   const RolloutPlan pl = rollout_plan(p, m);
-  if (pl.mfma && !mfma_ok(p->dtype, m->d)) return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32");
+  if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
   PI_TRY(check_folded(m, pl.mfma));
   PI_TRY(check_ws(ws, ws_bytes, rollout_ws(p, m)));
   PI_TRY(check_device());

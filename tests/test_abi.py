@@ -117,6 +117,23 @@ class TestValidation:
         ms.d = 0
         assert lib.pi_model_fold_bytes(C.byref(ms)) == C.c_size_t(-1).value
 
+    def test_models_past_2gib_of_tiles_keep_the_direct_form(self):
+        # d = 16: one tile of 16 models takes 11 KB of matrix-core fragments, a
+        # model 680 B in the direct form; tile offsets are 32-bit
+        ps, ms = _structs()
+        lib = pi.load()
+        assert ms.d == 16
+
+        def fold_bytes(L):      # L models spread over the quadrotor's 6 outputs
+            for o in range(7):
+                ms.L_off[o] = o * (L // 6)
+            return lib.pi_model_fold_bytes(C.byref(ms))
+        assert ms.n_out == 6
+        assert fold_bytes(1 << 20) > 1.4e9          # 713 MB direct + 738 MB of tiles
+        assert fold_bytes(1 << 22) < 3.0e9          # 2.85 GB direct only (tiles would be 2.95 GB)
+        ps.variant = pi.PI_VARIANT_MFMA
+        assert _rollout(ps, ms) == 7 and "2 GiB" in pi.last_error()
+
     def test_bad_model(self):
         ps, ms = _structs()
         ms.d = 17
