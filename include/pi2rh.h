@@ -67,7 +67,11 @@ enum { PI_OBS_INDICATOR = 0, PI_OBS_SMOOTH = 1 };
 /* Weighting of the update: Eq. (2) with the cost-to-go S(tau_i) of every
  * time step (default), or the whole-trajectory cost S(tau_0) for all steps. */
 enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
-/* Kernel variants (autotuner / override). */
+/* Kernel variants.  The matrix-core form (PI_VARIANT_MFMA) needs float32,
+ * d in {4, 6, 16} and folded tiles under 2 GiB (about 3 M local models at
+ * d = 16); PI_VARIANT_AUTO picks it whenever those hold, and requesting it
+ * otherwise returns PI_ERR_UNSUPPORTED.  PI_VARIANT_DIRECT is the per-sample
+ * form (any d, float32 or float64).                                         */
 enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2 };
 /* Operations for pi_workspace_bytes. */
 enum { PI_OP_PREDICT = 0, PI_OP_ROLLOUT = 1, PI_OP_UPDATE = 2, PI_OP_ADJOINT = 3,
@@ -209,7 +213,7 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
  * the metrics g_metric dev [Ltot][d][d] (problem dtype).  States are
  * checkpointed every `ckpt_every` steps (0: ceil(sqrt(T))) and recomputed
  * segment by segment in the reverse sweep.  Float32 problems whose model has
- * a matrix-core form (d in {6, 16}, variant not PI_VARIANT_DIRECT) instead run
+ * a matrix-core form (see PI_VARIANT_MFMA; variant not PI_VARIANT_DIRECT) run
  * the forward on the matrix cores and keep every step's state and mixture
  * moments (no recompute; ckpt_every is then unused).
  * pi_workspace_bytes(PI_OP_ADJOINT) sizes the workspace for the default
