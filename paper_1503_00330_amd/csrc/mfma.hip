@@ -258,7 +258,9 @@ __device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
   }
 }
 
-// Stage 1 (all lanes): A fragments from sm.z; resets the partial sums.
+// Stage 1 (all lanes): the samples' fragments sm.A from sm.z (named for the
+// parameter pass, where they are the A operand; the rollout and the reverse
+// sweep use them as the B operand).
 template <int D, int MT, int NW>
 __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
   using G = Geo<D>;
