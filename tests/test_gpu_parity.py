@@ -283,6 +283,22 @@ def test_rollout_config1_full_launch_sampled_rows(split):
     print("config 1 sampled rows: max S rel %.2e, flips %d" % (r, flips))
 
 
+def test_rollout_config2_full_launch_sampled_rows():
+    # 65536 rollouts over T = 200 against 6 x 1024 models: 4096 one-workgroup
+    # tiles, two workgroups per compute unit; sampled rows at both ends and
+    # across the tile boundary at rollout 32768
+    prob, model, _ = synth.config(2)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    assert pi.rollout_describe(dp, dm)["tile_split"] == 1
+    cost = pi.rollout_cost(dp, dm).cpu().numpy()
+    assert cost.shape == (65536, 200) and np.all(np.isfinite(cost))
+    starts = (0, 32760, 65520)
+    rows = [a + i for a in starts for i in range(16)]
+    ref = np.concatenate([oracle.rollout_cost(prob, model, k_range=(a, a + 16)) for a in starts])
+    r, flips = cost_check(cost[rows], ref, prob, 1e-4)
+    print("config 2 sampled rows: max S rel %.2e, flips %d" % (r, flips))
+
+
 def test_prefolded_model_gives_identical_results():
     # pi_model_fold once, then every entry point reads the folded buffer: the
     # same kernels on the same folded values, so results are bitwise equal
