@@ -66,3 +66,30 @@ def test_batched_rerun_is_repeatable():
     b = br.run()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def test_batched_full_workload():
+    # the 64 uneven quadrotor problems (K 512..16384, 6 x (64..1024) models,
+    # T 50..200) in one persistent launch: bitwise equal to each problem's
+    # plain 4-wave one-workgroup-per-tile launch, and sampled rollouts of the
+    # first, the largest and the last problem against the oracle
+    batch = synth.batched_config()
+    dps = [pi.DeviceProblem(p, tile_split=1, tile_waves=4) for p, _ in batch]
+    dms = [pi.DeviceModel(m) for _, m in batch]
+    br = pi.BatchedRollout(dps, dms)
+    costs = [c.clone() for c in br.run()]
+    for b, (dp, dm) in enumerate(zip(dps, dms)):
+        assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
+    big = max(range(len(batch)), key=lambda b: batch[b][0].K * batch[b][1].centre.shape[0])
+    for b in sorted({0, big, len(batch) - 1}):
+        prob, model = batch[b]
+        g = costs[b].cpu().numpy().astype(np.float64)
+        assert g.shape == (prob.K, prob.T) and np.all(np.isfinite(g))
+        starts = (0, prob.K - 16)
+        rows = [a + i for a in starts for i in range(16)]
+        ref = np.concatenate([oracle.rollout_cost(prob, model, k_range=(a, a + 16)) for a in starts])
+        r = np.abs(g[rows].sum(1) - ref.sum(1)) / np.abs(ref.sum(1))
+        flips = np.abs(g[rows] - ref).max(1) > 0.25 * prob.dt * prob.obs_penalty
+        assert flips.sum() <= 1 and r[~flips].max() <= 1e-4, (b, r.max())
+        print("batched problem %d (K=%d, T=%d): max S rel %.2e, flips %d"
+              % (b, prob.K, prob.T, r[~flips].max(), flips.sum()))
