@@ -225,6 +225,20 @@ def test_rollout_hybrid_quadrotor(shape, M):
     assert nrel(cost, ref) <= 1e-4
 
 
+@pytest.mark.parametrize("M", [0, 1, 4, 8, 16, 32])
+def test_rollout_paper_shapes_full(M):
+    # the paper's timing shapes at full size (1000 rollouts x 50 steps, M
+    # sub-rollouts each) in the launch the timing uses; every rollout against
+    # the oracle
+    prob, model = synth.paper_shape(M=M)
+    assert (prob.K, prob.T) == (1000, 50)
+    prob.u_nom = np.random.default_rng(100 + M).normal(0.0, 0.3, prob.u_nom.shape).astype(F32)
+    cost = pi.rollout_cost(pi.DeviceProblem(prob), pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    r, flips = cost_check(cost, ref, prob, 1e-4)
+    print("paper shape M=%d: max S rel %.2e, flips %d" % (M, r, flips))
+
+
 def test_hybrid_fp64_iteration_and_shift():
     prob, model = synth.paper_shape(M=2, K=64, T=15, dtype=F64)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
