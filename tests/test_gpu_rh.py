@@ -52,6 +52,30 @@ def test_graph_replay_equals_eager(iterations):
     assert int(graph.prob.iter.item()) == 5 * iterations
 
 
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_graph_replay_equals_eager_full_size(cfg):
+    # the benchmarked launches inside captured control steps: 2048 x 100 on
+    # paired 8-wave workgroups, 65536 x 200 with two workgroups per compute unit
+    def ctrl(graph):
+        prob, model, _ = synth.config(cfg)
+        return RHController(pi.DeviceProblem(prob), pi.DeviceModel(model), iterations=1, graph=graph)
+    eager = ctrl(False)
+    ref = []
+    for _ in range(3):
+        eager.step()
+        ref.append(_snap(eager))
+    del eager
+    graph = ctrl(True)
+    for i in range(3):
+        graph.step()
+        got = _snap(graph)
+        torch.cuda.synchronize()
+        _ = float(graph.cost.sum().item())
+        assert torch.all(torch.isfinite(got[3]))
+        for a, b in zip(got, ref[i]):
+            assert torch.equal(a, b), i
+
+
 def test_resume_is_bit_identical():
     c, _, _ = _ctrl(False)
     c.step()
