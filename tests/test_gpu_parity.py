@@ -384,6 +384,18 @@ def test_update_teacher_forced(dtype, weighting, K):
     assert np.max(np.abs(W.cpu().numpy() - oW)) <= 1e-12
 
 
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_update_teacher_forced_full_size(cfg):
+    # the benchmarked update sizes (2048 x 100 and 65536 x 200) from seeded costs
+    prob, _, _ = synth.config(cfg)
+    cost = np.random.default_rng(cfg).uniform(0.0, 1.0, (prob.K, prob.T)).astype(F32)
+    dp = pi.DeviceProblem(prob)
+    u, W = pi.update(dp, torch.from_numpy(cost).cuda(), weights=True)
+    ou, oW = oracle.update(prob, cost, it=0, weights=True)
+    assert np.max(np.abs(u.cpu().numpy() - ou)) <= 1e-4
+    assert np.max(np.abs(W.cpu().numpy() - oW)) <= 1e-12
+
+
 def test_iteration_fp64_end_to_end():
     prob, model, _ = synth.config(0)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
