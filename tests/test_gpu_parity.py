@@ -98,12 +98,20 @@ PRED_CASES = [("cfg1", pi.PI_VARIANT_MFMA, F32), ("cfg1", pi.PI_VARIANT_DIRECT, 
               ("ragged16", pi.PI_VARIANT_DIRECT, F64), ("pm6", pi.PI_VARIANT_MFMA, F32),
               ("pm6", pi.PI_VARIANT_DIRECT, F64), ("d3", pi.PI_VARIANT_DIRECT, F32),
               ("d3", pi.PI_VARIANT_DIRECT, F64), ("paper4", pi.PI_VARIANT_MFMA, F32),
-              ("paper4", pi.PI_VARIANT_DIRECT, F32), ("paper4", pi.PI_VARIANT_DIRECT, F64)]
+              ("paper4", pi.PI_VARIANT_DIRECT, F32), ("paper4", pi.PI_VARIANT_DIRECT, F64),
+              ("cfg2", pi.PI_VARIANT_MFMA, F32), ("cfg2", pi.PI_VARIANT_DIRECT, F64)]
+
+
+def _model(name):
+    # the 6 x 1024-model set of the 65536-rollout workload is built on first use
+    if name == "cfg2":
+        return synth.config(2)[1].astype(F64)
+    return MODELS[name]
 
 
 @pytest.mark.parametrize("name,variant,dtype", PRED_CASES)
 def test_lwpr_predict_parity(name, variant, dtype):
-    model = MODELS[name].astype(dtype)
+    model = _model(name).astype(dtype)
     N = 16 * 37 + 5
     Z = np.random.default_rng(5).uniform(-1, 1, (N, model.d)).astype(dtype)
     dm = pi.DeviceModel(model)
