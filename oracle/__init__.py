@@ -254,3 +254,27 @@ def rh_loop(prob, model, steps: int, iterations: int = 1, x0=None, u_nom=None, i
             it += 1
         x, u = rh_shift(prob, model, x, u, it)
     return x, u, it
+
+
+def rh_loop_goals(prob, model, steps: int, goals, radius: float = 0.25, iterations: int = 1,
+                  g: int = 0, x0=None, u_nom=None, it: int = 0):
+    """The receding-horizon loop of the flight experiments (Sec. 5): the state
+    cost pulls toward goals[g]; once the plant's position has come within
+    `radius` (Euclidean, over the position components) of that point, the
+    goal moves to the next point of the cycle.  The controller is not told
+    of a switch in advance, so the check follows each control step's plant
+    update and takes effect from the next control step.
+    Returns (x0, u_nom, it, g) after `steps` control steps."""
+    import copy
+    from synth import DYN_POINTMASS2D
+    goals = np.asarray(goals, dtype=np.float64).reshape(-1, 3)
+    npos = 2 if int(prob.dyn) == DYN_POINTMASS2D else 3
+    pc = copy.deepcopy(prob)
+    x = _f64(prob.x0 if x0 is None else x0).copy()
+    u = _f64(prob.u_nom if u_nom is None else u_nom).copy()
+    for _ in range(steps):
+        pc.goal = goals[g].copy()
+        x, u, it = rh_loop(pc, model, 1, iterations=iterations, x0=x, u_nom=u, it=it)
+        if np.sqrt(np.sum((x[:npos] - goals[g, :npos]) ** 2)) < radius:
+            g = (g + 1) % len(goals)
+    return x, u, it, g

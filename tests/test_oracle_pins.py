@@ -447,6 +447,48 @@ def test_rh_shift_moves_the_plan():
     assert np.allclose(x[:2], prob.x0[:2]) and not np.allclose(x[2:], prob.x0[2:])
 
 
+def _goal_case():
+    prob, model = synth.tiny_problem(9, K=6, T=5)
+    goals = np.array([[0.5, -0.5, 0.0], [-0.7, 0.2, 0.0], [0.1, 0.9, 0.0]])
+    return prob, model, goals
+
+
+def test_goal_switching_with_zero_radius_is_the_plain_loop():
+    # nothing is ever within distance 0: the loop is the fixed-goal loop
+    prob, model, goals = _goal_case()
+    x, u, it, g = oracle.rh_loop_goals(prob, model, 3, goals, radius=0.0)
+    prob.goal = goals[0].copy()
+    xr, ur, itr = oracle.rh_loop(prob, model, 3)
+    assert g == 0 and it == itr and np.array_equal(x, xr) and np.array_equal(u, ur)
+
+
+def test_goal_switching_with_unbounded_radius_cycles_every_step():
+    # every plant update is within reach: step n optimises toward goal n mod 3,
+    # which is the plain loop with that goal, one control step at a time
+    prob, model, goals = _goal_case()
+    x, u, it, g = oracle.rh_loop_goals(prob, model, 4, goals, radius=np.inf)
+    assert g == 4 % 3
+    xr, ur, itr = prob.x0, prob.u_nom, 0
+    for n in range(4):
+        prob.goal = goals[n % 3].copy()
+        xr, ur, itr = oracle.rh_loop(prob, model, 1, x0=xr, u_nom=ur, it=itr)
+    assert np.array_equal(x, xr) and np.array_equal(u, ur) and it == itr
+
+
+def test_goal_switching_waits_for_the_plant_update():
+    # the start lies on goal 0: the switch follows the first control step (the
+    # plant moves by about dt^2 a / 2 from rest, far less than the radius),
+    # not the initial state, so the first step still optimises toward goal 0
+    prob, model, goals = _goal_case()
+    goals[0, :2] = prob.x0[:2]
+    x1, u1, _, g1 = oracle.rh_loop_goals(prob, model, 1, goals)
+    assert g1 == 1
+    prob.goal = goals[0].copy()
+    xr, ur, _ = oracle.rh_loop(prob, model, 1)
+    assert np.array_equal(x1, xr) and np.array_equal(u1, ur)
+    assert np.linalg.norm(x1[:2] - goals[0, :2]) < 0.25
+
+
 # ------------------------------------------------------------------ adjoint
 
 def _fd(fun, x, idx, h):
