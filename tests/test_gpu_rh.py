@@ -102,3 +102,26 @@ def test_rh_loop_fp64_matches_oracle():
         assert int(dp.iter.item()) == it == 2 * (step + 1)
         assert np.max(np.abs(dp.x0.cpu().numpy() - x)) <= 1e-10
         assert np.max(np.abs(dp.u_nom.cpu().numpy() - u)) <= 1e-9
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_goal_switching_matches_oracle(graph):
+    # FP64 point mass with the flight experiments' task layer: the start lies
+    # 0.1 from goal 0, so the first control step reaches it and the goal moves
+    # on (a captured step is captured again with the new goal)
+    prob, model, _ = synth.config(0)
+    goals = np.array([[prob.x0[0] + 0.1, prob.x0[1], 0.0], prob.goal, [0.0, 0.0, 0.0]])
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    c = RHController(dp, dm, iterations=2, graph=graph, goals=goals)
+    x, u, it, g = prob.x0.copy(), prob.u_nom.copy(), 0, 0
+    seen = {0}
+    for step in range(4):
+        c.step()
+        x, u, it, g = oracle.rh_loop_goals(prob, model, 1, goals, iterations=2, g=g, x0=x, u_nom=u, it=it)
+        seen.add(g)
+        assert c.goal_index == g, step
+        assert np.max(np.abs(dp.x0.cpu().numpy() - x)) <= 1e-10
+        assert np.max(np.abs(dp.u_nom.cpu().numpy() - u)) <= 1e-9
+    assert 1 in seen
+    st = c.state()
+    assert st["goal_index"] == g
