@@ -11,7 +11,9 @@
                        adjoint (pi_rollout_adjoint) vs the forward rollout alone
   --workload paper     the paper's model (hybrid quadrotor, d = 4, 15/15/24 local
                        models) at its GPU timing shapes (1000 rollouts x 50 steps,
-                       M sub-rollouts), and the largest K per 20 ms iteration
+                       M sub-rollouts), the largest K per 20 ms iteration, and
+                       whole control steps at the rollout and iteration counts
+                       of the paper's Table 2
 """
 import argparse
 import json
@@ -208,10 +210,24 @@ def w_paper(args):
         rows.append({"M": M, "iteration_ms_p50": pct(ms, 50), "iteration_ms_p99": pct(ms, 99),
                      "sub_rollout_steps_per_s": 1000 * max(M, 1) * 50 / (pct(ms, 50) * 1e-3),
                      "max_K_in_20ms": lo})
+    # Table 2's settings (rollouts, iterations per control step) for the
+    # sub-rollout counts: one whole control step (iterations x (rollouts +
+    # update), then the plant step and shift) replayed as a HIP graph
+    from paper_1503_00330_amd.rh import RHController
+    table2 = []
+    for M, K, iters in ((1, 1000, 2), (4, 1000, 2), (8, 1000, 1), (16, 970, 1), (32, 950, 1)):
+        prob, model = synth.paper_shape(M=M, K=K)
+        ctl = RHController(pi.DeviceProblem(prob), pi.DeviceModel(model), iterations=iters, graph=True)
+        for _ in range(3):
+            ctl.step()
+        torch.cuda.synchronize()
+        ms = timed(ctl.step, args.steps or 20, stream)
+        table2.append({"M": M, "K": K, "iterations": iters, "control_step_ms_p50": pct(ms, 50),
+                       "control_step_ms_p99": pct(ms, 99)})
     return {"workload": "paper's model and timing shapes: hybrid quadrotor, LWPR (phi, theta, psi, F) -> "
                         "(x'', y'', z''), 15/15/24 local models, R = 2, 1000 rollouts x 50 steps, "
                         "M sub-rollouts (M = 0: mean prediction only); iteration = rollouts + update",
-            "rows": rows, "dtype": "f32",
+            "rows": rows, "table2_control_steps": table2, "dtype": "f32",
             "paper_reference": "GTX 780 Ti: 6.5 ms (M = 0) and 18 ms (M = 32) per iteration (Sec. 4)"}
 
 
