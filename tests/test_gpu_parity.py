@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (spec figures; readings in the design notes):
+Tolerances (each follows from the working precision of the path it checks):
   * LWPR mean/variance: normwise per output, max|g-o| / max|o| <= 1e-5 for
     FP32 (in-distribution inputs), 1e-11 for FP64;
   * trajectory costs S_k = sum_t cbar_{k,t}: relative 1e-4 per rollout for
