@@ -73,7 +73,7 @@ def main():
                          "known size for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(rollouts would shard by k with one small all-reduce per update)", file=sys.stderr)
         sys.exit(2)
 

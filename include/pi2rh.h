@@ -42,7 +42,7 @@ typedef enum {
   PI_ERR_DTYPE = 4,       /* unknown dtype or problem/model dtype mismatch    */
   PI_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than required          */
   PI_ERR_DEVICE = 6,      /* no usable gfx950 device or a launch failed       */
-  PI_ERR_UNSUPPORTED = 7  /* valid request this build does not implement      */
+  PI_ERR_UNSUPPORTED = 7  /* valid request the library does not implement     */
 } pi_status;
 
 typedef enum { PI_F32 = 0, PI_F64 = 1 } pi_dtype;

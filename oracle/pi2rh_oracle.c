@@ -20,8 +20,7 @@
  *   - state cost, phi = 0 ............... Sec. 5 (q(x) and the terminal cost)
  *   - Euler integration ................. Table 1 caption
  *
- * Readings where the paper is silent or garbled (each also listed with the
- * design notes):
+ * Readings where the paper is silent or garbled:
  *   R1  Eq. (1) mixes indices; read as the normalised Gaussian mixture:
  *       w_j = softmax_j(-q_j/2), mu = sum w_j y_j,
  *       var = sum w_j ((mu - y_j)^2 + sigma_j^2).
