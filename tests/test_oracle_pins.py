@@ -380,6 +380,84 @@ def test_obstacle_penalty_counts_steps_inside():
     assert np.allclose(cost[0], expect, rtol=1e-13)
 
 
+@pytest.mark.parametrize("dyn", [DYN_POINTMASS2D, DYN_QUAD12])
+def test_smooth_obstacle_cost_on_a_constant_acceleration_path(dyn):
+    # Sec. 5: the smooth obstacle term is 100 sum_i exp(-10 (dx_i^2 + dy_i^2))
+    # over the horizontal distances to every obstacle centre.  One affine model
+    # with only its offset set makes the acceleration constant, so explicit
+    # Euler from rest gives the closed form v_n = n dt a,
+    # p_n = p_0 + a dt^2 n (n - 1) / 2, and every step cost is dt q(x_{n+1})
+    # written out from the task's weights.
+    prob, model = synth.tiny_problem(6, dyn=dyn, L=1, R=1, K=1, T=50, M=0, n_obs=2,
+                                     obs_kind=OBS_SMOOTH)
+    assert prob.obs_penalty == 100.0 and prob.obs_decay == 10.0
+    npos = 2 if dyn == DYN_POINTMASS2D else 3
+    prob.noise_std[:] = 0.0
+    prob.x0[:] = 0.0
+    prob.x0[:npos] = [-0.5, -0.1, 0.2][:npos]
+    prob.obs[:] = [[0.0, 0.0, 0.2], [0.25, 0.1, 0.2]]
+    prob.goal[:] = [0.3, -0.2, 0.4]
+    prob.w_vel = 0.3
+    model.beta[:] = 0.0
+    a = np.zeros(model.n_out)
+    a[:2] = [2.0, 0.5]
+    model.beta[:, 0] = a                    # y_o = beta_o0: constant accelerations
+    cost, X = oracle.rollout_cost(prob, model, states=True)
+    n = np.arange(1, prob.T + 1)[:, None]
+    p = prob.x0[:npos] + a[:npos] * prob.dt ** 2 * n * (n - 1) / 2
+    v = a[:npos] * prob.dt * n
+    assert np.allclose(X[0, 0, 1:, :npos], p, rtol=1e-12, atol=1e-14)
+    q = ((p - prob.goal[:npos]) ** 2 * prob.w_pos[:npos]).sum(1) + prob.w_vel * (v ** 2).sum(1)
+    bumps = sum(100.0 * np.exp(-10.0 * ((p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2))
+                for cx, cy, _ in prob.obs)
+    # the path passes close enough for the bumps to dominate some steps
+    assert bumps.max() > 50.0 and bumps.max() > 5.0 * bumps.min()
+    assert np.allclose(cost[0], prob.dt * (q + bumps), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("dyn", [DYN_POINTMASS2D, DYN_QUAD12])
+def test_rh_shift_plant_draw_is_a_sample_of_the_model(rocrand_ref, dyn):
+    # Sec. 3.1, last paragraph: the first control of the plan is executed on
+    # the plant -- here one draw from the learned model, N(y(z), sigma^2) per
+    # output with a single affine local model -- and the plan shifts by one
+    # step.  The draw's standard normals are formed here from rocRAND's Philox
+    # words at the plant stream's counter (t = 0, k = 0, block, tag 2 with the
+    # problem and iteration words) and the Box-Muller pairs written out.
+    prob, model = synth.tiny_problem(31, dyn=dyn, L=1, R=3, K=2, T=5, n_obs=0)
+    prob.problem_id = 5
+    model.sigma2[:] = np.linspace(0.04, 0.09, model.n_out)
+    it = 0x12345 + 3
+    x0 = prob.x0.copy()
+    x0[prob.n_x // 2:] = np.linspace(-0.3, 0.4, prob.n_x - prob.n_x // 2)
+    x, u = oracle.rh_shift(prob, model, x0, prob.u_nom, it)
+    assert np.array_equal(u[:-1], prob.u_nom[1:]) and np.array_equal(u[-1], prob.u_nom[-1])
+    word3 = (2 << 30) | ((prob.problem_id & 0x3FF) << 20) | (it & 0xFFFFF)
+    key = (prob.seed & 0xFFFFFFFF, prob.seed >> 32)
+    nblk = (model.n_out + 3) // 4
+    lines = "\n".join("0 0 %d %d %d %d" % (b, word3, key[0], key[1]) for b in range(nblk))
+    raw = np.array(subprocess.run([rocrand_ref], input=lines + "\n", capture_output=True,
+                                  text=True, check=True).stdout.split(), np.uint64).reshape(nblk, 4)
+    un = ((raw >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
+    rad0, rad1 = np.sqrt(-2 * np.log(un[:, 0])), np.sqrt(-2 * np.log(un[:, 2]))
+    xi = np.stack([rad0 * np.cos(2 * np.pi * un[:, 1]), rad0 * np.sin(2 * np.pi * un[:, 1]),
+                   rad1 * np.cos(2 * np.pi * un[:, 3]), rad1 * np.sin(2 * np.pi * un[:, 3])],
+                  1).reshape(-1)[:model.n_out]
+    bs, offs = _affine_system(prob, model)
+    acc = bs @ np.concatenate([x0, prob.u_nom[0]]) + offs + np.sqrt(model.sigma2) * xi
+    npos = 2 if dyn == DYN_POINTMASS2D else 3
+    expect = x0.copy()
+    expect[:npos] += prob.dt * x0[npos:2 * npos]
+    expect[npos:2 * npos] += prob.dt * acc[:npos]
+    if dyn == DYN_QUAD12:
+        expect[6:9] += prob.dt * x0[9:12]
+        expect[9:12] += prob.dt * acc[3:6]
+    assert np.allclose(x, expect, rtol=1e-12, atol=1e-14)
+    # the draw is not the mean: the noise term moves the velocities measurably
+    mean_only = expect.copy()
+    mean_only[npos:2 * npos] -= prob.dt * (np.sqrt(model.sigma2) * xi)[:npos]
+    assert np.max(np.abs(x - mean_only)) > 1e-4
+
+
 # ------------------------------------------------------------------ update, Eq. (2)
 
 def _upd_case(seed=0, K=6, T=5, **kw):
