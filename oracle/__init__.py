@@ -47,7 +47,8 @@ class _Problem(C.Structure):
                 ("goal", C.c_double * 3), ("w_pos", C.c_double * 3), ("w_ang", C.c_double),
                 ("w_vel", C.c_double), ("obs_kind", C.c_int32), ("n_obs", C.c_int32),
                 ("obs", C.c_void_p), ("obs_penalty", C.c_double), ("obs_decay", C.c_double),
-                ("weighting", C.c_int32), ("seed", C.c_uint64), ("problem_id", C.c_uint32)]
+                ("weighting", C.c_int32), ("seed", C.c_uint64), ("problem_id", C.c_uint32),
+                ("ctrl_cost", C.c_int32)]
 
 
 _lib = None
@@ -124,6 +125,7 @@ def _problem_struct(prob, keep):
     s.obs_penalty, s.obs_decay = float(prob.obs_penalty), float(prob.obs_decay)
     s.weighting = prob.weighting
     s.seed, s.problem_id = int(prob.seed) & (2**64 - 1), int(prob.problem_id)
+    s.ctrl_cost = int(getattr(prob, "ctrl_cost", 0))
     return s
 
 

@@ -46,6 +46,17 @@
  *       first-order response dr/dt = 25 (r_commanded - r); three LWPR models
  *       with inputs (phi, theta, psi, F) give the cartesian accelerations.
  *       State [p, v, r] (9), integrated by explicit Euler like the others.
+ *   R10 the control terms of S-tilde (Sec. 3.1, below Eq. 2), which the
+ *       experiments drop (Sec. 5), as an option: per step of rollout k
+ *       u^T G_c^T H^-1 G_c u dt + u^T G_c^T H^-1 B dw with H = G_c R^-1 G_c^T,
+ *       u the nominal control.  The control-affine channel is the hybrid
+ *       model's commanded rates, G_c = 25 I on those three controls (R9); the
+ *       noise enters through the same channel, B dw = G_c eps dt with eps the
+ *       step's sampled perturbation; B B^T = lambda G_c R^-1 G_c^T (Sec. 3.1)
+ *       with eps ~ N(0, diag(sigma^2)) per step fixes R = lambda
+ *       diag(1/sigma^2) / dt.  The sum over steps runs from the step i on,
+ *       like S, so the term is added to every step's cost (the paper's lower
+ *       index of that sum is garbled).
  */
 #include <math.h>
 #include <stdint.h>
@@ -88,6 +99,7 @@ typedef struct {
   int32_t weighting;
   uint64_t seed;
   uint32_t problem_id;
+  int32_t ctrl_cost;      /* 1: add the control terms of S-tilde (reading R10) */
 } orc_problem;
 
 /* ------------------------------------------------------------------ Philox */
@@ -325,6 +337,40 @@ static void state_cost_grad(const orc_problem *p, const double *x, double *g) {
   }
 }
 
+/* Control terms of S-tilde for one step (reading R10): u the nominal
+ * control, eps the step's sampled perturbation of it (both [n_u]). */
+static double control_cost(const orc_problem *p, const double *u, const double *eps) {
+  if (!p->ctrl_cost) return 0.0;
+  double G[3][3] = {{0}}, Rinv[3][3] = {{0}}, H[3][3] = {{0}}, Hinv[3][3] = {{0}};
+  for (int a = 0; a < 3; ++a) {
+    G[a][a] = ORC_RATE_GAIN;
+    Rinv[a][a] = p->noise_std[a] * p->noise_std[a] * p->dt / p->lam;
+  }
+  /* H = G R^-1 G^T (diagonal here, since G and R are) */
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c)
+        for (int e = 0; e < 3; ++e) H[a][b] += G[a][c] * Rinv[c][e] * G[b][e];
+  for (int a = 0; a < 3; ++a) Hinv[a][a] = 1.0 / H[a][a];
+  /* M = G^T H^-1 G */
+  double M[3][3] = {{0}};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c)
+        for (int e = 0; e < 3; ++e) M[a][b] += G[c][a] * Hinv[c][e] * G[e][b];
+  /* B dw = G eps dt */
+  double Bdw[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Bdw[a] += G[a][b] * eps[b] * p->dt;
+  double quad = 0.0, cross = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) quad += u[a] * M[a][b] * u[b];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) cross += u[a] * G[b][a] * Hinv[b][c] * Bdw[c];
+  return quad * p->dt + cross;
+}
+
 /* Per-rollout scratch for the step function. */
 typedef struct {
   double *w, *y, *work;
@@ -333,15 +379,20 @@ typedef struct {
 /* One sampled step of sub-rollout m of rollout k (readings R3, R4). */
 static void rollout_step(const orc_problem *p, const orc_model *md, const double *x,
                          const double *u_nom_t, uint32_t iter, int64_t k, int m, int t,
-                         step_scratch *s, double *xn, double *mean_out, double *var_out) {
+                         step_scratch *s, double *xn, double *mean_out, double *var_out,
+                         double *ctrl_out) {
   const int nx = n_state(p->dyn), nu = n_control(p->dyn), no = md->n_out;
-  double eps[4], xi[8], z[32], acc[8], u[4];
+  double eps[4], xi[8], z[32], acc[8], u[4], pert[4];
   (void)nx;
   orc_normals(p->seed, ORC_TAG_CTRL, p->problem_id, iter, (uint32_t)k, 0u, (uint32_t)t, nu, eps);
   if (p->M > 0)
     orc_normals(p->seed, ORC_TAG_DYN, p->problem_id, iter, (uint32_t)k, (uint32_t)m,
                 (uint32_t)t, no, xi);
-  for (int a = 0; a < nu; ++a) u[a] = u_nom_t[a] + p->noise_std[a] * eps[a];
+  for (int a = 0; a < nu; ++a) {
+    pert[a] = p->noise_std[a] * eps[a];
+    u[a] = u_nom_t[a] + pert[a];
+  }
+  if (ctrl_out) *ctrl_out = control_cost(p, u_nom_t, pert);
   model_input(p->dyn, x, u, z);
   for (int o = 0; o < no; ++o) {
     double mu, v;
@@ -379,9 +430,10 @@ void orc_rollout_cost(const orc_problem *p, const orc_model *md, const double *x
       for (int m = 0; m < Ms; ++m) {
         for (int a = 0; a < nx; ++a) xs[a] = x0[a];
         for (int t = 0; t < T; ++t) {
+          double ctrl = 0.0;
           rollout_step(p, md, xs + t * nx, u_nom + t * nu, iter, k, m, t, &s, xs + (t + 1) * nx,
-                       NULL, NULL);
-          csum[t] += p->dt * state_cost(p, xs + (t + 1) * nx);
+                       NULL, NULL, &ctrl);
+          csum[t] += p->dt * state_cost(p, xs + (t + 1) * nx) + ctrl;
         }
         if (states)
           memcpy(states + ((k - k0) * Ms + m) * (int64_t)(T + 1) * nx, xs,
@@ -511,7 +563,7 @@ double orc_adjoint(const orc_problem *p, const orc_model *md, const double *x0,
         for (int a = 0; a < nx; ++a) xs[a] = x0[a];
         for (int t = 0; t < T; ++t) {
           rollout_step(p, md, xs + t * nx, u_nom + t * nu, iter, k, m, t, &s, xs + (t + 1) * nx,
-                       NULL, NULL);
+                       NULL, NULL, NULL);
           acc_J[tid] += p->dt * state_cost(p, xs + (t + 1) * nx);
         }
         /* backward sweep; xbar is the adjoint of x_{t+1} */

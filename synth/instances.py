@@ -104,6 +104,7 @@ class Problem:
     x0: np.ndarray              # [n_x]
     u_nom: np.ndarray           # [T, n_u]
     dtype: type = np.float64
+    ctrl_cost: int = 0          # 1: the control terms of the cost-to-go (hybrid model only)
 
     @property
     def n_x(self):

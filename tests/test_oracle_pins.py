@@ -641,3 +641,50 @@ def test_adjoint_linear_quadratic_closed_form():
                 grad[s] += Gts.T @ r
     grad /= prob.K
     assert np.allclose(gu, grad, rtol=1e-11, atol=1e-13)
+
+
+# ------------------------------------------------------------------ control terms of S-tilde
+
+def _ctrl_case(seed=51, K=6, T=7, M=1):
+    prob, model = synth.tiny_problem(seed, dyn=DYN_QUAD_HYBRID, L=[3, 4, 2], R=2, K=K, T=T, M=M,
+                                     n_obs=2)
+    prob.noise_std[:] = [0.5, 0.3, 0.4, 0.6]
+    prob.lam = 0.7
+    return prob, model
+
+
+def test_control_terms_are_the_noise_likelihood_ratio():
+    # Sec. 3.1: with B B^T = lambda G R^-1 G^T the control terms of S-tilde,
+    # divided by lambda, are  u^T S^-1 u + u^T S^-1 eps  (S = diag(sigma^2) of
+    # the commanded rates' perturbation eps):  the log-density ratio
+    # log N(eps; 0, S) - log N(u + eps; 0, S) plus (1/2) u^T S^-1 u, written
+    # here with SciPy's Gaussian.  The dynamics do not change, so the state
+    # costs cancel in the difference of the two cost arrays.
+    for M in (1, 3):
+        prob, model = _ctrl_case(M=M)
+        off = oracle.rollout_cost(prob, model)
+        p = prob.copy()
+        p.ctrl_cost = 1
+        on = oracle.rollout_cost(p, model)
+        eps = oracle.control_noise(prob)[:, :, :3]
+        Sig = np.diag(prob.noise_std[:3] ** 2)
+        g = stats.multivariate_normal(mean=np.zeros(3), cov=Sig)
+        u = prob.u_nom[:, :3]
+        for k in range(prob.K):
+            ratio = g.logpdf(eps[k]) - g.logpdf(u + eps[k]) + 0.5 * np.einsum(
+                "ta,ab,tb->t", u, np.linalg.inv(Sig), u)
+            assert np.allclose((on[k] - off[k]) / prob.lam, ratio, rtol=1e-10, atol=1e-12)
+
+
+def test_control_terms_vanish_for_a_zero_plan_and_keep_the_one_sample_update():
+    prob, model = _ctrl_case()
+    prob.u_nom[:] = 0.0
+    p = prob.copy()
+    p.ctrl_cost = 1
+    assert np.array_equal(oracle.rollout_cost(p, model), oracle.rollout_cost(prob, model))
+    # K = 1: the update returns its own perturbation whatever the costs
+    p1, m1 = _ctrl_case(K=1)
+    p1.ctrl_cost = 1
+    cost = oracle.rollout_cost(p1, m1)
+    u = oracle.update(p1, cost)
+    assert np.allclose(u - p1.u_nom, oracle.control_noise(p1)[0], rtol=1e-14, atol=1e-15)
