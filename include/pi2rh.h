@@ -138,6 +138,21 @@ typedef struct {
                                     * matrix-core rollouts with tile_samples
                                     * <= 16 (4 waves, or 8 for the quadrotor)
                                     * only; otherwise 1.                       */
+  int32_t ctrl_cost;               /* 1: add the control terms of the
+                                    * cost-to-go S-tilde (Sec. 3.1, below
+                                    * Eq. 2), which the experiments drop
+                                    * (Sec. 5), to every step's cost:
+                                    * u^T G_c^T H^-1 G_c u dt + u^T G_c^T H^-1 B dw
+                                    * with u the nominal control.  Hybrid model
+                                    * only (PI_ERR_UNSUPPORTED otherwise): its
+                                    * commanded rates are the control-affine
+                                    * channel, G_c = 25 I, the noise enters
+                                    * through it (B dw = G_c eps dt) and
+                                    * B B^T = lambda G_c R^-1 G_c^T fixes
+                                    * R = lambda diag(1/sigma^2)/dt, so the terms
+                                    * are sum_a lambda/sigma_a^2 u_a (u_a + eps_a)
+                                    * over the three rates; noise_std[0..2]
+                                    * must be > 0 (PI_ERR_VALUE).  0: off.     */
 } pi_problem;
 
 /* Bytes of workspace `op` needs for this problem/model (0 is a valid answer;

@@ -60,7 +60,7 @@ class pi_problem(C.Structure):
                 ("obs_penalty", C.c_double), ("obs_decay", C.c_double),
                 ("weighting", C.c_int32), ("problem_id", C.c_uint32), ("seed", C.c_uint64),
                 ("variant", C.c_int32), ("tile_samples", C.c_int32), ("tile_waves", C.c_int32),
-                ("tile_split", C.c_int32)]
+                ("tile_split", C.c_int32), ("ctrl_cost", C.c_int32)]
 
 
 _lib = None
@@ -268,6 +268,7 @@ class DeviceProblem:
         s.variant, s.tile_samples = int(self.variant), int(self.tile_samples)
         s.tile_waves = int(self.tile_waves)
         s.tile_split = int(self.tile_split)
+        s.ctrl_cost = int(getattr(p, "ctrl_cost", 0))
         return s
 
 

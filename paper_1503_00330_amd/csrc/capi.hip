@@ -89,6 +89,14 @@ pi_status check_problem(const pi_problem *p) {
     return fail(PI_ERR_VALUE, "tile_waves=%d must be 0, 4 or 8", p->tile_waves);
   if (p->tile_split < 0 || p->tile_split > 2)
     return fail(PI_ERR_VALUE, "tile_split=%d must be 0, 1 or 2", p->tile_split);
+  if (p->ctrl_cost != 0 && p->ctrl_cost != 1) return fail(PI_ERR_VALUE, "ctrl_cost=%d must be 0 or 1", p->ctrl_cost);
+  if (p->ctrl_cost) {
+    if (p->dyn != PI_DYN_QUAD_HYBRID)
+      return fail(PI_ERR_UNSUPPORTED, "ctrl_cost needs the hybrid model's control-affine rate channel");
+    for (int a = 0; a < 3; ++a)
+      if (!(p->noise_std[a] > 0) || !isfinite(p->noise_std[a]))
+        return fail(PI_ERR_VALUE, "ctrl_cost needs finite noise_std[%d] > 0 (R = lambda diag(1/sigma^2)/dt)", a);
+  }
   return PI_OK;
 }
 
@@ -177,6 +185,9 @@ ProbDev<Real> prob_dev(const pi_problem *p) {
   d.key0 = (uint32_t)p->seed;
   d.key1 = (uint32_t)(p->seed >> 32);
   d.problem_id = p->problem_id;
+  d.ctrl_cost = p->ctrl_cost;
+  for (int a = 0; a < 3; ++a)
+    d.ctrl_w[a] = p->ctrl_cost ? (Real)(p->lambda / (p->noise_std[a] * p->noise_std[a])) : (Real)0;
   return d;
 }
 
@@ -337,9 +348,14 @@ size_t sub_bytes(const pi_problem *p) {
   return Ms > 1 ? align_up((size_t)p->K * Ms * p->T * (p->dtype == PI_F64 ? 8 : 4), 256) : 0;
 }
 
+// Workspace of a rollout: the folded model (none when the caller passes one in
+// pi_lwpr.folded), then the sub-rollout costs (M > 1), then the exchange slots
+// of a pair-capable plan.
+size_t rollout_fold_region(const pi_lwpr *m, const RolloutPlan &pl) { return m->folded ? 0 : fold_bytes(m, pl.mfma); }
+
 size_t rollout_ws(const pi_problem *p, const pi_lwpr *m) {
   const RolloutPlan pl = rollout_plan(p, m);
-  size_t b = fold_bytes(m, pl.mfma) + sub_bytes(p);
+  size_t b = rollout_fold_region(m, pl) + sub_bytes(p);
   if (pl.pair_ok) b += pair_ws_bytes(pl.groups);
   return b;
 }
@@ -407,6 +423,50 @@ pi_status batch_sizes(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchSiz
   bs.plan_bytes = align_up(bs.items_off + (size_t)n * sizeof(BatchedItem), 256);
   *out = bs;
   return PI_OK;
+}
+
+// Validation of a rollout request (everything but the workspace).
+pi_status check_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
+                        const uint32_t *iter, const void *cost) {
+  PI_TRY(check_pair(p, m));
+  if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost must be non-NULL");
+  const RolloutPlan pl = rollout_plan(p, m);
+  if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
+    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
+  return check_folded(m, pl.mfma);
+}
+
+// The launches of a validated rollout, with its workspace at `ws` (laid out
+// as rollout_ws describes).
+hipError_t run_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
+                       const uint32_t *iter, void *cost, void *ws, hipStream_t s) {
+  const RolloutPlan pl = rollout_plan(p, m);
+  const ModelArgs a = model_args(m);
+  const int Ms = p->M > 0 ? p->M : 1;
+  const size_t fb = rollout_fold_region(m, pl);
+  void *sub = Ms > 1 ? (void *)((char *)ws + fb) : cost;
+  const void *base = nullptr;
+  hipError_t e = folded_base(m, pl.mfma, ws, s, &base);
+  if (e == hipSuccess) {
+    if (p->dtype == PI_F64) {
+      RolloutArgs<double> ra{prob_dev<double>(p), (const double *)x0, (const double *)u_nom, iter, (double *)sub};
+      e = launch_rollout_direct(PI_F64, &ra, a, base, s);
+    } else {
+      RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
+      if (pl.mfma) {
+        const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+        const RolloutLaunch rl = rollout_launch(p, m);
+        if (rl.pair)
+          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, (char *)ws + fb + sub_bytes(p), s);
+        else
+          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, s);
+      } else {
+        e = launch_rollout_direct(PI_F32, &ra, a, base, s);
+      }
+    }
+  }
+  if (e == hipSuccess && Ms > 1) e = launch_subcost_reduce(p->dtype, sub, cost, p->K, Ms, p->T, s);
+  return e;
 }
 
 }  // namespace
@@ -504,41 +564,10 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
 
 pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
                           const uint32_t *iter, void *cost, void *ws, size_t ws_bytes, void *stream) {
-  PI_TRY(check_pair(p, m));
-  if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost must be non-NULL");
-  const RolloutPlan pl = rollout_plan(p, m);
-  if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
-    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
-  PI_TRY(check_folded(m, pl.mfma));
+  PI_TRY(check_rollout(p, m, x0, u_nom, iter, cost));
   PI_TRY(check_ws(ws, ws_bytes, rollout_ws(p, m)));
   PI_TRY(check_device());
-  hipStream_t s = (hipStream_t)stream;
-  const ModelArgs a = model_args(m);
-  const int Ms = p->M > 0 ? p->M : 1;
-  const size_t fb = fold_bytes(m, pl.mfma);
-  void *sub = Ms > 1 ? (void *)((char *)ws + fb) : cost;
-  const void *base = nullptr;
-  hipError_t e = folded_base(m, pl.mfma, ws, s, &base);
-  if (e == hipSuccess) {
-    if (p->dtype == PI_F64) {
-      RolloutArgs<double> ra{prob_dev<double>(p), (const double *)x0, (const double *)u_nom, iter, (double *)sub};
-      e = launch_rollout_direct(PI_F64, &ra, a, base, s);
-    } else {
-      RolloutArgs<float> ra{prob_dev<float>(p), (const float *)x0, (const float *)u_nom, iter, (float *)sub};
-      if (pl.mfma) {
-        const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
-        const RolloutLaunch rl = rollout_launch(p, m);
-        if (rl.pair)
-          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, (char *)ws + fb + sub_bytes(p), s);
-        else
-          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, s);
-      } else {
-        e = launch_rollout_direct(PI_F32, &ra, a, base, s);
-      }
-    }
-  }
-  if (e == hipSuccess && Ms > 1) e = launch_subcost_reduce(p->dtype, sub, cost, p->K, Ms, p->T, s);
-  return launched(e, "pi_rollout_cost");
+  return launched(run_rollout(p, m, x0, u_nom, iter, cost, ws, (hipStream_t)stream), "pi_rollout_cost");
 }
 
 pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter, void *u_nom,

@@ -34,6 +34,8 @@ struct ProbDev {
   const Real *obs;             // dev [n_obs][3]
   Real obs_penalty, obs_decay;
   uint32_t key0, key1, problem_id;
+  int ctrl_cost;               // 1: add the control terms of the cost-to-go (hybrid model)
+  Real ctrl_w[3];              // lambda / sigma_a^2 of the commanded-rate channels
 };
 
 // ---------------------------------------------------------------- Philox
@@ -197,6 +199,23 @@ __device__ __forceinline__ Real state_cost(const ProbDev<Real> &p, const Real *o
       c += p.obs_penalty * exp_(-p.obs_decay * (dx * dx + dy * dy));
     }
   }
+  return c;
+}
+
+// Control terms of the cost-to-go S-tilde (Sec. 3.1, below Eq. 2) for one step
+// of the hybrid model, whose commanded rates are its control-affine channel:
+// G_c = kRateGain I and the noise enters through the same channel, B dw =
+// G_c eps dt.  Then G_c^T H^-1 G_c = R with H = G_c R^-1 G_c^T, and
+// B B^T = lambda G_c R^-1 G_c^T with eps ~ N(0, diag(sigma^2)) per step gives
+// R = lambda diag(1/sigma^2) / dt, so
+//   u^T G_c^T H^-1 G_c u dt + u^T G_c^T H^-1 B dw = sum_a lambda/sigma_a^2 u_a (u_a + eps_a)
+// over the three commanded rates; u is the nominal control, eps its sampled
+// perturbation.
+template <typename Real>
+__device__ __forceinline__ Real control_cost(const ProbDev<Real> &p, const Real *u_nom_t, const Real *pert) {
+  Real c = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c += p.ctrl_w[a] * u_nom_t[a] * (u_nom_t[a] + pert[a]);
   return c;
 }
 

@@ -149,10 +149,16 @@ __global__ void __launch_bounds__(128) rollout_direct_kernel(RolloutArgs<Real> r
   for (int a = 0; a < NX; ++a) x[a] = ra.x0[a];
   __syncthreads();
   for (int t = 0; t < p.T; ++t) {
-    Real eps[4], u[NU];
+    Real eps[4], u[NU], pert[NU];
     normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)t, eps);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) u[a] = ra.u_nom[t * NU + a] + p.noise_std[a] * eps[a];
+    for (int a = 0; a < NU; ++a) {
+      pert[a] = p.noise_std[a] * eps[a];
+      u[a] = ra.u_nom[t * NU + a] + pert[a];
+    }
+    Real cu = 0;
+    if constexpr (DYN == kDynQuadHybrid)
+      if (p.ctrl_cost) cu = control_cost<Real>(p, ra.u_nom + t * NU, pert);
     Real z[D];
     lwpr_input<DYN>(x, u, z);
     direct_mixture<Real, D>(m, rec, z, tile, out);
@@ -170,7 +176,7 @@ __global__ void __launch_bounds__(128) rollout_direct_kernel(RolloutArgs<Real> r
     euler_step<Real>(DYN, p.dt, x, acc, u, xn);
 #pragma unroll
     for (int a = 0; a < NX; ++a) x[a] = xn[a];
-    const Real c = p.dt * state_cost<Real>(p, obs, x);
+    const Real c = p.dt * state_cost<Real>(p, obs, x) + cu;
     if (active) ra.cost[s * p.T + t] = c;
   }
 }
@@ -214,11 +220,17 @@ __global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(
     if (tc == 0) {
       __syncthreads();   // lane 0 of every row is done with the previous chunk
       if (active && t + l < p.T) {
-        Real e[NU];
+        Real e[NU], pert[NU];
         normals<Real, NU>(p.key0, p.key1, wc, k, 0u, (uint32_t)(t + l), e);
 #pragma unroll
-        for (int a = 0; a < NU; ++a) us_s[l][g][a] = ra.u_nom[(t + l) * NU + a] + p.noise_std[a] * e[a];
+        for (int a = 0; a < NU; ++a) {
+          pert[a] = p.noise_std[a] * e[a];
+          us_s[l][g][a] = ra.u_nom[(t + l) * NU + a] + pert[a];
+        }
         if (p.M > 0) normals<Real, NO>(p.key0, p.key1, wd, k, mm, (uint32_t)(t + l), xi_s[l][g]);
+        // the step's control terms ride in the draw slot the hybrid model leaves unused
+        if constexpr (DYN == kDynQuadHybrid)
+          if (p.ctrl_cost) xi_s[l][g][7] = control_cost<Real>(p, ra.u_nom + (t + l) * NU, pert);
       }
     }
     if (l == 0) {
@@ -270,7 +282,10 @@ __global__ void __launch_bounds__(kGroupLanes *kGroupRows) rollout_group_kernel(
       euler_step<Real>(DYN, p.dt, x, acc, u, xn);
 #pragma unroll
       for (int a = 0; a < NX; ++a) x[a] = xn[a];
-      ra.cost[s * p.T + t] = p.dt * state_cost<Real>(p, obs, x);
+      Real c = p.dt * state_cost<Real>(p, obs, x);
+      if constexpr (DYN == kDynQuadHybrid)
+        if (p.ctrl_cost) c += xi_s[tc][g][7];
+      ra.cost[s * p.T + t] = c;
     }
   }
 }

@@ -782,7 +782,10 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       const int rr = i / n, cc = i - rr * n;
       const int64_t ss = s_base + rr;
       if (rr >= spw || ss >= (int64_t)p.K * p.Ms) continue;
-      cost[ss * p.T + t0 + cc] = failed ? __builtin_nanf("") : p.dt * state_cost<float>(p, rs.obs_s, rs.xc[cc][rr]);
+      float c = p.dt * state_cost<float>(p, rs.obs_s, rs.xc[cc][rr]);
+      if constexpr (DYN == kDynQuadHybrid)
+        if (p.ctrl_cost) c += rs.xi_s[cc][rr][7];
+      cost[ss * p.T + t0 + cc] = failed ? __builtin_nanf("") : c;
     }
   };
   for (int t = 0; t < p.T; ++t) {
@@ -791,6 +794,9 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       if (t > 0) {
         __syncthreads();  // the chunk's states are in rs.xc
         flush_costs(t - kNoiseChunk, kNoiseChunk);
+        // the control terms of the flushed chunk are read from the draw slots
+        // the next chunk overwrites
+        if (DYN == kDynQuadHybrid && p.ctrl_cost) __syncthreads();
       }
       // draw the next chunk: one lane per (step, row, counter block)
       constexpr int NB = 1 + (NO + 3) / 4;
@@ -801,11 +807,16 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
         if (!act) continue;
         const uint32_t kk = (uint32_t)(ss / p.Ms), mm = (uint32_t)(ss % p.Ms);
         if (blk == 0) {
-          float e4[4];
+          float e4[4], pert[NU];
           normals<float, 4>(p.key0, p.key1, wc, kk, 0u, (uint32_t)(t + cc), e4);
 #pragma unroll
-          for (int a = 0; a < NU; ++a)
-            rs.us_s[cc][rr][a] = u_nom[(t + cc) * NU + a] + p.noise_std[a] * e4[a];
+          for (int a = 0; a < NU; ++a) {
+            pert[a] = p.noise_std[a] * e4[a];
+            rs.us_s[cc][rr][a] = u_nom[(t + cc) * NU + a] + pert[a];
+          }
+          // the step's control terms ride in the draw slot the hybrid model leaves unused
+          if constexpr (DYN == kDynQuadHybrid)
+            if (p.ctrl_cost) rs.xi_s[cc][rr][7] = control_cost<float>(p, u_nom + (t + cc) * NU, pert);
         } else if (p.M > 0) {
           // counter block blk-1 of the sub-rollout's draw: normals 4(blk-1) .. 4(blk-1)+3
           const Philox4 r4 = philox4x32_10((uint32_t)(t + cc), kk, (mm << 4) | (uint32_t)(blk - 1), wd,

@@ -153,6 +153,21 @@ class TestValidation:
         ps.noise_std[1] = -0.1
         assert _rollout(ps, ms) == 3
 
+    def test_control_terms_need_the_hybrid_rate_channel(self):
+        # the control terms of S-tilde need a control-affine channel (the hybrid
+        # model's commanded rates) and R = lambda diag(1/sigma^2)/dt finite
+        ps, ms = _structs()
+        ps.ctrl_cost = 1
+        assert _rollout(ps, ms) == 7 and "hybrid" in pi.last_error()
+        ps, ms = _structs(dyn=synth.DYN_QUAD_HYBRID)
+        ps.ctrl_cost = 2
+        assert _rollout(ps, ms) == 3
+        ps.ctrl_cost = 1
+        ps.noise_std[1] = 0.0
+        assert _rollout(ps, ms) == 3 and "noise_std[1]" in pi.last_error()
+        ps.noise_std[1] = 0.3
+        assert _rollout(ps, ms) == 6          # valid: reaches the device check
+
     def test_workspace_too_small(self):
         ps, ms = _structs()
         need = pi.load().pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms))

@@ -233,6 +233,44 @@ def test_rollout_hybrid_quadrotor(shape, M):
     assert nrel(cost, ref) <= 1e-4
 
 
+# the control terms of S-tilde on the hybrid model: the matrix-core tiles
+# (paired, single, 32 rows), the 16-lane direct kernel and, past 8192
+# sub-rollouts, the lane-per-sub-rollout direct kernel
+CTRL_SHAPES = HYBRID_SHAPES + [(pi.PI_VARIANT_DIRECT, 0, 0, 2100)]
+
+
+@pytest.mark.parametrize("shape", CTRL_SHAPES)
+@pytest.mark.parametrize("M", [0, 1, 4])
+def test_rollout_control_terms(shape, M):
+    variant, spw, split = shape[:3]
+    K = shape[3] if len(shape) > 3 else 150
+    prob, model = synth.paper_shape(M=M, K=K, T=37)
+    prob.u_nom = np.random.default_rng(7 + M).normal(0.0, 0.3, prob.u_nom.shape).astype(F32)
+    prob.ctrl_cost = 1
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    off = prob.copy()
+    off.ctrl_cost = 0
+    ctrl = ref - oracle.rollout_cost(off, model)
+    assert np.abs(ctrl).max() > 0.1 * np.abs(ref).max()    # the terms matter here
+    cost_check(cost, ref, prob, 1e-4)
+
+
+def test_control_terms_fp64_iteration():
+    # end to end in double: rollouts with the control terms, then the update
+    # weighting by S-tilde
+    prob, model = synth.paper_shape(M=1, K=96, T=17, dtype=F64)
+    prob.u_nom = np.random.default_rng(3).normal(0.0, 0.3, prob.u_nom.shape)
+    prob.ctrl_cost = 1
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    cost = pi.rollout_cost(dp, dm)
+    ref_cost, ref_u = oracle.iteration(prob, model)
+    assert np.max(np.abs(cost.cpu().numpy() - ref_cost)) <= 1e-10 * np.abs(ref_cost).max()
+    pi.update(dp, cost)
+    assert np.max(np.abs(dp.u_nom.cpu().numpy() - ref_u)) <= 1e-10
+
+
 @pytest.mark.parametrize("M", [0, 1, 4, 8, 16, 32])
 def test_rollout_paper_shapes_full(M):
     # the paper's timing shapes at full size (1000 rollouts x 50 steps, M
