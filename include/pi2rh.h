@@ -195,7 +195,9 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
  * so S_k = sum_t cost[k][t].  `iter` (dev, one uint32) is the iteration
  * counter of the random stream.  With paired workgroups (tile_split) every
  * wait of a workgroup on its partner is bounded; should one run out (the
- * pair was not resident at once), the affected costs are written as NaN.
+ * pair was not resident at once), that pair abandons its tile: its costs are
+ * written as NaN from that step on (never finite values from a half whose
+ * state went stale) and the abandonment is counted (pi_pair_give_ups).
  * The library pairs only grids that fit the device's compute units at once;
  * the 8-wave paired grid of the library's choice can fill them exactly (one
  * workgroup per unit), so a caller that runs other kernels concurrently on
@@ -203,6 +205,15 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
 pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
                           const void *u_nom, const uint32_t *iter, void *cost, void *ws,
                           size_t ws_bytes, void *stream);
+
+/* Workgroups of paired rollout launches (pi_rollout_cost with tile_split)
+ * that abandoned their tile because a bounded wait on their partner ran out,
+ * counted on the current device since the library was loaded: writes one
+ * uint64 to *count (dev), stream-ordered after the launches before it.  Read
+ * it before and after a launch: an increase means some of that launch's costs
+ * are NaN.  (The environment variable PI2RH_PAIR_SPIN_LIMIT, read at each
+ * launch, sets the polls of one wait -- for tests that force a give-up.)     */
+pi_status pi_pair_give_ups(uint64_t *count, void *stream);
 
 /* Path-integral update, Eq. (2): S_{k,i} = sum_{t>=i} cost[k][t] (or S_{k,0}
  * for PI_W_TRAJECTORY); P_{k,i} = softmax_k(-S_{k,i}/lambda);

@@ -32,7 +32,7 @@ STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4:
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6), PI_DYN_QUAD_HYBRID: (9, 4, 3)}
 EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
             "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
-            "pi_batched_plan", "pi_rollout_cost_batched", "pi_philox4x32_10", "pi_noise",
+            "pi_batched_plan", "pi_rollout_cost_batched", "pi_pair_give_ups", "pi_philox4x32_10", "pi_noise",
             "pi_last_error", "pi_version"]
 PI_TAG_CTRL, PI_TAG_DYN, PI_TAG_PLANT = 0, 1, 2
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.pi_batched_workspace_bytes.restype = sz
     lib.pi_batched_plan.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz, vp, sz]
     lib.pi_rollout_cost_batched.argtypes = [vp, vp, vp]
+    lib.pi_pair_give_ups.argtypes = [vp, vp]
+    lib.pi_pair_give_ups.restype = i32
     lib.pi_philox4x32_10.argtypes = [vp, C.c_uint64, vp, i64, vp]
     lib.pi_noise.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.pi_last_error.restype = C.c_char_p
@@ -427,6 +429,15 @@ def rollout_adjoint(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None
                                         ws.numel(), _stream())
     _check(st)
     return J, gu, gc, gD
+
+
+def pair_give_ups() -> int:
+    """Paired-rollout workgroups that abandoned their tile on the current
+    device so far (pi_pair_give_ups); synchronises the current stream."""
+    torch = _torch()
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _check(load().pi_pair_give_ups(_ptr(out), _stream()))
+    return int(out.item())
 
 
 def philox4x32_10(ctr, key: int):

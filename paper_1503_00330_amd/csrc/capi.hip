@@ -644,6 +644,12 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
   return launched(e, "pi_rollout_adjoint");
 }
 
+pi_status pi_pair_give_ups(uint64_t *count, void *stream) {
+  if (!count) return fail(PI_ERR_NULL, "count must be non-NULL");
+  PI_TRY(check_device());
+  return launched(launch_read_give_ups(count, (hipStream_t)stream), "pi_pair_give_ups");
+}
+
 pi_status pi_philox4x32_10(const uint32_t *ctr, uint64_t key, uint32_t *out, int64_t N,
                            void *stream) {
   if (N < 0) return fail(PI_ERR_SHAPE, "N must be >= 0");

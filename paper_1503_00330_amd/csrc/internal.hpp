@@ -153,6 +153,8 @@ int pair_grid(int64_t n_groups);
 int pair_blocks_per_cu(int dyn, int waves);
 hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
                                int waves, void *pair_ws, hipStream_t s);
+// The device's count of paired workgroups that gave up a wait, to out[0].
+hipError_t launch_read_give_ups(uint64_t *out, hipStream_t s);
 
 // ---- adjoint -------------------------------------------------------------------
 int adjoint_default_ckpt(int T);

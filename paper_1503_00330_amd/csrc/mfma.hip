@@ -31,6 +31,8 @@
 // step always takes this second pass so its reference mean is the first
 // pass's mean.
 // (PI^2-RH with LWPR dynamics, arXiv:1503.00330.)
+#include <stdlib.h>
+
 #include "internal.hpp"
 
 namespace pi2rh {
@@ -538,15 +540,25 @@ __device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out, u
 // every one of our lanes has read it (it needs our next evaluation's words,
 // published after a barrier that follows the reads).  The slots are zeroed
 // before each launch.  Every wait is bounded: on running out, pair_fail is
-// set, no further waits are made and the rollout's costs are written as NaN.
+// set, no further waits are made and the rollout's costs are written as NaN
+// from then on.  A workgroup that has given up no longer holds valid state,
+// so every word it publishes afterwards carries the poison sequence number
+// instead of a valid one; a partner that reads a poisoned word gives up too.
+// Each workgroup that gave up is counted in pair_give_ups_total.
 struct PairCtx {
-  uint64_t *xbuf;    // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
-  int half;          // 0 or 1; -1 when not paired
+  uint64_t *xbuf;       // the pair's slots: [half][parity][5][kXSlots] (sums Z, S1, S2, S3, mx)
+  int half;             // 0 or 1; -1 when not paired
+  uint32_t spin_limit;  // polls of one wait before giving up
 };
 __device__ __forceinline__ bool writer_of(const PairCtx *pc) { return pc == nullptr || pc->half == 0; }
 constexpr int kXSlots = 16 * kMaxOut;
 constexpr int kPairWords = 2 * 2 * kXSlots * 5;
 constexpr uint32_t kSpinLimit = 1u << 20;
+// Sequence number of the words of a workgroup that has given up; valid ones
+// run from 1 to twice the horizon, far below it.
+constexpr uint32_t kPoisonSeq = 0xFFFFFFFFu;
+// Workgroups of paired launches on this device that gave up a wait, since load.
+__device__ unsigned long long pair_give_ups_total = 0;
 
 __device__ __forceinline__ void put_word(uint64_t *p, float v, uint32_t seq) {
   __hip_atomic_store(p, ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
@@ -564,23 +576,27 @@ __device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, co
   const Acc loc = sum_waves(sm, row, o);
   // consecutive lanes write consecutive words of each sum
   uint64_t *dst = pc.xbuf + (size_t)(pc.half * 2 + (seq & 1)) * 5 * kXSlots + i;
-  put_word(dst + 0 * kXSlots, loc.Z, seq);
-  put_word(dst + 1 * kXSlots, loc.S1, seq);
-  put_word(dst + 2 * kXSlots, loc.S2, seq);
-  put_word(dst + 3 * kXSlots, loc.S3, seq);
-  put_word(dst + 4 * kXSlots, loc.mx, seq);
+  // pair_fail is read after the barrier that closed the previous evaluation:
+  // every lane agrees whether this workgroup's state is still valid
+  const uint32_t tag = sm.pair_fail ? kPoisonSeq : seq;
+  put_word(dst + 0 * kXSlots, loc.Z, tag);
+  put_word(dst + 1 * kXSlots, loc.S1, tag);
+  put_word(dst + 2 * kXSlots, loc.S2, tag);
+  put_word(dst + 3 * kXSlots, loc.S3, tag);
+  put_word(dst + 4 * kXSlots, loc.mx, tag);
   const uint64_t *src = pc.xbuf + (size_t)((1 - pc.half) * 2 + (seq & 1)) * 5 * kXSlots + i;
   uint64_t w[5];
   uint32_t n = 0;
   for (;;) {
-    bool ready = true;
+    bool ready = true, poisoned = false;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       w[k] = __hip_atomic_load(src + k * kXSlots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       ready = ready && (uint32_t)(w[k] >> 32) == seq;
+      poisoned = poisoned || (uint32_t)(w[k] >> 32) == kPoisonSeq;
     }
     if (ready) break;
-    if (sm.pair_fail || ++n >= kSpinLimit) {
+    if (poisoned || sm.pair_fail || ++n >= pc.spin_limit) {
       sm.pair_fail = 1;
       break;
     }
@@ -918,16 +934,21 @@ rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
 template <int DYN, int NW>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, 1, NW>())))
 rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
-                                                               int n_groups, uint64_t *__restrict__ xbuf) {
+                                                               int n_groups, uint64_t *__restrict__ xbuf,
+                                                               uint32_t spin_limit) {
   __shared__ RollSmem<DYN, 1, NW> rs;
   const int blk = blockIdx.x;
   const int g = (blk / 16) * 8 + (blk % 8);
   if (g >= n_groups) return;  // both halves of an unused pair leave
-  const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1};
+  const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1, spin_limit};
   mix_setup(rs.sm);
   rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
                            ra.trace);
+  // pair_fail is final: the tile's last evaluation ended with a barrier
+  if (threadIdx.x == 0 && rs.sm.pair_fail) atomicAdd(&pair_give_ups_total, 1ull);
 }
+
+__global__ void read_give_ups_kernel(unsigned long long *out) { out[0] = pair_give_ups_total; }
 
 // Persistent form for many independent problems: every workgroup pulls
 // (problem, tile) items from a queue (items are ordered by decreasing work)
@@ -1011,21 +1032,29 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
   // sequence numbers restart at 1 every launch: clear the previous launch's
   hipError_t e = launch_zero_u32((uint32_t *)xbuf, 2 * n_groups * kPairWords, s);
   if (e != hipSuccess) return e;
+  // PI2RH_PAIR_SPIN_LIMIT (testing): polls of one wait before giving up
+  uint32_t spin = kSpinLimit;
+  if (const char *env = getenv("PI2RH_PAIR_SPIN_LIMIT")) spin = (uint32_t)strtoul(env, nullptr, 10);
   const dim3 grid((unsigned)pair_grid(n_groups));
   if (ra.p.dyn == kDynQuad12) {
     if (waves == 8)
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8>), grid, dim3(512), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf);
+                         xbuf, spin);
     else
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4>), grid, dim3(256), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf);
+                         xbuf, spin);
   } else if (ra.p.dyn == kDynQuadHybrid) {
     hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4>), grid, dim3(256), 0, s, ra, md, spw,
-                       (int)n_groups, xbuf);
+                       (int)n_groups, xbuf, spin);
   } else {
     hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4>), grid, dim3(256), 0, s, ra, md, spw,
-                       (int)n_groups, xbuf);
+                       (int)n_groups, xbuf, spin);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_read_give_ups(uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(read_give_ups_kernel, dim3(1), dim3(1), 0, s, (unsigned long long *)out);
   return hipGetLastError();
 }
 
