@@ -22,7 +22,11 @@
  *  - `dtype` of a problem and of its model must agree.  PI_F32 computes in
  *    single precision (the update's normalisation and weighted sums are
  *    always double); PI_F64 runs the same method entirely in double.
- *  - Non-finite inputs propagate; nothing is clamped.
+ *  - Non-finite inputs propagate (NaN/Inf in x0, u_nom or a model parameter
+ *    reach the affected costs and updates as they would in exact IEEE
+ *    arithmetic).  The one clamp: the spread term sum_j w_j (y_j - mean)^2 of
+ *    the mixture variance (Eq. 1), non-negative by definition, is held at
+ *    >= 0 where float32 rounding of its running form would make it negative.
  */
 #ifndef PI2RH_H_
 #define PI2RH_H_
@@ -232,48 +236,64 @@ pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter,
 pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_nom,
                       const uint32_t *iter, void *ws, size_t ws_bytes, void *stream);
 
-/* Adjoint of the expected rollout cost with the noise held fixed:
+/* Adjoint of the expected rollout cost with the noise held fixed
+ * (reparameterised; not in the paper, which optimises by sampling alone):
  *   J = (1/(K max(M,1))) sum_{k,m,t} dt q(x_{k,m,t+1}),
- * writes J (dev, one double) and its gradients w.r.t. the nominal controls
- * g_u_nom dev [T][n_u], the centres g_centre dev [Ltot][d] and every entry of
- * the metrics g_metric dev [Ltot][d][d] (problem dtype).  States are
- * checkpointed every `ckpt_every` steps (0: ceil(sqrt(T))) and recomputed
- * segment by segment in the reverse sweep.  Float32 problems whose model has
- * a matrix-core form (see PI_VARIANT_MFMA; variant not PI_VARIANT_DIRECT) run
- * the forward on the matrix cores and keep every step's state and mixture
- * moments (no recompute; ckpt_every is then unused).
- * pi_workspace_bytes(PI_OP_ADJOINT) sizes the workspace for the default
- * checkpoint interval; another interval may need more (PI_ERR_WORKSPACE says
- * how much).  The indicator obstacle term has zero derivative almost
- * everywhere.                                                                */
-/* (PI_DYN_POINTMASS2D and PI_DYN_QUAD12; PI_ERR_UNSUPPORTED otherwise.)     */
+ * the mean over sub-rollouts of the sampled cost S of Sec. 3.1/3.2 under the
+ * LWPR dynamics of Eq. (1).  Writes J (dev, one double, unscaled) and the
+ * gradients of gJ * J w.r.t. the nominal controls g_u_nom dev [T][n_u], the
+ * centres g_centre dev [Ltot][d] and every entry of the metrics g_metric dev
+ * [Ltot][d][d] (problem dtype; the metric gradient is symmetric).  gJ (dev,
+ * one double) seeds the reverse pass; NULL means 1.  States are checkpointed
+ * every `ckpt_every` steps (0: ceil(sqrt(T))) and each segment is recomputed
+ * from its checkpoints before its reverse sweep, so the workspace holds the
+ * checkpoints and one segment: pi_adjoint_workspace_bytes(p, m, ckpt_every)
+ * (or pi_workspace_bytes(PI_OP_ADJOINT), for ckpt_every 0).  Float32
+ * problems whose model has a matrix-core form (see PI_VARIANT_MFMA; variant
+ * not PI_VARIANT_DIRECT) run the forward, the recompute and the reverse sweep
+ * on the matrix cores and keep per-step records for one segment only; the
+ * direct kernels (float64, PI_VARIANT_DIRECT) keep them for every step.  The
+ * indicator obstacle term has zero derivative almost everywhere.
+ * (PI_DYN_POINTMASS2D and PI_DYN_QUAD12 without ctrl_cost;
+ * PI_ERR_UNSUPPORTED otherwise.)                                             */
+size_t pi_adjoint_workspace_bytes(const pi_problem *p, const pi_lwpr *m, int32_t ckpt_every);
 pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0,
                              const void *u_nom, const uint32_t *iter, int32_t ckpt_every,
-                             void *J, void *g_u_nom, void *g_centre, void *g_metric, void *ws,
-                             size_t ws_bytes, void *stream);
+                             const void *gJ, void *J, void *g_u_nom, void *g_centre,
+                             void *g_metric, void *ws, size_t ws_bytes, void *stream);
 
-/* Batched rollouts of B independent problems in one persistent launch
- * (problems may differ in K, T, M, models, obstacles and start states).
- * Step 1: size the caller-owned workspace (pi_batched_workspace_bytes) and
- * the HOST plan buffer (pi_batched_plan_bytes).  Step 2: pi_batched_plan
- * fills the plan with per-problem descriptors and a work list of
- * (problem, sample tile) items ordered by decreasing work; it records the
- * workspace and every per-problem device pointer.  Step 3: the caller copies
- * the plan to device memory of the same size.  Step 4:
- * pi_rollout_cost_batched runs every item -- one workgroup per item, pulled
- * from a queue by a persistent grid -- and writes each problem's cost[b]
- * (dev [K_b][T_b]) exactly as pi_rollout_cost would.  Per-problem arrays are
- * host arrays of B device pointers.  All problems must be PI_F32 and
- * PI_DYN_QUAD12; tile_samples/tile_waves of problem 0 apply to the batch.
- * The plan, workspace and every recorded pointer must stay valid while a
- * launch that uses them is in flight.                                        */
+/* Batched controllers: B independent PI^2-RH problems (Sec. 3.1, 3.2 each;
+ * batching is this library's, not the paper's) that may differ in K, T, M,
+ * models, obstacles, goals and start states, with every problem's rollout
+ * tiles in one persistent launch: a grid sized to the device pulls (problem,
+ * tile) work items, ordered by decreasing work, from a queue.  Per-problem
+ * arrays are host arrays of B device pointers: x0[b] [n_x], u_nom[b]
+ * [T_b][n_u], iter[b] (one uint32), cost[b] [K_b][T_b].  All problems must be
+ * PI_F32 and PI_DYN_QUAD12 with matrix-core models (PI_ERR_UNSUPPORTED
+ * otherwise).  A problem's tile_samples (<= 32; 0 = 16) sets its tile;
+ * tile_waves of problem 0 applies to the batch (8 needs every tile <= 16).
+ * Models given pre-folded (pi_lwpr.folded) are read in place; the others are
+ * folded into the workspace on every call.  The launch plan (descriptors and
+ * work list) is written into the workspace by kernels on `stream`, so these
+ * calls copy no host memory and may be captured into a HIP graph.
+ *
+ * pi_batched_workspace_bytes: the workspace of either call ((size_t)-1 and
+ * pi_last_error() on invalid arguments).
+ * pi_rollout_cost_batched: writes every cost[b] exactly as pi_rollout_cost
+ * would with one 4-wave (or tile_waves) workgroup per tile (tile_split 1).
+ * pi_control_step_batched: the same rollouts, then per problem, in problem
+ * order, the update of pi_update (Eq. 2; *iter[b] advances) and the
+ * receding-horizon advance of pi_rh_shift (Sec. 3.1, last paragraph):
+ * x0[b], u_nom[b] and iter[b] end exactly as after one plain control step
+ * (pi_rollout_cost, pi_update, pi_rh_shift) of each problem.                 */
 size_t pi_batched_workspace_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m);
-size_t pi_batched_plan_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m);
-pi_status pi_batched_plan(int32_t B, const pi_problem *p, const pi_lwpr *m,
-                          const void *const *x0, const void *const *u_nom,
-                          const uint32_t *const *iter, void *const *cost, void *ws,
-                          size_t ws_bytes, void *plan_host, size_t plan_bytes);
-pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *stream);
+pi_status pi_rollout_cost_batched(int32_t B, const pi_problem *p, const pi_lwpr *m,
+                                  const void *const *x0, const void *const *u_nom,
+                                  const uint32_t *const *iter, void *const *cost, void *ws,
+                                  size_t ws_bytes, void *stream);
+pi_status pi_control_step_batched(int32_t B, const pi_problem *p, const pi_lwpr *m,
+                                  void *const *x0, void *const *u_nom, uint32_t *const *iter,
+                                  void *const *cost, void *ws, size_t ws_bytes, void *stream);
 
 /* Streams of the counter-based generator (see pi_noise). */
 enum { PI_TAG_CTRL = 0, PI_TAG_DYN = 1, PI_TAG_PLANT = 2 };

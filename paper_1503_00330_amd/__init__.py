@@ -31,8 +31,8 @@ STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4:
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6), PI_DYN_QUAD_HYBRID: (9, 4, 3)}
 EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
-            "pi_rollout_adjoint", "pi_batched_workspace_bytes", "pi_batched_plan_bytes",
-            "pi_batched_plan", "pi_rollout_cost_batched", "pi_pair_give_ups", "pi_philox4x32_10", "pi_noise",
+            "pi_rollout_adjoint", "pi_adjoint_workspace_bytes", "pi_batched_workspace_bytes",
+            "pi_rollout_cost_batched", "pi_control_step_batched", "pi_pair_give_ups", "pi_philox4x32_10", "pi_noise",
             "pi_last_error", "pi_version"]
 PI_TAG_CTRL, PI_TAG_DYN, PI_TAG_PLANT = 0, 1, 2
 
@@ -88,13 +88,13 @@ def load(path: str = LIB_PATH):
     lib.pi_rollout_cost.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_update.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_rh_shift.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
-    lib.pi_rollout_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
-    lib.pi_batched_plan_bytes.argtypes = [i32, vp, vp]
-    lib.pi_batched_plan_bytes.restype = sz
+    lib.pi_rollout_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pi_adjoint_workspace_bytes.argtypes = [vp, vp, i32]
+    lib.pi_adjoint_workspace_bytes.restype = sz
     lib.pi_batched_workspace_bytes.argtypes = [i32, vp, vp]
     lib.pi_batched_workspace_bytes.restype = sz
-    lib.pi_batched_plan.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz, vp, sz]
-    lib.pi_rollout_cost_batched.argtypes = [vp, vp, vp]
+    lib.pi_rollout_cost_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pi_control_step_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_pair_give_ups.argtypes = [vp, vp]
     lib.pi_pair_give_ups.restype = i32
     lib.pi_philox4x32_10.argtypes = [vp, C.c_uint64, vp, i64, vp]
@@ -102,7 +102,7 @@ def load(path: str = LIB_PATH):
     lib.pi_last_error.restype = C.c_char_p
     lib.pi_version.restype = C.c_char_p
     for name in ("lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
-                 "pi_rollout_adjoint", "pi_batched_plan", "pi_rollout_cost_batched",
+                 "pi_rollout_adjoint", "pi_rollout_cost_batched", "pi_control_step_batched",
                  "pi_philox4x32_10", "pi_noise"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -366,44 +366,80 @@ def iteration(prob: DeviceProblem, model: DeviceModel, cost=None):
 
 
 class BatchedRollout:
-    """Rollouts of many independent problems in one persistent launch
-    (pi_rollout_cost_batched).  The plan records the device pointers of every
-    problem's x0, u_nom, iter and cost, so those tensors must stay alive."""
+    """Many independent problems in one persistent launch: run() gives every
+    problem's rollout costs (pi_rollout_cost_batched); control_step() runs
+    their rollouts, updates and receding-horizon advances
+    (pi_control_step_batched).  The struct arrays and the pointer arrays are
+    built here once; the problems' tensors (x0, u_nom, iter, costs) are
+    updated in place, so a call can be captured into a HIP graph (capture())
+    and replayed."""
 
     def __init__(self, problems, models, costs=None):
         torch = _torch()
         lib = load()
         self.problems, self.models = list(problems), list(models)
-        B = len(self.problems)
+        B = self.B = len(self.problems)
         self.ps = (pi_problem * B)(*[p.struct() for p in self.problems])
         self.ms = (pi_lwpr * B)(*[m.struct() for m in self.models])
         dev = self.problems[0].device
         self.costs = costs if costs is not None else [
             torch.empty((p.K, p.T), dtype=torch.float32, device=dev) for p in self.problems]
         nws = lib.pi_batched_workspace_bytes(B, self.ps, self.ms)
-        npl = lib.pi_batched_plan_bytes(B, self.ps, self.ms)
-        if nws == C.c_size_t(-1).value or npl == C.c_size_t(-1).value:
+        if nws == C.c_size_t(-1).value:
             raise PiError(2, last_error())
         self.ws = torch.empty(max(int(nws), 256), dtype=torch.uint8, device=dev)
-        self.plan_host = np.zeros(int(npl), dtype=np.uint8)
         arr = lambda xs: (C.c_void_p * B)(*[int(x) for x in xs])
-        _check(lib.pi_batched_plan(B, self.ps, self.ms, arr(p.x0.data_ptr() for p in self.problems),
-                                   arr(p.u_nom.data_ptr() for p in self.problems),
-                                   arr(p.iter.data_ptr() for p in self.problems),
-                                   arr(c.data_ptr() for c in self.costs), self.ws.data_ptr(),
-                                   self.ws.numel(), self.plan_host.ctypes.data, self.plan_host.size))
-        self.plan_dev = torch.from_numpy(self.plan_host).to(dev)
+        self.x0 = arr(p.x0.data_ptr() for p in self.problems)
+        self.u_nom = arr(p.u_nom.data_ptr() for p in self.problems)
+        self.iter = arr(p.iter.data_ptr() for p in self.problems)
+        self.cost_ptrs = arr(c.data_ptr() for c in self.costs)
+        self.graph = None
 
     def run(self):
-        _check(load().pi_rollout_cost_batched(self.plan_host.ctypes.data, self.plan_dev.data_ptr(),
-                                              _stream()))
+        _check(load().pi_rollout_cost_batched(self.B, self.ps, self.ms, self.x0, self.u_nom, self.iter,
+                                              self.cost_ptrs, self.ws.data_ptr(), self.ws.numel(), _stream()))
         return self.costs
+
+    def control_step(self):
+        _check(load().pi_control_step_batched(self.B, self.ps, self.ms, self.x0, self.u_nom, self.iter,
+                                              self.cost_ptrs, self.ws.data_ptr(), self.ws.numel(), _stream()))
+
+    def capture(self):
+        """Records one batched control step into a HIP graph (state not advanced)."""
+        torch = _torch()
+        saved = [(p.x0.clone(), p.u_nom.clone(), p.iter.clone()) for p in self.problems]
+        self.control_step()           # per-device checks before capture
+        torch.cuda.synchronize()
+        for p, (x, u, it) in zip(self.problems, saved):
+            p.x0.copy_(x)
+            p.u_nom.copy_(u)
+            p.iter.copy_(it)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.control_step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = g
+        return g
+
+    def step(self, graph: bool = True):
+        """One batched control step (graph replay unless graph=False)."""
+        if not graph:
+            self.control_step()
+            return
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
 
 
 def rollout_adjoint(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, iter=None,
-                    ckpt_every: int = 0):
-    """J and (dJ/du_nom, dJ/dc, dJ/dD) of the expected rollout cost with the noise
-    held fixed (pi_rollout_adjoint)."""
+                    ckpt_every: int = 0, gJ=None):
+    """J and the gradients of gJ * J w.r.t. (u_nom, centres, metrics) of the
+    expected rollout cost with the noise held fixed (pi_rollout_adjoint);
+    gJ: optional device double scalar seed (None = 1)."""
     torch = _torch()
     lib = load()
     x0 = prob.x0 if x0 is None else x0
@@ -415,19 +451,15 @@ def rollout_adjoint(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None
     gc = torch.empty_like(model.centre)
     gD = torch.empty_like(model.metric)
     ps, ms = prob.struct(), model.struct()
-    need = workspace_bytes(PI_OP_ADJOINT, prob, model)
-    ws = workspace(need, dev)
-    st = lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it), int(ckpt_every),
-                                _ptr(J), _ptr(gu), _ptr(gc), _ptr(gD), _ptr(ws), ws.numel(), _stream())
-    if st == 5:   # a non-default checkpoint interval may need a larger workspace
-        import re
-        m = re.search(r"of (\d+) bytes needed", last_error())
-        if m:
-            ws = workspace(int(m.group(1)), dev)
-            st = lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it),
-                                        int(ckpt_every), _ptr(J), _ptr(gu), _ptr(gc), _ptr(gD), _ptr(ws),
-                                        ws.numel(), _stream())
-    _check(st)
+    need = lib.pi_adjoint_workspace_bytes(C.byref(ps), C.byref(ms), int(ckpt_every))
+    if need == C.c_size_t(-1).value:
+        raise PiError(2, last_error())
+    ws = workspace(int(need), dev)
+    if gJ is not None:
+        gJ = gJ.to(device=dev, dtype=torch.float64).reshape(1).contiguous()
+    _check(lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it), int(ckpt_every),
+                                  _ptr(gJ), _ptr(J), _ptr(gu), _ptr(gc), _ptr(gD), _ptr(ws), ws.numel(),
+                                  _stream()))
     return J, gu, gc, gD
 
 

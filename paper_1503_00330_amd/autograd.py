@@ -4,7 +4,9 @@ J = PI2RHAdjoint.apply(u_nom, centre, metric, prob, model) returns the mean
 rollout cost with the noise held fixed; J.backward() yields dJ/du_nom,
 dJ/dcentre and dJ/dmetric.  The library computes J and all three gradients in
 one fused forward + reverse pass, so the forward saves the gradients and the
-backward only scales them by the incoming gradient.
+backward only scales them by the incoming gradient.  (pi_rollout_adjoint also
+takes that seed, gJ, as a device scalar; it is unknown when autograd's forward
+runs the fused pass, so here the scaling happens in backward.)
 """
 from __future__ import annotations
 

@@ -22,6 +22,12 @@
 //          sums per row chunk, reduced in a fixed order, then
 //            dJ/dD_j = sum qbar dl dl^T,
 //            dJ/dc_j = -(D_j + D_j^T) sum qbar dl - b_j sum ybar.
+// Float32 problems with a matrix-core model run stages 1 and 2 on the matrix
+// cores instead: the forward writes the costs and the checkpoints; then, per
+// segment from the last, the segment is recomputed from its checkpoints with
+// its states and moments traced, swept backwards, and its records feed the
+// parameter sums (accumulated over segments) and the control gradients, so
+// memory holds the checkpoints and one segment, not the whole horizon.
 // Every reduction has a fixed order, so results are run-to-run identical.
 // (PI^2-RH with LWPR dynamics, arXiv:1503.00330; the adjoint is not in the
 // paper.)
@@ -60,7 +66,6 @@ struct AdjArgs {
   Real *seg;            // [S][ckpt+1][SEGW]
   Real *recs;           // [S][T][RW]
   double *jsum;         // [S]
-  int recompute;        // 0: seg already holds every step ([S][T+1][SEGW], ckpt = T)
 };
 
 template <typename Real, int DYN>
@@ -232,8 +237,7 @@ __global__ void __launch_bounds__(kAThreads) adj_backward_kernel(AdjArgs<Real> a
   for (int ci = a.ncp - 1; ci >= 0; --ci) {
     const int t0 = ci * a.ckpt, t1 = min(p.T, t0 + a.ckpt);
     // recompute the segment's states and mixture moments from its checkpoint
-    // (a traced forward has already stored every step)
-    if (a.recompute) {
+    {
       if (l == 0)
         for (int i = 0; i < NX; ++i) sm.x[g][i] = active ? a.ckpt_buf[(s * a.ncp + ci) * NX + i] : (Real)0;
       for (int t = t0; t < t1; ++t) {
@@ -443,12 +447,13 @@ __device__ void param_grads_from_sums(int j, const Real *r, const double *sum, d
 // dJ/dD_j and dJ/dc_j.
 template <typename Real, int DYN>
 __global__ void adj_param_finish_kernel(ModelArgs m, const Real *__restrict__ model, int nch,
-                                        const Real *__restrict__ gpart, double scale, Real *__restrict__ gc,
-                                        Real *__restrict__ gD) {
+                                        const Real *__restrict__ gpart, double scale, const double *gJ,
+                                        Real *__restrict__ gc, Real *__restrict__ gD) {
   using G = AdjGeo<Real, DYN>;
   constexpr int D = G::D, RS = G::RS, PW = G::PW;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.Ltot) return;
+  if (gJ) scale *= *gJ;
   double sum[PW];
   for (int i = 0; i < PW; ++i) sum[i] = 0.0;
   for (int ch = 0; ch < nch; ++ch)
@@ -462,11 +467,12 @@ __global__ void adj_param_finish_kernel(ModelArgs m, const Real *__restrict__ mo
 template <int DYN>
 __global__ void adj_param_mfma_finish_kernel(ModelArgs m, MfmaLayout l, const float *__restrict__ model, int nch,
                                              const float *__restrict__ gpart, int width, double scale,
-                                             float *__restrict__ gc, float *__restrict__ gD) {
+                                             const double *gJ, float *__restrict__ gc, float *__restrict__ gD) {
   using G = AdjGeo<float, DYN>;
   constexpr int D = G::D, RS = G::RS, NP = G::NP, PW = G::PW;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.Ltot) return;
+  if (gJ) scale *= *gJ;
   int o = 0;
   while (o + 1 < m.n_out && j >= m.L_off[o + 1]) ++o;
   const int slot = (l.tile_off[o] + (j - m.L_off[o]) / 16) * 16 + (j - m.L_off[o]) % 16;
@@ -491,13 +497,15 @@ __global__ void adj_param_mfma_finish_kernel(ModelArgs m, MfmaLayout l, const fl
   param_grads_from_sums<float, D>(j, r, sum, scale, gc, gD);
 }
 
-// Stage 4b: dJ/du_nom[t] = scale * sum_s ubar[s][t] (block per step, fixed tree).
+// Stage 4b: dJ/du_nom[t] = scale * sum_s ubar[s][t] (block per step, fixed tree;
+// T steps of records from `recs`, written to gu[t]).
 template <typename Real, int DYN>
 __global__ void __launch_bounds__(256) adj_u_kernel(int64_t S, int T, const Real *__restrict__ recs,
-                                                    double scale, Real *__restrict__ gu) {
+                                                    double scale, const double *gJ, Real *__restrict__ gu) {
   using G = AdjGeo<Real, DYN>;
   __shared__ double red[256][G::NU];
   const int t = blockIdx.x;
+  if (gJ) scale *= *gJ;
   double acc[G::NU];
   for (int i = 0; i < G::NU; ++i) acc[i] = 0.0;
   for (int64_t s = threadIdx.x; s < S; s += 256)
@@ -544,52 +552,61 @@ int adjoint_default_ckpt(int T) {
 }
 
 int adjoint_param_chunks(int64_t R) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, R / 2048)); }
-// record chunks of the matrix-core parameter pass (each workgroup holds 8 model tiles)
-static int adjoint_param_chunks_mfma(int64_t R) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(64, R / 16384));
+
+// record chunks of the matrix-core parameter pass over one segment of
+// R records: each chunk's workgroups stream about 4096 records
+static int adjoint_param_chunks_seg(int64_t R) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, R / 4096));
 }
 
 // Partial sums of the parameter pass: per chunk and model, PW values (direct)
 // or adj_param_mfma_width(d) values per model slot (matrix cores; the padded
 // tiles of n_out outputs add at most 16 n_out slots).
-static size_t adj_gpart_bytes(int dtype, int d, int n_out, int Ltot, int64_t R, bool traced) {
+static size_t adj_gpart_bytes(int dtype, int d, int n_out, int Ltot, int64_t R, bool mfma) {
   const size_t rb = dtype == PI_F64 ? 8 : 4;
   const int pw = d * (d + 1) / 2 + d + 1;
-  size_t b = (size_t)adjoint_param_chunks(R) * Ltot * pw * rb;
-  if (traced)
-    b = std::max(b, (size_t)adjoint_param_chunks_mfma(R) * (size_t)(Ltot + 16 * n_out) * adj_param_mfma_width(d) * 4);
-  return align_up(b, 256);
+  if (mfma)
+    return align_up((size_t)adjoint_param_chunks_seg(R) * (size_t)(Ltot + 16 * n_out) * adj_param_mfma_width(d) * 4,
+                    256);
+  return align_up((size_t)adjoint_param_chunks(R) * Ltot * pw * rb, 256);
 }
 
+// Direct kernels: model records, checkpoints [S][ncp][NX], the segment buffer
+// [S][ckpt+1][SEGW], records of every step [S][T][RW], cost sums, parameter
+// partials.  Matrix-core form: model records, checkpoints, one segment's
+// trace [S][ckpt+1][SEGW] and records [S][ckpt][RW], cost sums, parameter
+// partials over one segment, the matrix-core tiles and reverse-sweep
+// parameters, the forward costs [S][T] and the state adjoint [S][NX].
 size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes) {
   const int Ms = M > 0 ? M : 1;
   const int64_t S = (int64_t)K * Ms;
   const int nx = dyn == kDynPointMass2D ? 4 : 12, nu = dyn == kDynPointMass2D ? 2 : 4,
             no = dyn == kDynPointMass2D ? 2 : 6;
   const size_t rb = dtype == PI_F64 ? 8 : 4;
-  const bool traced = mfma_bytes > 0;
-  if (traced) ckpt = T;
+  const bool mfma = mfma_bytes > 0;
+  ckpt = std::max(1, std::min(ckpt, T));
   const int ncp = (T + ckpt - 1) / ckpt;
-  const int segw = nx + 3 * no, rw = d + 5 * no + nu, pw = d * (d + 1) / 2 + d + 1;
-  (void)pw;
+  const int segw = nx + 3 * no, rw = d + 5 * no + nu;
+  const int64_t rec_steps = mfma ? ckpt : T;
   size_t b = direct_bytes(dtype, d, Ltot) + align_up((size_t)S * ncp * nx * rb, 256) +
-             align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * T * rw * rb, 256) +
-             align_up((size_t)S * 8, 256) + adj_gpart_bytes(dtype, d, no, Ltot, S * T, traced);
-  if (traced) b += align_up(mfma_bytes, 256) + align_up((size_t)S * T * 4, 256);
+             align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * rec_steps * rw * rb, 256) +
+             align_up((size_t)S * 8, 256) + adj_gpart_bytes(dtype, d, no, Ltot, S * rec_steps, mfma);
+  if (mfma)
+    b += align_up(mfma_bytes, 256) + align_up((size_t)S * T * 4, 256) + align_up((size_t)S * nx * 4, 256);
   return b;
 }
 
 template <typename Real, int DYN>
 static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Real *x0, const Real *u_nom,
-                            const uint32_t *iter, int ckpt, double *J, Real *gu, Real *gc, Real *gD, void *ws,
-                            const MfmaLayout *ml, hipStream_t s) {
+                            const uint32_t *iter, int ckpt, const double *gJ, double *J, Real *gu, Real *gc,
+                            Real *gD, void *ws, const MfmaLayout *ml, hipStream_t s) {
   using G = AdjGeo<Real, DYN>;
   const int64_t S = (int64_t)p.K * p.Ms;
-  const bool traced = ml != nullptr;
-  if (traced) ckpt = p.T;
+  const bool mfma = ml != nullptr;
+  ckpt = std::max(1, std::min(ckpt, p.T));
   const int ncp = (p.T + ckpt - 1) / ckpt;
-  const int64_t R = S * p.T;
-  const int nch = adjoint_param_chunks(R);
+  const int64_t rec_steps = mfma ? ckpt : p.T;
+  const int64_t R = S * rec_steps;
   char *w = (char *)ws;
   AdjArgs<Real> a;
   a.p = p;
@@ -605,88 +622,103 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   a.seg = (Real *)w;
   w += align_up((size_t)S * (ckpt + 1) * G::SEGW * sizeof(Real), 256);
   a.recs = (Real *)w;
-  w += align_up((size_t)S * p.T * G::RW * sizeof(Real), 256);
+  w += align_up((size_t)R * G::RW * sizeof(Real), 256);
   a.jsum = (double *)w;
   w += align_up((size_t)S * 8, 256);
   Real *gpart = (Real *)w;
-  w += adj_gpart_bytes(sizeof(Real) == 8 ? PI_F64 : PI_F32, m.d, m.n_out, m.Ltot, R, traced);
-  void *mbase = nullptr, *rfold = nullptr;
-  a.recompute = traced ? 0 : 1;
+  w += adj_gpart_bytes(sizeof(Real) == 8 ? PI_F64 : PI_F32, m.d, m.n_out, m.Ltot, R, mfma);
   hipError_t e = launch_fold_direct(sizeof(Real) == 8 ? PI_F64 : PI_F32, m, (void *)a.model, s);
   if (e != hipSuccess) return e;
-  const unsigned nb = (unsigned)((S + kAS - 1) / kAS);
+  const double scale = 1.0 / (double)S;
   if constexpr (sizeof(Real) == 4) {
-    if (traced) {
-      // forward on the matrix cores, storing every step's state and moments
-      mbase = w;
+    if (mfma) {
+      void *mbase = w;
       w += align_up(ml->bytes, 256);
-      rfold = w;
+      void *rfold = w;
       w += adj_rfold_bytes(*ml);
       float *cost = (float *)w;
+      w += align_up((size_t)S * p.T * 4, 256);
+      float *xbar = (float *)w;
+      const int spw = S >= 4096 ? 16 : 8;
       e = launch_fold_mfma(PI_F32, m, *ml, mbase, s);
+      if (e == hipSuccess) e = launch_adj_rfold(m, *ml, a.model, G::RS, rfold, s);
       if (e != hipSuccess) return e;
-      RolloutArgs<float> ra{p, x0, u_nom, iter, cost};
-      ra.trace = a.seg;
-      e = launch_rollout_mfma(ra, m, *ml, mbase, S >= 4096 ? 16 : 8, 4, s);
+      // forward: costs (for J) and the checkpoints; a single segment is traced
+      // here directly
+      RolloutArgs<float> fa{p, x0, u_nom, iter, cost};
+      if (ncp > 1) {
+        fa.ckpt = ckpt;
+        fa.ckpt_out = a.ckpt_buf;
+      } else {
+        fa.trace = a.seg;
+        fa.trace_T = ckpt;
+      }
+      e = launch_rollout_mfma(fa, m, *ml, mbase, spw, 4, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(adj_jsum_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, p.T,
                          (const float *)cost, a.jsum);
-    }
-  }
-  bool swept = false;
-  if constexpr (sizeof(Real) == 4) {
-    if (traced) {
-      // reverse sweep on the matrix cores, reading the trace
-      e = launch_adj_reverse_mfma(p, u_nom, iter, m, *ml, mbase, a.model, G::RS, rfold, a.seg, a.recs, s);
-      if (e != hipSuccess) return e;
-      swept = true;
-    }
-  }
-  if (!traced) hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
-  if (!swept) hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
-  const double scale = 1.0 / (double)S;
-  bool done = false;
-  if constexpr (sizeof(Real) == 4) {
-    if (traced) {
-      // parameter sums on the matrix cores from the folded tiles
-      const int nchm = adjoint_param_chunks_mfma(R);
-      const int width = adj_param_mfma_width(m.d);
-      e = launch_adj_param_mfma(*ml, mbase, (const float *)a.recs, G::RW, R, nchm, (float *)gpart, s);
+      const int nchm = adjoint_param_chunks_seg(R);
+      for (int g = ncp - 1; g >= 0 && e == hipSuccess; --g) {
+        const int tb = g * ckpt, te = std::min(p.T, tb + ckpt);
+        if (ncp > 1) {
+          // recompute the segment from its checkpoints, tracing states and moments
+          RolloutArgs<float> ra{p, x0, u_nom, iter, nullptr};
+          ra.t_begin = tb;
+          ra.t_end = te;
+          ra.ckpt = ckpt;
+          ra.xstart = a.ckpt_buf;
+          ra.trace = a.seg;
+          ra.trace_T = ckpt;
+          e = launch_rollout_mfma(ra, m, *ml, mbase, spw, 4, s);
+          if (e != hipSuccess) break;
+        }
+        e = launch_adj_reverse_mfma(p, u_nom, iter, *ml, mbase, rfold, a.seg, ckpt, tb, te, xbar, a.recs, s);
+        if (e != hipSuccess) break;
+        e = launch_adj_param_mfma(*ml, mbase, (const float *)a.recs, G::RW, S * (te - tb), nchm, (float *)gpart,
+                                  g != ncp - 1, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL((adj_u_kernel<Real, DYN>), dim3(te - tb), dim3(256), 0, s, S, te - tb,
+                           (const Real *)a.recs, scale, gJ, gu + (size_t)tb * G::NU);
+      }
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((adj_param_mfma_finish_kernel<DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m, *ml,
-                         (const float *)a.model, nchm, (const float *)gpart, width, scale, (float *)gc, (float *)gD);
-      done = true;
+                         (const float *)a.model, nchm, (const float *)gpart, adj_param_mfma_width(m.d), scale, gJ,
+                         (float *)gc, (float *)gD);
+      hipLaunchKernelGGL(adj_j_kernel, dim3(1), dim3(256), 0, s, S, (const double *)a.jsum, scale, J);
+      return hipGetLastError();
     }
   }
-  if (!done) {
-    hipLaunchKernelGGL((adj_param_kernel<Real, DYN>), dim3((m.Ltot + kParamThreads - 1) / kParamThreads, nch),
-                       dim3(kParamThreads), 0, s, m, a.model, (const Real *)a.recs, R, nch, gpart);
-    hipLaunchKernelGGL((adj_param_finish_kernel<Real, DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m,
-                       a.model, nch, (const Real *)gpart, scale, gc, gD);
-  }
+  const unsigned nb = (unsigned)((S + kAS - 1) / kAS);
+  const int nch = adjoint_param_chunks(R);
+  hipLaunchKernelGGL((adj_forward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
+  hipLaunchKernelGGL((adj_backward_kernel<Real, DYN>), dim3(nb), dim3(kAThreads), 0, s, a, m);
+  hipLaunchKernelGGL((adj_param_kernel<Real, DYN>), dim3((m.Ltot + kParamThreads - 1) / kParamThreads, nch),
+                     dim3(kParamThreads), 0, s, m, a.model, (const Real *)a.recs, R, nch, gpart);
+  hipLaunchKernelGGL((adj_param_finish_kernel<Real, DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m,
+                     a.model, nch, (const Real *)gpart, scale, gJ, gc, gD);
   hipLaunchKernelGGL((adj_u_kernel<Real, DYN>), dim3(p.T), dim3(256), 0, s, S, p.T, (const Real *)a.recs,
-                     scale, gu);
+                     scale, gJ, gu);
   hipLaunchKernelGGL(adj_j_kernel, dim3(1), dim3(256), 0, s, S, (const double *)a.jsum, scale, J);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
-                          const uint32_t *iter, int ckpt, double *J, void *gu, void *gc, void *gD, void *ws,
-                          const MfmaLayout *ml, hipStream_t s) {
+                          const uint32_t *iter, int ckpt, const double *gJ, double *J, void *gu, void *gc,
+                          void *gD, void *ws, const MfmaLayout *ml, hipStream_t s) {
   if (dtype == PI_F64) {
     const ProbDev<double> &p = *(const ProbDev<double> *)pargs;
     if (p.dyn == kDynPointMass2D)
-      return adjoint_t<double, kDynPointMass2D>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, J,
-                                                (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
-    return adjoint_t<double, kDynQuad12>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, J,
+      return adjoint_t<double, kDynPointMass2D>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, gJ,
+                                                J, (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
+    return adjoint_t<double, kDynQuad12>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, gJ, J,
                                          (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
   }
   const ProbDev<float> &p = *(const ProbDev<float> *)pargs;
   if (p.dyn == kDynPointMass2D)
-    return adjoint_t<float, kDynPointMass2D>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, J,
+    return adjoint_t<float, kDynPointMass2D>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, gJ, J,
                                              (float *)gu, (float *)gc, (float *)gD, ws, ml, s);
-  return adjoint_t<float, kDynQuad12>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, J, (float *)gu,
-                                      (float *)gc, (float *)gD, ws, ml, s);
+  return adjoint_t<float, kDynQuad12>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, gJ, J,
+                                      (float *)gu, (float *)gc, (float *)gD, ws, ml, s);
 }
 
 }  // namespace pi2rh

@@ -328,14 +328,30 @@ pi_status check_folded(const pi_lwpr *m, bool mfma) {
   return PI_OK;
 }
 
-// The float32 adjoint runs its forward on the matrix cores and keeps every
-// step (state and moments) when the model has a matrix-core form: bytes of
-// that form, or 0 for the checkpointed direct forward.
-size_t adjoint_traced_bytes(const pi_problem *p, const pi_lwpr *m) {
+// The float32 adjoint runs its forward, recompute and reverse sweep on the
+// matrix cores when the model has a matrix-core form: bytes of that form
+// (tiles and reverse-sweep parameters), or 0 for the direct kernels.
+size_t adjoint_mfma_bytes(const pi_problem *p, const pi_lwpr *m) {
   if (p->dtype != PI_F32 || !mfma_model_ok(m) || p->dyn == PI_DYN_QUAD_HYBRID) return 0;
   if (p->variant == PI_VARIANT_DIRECT) return 0;
   const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
   return align_up(l.bytes, 256) + adj_rfold_bytes(l);   // forward tiles + reverse-sweep parameters
+}
+
+pi_status check_adjoint(const pi_problem *p, const pi_lwpr *m, int32_t ckpt_every, int *ckpt) {
+  PI_TRY(check_pair(p, m));
+  if (p->dyn == PI_DYN_QUAD_HYBRID) return fail(PI_ERR_UNSUPPORTED, "the adjoint covers POINTMASS2D and QUAD12");
+  if (p->ctrl_cost) return fail(PI_ERR_UNSUPPORTED, "the adjoint does not cover the control terms of S-tilde");
+  if (ckpt_every < 0) return fail(PI_ERR_VALUE, "ckpt_every=%d must be >= 0", ckpt_every);
+  if ((int64_t)p->K * (p->M > 0 ? p->M : 1) * p->T > ((int64_t)1 << 36))
+    return fail(PI_ERR_SHAPE, "K*max(M,1)*T too large for the adjoint records");
+  *ckpt = ckpt_every == 0 ? adjoint_default_ckpt(p->T) : std::min<int>(ckpt_every, p->T);
+  return PI_OK;
+}
+
+size_t adjoint_ws(const pi_problem *p, const pi_lwpr *m, int ckpt) {
+  return adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d, ckpt,
+                          adjoint_mfma_bytes(p, m));
 }
 
 size_t fold_bytes(const pi_lwpr *m, bool mfma) {
@@ -367,30 +383,26 @@ pi_status check_ws(void *ws, size_t ws_bytes, size_t need) {
   return PI_OK;
 }
 
-// ---- batched plan layout ------------------------------------------------------
-constexpr uint32_t kPlanMagic = 0x50493252u;  // "PI2R"
-
-struct PlanHeader {
-  uint32_t magic;
-  int32_t B, n_items, spw, waves, pad;
-  size_t plan_bytes, probs_off, items_off, queue_off;
-  void *ws;
+// ---- allocation-free rollouts ---------------------------------------------------
+// ---- batched problems ------------------------------------------------------------
+// Workspace of a batched call (pi_rollout_cost_batched, pi_control_step_batched):
+//   [problem descriptors B][work items][queue word]
+//   [per problem: matrix-core fold (unless pre-folded), sub-rollout costs (M > 1)]
+//   [update scratch, shared in stream order: the largest of the problems']
+//   [RH-shift scratch, shared: the largest direct fold (unless pre-folded) + partials]
+// The descriptors and items are written by kernels on the stream, so a call
+// never copies host memory and may be captured into a HIP graph.
+struct BatchLayout {
+  int max_spw, waves, n_items;
+  size_t probs_off, items_off, queue_off, upd_off, shift_off, bytes;
+  std::vector<size_t> fold_off, sub_off;   // (size_t)-1: none
+  std::vector<int> spw;
+  std::vector<int64_t> n_tiles, item_off;
 };
 
-struct PlanProblemHost {
-  ModelArgs margs;
-  MfmaLayout layout;
-  size_t fold_off, sub_off;
-  int K, T, Ms;
-  void *cost;
-};
+int batch_spw(const pi_problem &p) { return p.tile_samples > 0 ? p.tile_samples : 16; }
 
-struct BatchSizes {
-  int spw, waves, n_items;
-  size_t ws_bytes, plan_bytes, host_off, probs_off, items_off, queue_off;
-};
-
-pi_status batch_sizes(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchSizes *out) {
+pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLayout *out) {
   if (B < 1 || B > (1 << 20)) return fail(PI_ERR_SHAPE, "B=%d outside [1, 2^20]", B);
   if (!p || !m) return fail(PI_ERR_NULL, "problem and model arrays must be non-NULL");
   for (int b = 0; b < B; ++b) {
@@ -400,28 +412,117 @@ pi_status batch_sizes(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchSiz
       return fail(PI_ERR_UNSUPPORTED, "problem %d: batched rollouts need float32 quadrotor problems", b);
     if (!mfma_model_ok(&m[b]))
       return fail(PI_ERR_UNSUPPORTED, "problem %d: the model's matrix-core tiles must stay under 2 GiB", b);
+    st = check_folded(&m[b], true);
+    if (st != PI_OK) return fail(st, "problem %d: %s", b, g_err);
   }
-  BatchSizes bs;
-  bs.spw = p[0].tile_samples > 0 ? p[0].tile_samples : 16;
-  bs.waves = p[0].tile_waves > 0 ? p[0].tile_waves : 4;
-  if (bs.waves == 8 && bs.spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
-  int64_t n = 0;
-  size_t ws = 0;
+  BatchLayout L;
+  L.waves = p[0].tile_waves > 0 ? p[0].tile_waves : 4;
+  L.max_spw = 0;
+  L.spw.resize(B);
+  L.n_tiles.resize(B);
   for (int b = 0; b < B; ++b) {
-    const int Ms = p[b].M > 0 ? p[b].M : 1;
-    n += ((int64_t)p[b].K * Ms + bs.spw - 1) / bs.spw;
-    ws += mfma_layout(m[b].d, m[b].n_out, m[b].L_off).bytes;
-    if (Ms > 1) ws += align_up((size_t)p[b].K * Ms * p[b].T * 4, 256);
+    L.spw[b] = batch_spw(p[b]);
+    L.max_spw = std::max(L.max_spw, L.spw[b]);
+    L.n_tiles[b] = ((int64_t)p[b].K * (p[b].M > 0 ? p[b].M : 1) + L.spw[b] - 1) / L.spw[b];
+  }
+  if (L.waves == 8 && L.max_spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
+  // work list: problems by decreasing per-tile work (T * model tiles), each
+  // problem's tiles in order
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  auto work = [&](int b) {
+    return (int64_t)p[b].T * mfma_layout(m[b].d, m[b].n_out, m[b].L_off).n_tiles * L.spw[b];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  L.item_off.resize(B);
+  int64_t n = 0;
+  for (int b : order) {
+    L.item_off[b] = n;
+    n += L.n_tiles[b];
   }
   if (n > INT32_MAX) return fail(PI_ERR_SHAPE, "too many work items");
-  bs.n_items = (int)n;
-  bs.queue_off = ws;
-  bs.ws_bytes = ws + 256;
-  bs.host_off = align_up(sizeof(PlanHeader), 64);
-  bs.probs_off = align_up(bs.host_off + (size_t)B * sizeof(PlanProblemHost), 256);
-  bs.items_off = align_up(bs.probs_off + (size_t)B * sizeof(BatchedProblem), 256);
-  bs.plan_bytes = align_up(bs.items_off + (size_t)n * sizeof(BatchedItem), 256);
-  *out = bs;
+  L.n_items = (int)n;
+  size_t off = 0;
+  L.probs_off = off;
+  off += align_up((size_t)B * sizeof(BatchedProblem), 256);
+  L.items_off = off;
+  off += align_up((size_t)n * sizeof(BatchedItem), 256);
+  L.queue_off = off;
+  off += 256;
+  L.fold_off.assign(B, (size_t)-1);
+  L.sub_off.assign(B, (size_t)-1);
+  size_t upd = 0, shift = 0;
+  for (int b = 0; b < B; ++b) {
+    if (!m[b].folded) {
+      L.fold_off[b] = off;
+      off += align_up(mfma_layout(m[b].d, m[b].n_out, m[b].L_off).bytes, 256);
+    }
+    const size_t sb = sub_bytes(&p[b]);
+    if (sb) {
+      L.sub_off[b] = off;
+      off += sb;
+    }
+    upd = std::max(upd, update_ws_bytes(p[b].K, p[b].T));
+    shift = std::max(shift, (m[b].folded ? 0 : align_up(fold_bytes(&m[b], false), 256)) +
+                                shift_partial_bytes(model_args(&m[b]), PI_F32));
+  }
+  L.upd_off = off;
+  off += align_up(upd, 256);
+  L.shift_off = off;
+  off += align_up(shift, 256);
+  L.bytes = off;
+  *out = std::move(L);
+  return PI_OK;
+}
+
+// The device-side plan (descriptors and work items) and the persistent
+// rollout launch of a validated batch, then each problem's sub-rollout means.
+hipError_t run_batched_rollouts(int32_t B, const pi_problem *p, const pi_lwpr *m, const void *const *x0,
+                                const void *const *u_nom, const uint32_t *const *iter, void *const *cost,
+                                const BatchLayout &L, char *ws, hipStream_t s) {
+  BatchedProblem *probs = (BatchedProblem *)(ws + L.probs_off);
+  BatchedItem *items = (BatchedItem *)(ws + L.items_off);
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < B && e == hipSuccess; ++b) {
+    const MfmaLayout l = mfma_layout(m[b].d, m[b].n_out, m[b].L_off);
+    const void *base;
+    if (m[b].folded) {
+      base = (const char *)m[b].folded + folded_layout(&m[b]).mfma_off;
+    } else {
+      base = ws + L.fold_off[b];
+      e = launch_fold_mfma(PI_F32, model_args(&m[b]), l, ws + L.fold_off[b], s);
+      if (e != hipSuccess) break;
+    }
+    BatchedProblem bp;
+    bp.p = prob_dev<float>(&p[b]);
+    bp.x0 = (const float *)x0[b];
+    bp.u_nom = (const float *)u_nom[b];
+    bp.iter = iter[b];
+    bp.cost = L.sub_off[b] != (size_t)-1 ? (float *)(ws + L.sub_off[b]) : (float *)cost[b];
+    bp.md = mfma_model_view(l, base);
+    e = launch_batched_describe(bp, probs, items, b, L.item_off[b], L.n_tiles[b], L.spw[b], s);
+  }
+  int *queue = (int *)(ws + L.queue_off);
+  if (e == hipSuccess) e = launch_zero_int(queue, s);
+  if (e == hipSuccess) {
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = L.waves == 8 ? 1 : 2;
+    const int grid = std::max(1, std::min(L.n_items, ncu * per_cu));
+    e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, grid, queue, s);
+  }
+  for (int b = 0; b < B && e == hipSuccess; ++b)
+    if (L.sub_off[b] != (size_t)-1)
+      e = launch_subcost_reduce(PI_F32, ws + L.sub_off[b], cost[b], p[b].K, p[b].M, p[b].T, s);
+  return e;
+}
+
+pi_status check_batched_args(int32_t B, const void *const *x0, const void *const *u_nom,
+                             const uint32_t *const *iter, void *const *cost) {
+  if (!x0 || !u_nom || !iter || !cost) return fail(PI_ERR_NULL, "x0, u_nom, iter and cost arrays must be non-NULL");
+  for (int b = 0; b < B; ++b)
+    if (!x0[b] || !u_nom[b] || !iter[b] || !cost[b]) return fail(PI_ERR_NULL, "problem %d: NULL pointer", b);
   return PI_OK;
 }
 
@@ -530,7 +631,7 @@ size_t pi_workspace_bytes(int32_t op, const pi_problem *p, const pi_lwpr *m) {
     case PI_OP_ADJOINT:
       if (check_pair(p, m) != PI_OK) return (size_t)-1;
       return adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
-                              adjoint_default_ckpt(p->T), adjoint_traced_bytes(p, m));
+                              adjoint_default_ckpt(p->T), adjoint_mfma_bytes(p, m));
   }
   fail(PI_ERR_VALUE, "unknown op %d", op);
   return (size_t)-1;
@@ -613,33 +714,33 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
   return launched(e, "pi_rh_shift");
 }
 
+size_t pi_adjoint_workspace_bytes(const pi_problem *p, const pi_lwpr *m, int32_t ckpt_every) {
+  int ckpt = 0;
+  if (check_adjoint(p, m, ckpt_every, &ckpt) != PI_OK) return (size_t)-1;
+  return adjoint_ws(p, m, ckpt);
+}
+
 pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
-                             const uint32_t *iter, int32_t ckpt_every, void *J, void *g_u_nom, void *g_centre,
-                             void *g_metric, void *ws, size_t ws_bytes, void *stream) {
-  PI_TRY(check_pair(p, m));
-  if (p->dyn == PI_DYN_QUAD_HYBRID) return fail(PI_ERR_UNSUPPORTED, "the adjoint covers POINTMASS2D and QUAD12");
+                             const uint32_t *iter, int32_t ckpt_every, const void *gJ, void *J, void *g_u_nom,
+                             void *g_centre, void *g_metric, void *ws, size_t ws_bytes, void *stream) {
+  int ckpt = 0;
+  PI_TRY(check_adjoint(p, m, ckpt_every, &ckpt));
   if (!x0 || !u_nom || !iter || !J || !g_u_nom || !g_centre || !g_metric)
     return fail(PI_ERR_NULL, "x0, u_nom, iter, J and the gradient outputs must be non-NULL");
-  if (ckpt_every < 0) return fail(PI_ERR_VALUE, "ckpt_every=%d must be >= 0", ckpt_every);
-  const int ckpt = ckpt_every == 0 ? adjoint_default_ckpt(p->T) : std::min<int>(ckpt_every, p->T);
-  if ((int64_t)p->K * (p->M > 0 ? p->M : 1) * p->T > ((int64_t)1 << 36))
-    return fail(PI_ERR_SHAPE, "K*max(M,1)*T too large for the adjoint records");
-  const size_t traced = adjoint_traced_bytes(p, m);
-  PI_TRY(check_ws(ws, ws_bytes, adjoint_ws_bytes(p->dtype, p->dyn, p->K, p->M, p->T, m->L_off[m->n_out], m->d,
-                                                 ckpt, traced)));
+  PI_TRY(check_ws(ws, ws_bytes, adjoint_ws(p, m, ckpt)));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
   const ModelArgs a = model_args(m);
   hipError_t e;
   if (p->dtype == PI_F64) {
     const ProbDev<double> d = prob_dev<double>(p);
-    e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws,
-                       nullptr, s);
+    e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (const double *)gJ, (double *)J, g_u_nom, g_centre,
+                       g_metric, ws, nullptr, s);
   } else {
     const ProbDev<float> d = prob_dev<float>(p);
     const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
-    e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (double *)J, g_u_nom, g_centre, g_metric, ws,
-                       traced ? &l : nullptr, s);
+    e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (const double *)gJ, (double *)J, g_u_nom, g_centre,
+                       g_metric, ws, adjoint_mfma_bytes(p, m) ? &l : nullptr, s);
   }
   return launched(e, "pi_rollout_adjoint");
 }
@@ -680,110 +781,57 @@ pi_status pi_noise(const pi_problem *p, int32_t tag, const uint32_t *iter, int32
 }
 
 size_t pi_batched_workspace_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m) {
-  BatchSizes bs;
-  if (batch_sizes(B, p, m, &bs) != PI_OK) return (size_t)-1;
-  return bs.ws_bytes;
+  BatchLayout L;
+  if (batch_layout(B, p, m, &L) != PI_OK) return (size_t)-1;
+  return L.bytes;
 }
 
-size_t pi_batched_plan_bytes(int32_t B, const pi_problem *p, const pi_lwpr *m) {
-  BatchSizes bs;
-  if (batch_sizes(B, p, m, &bs) != PI_OK) return (size_t)-1;
-  return bs.plan_bytes;
+pi_status pi_rollout_cost_batched(int32_t B, const pi_problem *p, const pi_lwpr *m, const void *const *x0,
+                                  const void *const *u_nom, const uint32_t *const *iter, void *const *cost,
+                                  void *ws, size_t ws_bytes, void *stream) {
+  BatchLayout L;
+  PI_TRY(batch_layout(B, p, m, &L));
+  PI_TRY(check_batched_args(B, x0, u_nom, iter, cost));
+  PI_TRY(check_ws(ws, ws_bytes, L.bytes));
+  PI_TRY(check_device());
+  return launched(run_batched_rollouts(B, p, m, x0, u_nom, iter, cost, L, (char *)ws, (hipStream_t)stream),
+                  "pi_rollout_cost_batched");
 }
 
-pi_status pi_batched_plan(int32_t B, const pi_problem *p, const pi_lwpr *m, const void *const *x0,
-                          const void *const *u_nom, const uint32_t *const *iter, void *const *cost,
-                          void *ws, size_t ws_bytes, void *plan_host, size_t plan_bytes) {
-  BatchSizes bs;
-  PI_TRY(batch_sizes(B, p, m, &bs));
-  if (!x0 || !u_nom || !iter || !cost || !plan_host) return fail(PI_ERR_NULL, "NULL array argument");
-  for (int b = 0; b < B; ++b)
-    if (!x0[b] || !u_nom[b] || !iter[b] || !cost[b]) return fail(PI_ERR_NULL, "problem %d: NULL pointer", b);
-  PI_TRY(check_ws(ws, ws_bytes, bs.ws_bytes));
-  if (plan_bytes < bs.plan_bytes) return fail(PI_ERR_WORKSPACE, "plan buffer of %zu bytes needed", bs.plan_bytes);
-  char *base = (char *)plan_host;
-  memset(base, 0, bs.plan_bytes);
-  PlanHeader *h = (PlanHeader *)base;
-  PlanProblemHost *ph = (PlanProblemHost *)(base + bs.host_off);
-  BatchedProblem *bp = (BatchedProblem *)(base + bs.probs_off);
-  BatchedItem *items = (BatchedItem *)(base + bs.items_off);
-  h->magic = kPlanMagic;
-  h->B = B;
-  h->n_items = bs.n_items;
-  h->spw = bs.spw;
-  h->waves = bs.waves;
-  h->plan_bytes = bs.plan_bytes;
-  h->probs_off = bs.probs_off;
-  h->items_off = bs.items_off;
-  h->ws = ws;
-  h->queue_off = bs.queue_off;
-  size_t off = 0;
-  for (int b = 0; b < B; ++b) {
-    const MfmaLayout l = mfma_layout(m[b].d, m[b].n_out, m[b].L_off);
-    const int Ms = p[b].M > 0 ? p[b].M : 1;
-    ph[b].margs = model_args(&m[b]);
-    ph[b].layout = l;
-    ph[b].fold_off = off;
-    off += l.bytes;
-    ph[b].sub_off = Ms > 1 ? off : (size_t)-1;
-    if (Ms > 1) off += align_up((size_t)p[b].K * Ms * p[b].T * 4, 256);
-    ph[b].K = p[b].K;
-    ph[b].T = p[b].T;
-    ph[b].Ms = Ms;
-    ph[b].cost = cost[b];
-    bp[b].p = prob_dev<float>(&p[b]);
-    bp[b].x0 = (const float *)x0[b];
-    bp[b].u_nom = (const float *)u_nom[b];
-    bp[b].iter = iter[b];
-    bp[b].cost = Ms > 1 ? (float *)((char *)ws + ph[b].sub_off) : (float *)cost[b];
-    bp[b].md = mfma_model_view(l, (char *)ws + ph[b].fold_off);
-  }
-  // work list: problems by decreasing per-tile work (T * model tiles), tiles in order
-  std::vector<int> order(B);
-  for (int b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-    return (int64_t)ph[a].T * ph[a].layout.n_tiles > (int64_t)ph[c].T * ph[c].layout.n_tiles;
-  });
-  int n = 0;
-  for (int b : order) {
-    const int64_t ns = (int64_t)ph[b].K * ph[b].Ms;
-    for (int64_t s0 = 0; s0 < ns; s0 += bs.spw) {
-      items[n].b = b;
-      items[n].s_base = s0;
-      ++n;
-    }
-  }
-  return ok();
-}
-
-pi_status pi_rollout_cost_batched(const void *plan_host, const void *plan_dev, void *stream) {
-  if (!plan_host || !plan_dev) return fail(PI_ERR_NULL, "plan_host and plan_dev must be non-NULL");
-  const char *base = (const char *)plan_host;
-  const PlanHeader *h = (const PlanHeader *)base;
-  if (h->magic != kPlanMagic) return fail(PI_ERR_VALUE, "plan_host is not a batched plan");
+pi_status pi_control_step_batched(int32_t B, const pi_problem *p, const pi_lwpr *m, void *const *x0,
+                                  void *const *u_nom, uint32_t *const *iter, void *const *cost, void *ws,
+                                  size_t ws_bytes, void *stream) {
+  BatchLayout L;
+  PI_TRY(batch_layout(B, p, m, &L));
+  PI_TRY(check_batched_args(B, (const void *const *)x0, (const void *const *)u_nom,
+                            (const uint32_t *const *)iter, cost));
+  PI_TRY(check_ws(ws, ws_bytes, L.bytes));
   PI_TRY(check_device());
   hipStream_t s = (hipStream_t)stream;
-  const PlanProblemHost *ph = (const PlanProblemHost *)(base + align_up(sizeof(PlanHeader), 64));
-  hipError_t e = hipSuccess;
-  for (int b = 0; b < h->B && e == hipSuccess; ++b)
-    e = launch_fold_mfma(PI_F32, ph[b].margs, ph[b].layout, (char *)h->ws + ph[b].fold_off, s);
-  int *queue = (int *)((char *)h->ws + h->queue_off);
-  if (e == hipSuccess) e = launch_zero_int(queue, s);
-  if (e == hipSuccess) {
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = h->waves == 8 ? 1 : 2;
-    const int grid = std::max(1, std::min(h->n_items, ncu * per_cu));
-    e = launch_rollout_batched((const BatchedProblem *)((const char *)plan_dev + h->probs_off),
-                               (const BatchedItem *)((const char *)plan_dev + h->items_off), h->n_items,
-                               h->spw, h->waves, grid, queue, s);
+  char *w = (char *)ws;
+  hipError_t e = run_batched_rollouts(B, p, m, (const void *const *)x0, (const void *const *)u_nom,
+                                      (const uint32_t *const *)iter, cost, L, w, s);
+  // each problem's update (Eq. 2) and receding-horizon advance, in problem
+  // order, sharing one update and one shift scratch area
+  for (int b = 0; b < B && e == hipSuccess; ++b) {
+    const ProbDev<float> d = prob_dev<float>(&p[b]);
+    e = launch_update(PI_F32, &d, cost[b], iter[b], u_nom[b], nullptr, w + L.upd_off, 1, p[b].lambda,
+                      p[b].weighting, s);
+    if (e != hipSuccess) break;
+    const ModelArgs a = model_args(&m[b]);
+    const void *base;
+    char *part = w + L.shift_off;
+    if (m[b].folded) {
+      base = (const char *)m[b].folded + folded_layout(&m[b]).direct_off;
+    } else {
+      base = w + L.shift_off;
+      part += align_up(fold_bytes(&m[b], false), 256);
+      e = launch_fold_direct(PI_F32, a, w + L.shift_off, s);
+      if (e != hipSuccess) break;
+    }
+    e = launch_rh_shift(PI_F32, &d, a, base, part, x0[b], u_nom[b], iter[b], s);
   }
-  for (int b = 0; b < h->B && e == hipSuccess; ++b)
-    if (ph[b].Ms > 1)
-      e = launch_subcost_reduce(PI_F32, (char *)h->ws + ph[b].sub_off, ph[b].cost, ph[b].K, ph[b].Ms,
-                                ph[b].T, s);
-  return launched(e, "pi_rollout_cost_batched");
+  return launched(e, "pi_control_step_batched");
 }
 
 }  // extern "C"

@@ -106,8 +106,18 @@ struct RolloutArgs {
   const Real *x0, *u_nom;
   const uint32_t *iter;
   Real *cost;       // [K][T] (Ms == 1) or sub-rollout costs [K][Ms][T]
-  Real *trace = nullptr;  // optional [K*Ms][T+1][n_x + 3 n_out]: x_t, then (mu, var, lse)
+  Real *trace = nullptr;  // optional [K*Ms][trace_T+1][n_x + 3 n_out]: x_t, then (mu, var, lse)
                           // of every output at step t (matrix-core kernels only)
+  // Segments of the horizon (the adjoint's checkpointed forward; matrix-core
+  // kernels only): steps [t_begin, t_end) (t_end < 0: T), starting from x0
+  // or, with xstart, from each sub-rollout's checkpoint xstart [S][nck][n_x]
+  // at slot t_begin / ckpt (nck = ceil(T / ckpt)).  With ckpt_out the state
+  // before every step t with t % ckpt == 0 is stored to ckpt_out (same
+  // layout).  Trace rows count from t_begin, trace_T + 1 of them per
+  // sub-rollout (trace_T < 0: T).  cost may be null (nothing written).
+  int t_begin = 0, t_end = -1, trace_T = -1, ckpt = 0;
+  const Real *xstart = nullptr;
+  Real *ckpt_out = nullptr;
 };
 
 hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
@@ -139,12 +149,17 @@ struct BatchedProblem {
 };
 struct BatchedItem {
   int b;
-  int pad;
+  int spw;              // sub-rollouts of this item's tile (its problem's tile size)
   int64_t s_base;
 };
 MfmaModel mfma_model_view(const MfmaLayout &l, const void *base);
+// Writes problem b's descriptor to probs[b] and its n_tiles work items
+// (tiles of spw sub-rollouts, in order) to items[item_off ..], on the stream.
+hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *probs, BatchedItem *items, int b,
+                                   int64_t item_off, int64_t n_tiles, int spw, hipStream_t s);
+// max_spw: the largest tile of any item (<= 32); waves 8 needs max_spw <= 16.
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int spw, int waves, int grid, int *queue, hipStream_t s);
+                                  int max_spw, int waves, int grid, int *queue, hipStream_t s);
 hipError_t launch_zero_int(int *p, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // Paired-workgroup rollout (MFMA, 16 rows per pair of workgroups).
@@ -163,23 +178,30 @@ int adjoint_default_ckpt(int T);
 // padded to a multiple of 16) and sum_r ybar; adj_param_mfma_width(d) floats
 // per (chunk, model slot), gpart [nch][n_tiles * 16][width].
 int adj_param_mfma_width(int d);
-// Adjoint reverse sweep on the matrix cores (float32, traced forward): the
-// per-model parameters of the second contraction go to `rfold`
-// (adj_rfold_bytes), then one workgroup per 16 sub-rollouts sweeps t = T-1..0
-// writing the records [S][T][d + 5 n_out + n_u].
+// Adjoint reverse sweep on the matrix cores (float32): the per-model
+// parameters of the second contraction are written once to `rfold`
+// (adj_rfold_bytes, launch_adj_rfold); then, per segment [tb, te) of the
+// horizon, one workgroup per 16 sub-rollouts sweeps t = te-1..tb over the
+// segment's trace (rows counted from tb, trace_T + 1 per sub-rollout) and
+// writes the segment's records [S][te - tb][d + 5 n_out + n_u].  The state
+// adjoint enters from xbar_io (unless te = T) and leaves to it (unless tb = 0).
 size_t adj_rfold_bytes(const MfmaLayout &l);
+hipError_t launch_adj_rfold(const ModelArgs &m, const MfmaLayout &l, const void *rec, int RS, void *rfold,
+                            hipStream_t s);
 hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, const uint32_t *iter,
-                                   const ModelArgs &m, const MfmaLayout &l, const void *base, const void *rec,
-                                   int RS, void *rfold, const float *trace, float *recs, hipStream_t s);
+                                   const MfmaLayout &l, const void *base, const void *rfold, const float *trace,
+                                   int trace_T, int tb, int te, float *xbar_io, float *recs, hipStream_t s);
+// accumulate: add to gpart instead of overwriting it (later segments).
 hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const float *recs, int RW, int64_t R,
-                                 int nch, float *gpart, hipStream_t s);
-// mfma_bytes > 0: float32 forward on the matrix cores with every step traced
-// (no checkpoints, no recompute); 0: direct forward with checkpoints.
+                                 int nch, float *gpart, bool accumulate, hipStream_t s);
+// mfma_bytes > 0: float32 forward and reverse sweep on the matrix cores,
+// segment by segment; 0: the direct kernels.  Both checkpoint the states
+// every `ckpt` steps and recompute each segment.
 size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes);
+// gJ (dev, one double, nullable = 1): seed that scales every gradient.
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
-                          const uint32_t *iter, int ckpt, double *J, void *gu, void *gc, void *gD, void *ws,
-                          const MfmaLayout *ml,
-                          hipStream_t s);
+                          const uint32_t *iter, int ckpt, const double *gJ, double *J, void *gu, void *gc,
+                          void *gD, void *ws, const MfmaLayout *ml, hipStream_t s);
 
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
                          hipStream_t s);

@@ -33,6 +33,8 @@
 // (PI^2-RH with LWPR dynamics, arXiv:1503.00330.)
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace pi2rh {
@@ -759,17 +761,35 @@ struct RollSmem {
 // Euler.  Block-synchronous; rs.sm must have been set up.  With a pair
 // context (pc->half = 0 or 1) the workgroup runs its half of the model tiles,
 // exchanges sums with its partner, and only half 0 writes costs.
+// The steps a rollout tile runs and what it keeps besides the costs (see
+// RolloutArgs): the whole horizon from x0 unless the adjoint's checkpointed
+// forward asks for a segment or for checkpoints.
+struct RollSeg {
+  int tb, te, trace_T, ckpt;
+  const float *xstart;
+  float *ckpt_out;
+};
+__device__ __forceinline__ RollSeg roll_seg(const RolloutArgs<float> &ra) {
+  return RollSeg{ra.t_begin, ra.t_end < 0 ? ra.p.T : ra.t_end, ra.trace_T < 0 ? ra.p.T : ra.trace_T, ra.ckpt,
+                 ra.xstart, ra.ckpt_out};
+}
+
 template <int DYN, int MT, int NW>
 __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
                              uint32_t it, float *__restrict__ cost, const MfmaModel &md,
-                             int64_t s_base, int spw, const PairCtx *pc = nullptr, float *tr = nullptr) {
+                             int64_t s_base, int spw, const PairCtx *pc = nullptr, float *tr = nullptr,
+                             const RollSeg *sg = nullptr) {
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
   MixSmem<D, MT, NW> &sm = rs.sm;
   constexpr int SEGW = NX + 3 * NO;
-  const int64_t tstride = (int64_t)(p.T + 1) * SEGW;
+  const int tb = sg ? sg->tb : 0, te = sg ? sg->te : p.T;
+  const int ck = sg ? sg->ckpt : 0;
+  const int nck = ck > 0 ? (p.T + ck - 1) / ck : 0;
+  float *ckpt_out = sg ? sg->ckpt_out : nullptr;
+  const int64_t tstride = (int64_t)((sg ? sg->trace_T : p.T) + 1) * SEGW;
   float *trace = writer_of(pc) && tr ? tr + s_base * tstride : nullptr;
   const int trows = (int)min<int64_t>(spw, (int64_t)p.K * p.Ms - s_base);
   const int T0 = pc == nullptr || pc->half == 0 ? 0 : md.n_tiles / 2;
@@ -784,7 +804,12 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it);
   const uint32_t wd = stream_word(kTagDyn, p.problem_id, it);
   if (row < ROWS) {
-    for (int a = 0; a < NX; ++a) rs.xs[row][a] = x0[a];
+    if (sg && sg->xstart && active) {
+      const float *xs0 = sg->xstart + (s * nck + tb / ck) * NX;
+      for (int a = 0; a < NX; ++a) rs.xs[row][a] = xs0[a];
+    } else {
+      for (int a = 0; a < NX; ++a) rs.xs[row][a] = x0[a];
+    }
     sm.z[row][D] = 1.0f;
     sm.z[row][D + 1] = 0.0f;
   }
@@ -792,7 +817,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   // costs of steps t0 .. t0+n-1 from rs.xc, one (row, step) per lane, runs of
   // consecutive steps per row so the stores coalesce
   auto flush_costs = [&](int t0, int n) {
-    if (!writer) return;
+    if (!writer || cost == nullptr) return;
     const bool failed = sm.pair_fail != 0;
     for (int i = threadIdx.x; i < ROWS * n; i += NW * 64) {
       const int rr = i / n, cc = i - rr * n;
@@ -804,10 +829,10 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       cost[ss * p.T + t0 + cc] = failed ? __builtin_nanf("") : c;
     }
   };
-  for (int t = 0; t < p.T; ++t) {
-    const int tc = t % kNoiseChunk;
+  for (int t = tb; t < te; ++t) {
+    const int tc = (t - tb) % kNoiseChunk;
     if (tc == 0) {
-      if (t > 0) {
+      if (t > tb) {
         __syncthreads();  // the chunk's states are in rs.xc
         flush_costs(t - kNoiseChunk, kNoiseChunk);
         // the control terms of the flushed chunk are read from the draw slots
@@ -819,7 +844,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
       for (int i = threadIdx.x; i < kNoiseChunk * ROWS * NB; i += NW * 64) {
         const int blk = i % NB, rr = (i / NB) % ROWS, cc = i / (NB * ROWS);
         const int64_t ss = s_base + rr;
-        const bool act = rr < spw && ss < (int64_t)p.K * p.Ms && t + cc < p.T;
+        const bool act = rr < spw && ss < (int64_t)p.K * p.Ms && t + cc < te;
         if (!act) continue;
         const uint32_t kk = (uint32_t)(ss / p.Ms), mm = (uint32_t)(ss % p.Ms);
         if (blk == 0) {
@@ -864,7 +889,12 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
         for (int a = 0; a < NX; ++a) x[a] = rs.xs[row][a];
         if (trace) {
 #pragma unroll
-          for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)t * SEGW + a] = x[a];
+          for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)(t - tb) * SEGW + a] = x[a];
+        }
+        if (ckpt_out && t % ck == 0) {
+          float *dst = ckpt_out + (s * nck + t / ck) * NX;
+#pragma unroll
+          for (int a = 0; a < NX; ++a) dst[a] = x[a];
         }
         lwpr_input<DYN>(x, u, z);
 #pragma unroll
@@ -877,12 +907,12 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
     __syncthreads();
     SampleArgs sa{p.M > 0 ? &rs.xi_s[tc][0][0] : nullptr};
     if (trace) {
-      sa.trace = trace + (int64_t)t * SEGW;
+      sa.trace = trace + (int64_t)(t - tb) * SEGW;
       sa.trace_stride = tstride;
       sa.trace_off = NX;
       sa.trace_rows = trows;
     }
-    mixture_step(md, sm, t == 0, T0, T1, pc, seq, sa);
+    mixture_step(md, sm, t == tb, T0, T1, pc, seq, sa);
     if (active) {
       float acc[NO], xn[NX], x[NX], u[NU];
 #pragma unroll
@@ -900,11 +930,11 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   }
   if (trace && active) {
 #pragma unroll
-    for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)p.T * SEGW + a] = rs.xs[row][a];
+    for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)(te - tb) * SEGW + a] = rs.xs[row][a];
   }
   __syncthreads();
-  const int tl = p.T > 0 ? ((p.T - 1) / kNoiseChunk) * kNoiseChunk : 0;
-  flush_costs(tl, p.T - tl);
+  const int tl = tb + ((te - tb - 1) / kNoiseChunk) * kNoiseChunk;
+  flush_costs(tl, te - tl);
 }
 
 // Waves per SIMD the rollout kernels are compiled for: the small-model
@@ -923,8 +953,9 @@ rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
                                                                int spw) {
   __shared__ RollSmem<DYN, MT, NW> rs;
   mix_setup(rs.sm);
+  const RollSeg sg = roll_seg(ra);
   rollout_tile<DYN, MT, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
-                            (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace);
+                            (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace, &sg);
 }
 
 // Paired form (one 16-row tile per pair of workgroups, for problems with
@@ -956,8 +987,7 @@ __global__ void read_give_ups_kernel(unsigned long long *out) { out[0] = pair_gi
 template <int DYN, int MT, int NW>
 __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedProblem *__restrict__ probs,
                                                                   const BatchedItem *__restrict__ items,
-                                                                  int n_items, int spw,
-                                                                  int *__restrict__ queue) {
+                                                                  int n_items, int *__restrict__ queue) {
   __shared__ RollSmem<DYN, MT, NW> rs;
   __shared__ int item_s;
   mix_setup(rs.sm);
@@ -971,8 +1001,18 @@ __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedP
     const BatchedProblem &bp = probs[it.b];
     const ProbDev<float> p = bp.p;
     const MfmaModel md = bp.md;
-    rollout_tile<DYN, MT, NW>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, spw);
+    rollout_tile<DYN, MT, NW>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, it.spw);
   }
+}
+
+// One problem's descriptor and work items of a batched launch.
+__global__ void batched_describe_kernel(BatchedProblem bp, BatchedProblem *__restrict__ probs,
+                                        BatchedItem *__restrict__ items, int b, int64_t item_off, int64_t n_tiles,
+                                        int spw) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) probs[b] = bp;
+  for (int64_t i = i0; i < n_tiles; i += (int64_t)gridDim.x * blockDim.x)
+    items[item_off + i] = BatchedItem{b, spw, i * spw};
 }
 
 template <int DYN, int MT, int NW>
@@ -1058,19 +1098,27 @@ hipError_t launch_read_give_ups(uint64_t *out, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *probs, BatchedItem *items, int b,
+                                   int64_t item_off, int64_t n_tiles, int spw, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n_tiles + 255) / 256, 64));
+  hipLaunchKernelGGL(batched_describe_kernel, dim3((unsigned)nb), dim3(256), 0, s, bp, probs, items, b, item_off,
+                     n_tiles, spw);
+  return hipGetLastError();
+}
+
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int spw, int waves, int grid, int *queue, hipStream_t s) {
+                                  int max_spw, int waves, int grid, int *queue, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  if (spw <= 16) {
+  if (max_spw <= 16) {
     if (waves == 8)
       hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8>), dim3(grid), dim3(512), 0, s, probs,
-                         items, n_items, spw, queue);
+                         items, n_items, queue);
     else
       hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4>), dim3(grid), dim3(256), 0, s, probs,
-                         items, n_items, spw, queue);
+                         items, n_items, queue);
   } else {
     hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4>), dim3(grid), dim3(256), 0, s, probs,
-                       items, n_items, spw, queue);
+                       items, n_items, queue);
   }
   return hipGetLastError();
 }
@@ -1097,7 +1145,8 @@ constexpr int kPrmTilesPerWave = 2;
 
 template <int D>
 __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const float *__restrict__ recs, int RW,
-                                                              int64_t R, int nch, float *__restrict__ gpart) {
+                                                              int64_t R, int nch, float *__restrict__ gpart,
+                                                              int accumulate) {
   using G = Geo<D>;
   constexpr int NF = G::NP + D + 1;           // features of Phi
   constexpr int NFB = (NF + 15) / 16;
@@ -1261,11 +1310,17 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dst[(4 * (lane >> 4) + j) * PWM + 16 * fb + (lane & 15)] = acc[q][fb][j];
+      for (int j = 0; j < 4; ++j) {
+        float &g = dst[(4 * (lane >> 4) + j) * PWM + 16 * fb + (lane & 15)];
+        g = accumulate ? g + acc[q][fb][j] : acc[q][fb][j];
+      }
     float y = ysum[q];
     y += __shfl_xor(y, 16);
     y += __shfl_xor(y, 32);
-    if (lane < 16) dst[lane * PWM + NFB * 16] = y;
+    if (lane < 16) {
+      float &g = dst[lane * PWM + NFB * 16];
+      g = accumulate ? g + y : y;
+    }
   }
 }
 
@@ -1337,8 +1392,10 @@ struct RevArgs {
   const uint32_t *iter;
   MfmaModel md;
   const float4 *P;        // adj_rfold_kernel output
-  const float *trace;     // [S][T+1][NX + 3 NO]
-  float *recs;            // [S][T][D + 5 NO + NU]
+  const float *trace;     // [S][trace_T+1][NX + 3 NO], rows from step tb
+  float *recs;            // [S][te-tb][D + 5 NO + NU]
+  float *xbar_io;         // [S][NX]: the state adjoint between segments
+  int tb, te, trace_T;
 };
 
 template <int DYN>
@@ -1369,15 +1426,19 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
   const uint32_t wc = stream_word(kTagCtrl, p.problem_id, it), wd = stream_word(kTagDyn, p.problem_id, it);
   mix_setup(sm);
   for (int i = threadIdx.x; i < 3 * p.n_obs; i += 256) obs_s[i] = p.obs[i];
+  const int tb = ra.tb, te = ra.te;
   if (row < 16) {
-    for (int i = 0; i < NX; ++i) xbar[row][i] = 0.0f;
+    // the adjoint of x_te: zero at the horizon's end, else what the later
+    // segment's sweep left
+    for (int i = 0; i < NX; ++i) xbar[row][i] = (te < p.T && active) ? ra.xbar_io[s * NX + i] : 0.0f;
     sm.z[row][D] = 1.0f;
     sm.z[row][D + 1] = 0.0f;
   }
   const int t0w = (int)((int64_t)wave * md.n_tiles / 4), t1w = (int)((int64_t)(wave + 1) * md.n_tiles / 4);
-  const float *tr = ra.trace + (active ? s : 0) * (int64_t)(p.T + 1) * SEGW;
+  // trace rows count from step tb
+  const float *tr = ra.trace + (active ? s : 0) * (int64_t)(ra.trace_T + 1) * SEGW - (int64_t)tb * SEGW;
   __syncthreads();
-  for (int t = p.T - 1; t >= 0; --t) {
+  for (int t = te - 1; t >= tb; --t) {
     // (1) per sample: cost gradient at x_{t+1}, the draws of step t, z_t and the
     //     adjoints of the sampled accelerations
     if (row < 16) {
@@ -1526,7 +1587,7 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
       if (DYN == kDynQuad12)
         for (int i = 0; i < 3; ++i) xp[9 + i] += p.dt * xbar[row][6 + i];
       for (int i = 0; i < NX; ++i) xbar[row][i] = xp[i] + zb[row][i];
-      float *rec = ra.recs + (s * p.T + t) * RW;
+      float *rec = ra.recs + (s * (te - tb) + (t - tb)) * RW;
       for (int i = 0; i < D; ++i) rec[i] = sm.z[row][i];
       for (int o = 0; o < NO; ++o) {
         rec[D + 5 * o] = stt[row][o][2];
@@ -1539,6 +1600,9 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
     }
     __syncthreads();
   }
+  // the adjoint of x_tb for the earlier segment (each row wrote its own)
+  if (tb > 0 && active)
+    for (int i = 0; i < NX; ++i) ra.xbar_io[s * NX + i] = xbar[row][i];
 }
 
 size_t adj_rfold_bytes(const MfmaLayout &l) {
@@ -1546,12 +1610,17 @@ size_t adj_rfold_bytes(const MfmaLayout &l) {
   return align_up((size_t)l.n_tiles * (nfbq + 1) * 64 * 4 * sizeof(float), 256);
 }
 
-hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, const uint32_t *iter,
-                                   const ModelArgs &m, const MfmaLayout &l, const void *base, const void *rec,
-                                   int RS, void *rfold, const float *trace, float *recs, hipStream_t s) {
+hipError_t launch_adj_rfold(const ModelArgs &m, const MfmaLayout &l, const void *rec, int RS, void *rfold,
+                            hipStream_t s) {
   const int np = l.d * (l.d + 1) / 2, nfbq = (np + l.d + 15) / 16;
   hipLaunchKernelGGL(adj_rfold_kernel, dim3(l.n_tiles), dim3(256), 0, s, m, l, (const float *)rec, RS, nfbq,
                      (float *)rfold);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, const uint32_t *iter,
+                                   const MfmaLayout &l, const void *base, const void *rfold, const float *trace,
+                                   int trace_T, int tb, int te, float *xbar_io, float *recs, hipStream_t s) {
   RevArgs ra;
   ra.p = p;
   ra.u_nom = u_nom;
@@ -1560,6 +1629,10 @@ hipError_t launch_adj_reverse_mfma(const ProbDev<float> &p, const float *u_nom, 
   ra.P = (const float4 *)rfold;
   ra.trace = trace;
   ra.recs = recs;
+  ra.xbar_io = xbar_io;
+  ra.tb = tb;
+  ra.te = te;
+  ra.trace_T = trace_T;
   const int64_t S = (int64_t)p.K * p.Ms;
   const dim3 grid((unsigned)((S + 15) / 16));
   if (p.dyn == kDynQuad12)
@@ -1577,13 +1650,15 @@ int adj_param_mfma_width(int d) {
 }
 
 hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const float *recs, int RW, int64_t R,
-                                 int nch, float *gpart, hipStream_t s) {
+                                 int nch, float *gpart, bool accumulate, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
   const dim3 grid((unsigned)((md.n_tiles + 4 * kPrmTilesPerWave - 1) / (4 * kPrmTilesPerWave)), (unsigned)nch);
   if (l.d == 16)
-    hipLaunchKernelGGL(adj_param_mfma_kernel<16>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart);
+    hipLaunchKernelGGL(adj_param_mfma_kernel<16>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart,
+                       (int)accumulate);
   else if (l.d == 6)
-    hipLaunchKernelGGL(adj_param_mfma_kernel<6>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart);
+    hipLaunchKernelGGL(adj_param_mfma_kernel<6>, grid, dim3(256), 0, s, md, recs, RW, R, nch, gpart,
+                       (int)accumulate);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

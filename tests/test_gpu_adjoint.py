@@ -69,6 +69,36 @@ def test_adjoint_fp32_matches_oracle(dyn, M, variant):
         assert nrel(g.cpu().numpy(), o) <= 1e-4
 
 
+@pytest.mark.parametrize("ckpt", [1, 5, 7, 16])
+def test_adjoint_fp32_matrix_core_checkpoints(ckpt):
+    # the matrix-core adjoint recomputes every segment of `ckpt` steps from
+    # its checkpoints (ragged last segment at 5 and 7; one segment at 16)
+    prob, model = _case(DYN_QUAD12, 1, np.float32, K=40, T=16)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=ckpt)
+    oJ, ogu, ogc, ogD = oracle.adjoint(prob, model)
+    assert abs(J.item() - oJ) <= 1e-5 * abs(oJ)
+    for g, o in ((gu, ogu), (gc, ogc), (gD, ogD)):
+        assert nrel(g.cpu().numpy(), o) <= 1e-4
+
+
+def test_adjoint_seed_scales_the_gradients():
+    # gJ seeds the reverse pass: gradients of gJ * J, J itself unscaled
+    prob, model = _case(DYN_QUAD12, 1, np.float64, K=12, T=9)
+    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    a = [t.clone() for t in pi.rollout_adjoint(dp, dm)]
+    b = pi.rollout_adjoint(dp, dm, gJ=torch.tensor([-2.5], dtype=torch.float64))
+    assert torch.equal(a[0], b[0])
+    for x, y in zip(a[1:], b[1:]):
+        assert torch.allclose(-2.5 * x, y, rtol=1e-15, atol=0)
+    p32, m32 = _case(DYN_QUAD12, 1, np.float32, K=40, T=16)
+    d32, dm32 = pi.DeviceProblem(p32), pi.DeviceModel(m32)
+    a = [t.clone() for t in pi.rollout_adjoint(d32, dm32)]
+    b = pi.rollout_adjoint(d32, dm32, gJ=torch.tensor([4.0], dtype=torch.float64))
+    for x, y in zip(a[1:], b[1:]):
+        assert torch.equal(4.0 * x, y)
+
+
 def test_adjoint_fp32_odd_tile_count():
     # 7 model tiles: in the matrix-core parameter pass one wave holds a valid
     # and an absent tile (its prefetch must return to the valid one)

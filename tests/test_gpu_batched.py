@@ -1,6 +1,8 @@
-"""Batched persistent rollouts: each problem of an uneven batch gives exactly
-(bitwise) the costs of its own plain launch with one workgroup per tile, and
-matches the oracle."""
+"""Batched controllers in one persistent launch: each problem of an uneven
+batch gives exactly (bitwise) the costs of its own plain launch with one
+workgroup per tile and matches the oracle; a batched control step (rollouts,
+updates, receding-horizon advances) leaves every problem's state exactly as
+its own plain control step does, eagerly and replayed from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -93,3 +95,94 @@ def test_batched_full_workload():
         assert flips.sum() <= 1 and r[~flips].max() <= 1e-4, (b, r.max())
         print("batched problem %d (K=%d, T=%d): max S rel %.2e, flips %d"
               % (b, prob.K, prob.T, r[~flips].max(), flips.sum()))
+
+
+def _state(dps):
+    return [(d.x0.clone(), d.u_nom.clone(), d.iter.clone()) for d in dps]
+
+
+def _plain_control_step(dp, dm):
+    cost = pi.rollout_cost(dp, dm)
+    pi.update(dp, cost)
+    pi.rh_shift(dp, dm)
+    return cost
+
+
+def test_batched_tiles_per_problem():
+    # every problem keeps its own tile size (8, 16, 32 and the default) in one launch
+    host, dps, dms = _batch()
+    for dp, spw in zip(dps, (8, 32, 16, 0, 8)):
+        dp.tile_samples = spw
+    br = pi.BatchedRollout(dps, dms)
+    costs = [c.clone() for c in br.run()]
+    for b, (dp, dm) in enumerate(zip(dps, dms)):
+        assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
+
+
+@pytest.mark.parametrize("prefold", [False, True])
+def test_batched_control_step_equals_plain_control_steps(prefold):
+    host, dps, dms = _batch()
+    if prefold:          # models read in place from their pi_model_fold buffers
+        for dm in dms[::2]:
+            dm.fold()
+    for b, dp in enumerate(dps):
+        dp.iter.fill_(b)
+    start = _state(dps)
+    br = pi.BatchedRollout(dps, dms)
+    br.control_step()
+    after = _state(dps)
+    costs = [c.clone() for c in br.costs]
+    for dp, (x, u, it) in zip(dps, start):
+        dp.x0.copy_(x), dp.u_nom.copy_(u), dp.iter.copy_(it)
+    for b, (dp, dm) in enumerate(zip(dps, dms)):
+        cost = _plain_control_step(dp, dm)
+        assert torch.equal(cost, costs[b]), b
+        assert torch.equal(dp.x0, after[b][0]) and torch.equal(dp.u_nom, after[b][1]), b
+        assert int(dp.iter.item()) == b + 1 == int(after[b][2].item())
+    # against the oracle's control step (rollouts, update, plant step, shift)
+    for b, (prob, model) in enumerate(host):
+        p = prob.copy()
+        x, u, it = oracle.rh_loop(p, model, steps=1, iterations=1, it=b)
+        assert it == b + 1
+        assert np.max(np.abs(after[b][1].cpu().numpy() - u)) <= 1e-4, b
+        assert np.max(np.abs(after[b][0].cpu().numpy() - x)) <= 1e-4 * max(1.0, np.abs(x).max()), b
+
+
+def test_batched_control_step_graph_replays():
+    # one batched control step captured once and replayed three times, each
+    # replay checked against the same step run eagerly from the same state
+    _, dps, dms = _batch()
+    br = pi.BatchedRollout(dps, dms)
+    br.capture()
+    for rep in range(3):
+        start = _state(dps)
+        br.step(graph=True)
+        torch.cuda.synchronize()
+        replay = _state(dps)
+        for dp, (x, u, it) in zip(dps, start):
+            dp.x0.copy_(x), dp.u_nom.copy_(u), dp.iter.copy_(it)
+        br.step(graph=False)
+        torch.cuda.synchronize()
+        eager = _state(dps)
+        for a, b in zip(replay, eager):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), rep
+        assert int(dps[0].iter.item()) == rep + 1
+
+
+def test_batched_control_step_full_workload():
+    # the 64 uneven problems of the batched workload: one batched control step
+    # leaves every (x0, u_nom, iter) exactly as 64 plain control steps do
+    batch = synth.batched_config()
+    dps = [pi.DeviceProblem(p, tile_split=1, tile_waves=4) for p, _ in batch]
+    dms = [pi.DeviceModel(m).fold() for _, m in batch]
+    start = _state(dps)
+    br = pi.BatchedRollout(dps, dms)
+    br.control_step()
+    after = _state(dps)
+    for dp, (x, u, it) in zip(dps, start):
+        dp.x0.copy_(x), dp.u_nom.copy_(u), dp.iter.copy_(it)
+    for b, (dp, dm) in enumerate(zip(dps, dms)):
+        _plain_control_step(dp, dm)
+        assert torch.equal(dp.x0, after[b][0]) and torch.equal(dp.u_nom, after[b][1]), b
+        assert torch.equal(dp.iter, after[b][2]), b
