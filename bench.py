@@ -105,13 +105,16 @@ def events_ms(pairs):
 
 def extra_config1(steps):
     """The 2048-rollout, 100-step quadrotor iteration (rollout + update + shift),
-    eager launches: small enough to leave compute units idle with one tile per
-    workgroup, so the library pairs workgroups."""
+    eager launches, launch shape from the autotuner: small enough to leave
+    compute units idle with one tile per workgroup, so pairs of workgroups
+    share a tile."""
     import torch
     import paper_1503_00330_amd as pi
     import synth
+    from paper_1503_00330_amd import tune
     prob, model, _ = synth.config(1)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model).fold()
+    tune.ensure(dp, dm)
     cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -141,12 +144,14 @@ def extra_config1(steps):
             "rollout_steps_per_s": prob.K * prob.T / (float(np.mean(it)) * 1e-3),
             "iteration_ms_p50": percentile(it, 50), "iteration_ms_p99": percentile(it, 99),
             "rollout_ms_mean": float(np.mean(roll)), "kernel": plan["kernel"],
+            "launch": {k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")},
             "rollout_frac_fp32_peak": flop / (float(np.mean(roll)) * 1e-3) / PEAK_FP32_MFMA}
 
 
 def extra_batched(reps):
-    """64 quadrotor controllers with uneven K, L, T and obstacles: one batched
-    control step against 64 plain control steps on the same stream."""
+    """64 quadrotor controllers with uneven K, L, T and obstacles (autotuned
+    tiles): batched rollouts and one batched control step against 64 plain
+    ones on the same stream."""
     import bench_extra
     r = bench_extra.w_batched(argparse.Namespace(steps=reps, tile_samples=0))
     return r
@@ -168,6 +173,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rollouts", type=int, default=1024, help="oracle sample: rollouts 0..n-1")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-tune", action="store_true", help="library default launch shapes (no autotuner)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the control steps directly instead of replaying graphs "
                          "(the same kernels; for profilers that count per dispatch)")
@@ -188,6 +194,11 @@ def main():
     prob, model, _ = synth.config(2)
     dp = pi.DeviceProblem(prob)
     dm = pi.DeviceModel(model).fold()      # the model is fixed over the loop: fold once
+    if not args.no_tune:
+        # the rollout launch shape from the autotuner (tuned now unless cached)
+        from paper_1503_00330_amd import tune
+        tune.ensure(dp, dm)
+        log("launch tuned: %s" % (pi.rollout_describe(dp, dm),))
     cost = torch.empty((prob.K, prob.T), dtype=torch.float32, device="cuda")
     saved = (dp.x0.clone(), dp.u_nom.clone(), dp.iter.clone())
     # one eager control step reserves every workspace and runs the library's
@@ -278,7 +289,8 @@ def main():
                      "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
                      "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model),
                      "sample_steps_per_launch": ssteps,
-                     "launch": {k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")}},
+                     "launch": dict({k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")},
+                                    autotuned=not args.no_tune)},
     }
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")

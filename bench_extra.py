@@ -108,14 +108,33 @@ def w_rh_graph(args):
 
 
 def w_batched(args):
+    """64 independent controllers with uneven K, L, T and obstacles.  Tiles
+    are picked by the autotuner (uniform tile shape over the batch; cached).
+    Reported: the batched rollouts against 64 plain rollout launches, and one
+    batched control step (rollouts, updates, plant steps and shifts; one HIP
+    graph) against 64 plain control steps (one HIP graph of all 64), with the
+    bitwise check that both leave every problem's state the same."""
     import torch
     import paper_1503_00330_amd as pi
+    from paper_1503_00330_amd import tune
     import synth
     batch = synth.batched_config()
-    dps = [pi.DeviceProblem(p, tile_samples=args.tile_samples) for p, _ in batch]
-    dms = [pi.DeviceModel(m) for _, m in batch]
-    br = pi.BatchedRollout(dps, dms)
+    dms = [pi.DeviceModel(m).fold() for _, m in batch]
+    dps = [pi.DeviceProblem(p, tile_samples=args.tile_samples, tile_split=1) for p, _ in batch]
+    if not args.tile_samples:
+        tiles = tune.ensure_batch(dps, dms)
+    else:
+        tiles = (args.tile_samples, 4)
+    for dp in dps:               # plain launches with the batch's tile and waves
+        dp.tile_waves = tiles[1]
     stream = torch.cuda.current_stream()
+    start = [(d.x0.clone(), d.u_nom.clone(), d.iter.clone()) for d in dps]
+
+    def restore():
+        for d, (x, u, it) in zip(dps, start):
+            d.x0.copy_(x), d.u_nom.copy_(u), d.iter.copy_(it)
+
+    br = pi.BatchedRollout(dps, dms)
     br.run()
     costs = [torch.empty((p.K, p.T), dtype=torch.float32, device="cuda") for p in dps]
 
@@ -126,21 +145,51 @@ def w_batched(args):
     torch.cuda.synchronize()
     tb = timed(br.run, args.steps or 3, stream)
     ts = timed(seq, args.steps or 3, stream)
+    same_cost = all(torch.equal(a, c) for a, c in zip(br.costs, costs))
+
+    def seq_step():
+        for dp, dm, c in zip(dps, dms, costs):
+            pi.rollout_cost(dp, dm, out=c)
+            pi.update(dp, c)
+            pi.rh_shift(dp, dm)
+    seq_step()              # reserves the workspaces before capture
+    torch.cuda.synchronize()
+    restore()
+    g_seq = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g_seq, stream=side):
+            seq_step()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    restore()
+    br.capture()
+    torch.cuda.synchronize()
+    reps = args.steps or 3
+    tcb = timed(br.graph.replay, reps, stream)
+    after_b = [(d.x0.clone(), d.u_nom.clone(), d.iter.clone()) for d in dps]
+    restore()
+    tcs = timed(g_seq.replay, reps, stream)
+    after_s = [(d.x0.clone(), d.u_nom.clone(), d.iter.clone()) for d in dps]
+    same_step = all(torch.equal(x, y) for a, b in zip(after_b, after_s) for x, y in zip(a, b))
+    restore()
     flop = sum(flops_per_sample_step(m) * p.K * p.T for p, m in batch)
     ss = sum(p.K * p.T for p, _ in batch)
-    # the persistent form runs one 4-wave workgroup per tile: bitwise equal to
-    # plain launches of that form (the timed plain launches may pair
-    # workgroups or run 8 waves)
-    one = [pi.DeviceProblem(p, tile_samples=args.tile_samples, tile_split=1, tile_waves=4) for p, _ in batch]
-    same = all(torch.equal(a, pi.rollout_cost(d, m)) for a, d, m in zip(br.costs, one, dms))
+    mb = float(np.median(tb))
     return {"workload": "64 quadrotor problems, K in 512..16384, L in 64..1024 per output, "
                         "T in 50..200, 10..40 obstacles",
-            "batched_ms": float(np.median(tb)), "sequential_ms": float(np.median(ts)),
-            "speedup": float(np.median(ts) / np.median(tb)),
-            "batched_rollout_steps_per_s": ss / (float(np.median(tb)) * 1e-3),
-            "batched_tflops": flop / (float(np.median(tb)) * 1e-3) / 1e12,
-            "batched_frac_fp32_peak": flop / (float(np.median(tb)) * 1e-3) / PEAK_FP32,
-            "bitwise_equal_to_plain": bool(same), "dtype": "f32"}
+            "tiles": {"tile_samples": tiles[0], "tile_waves": tiles[1], "autotuned": not args.tile_samples},
+            "batched_ms": mb, "sequential_ms": float(np.median(ts)),
+            "speedup": float(np.median(ts) / mb),
+            "control_step_batched_ms": float(np.median(tcb)),
+            "control_step_sequential_ms": float(np.median(tcs)),
+            "control_step_speedup": float(np.median(tcs) / np.median(tcb)),
+            "batched_rollout_steps_per_s": ss / (mb * 1e-3),
+            "batched_tflops": flop / (mb * 1e-3) / 1e12,
+            "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,
+            "bitwise_equal_to_plain": bool(same_cost), "control_step_bitwise_equal": bool(same_step),
+            "dtype": "f32"}
 
 
 def w_adjoint(args):
@@ -160,8 +209,13 @@ def w_adjoint(args):
     d = model.d
     f_fwd = flops_per_sample_step(model) * ss
     f_adj = model.Ltot * (3 * d * d + 9 * d + 15) * ss
+    import ctypes
+    ps, ms = dp.struct(), dm.struct()
+    ws_bytes = int(pi.load().pi_adjoint_workspace_bytes(ctypes.byref(ps), ctypes.byref(ms), extra["ckpt"]))
     return {"workload": "quadrotor adjoint K=8192 T=400 d=16 6x256 models, checkpoints every 20, "
                         "smooth obstacles",
+            "ckpt_every": extra["ckpt"], "workspace_bytes": ws_bytes,
+            "executed_forward_passes": 2,
             "forward_ms": float(np.median(tf)), "fused_forward_adjoint_ms": float(np.median(ta)),
             "ratio": float(np.median(ta) / np.median(tf)),
             "forward_rollout_steps_per_s": ss / (float(np.median(tf)) * 1e-3),

@@ -29,14 +29,19 @@ from . import (DeviceModel, DeviceProblem, PI_DYN_POINTMASS2D, PI_OP_ROLLOUT, PI
 class RHController:
     """The model is folded once here (DeviceModel.fold) unless fold_model is
     False: it stays fixed over the loop; call model.fold() again after changing
-    its tensors.  With `goals` (points of the cycle, rows of 3 coordinates)
+    its tensors.  With tune=True the rollout launch shape comes from the
+    autotuner (tune.ensure).  With `goals` (points of the cycle, rows of 3 coordinates)
     the controller sets the problem's goal itself (it writes prob.prob.goal)
     and switches to the next point within `switch_radius` of the current one."""
 
     def __init__(self, prob: DeviceProblem, model: DeviceModel, iterations: int = 1,
                  graph: bool = True, fold_model: bool = True, goals=None,
-                 switch_radius: float = 0.25):
+                 switch_radius: float = 0.25, tune: bool = False):
         self.prob, self.model = prob, model
+        if tune:
+            # the rollout launch from the autotuner's cache, tuned now if absent
+            from . import tune as _tune
+            _tune.ensure(prob, model)
         self.goals = None
         self.goal_index = 0
         self.switch_radius = float(switch_radius)
