@@ -10,7 +10,8 @@
  *  - Pointers marked "dev" are device (HBM) pointers; "host" pointers are read
  *    only during the call.  Every buffer is owned by the caller.  No entry
  *    point allocates device or pinned memory; scratch space is the caller's
- *    workspace `ws` of at least pi_workspace_bytes(...) bytes.
+ *    workspace `ws` of at least pi_workspace_bytes(...) bytes (except for
+ *    pi_rollout_cost_noalloc, whose scratch is a static device array).
  *  - All device work is enqueued on `stream` (a hipStream_t; NULL = the null
  *    stream) and is asynchronous; results are valid once the stream has been
  *    synchronised.  Because nothing is allocated and nothing is copied from
@@ -218,6 +219,24 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
  * are NaN.  (The environment variable PI2RH_PAIR_SPIN_LIMIT, read at each
  * launch, sets the polls of one wait -- for tests that force a give-up.)     */
 pi_status pi_pair_give_ups(uint64_t *count, void *stream);
+
+/* Allocation-free sampled rollouts, for callers that cannot allocate device
+ * memory or size a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): pi_rollout_cost with the same
+ * arguments, results and launches, minus the workspace.  Its scratch (the
+ * folded model unless pi_lwpr.folded is given, the sub-rollout costs when
+ * M > 1 and the pair-exchange slots) lives in a static device array of
+ * PI_NOALLOC_SCRATCH_BYTES per device, held from the first call on a device
+ * until the process ends; a rollout whose pi_workspace_bytes(PI_OP_ROLLOUT)
+ * exceeds it returns PI_ERR_WORKSPACE and enqueues nothing.  Calls allocate
+ * nothing; the first call on a device looks up the array's address (make it
+ * outside stream capture).  Every call on a device shares that one array:
+ * calls that overlap on the same device (concurrent streams or host threads)
+ * race and give undefined costs; calls ordered on one stream are safe.      */
+enum { PI_NOALLOC_SCRATCH_BYTES = 32 << 20 };
+pi_status pi_rollout_cost_noalloc(const pi_problem *p, const pi_lwpr *m, const void *x0,
+                                  const void *u_nom, const uint32_t *iter, void *cost,
+                                  void *stream);
 
 /* Path-integral update, Eq. (2): S_{k,i} = sum_{t>=i} cost[k][t] (or S_{k,0}
  * for PI_W_TRAJECTORY); P_{k,i} = softmax_k(-S_{k,i}/lambda);

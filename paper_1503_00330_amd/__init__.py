@@ -30,7 +30,7 @@ PI_MAX_OUT, PI_MAX_U = 8, 4
 STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4: "PI_ERR_DTYPE",
           5: "PI_ERR_WORKSPACE", 6: "PI_ERR_DEVICE", 7: "PI_ERR_UNSUPPORTED"}
 DYN_DIMS = {PI_DYN_POINTMASS2D: (4, 2, 2), PI_DYN_QUAD12: (12, 4, 6), PI_DYN_QUAD_HYBRID: (9, 4, 3)}
-EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
+EXPORTED = ["pi_workspace_bytes", "pi_model_fold_bytes", "pi_model_fold", "pi_rollout_describe", "lwpr_predict", "pi_rollout_cost", "pi_rollout_cost_noalloc", "pi_update", "pi_rh_shift",
             "pi_rollout_adjoint", "pi_adjoint_workspace_bytes", "pi_batched_workspace_bytes",
             "pi_rollout_cost_batched", "pi_control_step_batched", "pi_pair_give_ups", "pi_philox4x32_10", "pi_noise",
             "pi_last_error", "pi_version"]
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.pi_model_fold.restype = i32
     lib.lwpr_predict.argtypes = [vp, vp, i64, vp, vp, i32, vp, sz, vp]
     lib.pi_rollout_cost.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pi_rollout_cost_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.pi_update.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_rh_shift.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pi_rollout_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -101,7 +102,7 @@ def load(path: str = LIB_PATH):
     lib.pi_noise.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.pi_last_error.restype = C.c_char_p
     lib.pi_version.restype = C.c_char_p
-    for name in ("lwpr_predict", "pi_rollout_cost", "pi_update", "pi_rh_shift",
+    for name in ("lwpr_predict", "pi_rollout_cost", "pi_rollout_cost_noalloc", "pi_update", "pi_rh_shift",
                  "pi_rollout_adjoint", "pi_rollout_cost_batched", "pi_control_step_batched",
                  "pi_philox4x32_10", "pi_noise"):
         getattr(lib, name).restype = i32
@@ -328,6 +329,22 @@ def rollout_cost(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, i
     ws = workspace(workspace_bytes(PI_OP_ROLLOUT, prob, model), x0.device)
     _check(lib.pi_rollout_cost(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it),
                                _ptr(cost), _ptr(ws), ws.numel(), _stream()))
+    return cost
+
+
+def rollout_cost_noalloc(prob: DeviceProblem, model: DeviceModel, x0=None, u_nom=None, iter=None,
+                         out=None):
+    """rollout_cost through pi_rollout_cost_noalloc: no workspace, the library's
+    static per-device scratch instead (pass `out` to allocate nothing here)."""
+    torch = _torch()
+    x0 = prob.x0 if x0 is None else x0
+    u_nom = prob.u_nom if u_nom is None else u_nom
+    it = prob.iter if iter is None else iter
+    cost = out if out is not None else torch.empty((prob.K, prob.T), dtype=prob.dtype,
+                                                   device=x0.device)
+    ps, ms = prob.struct(), model.struct()
+    _check(load().pi_rollout_cost_noalloc(C.byref(ps), C.byref(ms), _ptr(x0), _ptr(u_nom), _ptr(it),
+                                          _ptr(cost), _stream()))
     return cost
 
 

@@ -14,6 +14,13 @@
 
 using namespace pi2rh;
 
+// Workspace of pi_rollout_cost_noalloc (folded model, sub-rollout costs,
+// pair-exchange slots), used instead of a caller buffer.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, never the device memory: kernels
+// receive the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PI_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -384,6 +391,26 @@ pi_status check_ws(void *ws, size_t ws_bytes, size_t need) {
 }
 
 // ---- allocation-free rollouts ---------------------------------------------------
+// The address of `scratch` on the current device (see its definition),
+// looked up once per device and cached.
+pi_status noalloc_scratch(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PI_ERR_DEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(PI_ERR_DEVICE, "device id out of range");
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {nullptr};
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[dev] == nullptr) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(PI_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return PI_OK;
+}
+
 // ---- batched problems ------------------------------------------------------------
 // Workspace of a batched call (pi_rollout_cost_batched, pi_control_step_batched):
 //   [problem descriptors B][work items][queue word]
@@ -669,6 +696,22 @@ pi_status pi_rollout_cost(const pi_problem *p, const pi_lwpr *m, const void *x0,
   PI_TRY(check_ws(ws, ws_bytes, rollout_ws(p, m)));
   PI_TRY(check_device());
   return launched(run_rollout(p, m, x0, u_nom, iter, cost, ws, (hipStream_t)stream), "pi_rollout_cost");
+}
+
+pi_status pi_rollout_cost_noalloc(const pi_problem *p, const pi_lwpr *m, const void *x0, const void *u_nom,
+                                  const uint32_t *iter, void *cost, void *stream) {
+  PI_TRY(check_rollout(p, m, x0, u_nom, iter, cost));
+  const size_t need = rollout_ws(p, m);
+  const size_t cap = (size_t)PI_NOALLOC_SCRATCH_BYTES;
+  if (need > cap)
+    return fail(PI_ERR_WORKSPACE,
+                "this rollout needs %zu bytes of scratch; the allocation-free entry point holds %zu "
+                "(pass a folded model, fewer sub-rollouts, or use pi_rollout_cost with a workspace)",
+                need, cap);
+  PI_TRY(check_device());
+  void *ptr = nullptr;
+  PI_TRY(noalloc_scratch(&ptr));
+  return launched(run_rollout(p, m, x0, u_nom, iter, cost, ptr, (hipStream_t)stream), "pi_rollout_cost_noalloc");
 }
 
 pi_status pi_update(const pi_problem *p, const void *cost, const uint32_t *iter, void *u_nom,

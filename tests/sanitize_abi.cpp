@@ -86,6 +86,9 @@ int main() {
           p.tile_split = split;
           EXPECT(pi_rollout_cost(&p, &m, FAKE, FAKE, (const uint32_t *)FAKE, FAKE, FAKE, (size_t)1 << 40,
                                  NULL) == PI_ERR_DEVICE);
+          EXPECT(pi_rollout_cost_noalloc(&p, &m, FAKE, FAKE, (const uint32_t *)FAKE, FAKE, NULL) ==
+                 (pi_workspace_bytes(PI_OP_ROLLOUT, &p, &m) > PI_NOALLOC_SCRATCH_BYTES ? PI_ERR_WORKSPACE
+                                                                                        : PI_ERR_DEVICE));
           int32_t out[4];
           EXPECT(pi_rollout_describe(&p, &m, out) == PI_ERR_DEVICE);
         }

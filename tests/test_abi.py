@@ -175,6 +175,24 @@ class TestValidation:
         assert _rollout(ps, ms, ws_bytes=need - 1) == 5
         assert _rollout(ps, ms, ws=None) == 5
 
+    def test_noalloc_rollout_validates_before_the_device(self):
+        # the allocation-free rollout takes no workspace: it checks its request
+        # against the static scratch and never reaches the device when too big
+        lib = pi.load()
+        ps, ms = _structs()
+        call = lambda cost=FAKE: lib.pi_rollout_cost_noalloc(C.byref(ps), C.byref(ms), FAKE, FAKE,
+                                                             FAKE, cost, None)
+        assert call(cost=None) == 1
+        ps.K, ps.T, ps.M = 4096, 200, 8          # 26 MB of sub-rollout costs: fits
+        ps.tile_split = 1                        # (no pair-exchange slots)
+        assert lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms)) <= 32 << 20
+        assert call() == 6 and "device" in pi.last_error()
+        ps.M = 16                                # 52 MB: over the 32 MiB scratch
+        assert lib.pi_workspace_bytes(pi.PI_OP_ROLLOUT, C.byref(ps), C.byref(ms)) > 32 << 20
+        assert call() == 5 and "allocation-free" in pi.last_error()
+        ps.K = 0
+        assert call() == 2
+
     def test_mfma_needs_float32(self):
         ps, ms = _structs(dtype=np.float64)
         ps.variant = pi.PI_VARIANT_MFMA
