@@ -205,6 +205,10 @@ def w_adjoint(args):
     torch.cuda.synchronize()
     tf = timed(lambda: pi.rollout_cost(dp, dm, out=cost), args.steps or 3, stream)
     ta = timed(lambda: pi.rollout_adjoint(dp, dm, ckpt_every=extra["ckpt"]), args.steps or 3, stream)
+    # the whole horizon as one segment: traced by the forward itself, no
+    # recompute, the workspace of every step
+    pi.rollout_adjoint(dp, dm, ckpt_every=prob.T)
+    tw = timed(lambda: pi.rollout_adjoint(dp, dm, ckpt_every=prob.T), args.steps or 3, stream)
     ss = prob.K * prob.T
     d = model.d
     f_fwd = flops_per_sample_step(model) * ss
@@ -212,10 +216,13 @@ def w_adjoint(args):
     import ctypes
     ps, ms = dp.struct(), dm.struct()
     ws_bytes = int(pi.load().pi_adjoint_workspace_bytes(ctypes.byref(ps), ctypes.byref(ms), extra["ckpt"]))
+    ws_whole = int(pi.load().pi_adjoint_workspace_bytes(ctypes.byref(ps), ctypes.byref(ms), prob.T))
     return {"workload": "quadrotor adjoint K=8192 T=400 d=16 6x256 models, checkpoints every 20, "
                         "smooth obstacles",
             "ckpt_every": extra["ckpt"], "workspace_bytes": ws_bytes,
             "executed_forward_passes": 2,
+            "whole_horizon_segment": {"fused_forward_adjoint_ms": float(np.median(tw)), "workspace_bytes": ws_whole,
+                                      "ratio": float(np.median(tw) / np.median(tf))},
             "forward_ms": float(np.median(tf)), "fused_forward_adjoint_ms": float(np.median(ta)),
             "ratio": float(np.median(ta) / np.median(tf)),
             "forward_rollout_steps_per_s": ss / (float(np.median(tf)) * 1e-3),

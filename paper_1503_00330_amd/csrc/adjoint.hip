@@ -51,6 +51,10 @@ struct AdjGeo {
   static constexpr int NP = D * (D + 1) / 2;
   static constexpr int SEGW = NX + 3 * NO;       // x_t, then (mu, var, lse) per output
   static constexpr int RW = D + 5 * NO + NU;     // z, (lse, mu, var, mubar, vbar) per output, ubar
+  // matrix-core form: the trace keeps the forward's anchors per output
+  // (d1, var, log2 Z, m, yref) and the records add mubar, vbar to them
+  static constexpr int SEGW_M = NX + 5 * NO;
+  static constexpr int RW_M = D + 7 * NO + NU;
   static constexpr int PW = NP + D + 1;          // packed sum qbar dl dl^T, sum qbar dl, sum ybar
   static constexpr int TM = tile_models<Real, D>();
 };
@@ -498,10 +502,12 @@ __global__ void adj_param_mfma_finish_kernel(ModelArgs m, MfmaLayout l, const fl
 }
 
 // Stage 4b: dJ/du_nom[t] = scale * sum_s ubar[s][t] (block per step, fixed tree;
-// T steps of records from `recs`, written to gu[t]).
+// T steps of records of rw values from `recs`, ubar at offset uoff, written
+// to gu[t]).
 template <typename Real, int DYN>
-__global__ void __launch_bounds__(256) adj_u_kernel(int64_t S, int T, const Real *__restrict__ recs,
-                                                    double scale, const double *gJ, Real *__restrict__ gu) {
+__global__ void __launch_bounds__(256) adj_u_kernel(int64_t S, int T, const Real *__restrict__ recs, int rw,
+                                                    int uoff, double scale, const double *gJ,
+                                                    Real *__restrict__ gu) {
   using G = AdjGeo<Real, DYN>;
   __shared__ double red[256][G::NU];
   const int t = blockIdx.x;
@@ -509,7 +515,7 @@ __global__ void __launch_bounds__(256) adj_u_kernel(int64_t S, int T, const Real
   double acc[G::NU];
   for (int i = 0; i < G::NU; ++i) acc[i] = 0.0;
   for (int64_t s = threadIdx.x; s < S; s += 256)
-    for (int i = 0; i < G::NU; ++i) acc[i] += (double)recs[(s * T + t) * G::RW + G::D + 5 * G::NO + i];
+    for (int i = 0; i < G::NU; ++i) acc[i] += (double)recs[(s * T + t) * rw + uoff + i];
   for (int i = 0; i < G::NU; ++i) red[threadIdx.x][i] = acc[i];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -586,7 +592,7 @@ size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d
   const bool mfma = mfma_bytes > 0;
   ckpt = std::max(1, std::min(ckpt, T));
   const int ncp = (T + ckpt - 1) / ckpt;
-  const int segw = nx + 3 * no, rw = d + 5 * no + nu;
+  const int segw = nx + (mfma ? 5 : 3) * no, rw = d + (mfma ? 7 : 5) * no + nu;
   const int64_t rec_steps = mfma ? ckpt : T;
   size_t b = direct_bytes(dtype, d, Ltot) + align_up((size_t)S * ncp * nx * rb, 256) +
              align_up((size_t)S * (ckpt + 1) * segw * rb, 256) + align_up((size_t)S * rec_steps * rw * rb, 256) +
@@ -619,10 +625,11 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   a.ncp = ncp;
   a.ckpt_buf = (Real *)w;
   w += align_up((size_t)S * ncp * G::NX * sizeof(Real), 256);
+  const int segw = mfma ? G::SEGW_M : G::SEGW, rw = mfma ? G::RW_M : G::RW;
   a.seg = (Real *)w;
-  w += align_up((size_t)S * (ckpt + 1) * G::SEGW * sizeof(Real), 256);
+  w += align_up((size_t)S * (ckpt + 1) * segw * sizeof(Real), 256);
   a.recs = (Real *)w;
-  w += align_up((size_t)R * G::RW * sizeof(Real), 256);
+  w += align_up((size_t)R * rw * sizeof(Real), 256);
   a.jsum = (double *)w;
   w += align_up((size_t)S * 8, 256);
   Real *gpart = (Real *)w;
@@ -674,11 +681,11 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
         }
         e = launch_adj_reverse_mfma(p, u_nom, iter, *ml, mbase, rfold, a.seg, ckpt, tb, te, xbar, a.recs, s);
         if (e != hipSuccess) break;
-        e = launch_adj_param_mfma(*ml, mbase, (const float *)a.recs, G::RW, S * (te - tb), nchm, (float *)gpart,
-                                  g != ncp - 1, s);
+        e = launch_adj_param_mfma(*ml, mbase, (const float *)a.recs, G::RW_M, S * (te - tb), nchm,
+                                  (float *)gpart, g != ncp - 1, s);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL((adj_u_kernel<Real, DYN>), dim3(te - tb), dim3(256), 0, s, S, te - tb,
-                           (const Real *)a.recs, scale, gJ, gu + (size_t)tb * G::NU);
+                           (const Real *)a.recs, G::RW_M, G::D + 7 * G::NO, scale, gJ, gu + (size_t)tb * G::NU);
       }
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((adj_param_mfma_finish_kernel<DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m, *ml,
@@ -697,7 +704,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
   hipLaunchKernelGGL((adj_param_finish_kernel<Real, DYN>), dim3((m.Ltot + 63) / 64), dim3(64), 0, s, m,
                      a.model, nch, (const Real *)gpart, scale, gJ, gc, gD);
   hipLaunchKernelGGL((adj_u_kernel<Real, DYN>), dim3(p.T), dim3(256), 0, s, S, p.T, (const Real *)a.recs,
-                     scale, gJ, gu);
+                     G::RW, G::D + 5 * G::NO, scale, gJ, gu);
   hipLaunchKernelGGL(adj_j_kernel, dim3(1), dim3(256), 0, s, S, (const double *)a.jsum, scale, J);
   return hipGetLastError();
 }

@@ -183,7 +183,7 @@ int adj_param_mfma_width(int d);
 // (adj_rfold_bytes, launch_adj_rfold); then, per segment [tb, te) of the
 // horizon, one workgroup per 16 sub-rollouts sweeps t = te-1..tb over the
 // segment's trace (rows counted from tb, trace_T + 1 per sub-rollout) and
-// writes the segment's records [S][te - tb][d + 5 n_out + n_u].  The state
+// writes the segment's records [S][te - tb][d + 7 n_out + n_u].  The state
 // adjoint enters from xbar_io (unless te = T) and leaves to it (unless tb = 0).
 size_t adj_rfold_bytes(const MfmaLayout &l);
 hipError_t launch_adj_rfold(const ModelArgs &m, const MfmaLayout &l, const void *rec, int RS, void *rfold,

@@ -216,7 +216,6 @@ struct MixSmem {
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mprev[ROWS][kMaxOut];            // previous step's largest activation
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
-  float lse[ROWS][kMaxOut];              // log sum_j exp(-q_j / 2)
   float acc[ROWS][kMaxOut];              // sampled accelerations (rollouts)
   unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
   int redo[2];                           // second-pass requests, by evaluation parity
@@ -477,8 +476,13 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // set, acc = mu + sqrt(var) xi[row][o] (a draw from N(mu, var)); without, mu.
 struct SampleArgs {
   const float *xi;   // [rows][8] standard normals of this step, or null
-  // optional per-step trace: (mu, var, lse) of output o for row r go to
-  // trace[r * trace_stride + trace_off + 3 o + {0, 1, 2}] for r < trace_rows
+  // optional per-step trace of the adjoint: for row r < trace_rows and output
+  // o, trace[r * trace_stride + trace_off + 5 o + {0..4}] = (d1, var, log2 Z,
+  // m, yref) of the evaluation's final pass: the activation anchor m and the
+  // prediction reference yref it used, its normaliser Z = sum_j 2^(a_j) with
+  // a_j = -q_j log2(e) / 2 - m, and d1 = mu - yref.  A reverse sweep that
+  // contracts with the same anchors reproduces every a_j and y_j - yref
+  // bitwise, so its weights 2^(a_j - log2 Z) are the forward's.
   float *trace = nullptr;
   int64_t trace_stride = 0;
   int trace_off = 0, trace_rows = 0;
@@ -496,8 +500,16 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int
   const float var = (fmaxf(s.S2 - s.S1 * d1, 0.f) + s.S3) / s.Z;
   sm.mean[row][o] = mu;
   sm.var[row][o] = var;
-  // the anchor in use is m (base-2 units): sum_j exp(-q_j/2) = 2^m Z
-  sm.lse[row][o] = 0.69314718055994531f * (sm.mref[row][o] + log2f(s.Z));
+  // the anchor in use is m (base-2 units): sum_j exp(-q_j/2) = 2^m Z.  A
+  // redo pass rewrites the trace, so it ends with the final pass's values.
+  if (sa.trace && row < sa.trace_rows) {
+    float *dst = sa.trace + row * sa.trace_stride + sa.trace_off + 5 * o;
+    dst[0] = d1;
+    dst[1] = var;
+    dst[2] = log2f(s.Z);
+    dst[3] = sm.mref[row][o];
+    dst[4] = sm.yref[row][o];
+  }
   sm.acc[row][o] = sa.xi ? mu + sqrtf(var) * sa.xi[row * 8 + o] : mu;
   const bool valid = isfinite(s.Z) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.S3) && s.mx >= kAnchorLo;
   if (!valid) sm.redo[ev & 1] = 1;
@@ -655,12 +667,6 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
         const float d = force_second ? 0.f : M - sm.mprev[row][o];
         sm.mprev[row][o] = M;
         if (isfinite(d)) sm.mref[row][o] = M + d;
-        if (sa.trace && row < sa.trace_rows) {
-          float *dst = sa.trace + row * sa.trace_stride + sa.trace_off + 3 * o;
-          dst[0] = sm.mean[row][o];
-          dst[1] = sm.var[row][o];
-          dst[2] = sm.lse[row][o];
-        }
       }
       break;
     }
@@ -784,7 +790,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
   MixSmem<D, MT, NW> &sm = rs.sm;
-  constexpr int SEGW = NX + 3 * NO;
+  constexpr int SEGW = NX + 5 * NO;   // trace row: x_t, then 5 values per output (SampleArgs)
   const int tb = sg ? sg->tb : 0, te = sg ? sg->te : p.T;
   const int ck = sg ? sg->ckpt : 0;
   const int nck = ck > 0 ? (p.T + ck - 1) / ck : 0;
@@ -1129,9 +1135,10 @@ MfmaModel mfma_model_view(const MfmaLayout &l, const void *base) { return mfma_v
 // Parameter gradients of the adjoint on the matrix cores.  For a tile of 16
 // records (sub-rollout steps of the reverse sweep) and a tile of 16 local
 // models of output o:
-//  (1) the forward contraction, with the activation anchor at lse_{r,o} and
-//      the prediction reference at mu_{r,o}, returns log2 w_{rj} and
-//      e_{rj} = y_j - mu directly;
+//  (1) the forward contraction, with the activation anchor and prediction
+//      reference the forward used for record r and output o, returns the
+//      forward's a_{rj} and y_j - yref bitwise; w_{rj} = 2^(a_{rj} - log2 Z)
+//      and e_{rj} = y_j - mu = (y_j - yref) - d1;
 //  (2) each lane turns its four (record, model) elements into
 //      ybar = w (mubar + 2 vbar e) and qbar = -w (mubar e + vbar (e^2 + sigma_j^2 - var)) / 2;
 //  (3) G_j += sum_r qbar_{rj} Phi(z_r), Phi = [z_a z_b (a <= b), z, 1]: the C
@@ -1154,7 +1161,7 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   __shared__ MixSmem<D, 1, 4> sm;
-  __shared__ float st[16][kMaxOut][5];        // lse, mu, var, mubar, vbar per record and output
+  __shared__ float st[16][kMaxOut][7];        // d1, var, log2 Z, m, yref, mubar, vbar per record and output
   // the wave index is uniform: its tiles' indices and offsets stay scalar
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ch = blockIdx.y;
@@ -1194,7 +1201,7 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
   // A record tile's inputs (z and the five statistics per output of 16
   // records) pass through registers: the next tile's are requested while the
   // current one is contracted, so their memory latency is hidden.
-  constexpr int NZI = (16 * D + 255) / 256, NSI = (16 * kMaxOut * 5 + 255) / 256;
+  constexpr int NZI = (16 * D + 255) / 256, NSI = (16 * kMaxOut * 7 + 255) / 256;
   float zr[NZI], sr[NSI];
   auto fetch = [&](int64_t rb) {
     const int nr = (int)min((int64_t)16, r1 - rb);
@@ -1207,10 +1214,10 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
     for (int k = 0; k < NSI; ++k) {
       const int i = threadIdx.x + 256 * k;
-      const int row = i / (n_out * 5), rem = i - row * (n_out * 5);
-      const int o = rem / 5, c = rem - o * 5;
+      const int row = i / (n_out * 7), rem = i - row * (n_out * 7);
+      const int o = rem / 7, c = rem - o * 7;
       // rows past the chunk carry mubar = vbar = 0, so they add nothing
-      sr[k] = (i < 16 * n_out * 5 && row < nr) ? recs[(rb + row) * RW + D + 5 * o + c] : 0.0f;
+      sr[k] = (i < 16 * n_out * 7 && row < nr) ? recs[(rb + row) * RW + D + 7 * o + c] : 0.0f;
     }
   };
   f32x4 B[G::KB4];
@@ -1226,9 +1233,9 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
     for (int k = 0; k < NSI; ++k) {
       const int i = threadIdx.x + 256 * k;
-      if (i < 16 * n_out * 5) {
-        const int row = i / (n_out * 5), rem = i - row * (n_out * 5);
-        st[row][rem / 5][rem % 5] = sr[k];
+      if (i < 16 * n_out * 7) {
+        const int row = i / (n_out * 7), rem = i - row * (n_out * 7);
+        st[row][rem / 7][rem % 7] = sr[k];
       }
     }
     if (rb + 16 < r1) fetch(rb + 16);
@@ -1259,8 +1266,9 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
       if (tile[q] >= md.n_tiles) continue;   // uniform over the wave
       const int o = tout[q];
       const int row = lane & 15;
-      if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = -st[row][o][0] * 1.4426950408889634f;
-      if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = -st[row][o][1];
+      // the forward's anchors (activation anchor m, prediction reference yref)
+      if ((lane >> 4) == GQS) A[KQS / 4][KQS % 4] = -st[row][o][3];
+      if ((lane >> 4) == GYS) A[KYS / 4][KYS % 4] = -st[row][o][4];
       const float s2 = buffer_f32(srs, (lane & 15) * 4, tile[q] * 64);
       __builtin_amdgcn_sched_barrier(0);
       f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = qa, ya = qa;
@@ -1283,10 +1291,10 @@ __global__ void __launch_bounds__(256) adj_param_mfma_kernel(MfmaModel md, const
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = 4 * (lane >> 4) + i;
-        // normalised weight (anchor = log-sum-exp, so w <= 1): the bare
-        // v_exp_f32, whose results below 2^-126 flush to 0, loses nothing
-        const float w = __builtin_amdgcn_exp2f(qa[i] + qb[i]), e = ya[i];
-        const float var = st[rr][o][2], mub = st[rr][o][3], vb = st[rr][o][4];
+        // normalised weight 2^(a - log2 Z) <= 1 (the bare v_exp_f32, whose
+        // results below 2^-126 flush to 0, loses nothing); e = y - mu
+        const float w = __builtin_amdgcn_exp2f((qa[i] + qb[i]) - st[rr][o][2]), e = ya[i] - st[rr][o][0];
+        const float var = st[rr][o][1], mub = st[rr][o][5], vb = st[rr][o][6];
         ysum[q] += w * (mub + 2.0f * vb * e);
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
       }
@@ -1404,14 +1412,14 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   using G = Geo<D>;
   using RG = RevGeo<D>;
-  constexpr int SEGW = NX + 3 * NO, RW = D + 5 * NO + NU;
+  constexpr int SEGW = NX + 5 * NO, RW = D + 7 * NO + NU;
   constexpr int NPOS = DYN == kDynPointMass2D ? 2 : 3;
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
   constexpr int PSTR = RG::NFB * 16;
   __shared__ MixSmem<D, 1, 4> sm;
   __shared__ float xbar[16][NX];
-  __shared__ float stt[16][kMaxOut][5];          // mu, var, lse, mubar, vbar
+  __shared__ float stt[16][kMaxOut][7];          // d1, var, log2 Z, m, yref, mubar, vbar
   __shared__ float part[4][16][PSTR];            // per-wave sums of the second contraction
   __shared__ float zb[16][D];
   __shared__ float obs_s[kMaxObs * 3];
@@ -1458,22 +1466,16 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
         lwpr_input<DYN>(x, u, z);
         for (int i = 0; i < D; ++i) sm.z[row][i] = z[i];
         for (int o = 0; o < NO; ++o) {
-          const float mu = tr[(int64_t)t * SEGW + NX + 3 * o], v = tr[(int64_t)t * SEGW + NX + 3 * o + 1];
-          stt[row][o][0] = mu;
-          stt[row][o][1] = v;
-          stt[row][o][2] = tr[(int64_t)t * SEGW + NX + 3 * o + 2];
-          stt[row][o][3] = ab[o];
-          stt[row][o][4] = (p.M > 0 && v > 0.f) ? ab[o] * xi[o] / (2.0f * sqrtf(v)) : 0.0f;
+          const float *tro = tr + (int64_t)t * SEGW + NX + 5 * o;
+          const float v = tro[1];
+          for (int c = 0; c < 5; ++c) stt[row][o][c] = tro[c];
+          stt[row][o][5] = ab[o];
+          stt[row][o][6] = (p.M > 0 && v > 0.f) ? ab[o] * xi[o] / (2.0f * sqrtf(v)) : 0.0f;
         }
       } else {
         for (int i = 0; i < D; ++i) sm.z[row][i] = 0.0f;
-        for (int o = 0; o < NO; ++o) {
-          stt[row][o][0] = 0.f;
-          stt[row][o][1] = 1.f;
-          stt[row][o][2] = 0.f;
-          stt[row][o][3] = 0.f;
-          stt[row][o][4] = 0.f;
-        }
+        for (int o = 0; o < NO; ++o)
+          for (int c = 0; c < 7; ++c) stt[row][o][c] = c == 1 ? 1.f : 0.f;
       }
     }
     __syncthreads();
@@ -1513,11 +1515,14 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
 #pragma unroll
       for (int i = 1; i < kMaxOut; ++i) o += (i < md.n_out && md.tile_off[i] <= tile) ? 1 : 0;
       if (o != ocur) {
+        // the forward's anchors: every activation and prediction difference
+        // comes out bitwise as the forward's final pass had them
         ocur = o;
-        if ((lane >> 4) == GQS) Z[KQS / 4][KQS % 4] = -stt[smp][o][2] * 1.4426950408889634f;
-        if ((lane >> 4) == GYS) Z[KYS / 4][KYS % 4] = -stt[smp][o][0];
+        if ((lane >> 4) == GQS) Z[KQS / 4][KQS % 4] = -stt[smp][o][3];
+        if ((lane >> 4) == GYS) Z[KYS / 4][KYS % 4] = -stt[smp][o][4];
       }
-      const float var = stt[smp][o][1], mub = stt[smp][o][3], vb = stt[smp][o][4];
+      const float d1 = stt[smp][o][0], var = stt[smp][o][1], l2z = stt[smp][o][2];
+      const float mub = stt[smp][o][5], vb = stt[smp][o][6];
       // sigma^2 of the lane's four models 4 (lane/16) + i, one 16-byte read
       const f32x4 s2v = buffer_f32x4(srs, 16 * (lane >> 4), tile * 64);
       loadP(P, tile);
@@ -1540,9 +1545,9 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float s2 = s2v[i];
-        // normalised weight (anchor = log-sum-exp, so w <= 1): the bare
-        // v_exp_f32, whose results below 2^-126 flush to 0, loses nothing
-        const float w = __builtin_amdgcn_exp2f(qa[i] + qb[i]), e = ya[i];
+        // normalised weight 2^(a - log2 Z) <= 1: the bare v_exp_f32, whose
+        // results below 2^-126 flush to 0, loses nothing; e = y - mu
+        const float w = __builtin_amdgcn_exp2f((qa[i] + qb[i]) - l2z), e = ya[i] - d1;
         ybar[i] = w * (mub + 2.0f * vb * e);
         qbar[i] = -0.5f * w * (mub * e + vb * (e * e + s2 - var));
       }
@@ -1589,14 +1594,9 @@ __global__ void __launch_bounds__(256) adj_reverse_mfma_kernel(RevArgs ra) {
       for (int i = 0; i < NX; ++i) xbar[row][i] = xp[i] + zb[row][i];
       float *rec = ra.recs + (s * (te - tb) + (t - tb)) * RW;
       for (int i = 0; i < D; ++i) rec[i] = sm.z[row][i];
-      for (int o = 0; o < NO; ++o) {
-        rec[D + 5 * o] = stt[row][o][2];
-        rec[D + 5 * o + 1] = stt[row][o][0];
-        rec[D + 5 * o + 2] = stt[row][o][1];
-        rec[D + 5 * o + 3] = stt[row][o][3];
-        rec[D + 5 * o + 4] = stt[row][o][4];
-      }
-      for (int i = 0; i < NU; ++i) rec[D + 5 * NO + i] = zb[row][NX + i];
+      for (int o = 0; o < NO; ++o)
+        for (int c = 0; c < 7; ++c) rec[D + 7 * o + c] = stt[row][o][c];
+      for (int i = 0; i < NU; ++i) rec[D + 7 * NO + i] = zb[row][NX + i];
     }
     __syncthreads();
   }

@@ -23,11 +23,6 @@ def _device():
     torch.cuda.synchronize()
 
 
-# FP32 against FP64 for the mean cost at the 400-step adjoint workload, where
-# rounding differences grow chaotically (2.8e-3 measured)
-FP32_LONG_J_TOL = 1e-2
-
-
 def nrel(g, o):
     g, o = np.asarray(g, np.float64).ravel(), np.asarray(o, np.float64).ravel()
     return float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-300))
@@ -200,17 +195,62 @@ def test_adjoint_full_size_fp64():
         assert nrel(g.cpu().numpy(), o) <= 1e-5
 
 
+def _x0_envelope(prob, model, rel=2.0 ** -24):
+    """FP64 sensitivity of the rollout costs to one FP32 unit roundoff in the
+    start position: per-rollout relative cost changes (max over the two signs)
+    and the change of the mean cost, with the unperturbed costs."""
+    m64 = pi.DeviceModel(model, dtype=torch.float64)
+    S = pi.rollout_cost(pi.DeviceProblem(prob, dtype=torch.float64), m64).sum(1).cpu().numpy()
+    env, envJ = np.zeros_like(S), 0.0
+    for sgn in (1.0, -1.0):
+        dp = pi.DeviceProblem(prob, dtype=torch.float64)
+        dp.x0[:3] *= 1.0 + sgn * rel
+        Sp = pi.rollout_cost(dp, m64).sum(1).cpu().numpy()
+        env = np.maximum(env, np.abs(Sp - S) / np.abs(S))
+        envJ = max(envJ, abs(Sp.mean() - S.mean()) / abs(S.mean()))
+    return S, env, envJ
+
+
 def test_adjoint_full_size_fp32():
-    # the same workload in FP32: every gradient finite (the variance of
-    # Eq. (1) is clamped against rounding), and J consistent with the FP64
-    # forward kernel to the spread FP32 trajectories reach over 400 chaotic
-    # steps (per-rollout cost differences: median 3e-5, 99th percentile 0.12;
-    # mean cost 2.8e-3 measured)
+    # The adjoint workload in FP32 (K = 8192, T = 400, checkpoints every 20,
+    # smooth obstacles).  Over 400 steps many trajectories leave the models'
+    # support; the FP64 path itself then moves its per-rollout costs by up to
+    # O(1) under a single FP32 unit roundoff in the start position, while FP32
+    # rounds at every step.  So FP32 is held to that envelope, measured here in
+    # FP64: the mean cost (J of the adjoint's own forward) within 10x the
+    # envelope's change of the mean, the non-chaotic majority of rollouts
+    # (median) within the 1e-4 cost tolerance, and the 90th percentile within
+    # 10x the envelope's.  Gradients must be finite (FP32 gradients are
+    # compared with FP64 where the trajectories stay well-conditioned: T <= 200).
     prob, model, _ = synth.config(4, obs_kind=OBS_SMOOTH)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
     J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=20)
     for g in (gu, gc, gD):
         assert torch.isfinite(g).all()
-    d64 = pi.DeviceProblem(prob, dtype=torch.float64)
-    J64 = pi.rollout_cost(d64, pi.DeviceModel(model, dtype=torch.float64)).sum(1).mean().item()
-    assert abs(J.item() - J64) <= FP32_LONG_J_TOL * abs(J64)
+    S64, env, envJ = _x0_envelope(prob, model)
+    Jrel = abs(J.item() - S64.mean()) / abs(S64.mean())
+    S32 = pi.rollout_cost(dp, dm).double().sum(1).cpu().numpy()
+    e = np.abs(S32 - S64) / np.abs(S64)
+    print("T=400 FP32: J rel %.2e (envelope %.2e); per-rollout median %.2e, p90 %.2e (envelope p90 %.2e)"
+          % (Jrel, envJ, np.median(e), np.percentile(e, 90), np.percentile(env, 90)))
+    assert Jrel <= 10 * envJ
+    assert np.median(e) <= 1e-4
+    assert np.percentile(e, 90) <= 10 * np.percentile(env, 90)
+
+
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_AUTO, pi.PI_VARIANT_DIRECT])
+def test_adjoint_fp32_gradients_over_200_steps(variant):
+    # the adjoint workload's batch over 200 steps, where trajectories stay near
+    # the models' support: FP32 gradients (matrix-core and direct) against the
+    # FP64 ones at full size (2.5e-4 measured for both: the sensitivity of the
+    # map grows like exp(0.04 T), 2.4e-7 at T = 100), and per rollout on the
+    # first 16 rollouts
+    for K in (8192, 16):
+        prob, model, _ = synth.config(4, obs_kind=OBS_SMOOTH, T=200, K=K)
+        r64 = pi.rollout_adjoint(pi.DeviceProblem(prob, dtype=torch.float64),
+                                 pi.DeviceModel(model, dtype=torch.float64), ckpt_every=20)
+        r32 = pi.rollout_adjoint(pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model), ckpt_every=20)
+        assert abs(r32[0].item() - r64[0].item()) <= 1e-6 * abs(r64[0].item())
+        errs = [nrel(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(r32[1:], r64[1:])]
+        print("T=200 K=%d variant %d: gradient errors %s" % (K, variant, ["%.2e" % x for x in errs]))
+        assert max(errs) <= 1e-3
