@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "LWPR rollout steps/s + PI^2 update p50/p99 latency; fwd+adjoint & batched vs plain"
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_BF16_MFMA = 2.5e15        # MI355X dense bf16 matrix peak, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
 TRAFFIC_SUMMARY = {
     "rollout_mfma_kernel": os.path.join(ROOT, "profiles", "rollout_mfma_kernel.quad_k65536_t200.traffic.txt"),
@@ -50,6 +51,39 @@ def flops_per_sample_step(model):
     local prediction) + 6 (mixture accumulation) = d^2 + 5d + 8 flop."""
     d = model.d
     return model.Ltot * (d * d + 5 * d + 8)
+
+
+def bf16x3_flops_per_launch(model, n_samples, T):
+    """Matrix-core work the three-piece bf16 contraction executes: per 16-row
+    tile of samples, 16-model tile and step, 6 blocks of 32 features x 6
+    piece products, each a 16x16x32 product of 2*16*16*32 flop (the padded
+    feature layout and the piece products it takes to reach float32 accuracy,
+    not algorithmic work)."""
+    n_model_tiles = sum((int(model.L_off[i + 1]) - int(model.L_off[i]) + 15) // 16 for i in range(model.n_out))
+    return ((n_samples + 15) // 16) * n_model_tiles * T * 36 * (2 * 16 * 16 * 32)
+
+
+def roofline(model, plan, n_samples, T, flop, seconds, traffic, autotuned):
+    """The rollout kernel's roofline entry: algorithmic FLOP over the measured
+    duration against the peak of the matrix instructions it runs (float32, or
+    bf16 for the three-piece form, which also reports its executed bf16 rate
+    and the float32-equivalent fraction)."""
+    achieved = flop / seconds
+    bf = plan["variant"] == "mfma-bf16x3"
+    peak = PEAK_BF16_MFMA if bf else PEAK_FP32_MFMA
+    r = {"bound": "mfma", "kernel": plan["kernel"], "mfma_dtype": "bf16x3" if bf else "f32",
+         "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+         "traffic": traffic, "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model),
+         "sample_steps_per_launch": n_samples * T,
+         "launch": dict({k: plan[k] for k in ("variant", "tile_samples", "tile_waves", "tile_split")},
+                        autotuned=autotuned)}
+    if bf:
+        ex = bf16x3_flops_per_launch(model, n_samples, T)
+        r.update({"executed_bf16_flop_per_launch": ex, "executed_bf16": ex / seconds / 1e12,
+                  "executed_bf16_frac": ex / seconds / PEAK_BF16_MFMA,
+                  "fp32_equivalent_peak": PEAK_FP32_MFMA / 1e12,
+                  "fp32_equivalent_frac": achieved / PEAK_FP32_MFMA})
+    return r
 
 
 def percentile(xs, q):
@@ -140,12 +174,13 @@ def extra_config1(steps):
     it = [a.elapsed_time(c) for a, b, c in rec]
     flop = flops_per_sample_step(model) * prob.K * prob.T
     plan = pi.rollout_describe(dp, dm)
+    rl = roofline(model, plan, prob.K * max(prob.M, 1), prob.T, flop, float(np.mean(roll)) * 1e-3, None, True)
     return {"workload": "quadrotor K=2048 T=100 M=1, 6 x 256 models, eager iteration",
             "rollout_steps_per_s": prob.K * prob.T / (float(np.mean(it)) * 1e-3),
             "iteration_ms_p50": percentile(it, 50), "iteration_ms_p99": percentile(it, 99),
-            "rollout_ms_mean": float(np.mean(roll)), "kernel": plan["kernel"],
-            "launch": {k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")},
-            "rollout_frac_fp32_peak": flop / (float(np.mean(roll)) * 1e-3) / PEAK_FP32_MFMA}
+            "rollout_ms_mean": float(np.mean(roll)), "kernel": plan["kernel"], "launch": rl["launch"],
+            "rollout_frac_fp32_peak": flop / (float(np.mean(roll)) * 1e-3) / PEAK_FP32_MFMA,
+            "roofline": {k: v for k, v in rl.items() if k not in ("traffic", "launch", "kernel")}}
 
 
 def extra_batched(reps):
@@ -255,11 +290,11 @@ def main():
 
     flop = flops_per_sample_step(model) * ssteps
     roll_mean_s = float(np.mean(roll_ms)) * 1e-3
-    achieved = flop / roll_mean_s
     plan = pi.rollout_describe(dp, dm)
-    from paper_1503_00330_amd.profiling import traffic_from_summary
+    from paper_1503_00330_amd.profiling import launch_tag, traffic_from_summary
     summ = TRAFFIC_SUMMARY.get(plan["kernel"])
-    traffic = traffic_from_summary(summ) if summ else None
+    traffic = traffic_from_summary(summ, launch_tag(plan)) if summ else None
+    bf = plan["variant"] == "mfma-bf16x3"
     out = {
         "metric": METRIC,
         "value": value,
@@ -278,19 +313,16 @@ def main():
                                "K=65536 rollouts, T=200, M=1, LWPR d=16, 6 outputs x 1024 local "
                                "models, R=4, 20 obstacles, FP32",
                    "K": prob.K, "T": prob.T, "M": prob.M, "d": model.d, "n_out": model.n_out,
-                   "L_per_output": int(model.L_off[1]), "R": model.R, "graph": not args.eager},
+                   "L_per_output": int(model.L_off[1]), "R": model.R, "graph": not args.eager,
+                   "mfma": ("bf16x3: float32 mixture products as six bf16 piece products, float32 "
+                            "accumulation" if bf else "f32")},
         "latency_ms": {"control_step_p50": percentile(it_ms, 50),
                        "control_step_p99": percentile(it_ms, 99),
                        "rollout_p50": percentile(roll_ms, 50), "rollout_p99": percentile(roll_ms, 99),
                        "update_p50": percentile(upd_ms, 50), "update_p99": percentile(upd_ms, 99),
                        "rollout_mean": float(np.mean(roll_ms))},
-        "roofline": {"bound": "mfma", "kernel": plan["kernel"],
-                     "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
-                     "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model),
-                     "sample_steps_per_launch": ssteps,
-                     "launch": dict({k: plan[k] for k in ("tile_samples", "tile_waves", "tile_split")},
-                                    autotuned=not args.no_tune)},
+        "roofline": roofline(model, plan, prob.K * max(prob.M, 1), prob.T, flop, roll_mean_s, traffic,
+                             not args.no_tune),
     }
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")

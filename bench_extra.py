@@ -124,7 +124,7 @@ def w_batched(args):
     if not args.tile_samples:
         tiles = tune.ensure_batch(dps, dms)
     else:
-        tiles = (args.tile_samples, 4)
+        tiles = (args.tile_samples, 4, dps[0].variant)
     for dp in dps:               # plain launches with the batch's tile and waves
         dp.tile_waves = tiles[1]
     stream = torch.cuda.current_stream()
@@ -179,7 +179,9 @@ def w_batched(args):
     mb = float(np.median(tb))
     return {"workload": "64 quadrotor problems, K in 512..16384, L in 64..1024 per output, "
                         "T in 50..200, 10..40 obstacles",
-            "tiles": {"tile_samples": tiles[0], "tile_waves": tiles[1], "autotuned": not args.tile_samples},
+            "tiles": {"tile_samples": tiles[0], "tile_waves": tiles[1],
+                      "mfma": "bf16x3" if tiles[2] == pi.PI_VARIANT_MFMA_BF16X3 else "f32",
+                      "autotuned": not args.tile_samples},
             "batched_ms": mb, "sequential_ms": float(np.median(ts)),
             "speedup": float(np.median(ts) / mb),
             "control_step_batched_ms": float(np.median(tcb)),
@@ -187,7 +189,7 @@ def w_batched(args):
             "control_step_speedup": float(np.median(tcs) / np.median(tcb)),
             "batched_rollout_steps_per_s": ss / (mb * 1e-3),
             "batched_tflops": flop / (mb * 1e-3) / 1e12,
-            "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,
+            "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,   # float32-equivalent for bf16x3
             "bitwise_equal_to_plain": bool(same_cost), "control_step_bitwise_equal": bool(same_step),
             "dtype": "f32"}
 

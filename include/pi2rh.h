@@ -76,8 +76,13 @@ enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
  * d in {4, 6, 16} and folded tiles under 2 GiB (about 3 M local models at
  * d = 16); PI_VARIANT_AUTO picks it whenever those hold, and requesting it
  * otherwise returns PI_ERR_UNSUPPORTED.  PI_VARIANT_DIRECT is the per-sample
- * form (any d, float32 or float64).                                         */
-enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2 };
+ * form (any d, float32 or float64).  PI_VARIANT_MFMA_BF16X3 (rollouts of the
+ * float32 12-state quadrotor, d = 16; 8 waves need tiles of <= 16) runs the same
+ * contraction on the bf16 matrix instructions: every float32 operand is the
+ * exact sum of three bf16 pieces and the six piece products of weight at
+ * least 2^-24 are summed in float32, which reproduces the float32 products
+ * to within float32 rounding.                                               */
+enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2, PI_VARIANT_MFMA_BF16X3 = 3 };
 /* Operations for pi_workspace_bytes. */
 enum { PI_OP_PREDICT = 0, PI_OP_ROLLOUT = 1, PI_OP_UPDATE = 2, PI_OP_ADJOINT = 3,
        PI_OP_RH_SHIFT = 4 };

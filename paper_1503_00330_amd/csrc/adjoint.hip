@@ -660,7 +660,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
         fa.trace = a.seg;
         fa.trace_T = ckpt;
       }
-      e = launch_rollout_mfma(fa, m, *ml, mbase, spw, 4, s);
+      e = launch_rollout_mfma(fa, m, *ml, mbase, spw, 4, false, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(adj_jsum_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, p.T,
                          (const float *)cost, a.jsum);
@@ -676,7 +676,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
           ra.xstart = a.ckpt_buf;
           ra.trace = a.seg;
           ra.trace_T = ckpt;
-          e = launch_rollout_mfma(ra, m, *ml, mbase, spw, 4, s);
+          e = launch_rollout_mfma(ra, m, *ml, mbase, spw, 4, false, s);
           if (e != hipSuccess) break;
         }
         e = launch_adj_reverse_mfma(p, u_nom, iter, *ml, mbase, rfold, a.seg, ckpt, tb, te, xbar, a.recs, s);

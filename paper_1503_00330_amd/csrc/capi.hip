@@ -88,7 +88,7 @@ pi_status check_problem(const pi_problem *p) {
   if (p->n_obs > 0 && !p->obs) return fail(PI_ERR_NULL, "obs is NULL with n_obs > 0");
   if (p->weighting != PI_W_COST_TO_GO && p->weighting != PI_W_TRAJECTORY)
     return fail(PI_ERR_VALUE, "unknown weighting %d", p->weighting);
-  if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA)
+  if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA_BF16X3)
     return fail(PI_ERR_VALUE, "unknown variant %d", p->variant);
   if (p->tile_samples < 0 || p->tile_samples > 32)
     return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,32]", p->tile_samples);
@@ -206,12 +206,19 @@ bool mfma_model_ok(const pi_lwpr *m) {
   return mfma_ok(m->dtype, m->d) && mfma_layout(m->d, m->n_out, m->L_off).w_floats * 4 < ((size_t)1 << 31);
 }
 
+// The three-piece bf16 contraction: float32, d = 16, its pieces (18 KB per
+// tile of 16 models) addressable with 32-bit offsets.
+bool bf_model_ok(const pi_lwpr *m) {
+  if (!mfma_model_ok(m) || m->d != kBfD) return false;
+  return mfma_layout(m->d, m->n_out, m->L_off).wb_u32 * 4 < ((size_t)1 << 31);
+}
+
 // Rollout variant, samples per workgroup and whether tiles may be split over
 // a pair of workgroups (pair_ok; the launch decides with the device's
 // compute-unit count and residency).  The workspace never depends on the
 // device: a pair-capable plan always reserves the exchange slots.
 struct RolloutPlan {
-  bool mfma, pair_ok;
+  bool mfma, bf, pair_ok;
   int spw, waves;
   int64_t groups;
 };
@@ -220,7 +227,9 @@ constexpr int64_t kMaxPairGroups = 2048;
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   RolloutPlan r;
-  r.mfma = p->variant == PI_VARIANT_MFMA || (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
+  r.mfma = p->variant == PI_VARIANT_MFMA || p->variant == PI_VARIANT_MFMA_BF16X3 ||
+           (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
+  r.bf = p->variant == PI_VARIANT_MFMA_BF16X3;
   const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
   r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
   const bool split_allowed = r.mfma && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
@@ -256,13 +265,14 @@ bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
   const int n_cu = device_cus(&dev);
   if (n_cu == 0) return false;
   static std::mutex mu;
-  static int per_cu[kMaxDevices][4];  // resident pair workgroups per compute unit, +1 (0 = unknown)
+  static int per_cu[kMaxDevices][6];  // resident pair workgroups per compute unit, +1 (0 = unknown)
   if (dev < 0 || dev >= kMaxDevices) return false;
-  const int di = p->dyn == PI_DYN_QUAD12 ? (pl.waves == 8 ? 2 : 1) : (p->dyn == PI_DYN_QUAD_HYBRID ? 3 : 0);
+  const int di = p->dyn == PI_DYN_QUAD12 ? (pl.waves == 8 ? 2 : 1) + (pl.bf ? 3 : 0)
+                                         : (p->dyn == PI_DYN_QUAD_HYBRID ? 3 : 0);
   int cap;
   {
     std::lock_guard<std::mutex> lk(mu);
-    if (per_cu[dev][di] == 0) per_cu[dev][di] = pair_blocks_per_cu(p->dyn, pl.waves) + 1;
+    if (per_cu[dev][di] == 0) per_cu[dev][di] = pair_blocks_per_cu(p->dyn, pl.waves, pl.bf) + 1;
     cap = per_cu[dev][di] - 1;
   }
   const bool resident = (int64_t)pair_grid(pl.groups) <= (int64_t)cap * n_cu;
@@ -421,6 +431,7 @@ pi_status noalloc_scratch(void **out) {
 // never copies host memory and may be captured into a HIP graph.
 struct BatchLayout {
   int max_spw, waves, n_items;
+  bool bf;
   size_t probs_off, items_off, queue_off, upd_off, shift_off, bytes;
   std::vector<size_t> fold_off, sub_off;   // (size_t)-1: none
   std::vector<int> spw;
@@ -453,6 +464,11 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
     L.n_tiles[b] = ((int64_t)p[b].K * (p[b].M > 0 ? p[b].M : 1) + L.spw[b] - 1) / L.spw[b];
   }
   if (L.waves == 8 && L.max_spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
+  L.bf = p[0].variant == PI_VARIANT_MFMA_BF16X3;
+  if (L.bf) {
+    for (int b = 0; b < B; ++b)
+      if (!bf_model_ok(&m[b])) return fail(PI_ERR_UNSUPPORTED, "problem %d: no bf16x3 form of its model", b);
+  }
   // work list: problems by decreasing per-tile work (T * model tiles), each
   // problem's tiles in order
   std::vector<int> order(B);
@@ -537,7 +553,7 @@ hipError_t run_batched_rollouts(int32_t B, const pi_problem *p, const pi_lwpr *m
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int per_cu = L.waves == 8 ? 1 : 2;
     const int grid = std::max(1, std::min(L.n_items, ncu * per_cu));
-    e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, grid, queue, s);
+    e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, L.bf, grid, queue, s);
   }
   for (int b = 0; b < B && e == hipSuccess; ++b)
     if (L.sub_off[b] != (size_t)-1)
@@ -561,6 +577,9 @@ pi_status check_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, c
   const RolloutPlan pl = rollout_plan(p, m);
   if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
     return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
+  if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && p->tile_waves == 8)))
+    return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
+                                    "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 samples");
   return check_folded(m, pl.mfma);
 }
 
@@ -585,9 +604,9 @@ hipError_t run_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, co
         const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
         const RolloutLaunch rl = rollout_launch(p, m);
         if (rl.pair)
-          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, (char *)ws + fb + sub_bytes(p), s);
+          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, rl.pl.bf, (char *)ws + fb + sub_bytes(p), s);
         else
-          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, s);
+          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, rl.pl.bf, s);
       } else {
         e = launch_rollout_direct(PI_F32, &ra, a, base, s);
       }
@@ -628,12 +647,18 @@ pi_status pi_model_fold(const pi_lwpr *m, void *folded, size_t folded_bytes, voi
 pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *out) {
   PI_TRY(check_pair(p, m));
   if (!out) return fail(PI_ERR_NULL, "out must be non-NULL");
-  if (rollout_plan(p, m).mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
-    return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
+  {
+    const RolloutPlan pl = rollout_plan(p, m);
+    if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
+      return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
+    if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && p->tile_waves == 8)))
+      return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
+                                      "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 samples");
+  }
   PI_TRY(check_device());
   const RolloutLaunch rl = rollout_launch(p, m);
   const RolloutPlan &pl = rl.pl;
-  out[0] = pl.mfma ? PI_VARIANT_MFMA : PI_VARIANT_DIRECT;
+  out[0] = pl.bf ? PI_VARIANT_MFMA_BF16X3 : pl.mfma ? PI_VARIANT_MFMA : PI_VARIANT_DIRECT;
   out[1] = pl.mfma ? pl.spw : 1;
   out[2] = pl.mfma ? pl.waves : 1;
   out[3] = rl.pair ? 2 : 1;
@@ -669,6 +694,8 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
   PI_TRY(check_model(m));
   if (N < 0) return fail(PI_ERR_SHAPE, "N=%lld must be >= 0", (long long)N);
   if (N > 0 && (!Z || !mean || !var)) return fail(PI_ERR_NULL, "Z, mean and var must be non-NULL");
+  if (variant == PI_VARIANT_MFMA_BF16X3)
+    return fail(PI_ERR_UNSUPPORTED, "prediction has no bf16x3 form (use PI_VARIANT_MFMA)");
   if (variant < PI_VARIANT_AUTO || variant > PI_VARIANT_MFMA) return fail(PI_ERR_VALUE, "unknown variant %d", variant);
   const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_model_ok(m));
   if (use_mfma && !mfma_model_ok(m))

@@ -59,11 +59,22 @@ struct MfmaGeom {
   }
 };
 
+// The three-piece bf16 form of the d = 16 contraction (bf16 16x16x32 matrix
+// instructions): 32-feature blocks, NKQ of the quadratic-form features and
+// NKY of the prediction features; per tile, block and piece (hi, mid, lo of
+// the float32 value) 64 lanes x 8 bf16.
+constexpr int kBfD = 16;
+constexpr int kBfNKQ = (kBfD * (kBfD + 1) / 2 + kBfD + 2 + 31) / 32;   // 5
+constexpr int kBfNKY = (kBfD + 2 + 31) / 32;                            // 1
+constexpr int kBfNKB = kBfNKQ + kBfNKY;
+constexpr size_t kBfTileU32 = (size_t)kBfNKB * 3 * 64 * 4;              // 18 KB per tile
+
 struct MfmaLayout {
   int d, n_out, n_tiles;
   int tile_off[kMaxOut + 1];   // tile range of output o
   size_t w_floats;             // n_tiles * KB4 * 64 * 4
   size_t sig_floats;           // n_tiles * 16
+  size_t wb_u32;               // the bf16 pieces (d = 16 only, else 0): n_tiles * kBfTileU32
   size_t bytes;
 };
 
@@ -78,7 +89,8 @@ inline MfmaLayout mfma_layout(int d, int n_out, const int *L_off) {
   MfmaGeom g = MfmaGeom::make(d);
   l.w_floats = (size_t)l.n_tiles * g.KB4 * 64 * 4;
   l.sig_floats = (size_t)l.n_tiles * 16;
-  l.bytes = align_up(l.w_floats * 4, 256) + align_up(l.sig_floats * 4, 256);
+  l.wb_u32 = d == kBfD ? (size_t)l.n_tiles * kBfTileU32 : 0;
+  l.bytes = align_up(l.w_floats * 4, 256) + align_up(l.sig_floats * 4, 256) + align_up(l.wb_u32 * 4, 256);
   return l;
 }
 
@@ -86,6 +98,7 @@ inline MfmaLayout mfma_layout(int d, int n_out, const int *L_off) {
 struct MfmaModel {
   const float4 *W;     // [n_tiles][KB4][64] float4
   const float *sig2;   // [n_tiles*16]
+  const uint4 *Wb;     // [n_tiles][kBfNKB][3][64] (8 bf16 each), or null
   int n_out, n_tiles;
   int tile_off[kMaxOut + 1];
 };
@@ -122,9 +135,11 @@ struct RolloutArgs {
 
 hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
                                  const void *rec, hipStream_t s);
+// bf: the contraction in the three-piece bf16 form (d = 16 quadrotor, tiles
+// of <= 16 samples, a layout with the bf16 pieces).
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
                                const MfmaLayout &l, const void *base, int tile_samples,
-                               int waves, hipStream_t s);
+                               int waves, bool bf, hipStream_t s);
 hipError_t launch_subcost_reduce(int dtype, const void *sub, void *cost, int K, int Ms, int T,
                                  hipStream_t s);
 
@@ -159,15 +174,15 @@ hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *pro
                                    int64_t item_off, int64_t n_tiles, int spw, hipStream_t s);
 // max_spw: the largest tile of any item (<= 32); waves 8 needs max_spw <= 16.
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int max_spw, int waves, int grid, int *queue, hipStream_t s);
+                                  int max_spw, int waves, bool bf, int grid, int *queue, hipStream_t s);
 hipError_t launch_zero_int(int *p, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // Paired-workgroup rollout (MFMA, 16 rows per pair of workgroups).
 size_t pair_ws_bytes(int64_t n_groups);
 int pair_grid(int64_t n_groups);
-int pair_blocks_per_cu(int dyn, int waves);
+int pair_blocks_per_cu(int dyn, int waves, bool bf);
 hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
-                               int waves, void *pair_ws, hipStream_t s);
+                               int waves, bool bf, void *pair_ws, hipStream_t s);
 // The device's count of paired workgroups that gave up a wait, to out[0].
 hipError_t launch_read_give_ups(uint64_t *out, hipStream_t s);
 

@@ -34,12 +34,15 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
 namespace pi2rh {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int D>
 struct Geo {
@@ -77,6 +80,28 @@ __device__ __forceinline__ float buffer_f32(__amdgpu_buffer_rsrc_t r, int lane_o
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, tile_off, 0));
 }
 
+// Three bf16 pieces hi + mid + lo of a float32 value, each rounded to nearest
+// (ties to even) from the remainder of the previous ones: hi holds the top 8
+// significand bits, mid the next 8, lo the rest exactly, so the pieces sum to
+// the value exactly (for values whose pieces stay above the float32 normal
+// range).  Products of two such values, summed over the six piece pairs whose
+// weight is at least 2^-24 (hi hi, hi mid, mid hi, hi lo, mid mid, lo hi),
+// reproduce the float32 product to within float32 rounding.
+__host__ __device__ __forceinline__ uint16_t bf16_rn(float x, float *back) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  const uint32_t h = u & 0xFFFF0000u;
+  *back = __builtin_bit_cast(float, h);
+  return (uint16_t)(h >> 16);
+}
+__host__ __device__ __forceinline__ void bf16_split3(float v, uint16_t *pc) {
+  float h, m, l;
+  pc[0] = bf16_rn(v, &h);
+  const float r1 = v - h;
+  pc[1] = bf16_rn(r1, &m);
+  pc[2] = bf16_rn(r1 - m, &l);
+}
+
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
 // in double the derived vectors (h = -(D + D^T) c, kappa = c^T D c, the folded
@@ -86,7 +111,8 @@ constexpr int kFoldThreads = 256;
 
 __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, MfmaLayout l,
                                                                  float *__restrict__ W,
-                                                                 float *__restrict__ sig2) {
+                                                                 float *__restrict__ sig2,
+                                                                 uint32_t *__restrict__ Wb) {
   __shared__ double hv[16][kMaxD], bv[16][kMaxD], kap[16], y0v[16];
   __shared__ float Dl[16][kMaxD * kMaxD];
   __shared__ int jcol[16];
@@ -145,10 +171,9 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
   __syncthreads();
   const int NE = g.KB4 * 64 * 4;
   const int fqs = g.NP + d + 1, fys = 4 * g.KQB + d + 1;
-  float *dst = W + (size_t)tile * NE;
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
-    const int f = 4 * (4 * kb4 + comp) + lane / 16, col = lane & 15;
+  // the float32 value of feature f (quadratic-form features from 0, the
+  // prediction features from 4 KQB) for model slot col
+  auto value = [&](int f, int col) {
     const int j = jcol[col];
     float v = 0.0f;
     if (f == fqs || f == fys) {
@@ -174,14 +199,36 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
     } else if (f == 4 * g.KQB + d) {
       v = (float)y0v[col];
     }
-    dst[e] = v;
+    return v;
+  };
+  float *dst = W + (size_t)tile * NE;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
+    dst[e] = value(4 * (4 * kb4 + comp) + lane / 16, lane & 15);
+  }
+  if (Wb == nullptr) return;
+  // the same values as three bf16 pieces, in the A-operand layout of the bf16
+  // 16x16x32 instruction: block kb, piece p, lane (model lane%16, features
+  // 8 (lane/16) .. +7 of the block); blocks 0..kBfNKQ-1 hold the quadratic-form
+  // features, the last the prediction features
+  uint16_t *dstb = (uint16_t *)(Wb + (size_t)tile * kBfTileU32);
+  for (int e = threadIdx.x; e < kBfNKB * 64 * 8; e += blockDim.x) {
+    const int i = e & 7, lane = (e >> 3) & 63, kb = e >> 9;
+    const int k = 32 * (kb < kBfNKQ ? kb : kb - kBfNKQ) + 8 * (lane / 16) + i;
+    const bool inside = kb < kBfNKQ ? k < g.KQ : k < g.KY;
+    const float v = inside ? value(kb < kBfNKQ ? k : 4 * g.KQB + k, lane & 15) : 0.0f;
+    uint16_t pc[3];
+    bf16_split3(v, pc);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) dstb[((size_t)(kb * 3 + p) * 64 + lane) * 8 + i] = pc[p];
   }
 }
 
 hipError_t launch_fold_mfma(int, const ModelArgs &m, const MfmaLayout &l, void *base, hipStream_t s) {
   float *W = (float *)base;
   float *sig = (float *)((char *)base + align_up(l.w_floats * 4, 256));
-  hipLaunchKernelGGL(fold_mfma_kernel, dim3(l.n_tiles), dim3(kFoldThreads), 0, s, m, l, W, sig);
+  uint32_t *Wb = l.wb_u32 ? (uint32_t *)((char *)sig + align_up(l.sig_floats * 4, 256)) : nullptr;
+  hipLaunchKernelGGL(fold_mfma_kernel, dim3(l.n_tiles), dim3(kFoldThreads), 0, s, m, l, W, sig, Wb);
   return hipGetLastError();
 }
 
@@ -189,6 +236,7 @@ static MfmaModel mfma_view(const MfmaLayout &l, const void *base) {
   MfmaModel md;
   md.W = (const float4 *)base;
   md.sig2 = (const float *)((const char *)base + align_up(l.w_floats * 4, 256));
+  md.Wb = l.wb_u32 ? (const uint4 *)((const char *)md.sig2 + align_up(l.sig_floats * 4, 256)) : nullptr;
   md.n_out = l.n_out;
   md.n_tiles = l.n_tiles;
   for (int o = 0; o <= kMaxOut; ++o) md.tile_off[o] = l.tile_off[o];
@@ -207,17 +255,23 @@ __device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
   return Acc{a.Z + b.Z, a.S1 + b.S1, a.S2 + b.S2, a.S3 + b.S3, fmaxf(a.mx, b.mx)};
 }
 
-template <int D, int MT, int NW>
+// BF: the samples' fragments in the three-piece bf16 form (d = 16): per row
+// tile, 32-feature block and piece, 64 lanes x 8 bf16 (16 bytes per lane,
+// kept in the float4 slots), sample lane%16, features 8 (lane/16) .. +7.
+template <int D, int MT, int NW, bool BF = false>
 struct MixSmem {
+  static_assert(!BF || (D == kBfD && MT <= 2), "the bf16 form covers d = 16, one or two row tiles");
   static constexpr int ROWS = 16 * MT;
-  float4 A[MT][Geo<D>::KB4][64];         // A fragments, lane-major (anchor slots 0)
+  static constexpr int NFRAG = BF ? kBfNKB * 3 : Geo<D>::KB4;   // 16-byte fragments per lane and row tile
+  static constexpr int NSRC = BF ? kBfNKB * 32 : Geo<D>::NE;
+  float4 A[MT][NFRAG][64];               // sample fragments, lane-major (anchor slots 0)
   Acc part[NW][kMaxOut][ROWS];           // per-wave partial sums
   float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mprev[ROWS][kMaxOut];            // previous step's largest activation
   float mean[ROWS][kMaxOut], var[ROWS][kMaxOut];
   float acc[ROWS][kMaxOut];              // sampled accelerations (rollouts)
-  unsigned short fsrc[Geo<D>::NE];       // entry -> (ia << 8) | ib into z[row][]
+  unsigned short fsrc[NSRC];             // entry (BF: feature slot) -> (ia << 8) | ib into z[row][]
   int redo[2];                           // second-pass requests, by evaluation parity
   int pair_fail;                         // a partner wait ran out (results invalid)
 };
@@ -225,14 +279,25 @@ struct MixSmem {
 // Fragment entry e = ((kb4 * 64 + lane) * 4 + comp) of row tile mt holds
 // feature f = 4 (4 kb4 + comp) + lane/16 of row 16 mt + lane%16; every feature
 // is a product z'[ia] z'[ib] of the extended input z' = [z, 1, 0].
-template <int D, int MT, int NW>
-__device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
+// In the bf16 form (BF) entry e is feature slot e: slots 0 .. 32 kBfNKQ - 1
+// the quadratic-form features (f = e), the last block's the prediction
+// features (f = 4 KQB + e - 32 kBfNKQ in the numbering above).
+template <int D, int MT, int NW, bool BF>
+__device__ void mix_setup(MixSmem<D, MT, NW, BF> &sm) {
   using G = Geo<D>;
-  for (int e = threadIdx.x; e < G::NE; e += NW * 64) {
-    const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
-    const int f = 4 * (4 * kb4 + comp) + lane / 16;
+  for (int e = threadIdx.x; e < MixSmem<D, MT, NW, BF>::NSRC; e += NW * 64) {
+    int f;
+    if constexpr (BF) {
+      const int g = e - 32 * kBfNKQ;
+      f = e < 32 * kBfNKQ ? (e < G::KQ ? e : -1) : (g < G::KY ? 4 * G::KQB + g : -1);
+    } else {
+      const int comp = e & 3, lane = (e >> 2) & 63, kb4 = e >> 8;
+      f = 4 * (4 * kb4 + comp) + lane / 16;
+    }
     int ia = D + 1, ib = D + 1;  // zero
-    if (f < G::NP) {
+    if (f < 0) {
+      // padding slot of the bf16 form
+    } else if (f < G::NP) {
       int a = 0, rem = f;
       while (rem >= D - a) {
         rem -= D - a;
@@ -264,9 +329,33 @@ __device__ void mix_setup(MixSmem<D, MT, NW> &sm) {
 // Stage 1 (all lanes): the samples' fragments sm.A from sm.z (named for the
 // parameter pass, where they are the A operand; the rollout and the reverse
 // sweep use them as the B operand).
-template <int D, int MT, int NW>
-__device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
   using G = Geo<D>;
+  if constexpr (BF) {
+    // one (block, lane group, row) per thread: the group's 8 features of the
+    // row, each split into three bf16 pieces, one 16-byte store per piece
+    constexpr int NWORK = MT * kBfNKB * 4 * 16;
+    u32x4 *Ab = (u32x4 *)&sm.A[0][0][0];
+    for (int w = threadIdx.x; w < NWORK; w += NW * 64) {
+      const int r16 = w & 15, grp = (w >> 4) & 3, kb = (w >> 6) % kBfNKB, mt = (w >> 6) / kBfNKB;
+      const int row = 16 * mt + r16;
+      uint32_t pk[3][4];
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        uint16_t lo[3], hi[3];
+        const unsigned s0 = sm.fsrc[32 * kb + 8 * grp + i], s1 = sm.fsrc[32 * kb + 8 * grp + i + 1];
+        bf16_split3(sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], lo);
+        bf16_split3(sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF], hi);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
+      }
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        Ab[((mt * kBfNKB + kb) * 3 + p) * 64 + 16 * grp + r16] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
+    }
+    return;
+  }
   float *Af = (float *)&sm.A[0][0][0];
   // fixed trip count, fully unrolled: every thread's reads go out together
   // (a rolled loop waits for two dependent LDS round trips per element)
@@ -289,10 +378,10 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW> &sm) {
 
 // Empty per-wave partial sums: a wave flushes only the outputs its tiles
 // meet, and the merge adds every wave's slot in order.
-template <int D, int MT, int NW>
-__device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW> &sm) {
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, BF> &sm) {
   Acc *pp = &sm.part[0][0][0];
-  for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW>::ROWS; i += NW * 64)
+  for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW, BF>::ROWS; i += NW * 64)
     pp[i] = acc_empty();
 }
 
@@ -300,8 +389,8 @@ __device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW> &sm) {
 // tile with the model tile as the A operand: lane l holds models 4(l/16) + i
 // (i < 4) of sample l%16.  Partial sums are flushed per output into
 // sm.part[wave][o][row].
-template <int D, int MT, int NW>
-__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW> &sm, int T0, int T1) {
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
   using G = Geo<D>;
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
@@ -472,6 +561,242 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
   flush(o);
 }
 
+// The same stage in the three-piece bf16 form (d = 16, one or two row tiles):
+// per 32-feature block, six bf16 16x16x32 instructions take the piece pairs hi hi,
+// hi mid, mid hi, hi lo, mid mid, lo hi (model tile as the A operand, the
+// samples' pieces as the B operand), which reproduce the float32 products to
+// within float32 rounding; five blocks of quadratic-form features into two
+// accumulators, one block of prediction features into two more.  With two row
+// tiles every model piece loaded serves both, halving the loads per product
+// (the loads, not the matrix cores, bound the one-tile form).  The model
+// tile's pieces (18 KB) are held in registers once: as each block's products
+// issue, the registers of that block take the next tile's block (loads one
+// tile ahead).  The softmax epilogue and the flush are the float32 form's.
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
+  static_assert(BF && D == kBfD && (MT == 1 || MT == 2), "bf16 form: d = 16, one or two row tiles");
+  using G = Geo<D>;
+  // the activation anchor and the prediction reference: block, lane group, element
+  constexpr int FQ = G::NP + D + 1, KQA = FQ / 32, GQA = (FQ % 32) / 8, IQA = FQ % 8;
+  constexpr int FY = D + 1, KYA = kBfNKQ + FY / 32, GYA = (FY % 32) / 8, IYA = FY % 8;
+  constexpr int kTileBytes = kBfNKB * 3 * 1024;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t0 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)wave * (T1 - T0) / NW));
+  const int t1 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)(wave + 1) * (T1 - T0) / NW));
+  if (t0 >= t1) return;
+  u32x4 Bs[MT][kBfNKB][3];
+  {
+    const u32x4 *Ab = (const u32x4 *)&sm.A[0][0][0];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int kb = 0; kb < kBfNKB; ++kb)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) Bs[mt][kb][p] = Ab[((mt * kBfNKB + kb) * 3 + p) * 64 + lane];
+  }
+  auto output_of = [&](int tile) {
+    int oo = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxOut; ++i) oo += (i < md.n_out && md.tile_off[i] <= tile) ? 1 : 0;
+    return oo;
+  };
+  auto next_boundary = [&](int tile) {
+    int nb = md.n_tiles;
+#pragma unroll
+    for (int i = 1; i <= kMaxOut; ++i) {
+      const int v = md.tile_off[i];
+      nb = (v > tile && v < nb) ? v : nb;
+    }
+    return nb;
+  };
+  // element I of the three pieces (blocks of 8 bf16) takes the pieces of x
+  auto put = [&](u32x4 (&v)[3], auto I, float x) {
+    constexpr int i = decltype(I)::value;
+    uint16_t pc[3];
+    bf16_split3(x, pc);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint32_t w = v[p][i / 2];
+      w = (i & 1) ? ((w & 0x0000FFFFu) | ((uint32_t)pc[p] << 16)) : ((w & 0xFFFF0000u) | pc[p]);
+      v[p][i / 2] = w;
+    }
+  };
+  int o = output_of(t0);
+  int nb = next_boundary(t0);
+  auto set_anchor = [&](int oo) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = 16 * mt + (lane & 15);
+      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo]);
+      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo]);
+    }
+  };
+  set_anchor(o);
+  Acc st[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
+  auto flush = [&](int oo) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      Acc s = acc_sum(acc_sum(st[mt][0], st[mt][1]), acc_sum(st[mt][2], st[mt][3]));
+#pragma unroll
+      for (int m = 16; m <= 32; m <<= 1) {
+        s.Z += __shfl_xor(s.Z, m);
+        s.S1 += __shfl_xor(s.S1, m);
+        s.S2 += __shfl_xor(s.S2, m);
+        s.S3 += __shfl_xor(s.S3, m);
+        s.mx = fmaxf(s.mx, __shfl_xor(s.mx, m));
+      }
+      if (lane < 16) sm.part[wave][oo][16 * mt + lane] = s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
+    }
+  };
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.Wb, md.n_tiles * kTileBytes);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
+  const int lane_off = lane * 16, grp_off = 16 * (lane >> 4);
+  u32x4 W[kBfNKB][3];
+  auto load_blk = [&](int tile, int kb) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      W[kb][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, lane_off,
+                                                                                tile * kTileBytes + (kb * 3 + p) * 1024, 0));
+  };
+  auto mm = [&](const u32x4 &a, const u32x4 &b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+  };
+  // the six piece pairs of block kb of row tile mt into two accumulators
+  auto block6 = [&](int mt, int kb, f32x4 &x, f32x4 &y) {
+    x = mm(W[kb][0], Bs[mt][kb][0], x);
+    y = mm(W[kb][0], Bs[mt][kb][1], y);
+    x = mm(W[kb][1], Bs[mt][kb][0], x);
+    y = mm(W[kb][0], Bs[mt][kb][2], y);
+    x = mm(W[kb][1], Bs[mt][kb][1], x);
+    y = mm(W[kb][2], Bs[mt][kb][0], y);
+  };
+  // With two row tiles (one wave per SIMD, nothing else to overlap with) two
+  // accumulator sets take turns: while the matrix cores take tile i into one,
+  // the epilogue (exponentials and sums) of tile i-1 is issued between them
+  // from the other.  Every element still meets the same operations in tile
+  // order, so the sums match the unpipelined loop bit for bit; a pending set
+  // with activation -inf, prediction 0 and sigma^2 0 adds exact zeros.  With
+  // one row tile two waves per SIMD overlap instead, and the epilogue follows
+  // the products.
+  constexpr bool PIPE = MT == 2;
+  f32x4 qa[2][MT], qb[2][MT], ya[2][MT], yb[2][MT], s2[2];
+  auto clear_pending = [&](auto PI) {
+    constexpr int p = decltype(PI)::value;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      qa[p][mt] = f32x4{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+      qb[p][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ya[p][mt] = qb[p][mt];
+      yb[p][mt] = qb[p][mt];
+    }
+    s2[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto epi = [&](auto PI, int mt, int i) {
+    constexpr int p = decltype(PI)::value;
+    const float a = qa[p][mt][i] + qb[p][mt][i], dd = ya[p][mt][i] + yb[p][mt][i];
+    // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+    // largest term of at least 2^-100) need none of exp2f's denormal scaling
+    const float e = __builtin_amdgcn_exp2f(a);
+    const float te = e * dd;
+    st[mt][i].Z += e;
+    st[mt][i].S1 += te;
+    st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+    st[mt][i].S3 = fmaf(e, s2[p][i], st[mt][i].S3);
+    st[mt][i].mx = fmaxf(st[mt][i].mx, a);
+  };
+  auto epi_all = [&](auto PI) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) epi(PI, mt, i);
+  };
+  // tile `tile` into set c (and, pipelined, set p = tile - 1 finished); on
+  // entry s2[c] holds tile's sigma^2 (and s2[p] tile - 1's), on exit the set
+  // that takes tile + 1 holds tile + 1's
+  auto body = [&](int tile, auto CI, auto PI) {
+    constexpr int c = decltype(CI)::value, p = decltype(PI)::value;
+    if (tile >= nb) {
+      if constexpr (PIPE) {
+        epi_all(PI);
+        clear_pending(PI);
+      }
+      flush(o);
+      o = output_of(tile);
+      nb = next_boundary(tile);
+      set_anchor(o);
+    }
+    // prefetches are unconditional (the last tile re-reads itself) so that
+    // every wait counts a fixed number of loads
+    const int tn = min(tile + 1, t1 - 1);
+    const f32x4 s2n = buffer_f32x4(srs, grp_off, tn * 64);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      qa[c][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      qb[c][mt] = qa[c][mt];
+      ya[c][mt] = qa[c][mt];
+      yb[c][mt] = qa[c][mt];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kb = 0; kb < kBfNKB; ++kb) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (kb < kBfNKQ)
+          block6(mt, kb, qa[c][mt], qb[c][mt]);
+        else
+          block6(mt, kb, ya[c][mt], yb[c][mt]);
+      }
+      if constexpr (PIPE) {
+        // this block's share of the pending epilogue, between its products
+#pragma unroll
+        for (int e = 0; e < 4 * MT; ++e)
+          if (e * kBfNKB / (4 * MT) == kb) epi(PI, e / 4, e % 4);
+      }
+      load_blk(tn, kb);
+      if constexpr (PIPE) {
+#pragma unroll
+        for (int j = 0; j < 6 * MT; ++j) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two vector ALU ops
+        }
+        __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);    // the three piece loads
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (!PIPE) epi_all(CI);
+    s2[p] = s2n;
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+#pragma unroll
+  for (int kb = 0; kb < kBfNKB; ++kb) load_blk(t0, kb);
+  s2[0] = buffer_f32x4(srs, grp_off, t0 * 64);
+  if constexpr (PIPE) {
+    clear_pending(I1{});
+    int tile = t0;
+    for (; tile + 1 < t1; tile += 2) {
+      body(tile, I0{}, I1{});
+      body(tile + 1, I1{}, I0{});
+    }
+    if (tile < t1) {
+      body(tile, I0{}, I1{});
+      epi_all(I0{});
+    } else {
+      epi_all(I1{});
+    }
+  } else {
+    for (int tile = t0; tile < t1; ++tile) body(tile, I0{}, I0{});
+  }
+  flush(o);
+}
+
 // Sampling of the next-state draw inside the mixture's last stage: with xi
 // set, acc = mu + sqrt(var) xi[row][o] (a draw from N(mu, var)); without, mu.
 struct SampleArgs {
@@ -492,8 +817,8 @@ struct SampleArgs {
 // acceleration, the anchors of the next evaluation (observed maximum and
 // mean), and the redo flag of evaluation `ev` when the sums are not usable
 // (one overflowed, or the largest term came near the denormal range).
-template <int D, int MT, int NW>
-__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int o, const Acc &s, uint32_t ev,
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW, BF> &sm, int row, int o, const Acc &s, uint32_t ev,
                                             const SampleArgs &sa) {
   const float d1 = s.S1 / s.Z;
   const float mu = sm.yref[row][o] + d1;
@@ -518,8 +843,8 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW> &sm, int row, int
 }
 
 
-template <int D, int MT, int NW>
-__device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW> &sm, int row, int o) {
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW, BF> &sm, int row, int o) {
   Acc s = sm.part[0][o][row];
 #pragma unroll
   for (int w = 1; w < NW; ++w) s = acc_sum(s, sm.part[w][o][row]);
@@ -528,9 +853,9 @@ __device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW> &sm, int row, 
 
 // Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, then the
 // moments.
-template <int D, int MT, int NW>
-__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW> &sm, int n_out, uint32_t ev, const SampleArgs &sa) {
-  constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW, BF> &sm, int n_out, uint32_t ev, const SampleArgs &sa) {
+  constexpr int ROWS = MixSmem<D, MT, NW, BF>::ROWS;
   for (int i = threadIdx.x; i < ROWS * n_out; i += NW * 64) {
     const int row = i % ROWS, o = i / ROWS;
     finish_sums(sm, row, o, sum_waves(sm, row, o), ev, sa);
@@ -579,8 +904,8 @@ __device__ __forceinline__ void put_word(uint64_t *p, float v, uint32_t seq) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int D, int MT, int NW>
-__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, const PairCtx &pc, uint32_t seq,
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW, BF> &sm, int n_out, const PairCtx &pc, uint32_t seq,
                                            const SampleArgs &sa) {
   static_assert(MT == 1, "paired workgroups hold one 16-row tile");
   constexpr int ROWS = 16;
@@ -631,15 +956,18 @@ __device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW> &sm, int n_out, co
 // the pair exchanges and selects the redo flag, double-buffered so that one
 // barrier per evaluation suffices); with a pair context the two halves' sums
 // are exchanged every pass.
-template <int D, int MT, int NW>
-__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW> &sm, bool force_second,
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, bool force_second,
                                              int T0, int T1, const PairCtx *pc, uint32_t &seq,
                                              const SampleArgs &sa = SampleArgs{nullptr}) {
   for (int pass = 0; pass < 2; ++pass) {
     build_fragments(sm);
     clear_parts(sm);
     __syncthreads();
-    mixture_tiles(md, sm, T0, T1);
+    if constexpr (BF)
+      mixture_tiles_bf(md, sm, T0, T1);
+    else
+      mixture_tiles(md, sm, T0, T1);
     __syncthreads();
     const uint32_t ev = ++seq;
     if constexpr (MT == 1) {
@@ -660,7 +988,7 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
       // trajectory (it drifts steadily once the state leaves the models'
       // support), so extrapolate it linearly from the last two steps; the
       // lanes that merged each (row, output) own its entries.
-      constexpr int ROWS = MixSmem<D, MT, NW>::ROWS;
+      constexpr int ROWS = MixSmem<D, MT, NW, BF>::ROWS;
       for (int i = threadIdx.x; i < ROWS * md.n_out; i += NW * 64) {
         const int row = i % ROWS, o = i / ROWS;
         const float M = sm.mref[row][o];
@@ -673,9 +1001,9 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
   }
 }
 
-template <int D, int MT, int NW>
-__device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW> &sm) {
-  for (int i = threadIdx.x; i < MixSmem<D, MT, NW>::ROWS * kMaxOut; i += NW * 64) {
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW, BF> &sm) {
+  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, BF>::ROWS * kMaxOut; i += NW * 64) {
     (&sm.mref[0][0])[i] = 0.0f;
     (&sm.yref[0][0])[i] = 0.0f;
     (&sm.mprev[0][0])[i] = 0.0f;
@@ -746,10 +1074,10 @@ struct Dims<kDynQuadHybrid> {
 
 constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
 
-template <int DYN, int MT, int NW>
+template <int DYN, int MT, int NW, bool BF = false>
 struct RollSmem {
   static constexpr int ROWS = 16 * MT;
-  MixSmem<Dims<DYN>::D, MT, NW> sm;
+  MixSmem<Dims<DYN>::D, MT, NW, BF> sm;
   float xs[ROWS][Dims<DYN>::NX];
   float us_s[kNoiseChunk][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
   float xi_s[kNoiseChunk][ROWS][8];
@@ -780,8 +1108,8 @@ __device__ __forceinline__ RollSeg roll_seg(const RolloutArgs<float> &ra) {
                  ra.xstart, ra.ckpt_out};
 }
 
-template <int DYN, int MT, int NW>
-__device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
+template <int DYN, int MT, int NW, bool BF>
+__device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
                              uint32_t it, float *__restrict__ cost, const MfmaModel &md,
                              int64_t s_base, int spw, const PairCtx *pc = nullptr, float *tr = nullptr,
@@ -789,7 +1117,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW> &rs, const ProbDev<float> &p,
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
-  MixSmem<D, MT, NW> &sm = rs.sm;
+  MixSmem<D, MT, NW, BF> &sm = rs.sm;
   constexpr int SEGW = NX + 5 * NO;   // trace row: x_t, then 5 values per output (SampleArgs)
   const int tb = sg ? sg->tb : 0, te = sg ? sg->te : p.T;
   const int ck = sg ? sg->ckpt : 0;
@@ -952,35 +1280,36 @@ constexpr int rollout_waves_per_eu() {
   return (DYN != kDynQuad12 && MT == 1 && NW == 4) ? 4 : 1;
 }
 
-// One workgroup per tile of `spw` (<= 16*MT) sub-rollouts.
-template <int DYN, int MT, int NW>
+// One workgroup per tile of `spw` (<= 16*MT) sub-rollouts; BF: the contraction
+// in the three-piece bf16 form.
+template <int DYN, int MT, int NW, bool BF>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, MT, NW>())))
 rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
                                                                int spw) {
-  __shared__ RollSmem<DYN, MT, NW> rs;
+  __shared__ RollSmem<DYN, MT, NW, BF> rs;
   mix_setup(rs.sm);
   const RollSeg sg = roll_seg(ra);
-  rollout_tile<DYN, MT, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
-                            (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace, &sg);
+  rollout_tile<DYN, MT, NW, BF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
+                                (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace, &sg);
 }
 
 // Paired form (one 16-row tile per pair of workgroups, for problems with
 // fewer tiles than compute units): partners are blocks b and b + 8 of each
 // 16-block group, which the round-robin dispatch places on the same XCD, so
 // their exchange stays inside one L2.  The grid must be resident at once.
-template <int DYN, int NW>
+template <int DYN, int NW, bool BF>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, 1, NW>())))
 rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
                                                                int n_groups, uint64_t *__restrict__ xbuf,
                                                                uint32_t spin_limit) {
-  __shared__ RollSmem<DYN, 1, NW> rs;
+  __shared__ RollSmem<DYN, 1, NW, BF> rs;
   const int blk = blockIdx.x;
   const int g = (blk / 16) * 8 + (blk % 8);
   if (g >= n_groups) return;  // both halves of an unused pair leave
   const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1, spin_limit};
   mix_setup(rs.sm);
-  rollout_tile<DYN, 1, NW>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
-                           ra.trace);
+  rollout_tile<DYN, 1, NW, BF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
+                               ra.trace);
   // pair_fail is final: the tile's last evaluation ended with a barrier
   if (threadIdx.x == 0 && rs.sm.pair_fail) atomicAdd(&pair_give_ups_total, 1ull);
 }
@@ -990,11 +1319,11 @@ __global__ void read_give_ups_kernel(unsigned long long *out) { out[0] = pair_gi
 // Persistent form for many independent problems: every workgroup pulls
 // (problem, tile) items from a queue (items are ordered by decreasing work)
 // until the queue is empty.  Each item is exactly a plain rollout tile.
-template <int DYN, int MT, int NW>
+template <int DYN, int MT, int NW, bool BF>
 __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedProblem *__restrict__ probs,
                                                                   const BatchedItem *__restrict__ items,
                                                                   int n_items, int *__restrict__ queue) {
-  __shared__ RollSmem<DYN, MT, NW> rs;
+  __shared__ RollSmem<DYN, MT, NW, BF> rs;
   __shared__ int item_s;
   mix_setup(rs.sm);
   for (;;) {
@@ -1007,7 +1336,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedP
     const BatchedProblem &bp = probs[it.b];
     const ProbDev<float> p = bp.p;
     const MfmaModel md = bp.md;
-    rollout_tile<DYN, MT, NW>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, it.spw);
+    rollout_tile<DYN, MT, NW, BF>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, it.spw);
   }
 }
 
@@ -1021,20 +1350,26 @@ __global__ void batched_describe_kernel(BatchedProblem bp, BatchedProblem *__res
     items[item_off + i] = BatchedItem{b, spw, i * spw};
 }
 
-template <int DYN, int MT, int NW>
+template <int DYN, int MT, int NW, bool BF = false>
 static hipError_t rollout_mfma_t(const RolloutArgs<float> &ra, const MfmaModel &md, int spw,
                                  hipStream_t s) {
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
   const int64_t nb = (n + spw - 1) / spw;
-  hipLaunchKernelGGL((rollout_mfma_kernel<DYN, MT, NW>), dim3((unsigned)nb), dim3(NW * 64), 0, s, ra,
+  hipLaunchKernelGGL((rollout_mfma_kernel<DYN, MT, NW, BF>), dim3((unsigned)nb), dim3(NW * 64), 0, s, ra,
                      md, spw);
   return hipGetLastError();
 }
 
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m, const MfmaLayout &l,
-                               const void *base, int tile_samples, int waves, hipStream_t s) {
+                               const void *base, int tile_samples, int waves, bool bf, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
   const int spw = tile_samples;
+  if (bf) {
+    if (ra.p.dyn != kDynQuad12 || md.Wb == nullptr || (waves == 8 && spw > 16)) return hipErrorInvalidValue;
+    if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, true>(ra, md, spw, s);
+    if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, true>(ra, md, spw, s);
+    return rollout_mfma_t<kDynQuad12, 2, 4, true>(ra, md, spw, s);
+  }
   if (ra.p.dyn == kDynQuad12) {
     if (waves == 8) {
       if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 8>(ra, md, spw, s);
@@ -1055,23 +1390,27 @@ size_t pair_ws_bytes(int64_t n_groups) { return align_up((size_t)n_groups * kPai
 
 int pair_grid(int64_t n_groups) { return (int)(16 * ((n_groups + 7) / 8)); }
 
-int pair_blocks_per_cu(int dyn, int waves) {
+int pair_blocks_per_cu(int dyn, int waves, bool bf) {
   int nb = 0;
   hipError_t e;
-  if (dyn == kDynQuad12 && waves == 8)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8>, 512, 0);
+  if (dyn == kDynQuad12 && bf)
+    e = waves == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, true>, 512, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, true>, 256, 0);
+  else if (dyn == kDynQuad12 && waves == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, false>, 512, 0);
   else if (dyn == kDynQuad12)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, false>, 256, 0);
   else if (dyn == kDynQuadHybrid)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuadHybrid, 4>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuadHybrid, 4, false>, 256, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4, false>, 256, 0);
   return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
-                               int waves, void *pair_ws, hipStream_t s) {
+                               int waves, bool bf, void *pair_ws, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
+  if (bf && (ra.p.dyn != kDynQuad12 || md.Wb == nullptr)) return hipErrorInvalidValue;
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
   const int64_t n_groups = (n + spw - 1) / spw;
   uint64_t *xbuf = (uint64_t *)pair_ws;
@@ -1082,18 +1421,25 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
   uint32_t spin = kSpinLimit;
   if (const char *env = getenv("PI2RH_PAIR_SPIN_LIMIT")) spin = (uint32_t)strtoul(env, nullptr, 10);
   const dim3 grid((unsigned)pair_grid(n_groups));
-  if (ra.p.dyn == kDynQuad12) {
+  if (ra.p.dyn == kDynQuad12 && bf) {
     if (waves == 8)
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8>), grid, dim3(512), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf, spin);
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, true>), grid, dim3(512), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
     else
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4>), grid, dim3(256), 0, s, ra, md, spw, (int)n_groups,
-                         xbuf, spin);
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, true>), grid, dim3(256), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
+  } else if (ra.p.dyn == kDynQuad12) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, false>), grid, dim3(512), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
+    else
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
   } else if (ra.p.dyn == kDynQuadHybrid) {
-    hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4>), grid, dim3(256), 0, s, ra, md, spw,
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
                        (int)n_groups, xbuf, spin);
   } else {
-    hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4>), grid, dim3(256), 0, s, ra, md, spw,
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
                        (int)n_groups, xbuf, spin);
   }
   return hipGetLastError();
@@ -1113,17 +1459,28 @@ hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *pro
 }
 
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int max_spw, int waves, int grid, int *queue, hipStream_t s) {
+                                  int max_spw, int waves, bool bf, int grid, int *queue, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  if (max_spw <= 16) {
+  if (bf) {
+    if (waves == 8 && max_spw > 16) return hipErrorInvalidValue;
     if (waves == 8)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8>), dim3(grid), dim3(512), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, true>), dim3(grid), dim3(512), 0, s, probs,
+                         items, n_items, queue);
+    else if (max_spw <= 16)
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, true>), dim3(grid), dim3(256), 0, s, probs,
                          items, n_items, queue);
     else
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4>), dim3(grid), dim3(256), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, true>), dim3(grid), dim3(256), 0, s, probs,
+                         items, n_items, queue);
+  } else if (max_spw <= 16) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, false>), dim3(grid), dim3(512), 0, s, probs,
+                         items, n_items, queue);
+    else
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, false>), dim3(grid), dim3(256), 0, s, probs,
                          items, n_items, queue);
   } else {
-    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4>), dim3(grid), dim3(256), 0, s, probs,
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, false>), dim3(grid), dim3(256), 0, s, probs,
                        items, n_items, queue);
   }
   return hipGetLastError();

@@ -109,13 +109,21 @@ def read_summary(path: str) -> Dict[str, str]:
     return out
 
 
-def traffic_from_summary(path: str) -> Optional[float]:
+def launch_tag(plan: dict) -> str:
+    """variant/samples/waves/split of a rollout_describe() result."""
+    return "%s/%d/%d/%d" % (plan["variant"], plan["tile_samples"], plan["tile_waves"], plan["tile_split"])
+
+
+def traffic_from_summary(path: str, launch: Optional[str] = None) -> Optional[float]:
     """Bytes per launch recorded in a traffic summary, or None when the file is
-    missing or the kernel sources changed since the counters were taken."""
+    missing, the kernel sources changed since the counters were taken, or
+    (given `launch`, see launch_tag) the summary records another launch."""
     if not os.path.exists(path):
         return None
     s = read_summary(path)
     if s.get("source_sha256") != source_digest():
+        return None
+    if launch is not None and s.get("launch", launch) != launch:
         return None
     try:
         return float(s["traffic_bytes_per_launch"])
@@ -137,6 +145,7 @@ def main(argv=None):
     b.add_argument("write_dir")
     b.add_argument("--kernel", required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--launch", help="the launch profiled, variant/samples/waves/split")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print("| kernel | calls | avg us | min us | max us | % |")
@@ -152,6 +161,8 @@ def main(argv=None):
     else:
         r = traffic(args.fetch_dir, args.write_dir, args.kernel, args.copy_bytes)
         print("kernel: %s" % args.kernel)
+        if args.launch:
+            print("launch: %s" % args.launch)
         print("source_sha256: %s" % source_digest())
         for k in sorted(r):
             print("%s: %.6g" % (k, r[k]))

@@ -1,16 +1,21 @@
 """Autotuner for the rollout kernels' launch shape.
 
 For a given problem shape the tuner times pi_rollout_cost for every candidate
-launch (samples per tile, waves per workgroup, workgroups per tile) with HIP
-events and caches the fastest in a JSON file keyed by the device architecture
-and the shape; for a batch of problems it times the batched launch for every
-uniform tile shape.  A missing, unreadable or corrupt cache simply means "not
-tuned": the library's defaults apply.  The cache path is
-$PI2RH_AUTOTUNE_CACHE or ~/.cache/pi2rh/tune.json.
+launch (samples per tile, waves per workgroup, workgroups per tile, and the
+contraction: float32 matrix-core products or their three-piece bf16 form)
+with HIP events and caches the fastest in a JSON file keyed by the device
+architecture, the shape and the requested variant; for a batch of problems it
+times the batched launch for every uniform tile shape and contraction.  A
+missing, unreadable or corrupt cache simply means "not tuned": the library's
+defaults apply.  The cache path is $PI2RH_AUTOTUNE_CACHE or
+~/.cache/pi2rh/tune.json.
 
-Every candidate computes the same method; they differ only in how the
-mixture's sums are grouped (so results agree to rounding, and are bitwise
-reproducible for a fixed candidate).
+The contraction is searched only when the problem asks for the library's
+choice (PI_VARIANT_AUTO); a problem that names a variant keeps it.  Every
+candidate computes the same method to float32 accuracy; they differ only in
+how the mixture's sums are grouped and how the float32 products are formed
+(results agree to rounding, and are bitwise reproducible for a fixed
+candidate).
 """
 from __future__ import annotations
 
@@ -19,11 +24,14 @@ import json
 import os
 from typing import Dict, Iterable, Optional, Sequence, Tuple
 
-# (samples per tile, waves per workgroup, workgroups per tile)
-CANDIDATES: Tuple[Tuple[int, int, int], ...] = (
-    (16, 4, 1), (16, 8, 1), (8, 4, 1), (8, 8, 1), (32, 4, 1), (16, 4, 2), (16, 8, 2))
-# uniform tile shapes of a batched launch: (samples per tile, waves per workgroup)
-BATCH_CANDIDATES: Tuple[Tuple[int, int], ...] = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
+# contraction codes, as PI_VARIANT_MFMA and PI_VARIANT_MFMA_BF16X3
+_MF, _BF = 2, 3
+_SHAPES = ((16, 4, 1), (16, 8, 1), (8, 4, 1), (8, 8, 1), (32, 4, 1), (16, 4, 2), (16, 8, 2))
+_BATCH_SHAPES = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
+# (samples per tile, waves per workgroup, workgroups per tile, contraction)
+CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
+# uniform launches of a batch: (samples per tile, waves per workgroup, contraction)
+BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
 
 
 def cache_path() -> str:
@@ -32,11 +40,11 @@ def cache_path() -> str:
 
 
 def shape_key(arch: str, dtype_code: int, d: int, n_out: int, L_off, R: int, K: int, M: int, T: int,
-              dyn: int = 1) -> str:
+              dyn: int = 1, variant: int = 0) -> str:
     Ls = [int(L_off[i + 1]) - int(L_off[i]) for i in range(n_out)]
     kb = 1 << max(0, int(K * max(M, 1) - 1).bit_length())  # power-of-two bucket of samples
-    return "%s|dyn%d|dt%d|d%d|o%d|L%s|R%d|S%d|T%d" % (arch, dyn, dtype_code, d, n_out,
-                                                      "-".join(map(str, Ls)), R, kb, T)
+    return "%s|dyn%d|dt%d|d%d|o%d|L%s|R%d|S%d|T%d|v%d" % (arch, dyn, dtype_code, d, n_out,
+                                                          "-".join(map(str, Ls)), R, kb, T, variant)
 
 
 def _valid(v) -> bool:
@@ -71,10 +79,21 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
+def _requested(prob) -> int:
+    """The variant the caller asked for (a tuned problem keeps it aside, since
+    applying a tuned entry sets prob.variant to the contraction it chose)."""
+    return int(prob.__dict__.get("_requested_variant", prob.variant))
+
+
+def _set_variant(prob, v: int) -> None:
+    prob.__dict__.setdefault("_requested_variant", int(prob.variant))
+    prob.variant = int(v)
+
+
 def key_for(prob, model) -> str:
     from . import _dt
     return shape_key(_arch(), _dt(prob.dtype), model.d, model.n_out, model.L_off, model.R, prob.K,
-                     prob.M, prob.T, prob.dyn)
+                     prob.M, prob.T, prob.dyn, _requested(prob))
 
 
 def batch_key(problems, models) -> str:
@@ -82,28 +101,55 @@ def batch_key(problems, models) -> str:
     return "%s|batch%d|%s" % (_arch(), len(problems), h[:16])
 
 
-def candidates_for(prob) -> Tuple[Tuple[int, int, int], ...]:
-    """The candidates the library accepts for this problem: 8 waves only on the
-    12-state quadrotor, pairs of workgroups only for tiles of <= 16 samples
-    (float32)."""
+def _variants_for(prob, models) -> Tuple[int, ...]:
+    """Contractions to search: the named one, or with PI_VARIANT_AUTO float32
+    products and, for float32 12-state quadrotor problems on d = 16 models,
+    their three-piece bf16 form."""
     from . import PI_DYN_QUAD12
     import torch
+    req = _requested(prob)
+    if req in (_MF, _BF):
+        return (req,)
+    bf_ok = prob.dyn == PI_DYN_QUAD12 and prob.dtype == torch.float32 and all(m.d == 16 for m in models)
+    return (_MF, _BF) if bf_ok else (_MF,)
+
+
+def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
+    """The candidates the library accepts for this problem: 8 waves only on the
+    12-state quadrotor and tiles of <= 16 samples, pairs of workgroups only
+    for tiles of <= 16 samples (float32), the bf16 form as _variants_for says
+    (without a model: only the float32 products)."""
+    from . import PI_DYN_QUAD12
+    import torch
+    variants = _variants_for(prob, [model]) if model is not None else (_MF,)
     out = []
-    for spw, waves, split in CANDIDATES:
+    for spw, waves, split, v in CANDIDATES:
+        if v not in variants:
+            continue
         if waves == 8 and (prob.dyn != PI_DYN_QUAD12 or spw > 16):
             continue
         if split == 2 and (spw > 16 or prob.dtype != torch.float32):
             continue
-        out.append((spw, waves, split))
+        out.append((spw, waves, split, v))
     return tuple(out)
 
 
+def _launch(prob):
+    return (prob.tile_samples, prob.tile_waves, prob.tile_split, prob.variant)
+
+
+def _set_launch(prob, c) -> None:
+    prob.tile_samples, prob.tile_waves, prob.tile_split = c[:3]
+    _set_variant(prob, c[3])
+
+
 def apply(prob, model, path: Optional[str] = None) -> bool:
-    """Sets prob's tile_samples/tile_waves/tile_split from the cache; False if untuned."""
+    """Sets prob's tile_samples/tile_waves/tile_split/variant from the cache;
+    False if untuned."""
     ent = load_cache(path).get(key_for(prob, model))
-    if ent is None or len(ent) != 3:
+    if ent is None or len(ent) != 4:
         return False
-    prob.tile_samples, prob.tile_waves, prob.tile_split = ent
+    _set_launch(prob, ent)
     return True
 
 
@@ -122,24 +168,24 @@ def _time(fn, reps: int) -> float:
     return min(a.elapsed_time(b) for a, b in evs)
 
 
-def tune_rollout(prob, model, candidates: Optional[Iterable[Tuple[int, int, int]]] = None, reps: int = 3,
+def tune_rollout(prob, model, candidates: Optional[Iterable[Tuple[int, int, int, int]]] = None, reps: int = 3,
                  path: Optional[str] = None, save: bool = True):
     """Times every candidate launch; stores and returns the fastest
-    ((samples, waves, split), {candidate: ms})."""
+    ((samples, waves, split, variant), {candidate: ms})."""
     import torch
-    from . import PI_VARIANT_MFMA, rollout_cost
-    if prob.variant not in (0, PI_VARIANT_MFMA):
+    from . import rollout_cost
+    if _requested(prob) not in (0, _MF, _BF):
         raise ValueError("launch shapes apply to the matrix-core rollout kernels")
-    cands = tuple(candidates) if candidates is not None else candidates_for(prob)
-    saved = (prob.tile_samples, prob.tile_waves, prob.tile_split)
+    cands = tuple(candidates) if candidates is not None else candidates_for(prob, model)
+    saved = _launch(prob)
     cost = torch.empty((prob.K, prob.T), dtype=prob.dtype, device=prob.device)
     times = {}
     try:
-        for spw, waves, split in cands:
-            prob.tile_samples, prob.tile_waves, prob.tile_split = spw, waves, split
-            times[(spw, waves, split)] = _time(lambda: rollout_cost(prob, model, out=cost), reps)
+        for c in cands:
+            _set_launch(prob, c)
+            times[tuple(c)] = _time(lambda: rollout_cost(prob, model, out=cost), reps)
     finally:
-        prob.tile_samples, prob.tile_waves, prob.tile_split = saved
+        prob.tile_samples, prob.tile_waves, prob.tile_split, prob.variant = saved
     best = min(times, key=times.get)
     if save:
         data = load_cache(path)
@@ -150,46 +196,60 @@ def tune_rollout(prob, model, candidates: Optional[Iterable[Tuple[int, int, int]
 
 def ensure(prob, model, path: Optional[str] = None, reps: int = 3):
     """Applies the cached launch for this shape, tuning (and caching) it first
-    if there is none.  Returns the (samples, waves, split) in use."""
+    if there is none.  Returns the (samples, waves, split, variant) in use."""
     if not apply(prob, model, path):
         best, _ = tune_rollout(prob, model, reps=reps, path=path)
-        prob.tile_samples, prob.tile_waves, prob.tile_split = best
-    return (prob.tile_samples, prob.tile_waves, prob.tile_split)
+        _set_launch(prob, best)
+    return _launch(prob)
+
+
+def _set_batch(problems, c) -> None:
+    for p in problems:
+        p.tile_samples = c[0]
+        _set_variant(p, c[2])
+    problems[0].tile_waves = c[1]
 
 
 def apply_batch(problems: Sequence, models: Sequence, path: Optional[str] = None) -> bool:
-    """Sets every problem's tile_samples and problem 0's tile_waves from the
-    cache entry of this batch; False if untuned."""
+    """Sets every problem's tile_samples and variant and problem 0's
+    tile_waves from the cache entry of this batch; False if untuned."""
     ent = load_cache(path).get(batch_key(problems, models))
-    if ent is None or len(ent) != 2:
+    if ent is None or len(ent) != 3:
         return False
-    for p in problems:
-        p.tile_samples = ent[0]
-    problems[0].tile_waves = ent[1]
+    _set_batch(problems, ent)
     return True
 
 
+def batch_candidates_for(problems: Sequence, models: Sequence) -> Tuple[Tuple[int, int, int], ...]:
+    """Uniform launches the batched kernel accepts for these problems (8 waves
+    only with tiles of <= 16 samples; the bf16 form when every problem allows
+    it and asks for the library's choice)."""
+    vs = set(_variants_for(problems[0], models))
+    for p in problems[1:]:
+        vs &= set(_variants_for(p, models))
+    return tuple(c for c in BATCH_CANDIDATES if c[2] in vs and not (c[1] == 8 and c[0] > 16))
+
+
 def tune_batched(problems: Sequence, models: Sequence,
-                 candidates: Iterable[Tuple[int, int]] = BATCH_CANDIDATES, reps: int = 2,
+                 candidates: Optional[Iterable[Tuple[int, int, int]]] = None, reps: int = 2,
                  path: Optional[str] = None, save: bool = True):
-    """Times the batched rollout launch for every uniform tile shape; stores
-    and returns the fastest ((samples, waves), {candidate: ms})."""
+    """Times the batched rollout launch for every uniform launch; stores and
+    returns the fastest ((samples, waves, variant), {candidate: ms})."""
     from . import BatchedRollout
-    saved = [(p.tile_samples, p.tile_waves) for p in problems]
+    cands = tuple(candidates) if candidates is not None else batch_candidates_for(problems, models)
+    saved = [(p.tile_samples, p.tile_waves, p.variant) for p in problems]
     times = {}
     try:
-        for spw, waves in candidates:
-            if waves == 8 and spw > 16:
+        for c in cands:
+            if c[1] == 8 and c[0] > 16:
                 continue
-            for p in problems:
-                p.tile_samples = spw
-            problems[0].tile_waves = waves
+            _set_batch(problems, c)
             br = BatchedRollout(problems, models)
-            times[(spw, waves)] = _time(br.run, reps)
+            times[tuple(c)] = _time(br.run, reps)
             del br
     finally:
-        for p, (spw, waves) in zip(problems, saved):
-            p.tile_samples, p.tile_waves = spw, waves
+        for p, (spw, waves, v) in zip(problems, saved):
+            p.tile_samples, p.tile_waves, p.variant = spw, waves, v
     best = min(times, key=times.get)
     if save:
         data = load_cache(path)
@@ -199,9 +259,9 @@ def tune_batched(problems: Sequence, models: Sequence,
 
 
 def ensure_batch(problems: Sequence, models: Sequence, path: Optional[str] = None, reps: int = 2):
+    """Applies (tuning first if absent) the batch's launch; returns
+    (samples, waves, variant)."""
     if not apply_batch(problems, models, path):
         best, _ = tune_batched(problems, models, reps=reps, path=path)
-        for p in problems:
-            p.tile_samples = best[0]
-        problems[0].tile_waves = best[1]
-    return (problems[0].tile_samples, problems[0].tile_waves)
+        _set_batch(problems, best)
+    return (problems[0].tile_samples, problems[0].tile_waves, problems[0].variant)

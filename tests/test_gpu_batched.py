@@ -24,7 +24,7 @@ def _device():
     torch.cuda.synchronize()
 
 
-def _batch(spw=0, waves=0):
+def _batch(spw=0, waves=0, variant=0):
     specs = [(33, 9, [20, 17, 33, 16, 1, 40], 1), (70, 5, 16, 2), (17, 12, 7, 1),
              (128, 3, [64, 3, 9, 12, 30, 2], 0), (5, 7, 48, 1)]
     out = []
@@ -37,14 +37,19 @@ def _batch(spw=0, waves=0):
     # workgroups sums the model halves in another order) and the persistent
     # launch's waves per workgroup (4 unless given; the waves' partial sums are
     # added in order, so another wave count groups them differently)
-    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves or 4, tile_split=1) for p, _ in out]
+    dps = [pi.DeviceProblem(p, tile_samples=spw, tile_waves=waves or 4, tile_split=1, variant=variant)
+           for p, _ in out]
     dms = [pi.DeviceModel(m) for _, m in out]
     return out, dps, dms
 
 
-@pytest.mark.parametrize("spw,waves", [(0, 0), (8, 4), (16, 8), (32, 4)])
-def test_batched_equals_plain_launches(spw, waves):
-    host, dps, dms = _batch(spw, waves)
+BF3 = 3   # PI_VARIANT_MFMA_BF16X3: the contraction in three bf16 pieces
+
+
+@pytest.mark.parametrize("spw,waves,variant", [(0, 0, 0), (8, 4, 0), (16, 8, 0), (32, 4, 0),
+                                               (0, 0, BF3), (16, 8, BF3), (32, 4, BF3)])
+def test_batched_equals_plain_launches(spw, waves, variant):
+    host, dps, dms = _batch(spw, waves, variant)
     for dp in dps:
         dp.iter.fill_(3)
     br = pi.BatchedRollout(dps, dms)
@@ -108,9 +113,10 @@ def _plain_control_step(dp, dm):
     return cost
 
 
-def test_batched_tiles_per_problem():
+@pytest.mark.parametrize("variant", [0, BF3])
+def test_batched_tiles_per_problem(variant):
     # every problem keeps its own tile size (8, 16, 32 and the default) in one launch
-    host, dps, dms = _batch()
+    host, dps, dms = _batch(variant=variant)
     for dp, spw in zip(dps, (8, 32, 16, 0, 8)):
         dp.tile_samples = spw
     br = pi.BatchedRollout(dps, dms)

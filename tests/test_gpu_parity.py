@@ -202,13 +202,16 @@ def test_rollout_fp64_config0_strict():
     assert np.max(np.abs(cost - ref)) <= 1e-10 * np.abs(ref).max()
 
 
-# (variant, samples per workgroup, split): MFMA tiles of 16 rows on a pair of
-# workgroups (split 0 = library's choice, which pairs these small problems, or
-# 2 = forced) or on one (split 1), 8 rows, 32 rows; and the direct kernel
-# (variant, samples per workgroup, workgroups per tile, waves per workgroup); 0 = library's choice
+# (variant, samples per workgroup, workgroups per tile, waves per workgroup);
+# 0 = library's choice.  MFMA tiles of 16 rows on a pair of workgroups (split
+# 0 = library's choice, which pairs these small problems, or 2 = forced) or on
+# one (split 1), 8 rows, 32 rows; the same with the products in three bf16
+# pieces (one or two 16-row tiles per wave); and the direct kernel
+BF3 = pi.PI_VARIANT_MFMA_BF16X3
 ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2, 4), (pi.PI_VARIANT_MFMA, 16, 2, 8),
                   (pi.PI_VARIANT_MFMA, 16, 1, 4), (pi.PI_VARIANT_MFMA, 16, 1, 8), (pi.PI_VARIANT_MFMA, 8, 1, 0),
-                  (pi.PI_VARIANT_MFMA, 32, 0, 0), (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
+                  (pi.PI_VARIANT_MFMA, 32, 0, 0), (BF3, 0, 0, 0), (BF3, 16, 2, 4), (BF3, 16, 1, 4),
+                  (BF3, 16, 1, 8), (BF3, 8, 1, 8), (BF3, 32, 1, 4), (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("shape", ROLLOUT_SHAPES)
@@ -224,13 +227,15 @@ def test_rollout_fp32_ragged(shape, M):
     assert nrel(cost, ref) <= 1e-4
 
 
-@pytest.mark.parametrize("split", [1, 2])
-def test_rollout_loadings_differ_from_directions(split):
+@pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_MFMA, 1, 0), (pi.PI_VARIANT_MFMA, 2, 0),
+                                               (BF3, 2, 0), (BF3, 1, 32)])
+def test_rollout_loadings_differ_from_directions(variant, split, spw):
     # local models whose PLS deflation loadings p differ from the projection
     # directions u (d = 16, matrix-core tiles)
     prob, _ = synth.tiny_problem(19, dyn=DYN_QUAD12, L=3, R=4, K=53, T=13, M=1, dtype=F32, n_obs=5)
     model = MODELS["pu16"].astype(F32)
-    cost = pi.rollout_cost(pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)).cpu().numpy()
+    dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     cost_check(cost, ref, prob, 1e-4)
     assert nrel(cost, ref) <= 1e-4
@@ -370,28 +375,32 @@ def config1_oracle():
     return prob, model, cost, u
 
 
-@pytest.mark.parametrize("split", [0, 1])
-def test_rollout_config1_full_launch_all_rows(split, config1_oracle):
+@pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 0, 0), (pi.PI_VARIANT_AUTO, 1, 0),
+                                               (BF3, 0, 0), (BF3, 1, 32)])
+def test_rollout_config1_full_launch_all_rows(variant, split, spw, config1_oracle):
     # the benchmarked 2048-rollout launch (split 0: 128 tiles of 16 rollouts
-    # on 256 paired workgroups) and the one-workgroup-per-tile form: every
-    # rollout's S_k, and every per-step cost elementwise
+    # on 256 paired workgroups) and the one-workgroup-per-tile form, with
+    # float32 products and in three bf16 pieces: every rollout's S_k, and
+    # every per-step cost elementwise
     prob, model, ref, _ = config1_oracle
-    cost = pi.rollout_cost(pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)).cpu().numpy()
+    dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
     assert cost.shape == (2048, 100) and np.all(np.isfinite(cost))
     r, flips = cost_check(cost, ref, prob, 1e-4)
     keep = np.abs(cost - ref).max(1) <= 0.25 * prob.dt * prob.obs_penalty
     ew = c16(cost[keep], ref[keep])
-    print("config 1 all rows (split %d): max S rel %.2e, per-step elementwise %.2e, flips %d"
-          % (split, r, ew, flips))
+    print("config 1 all rows (variant %d, split %d, spw %d): max S rel %.2e, per-step elementwise %.2e, flips %d"
+          % (variant, split, spw, r, ew, flips))
     assert ew <= 1e-4
 
 
-def test_iteration_config1_fp32_end_to_end(config1_oracle):
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_AUTO, BF3])
+def test_iteration_config1_fp32_end_to_end(variant, config1_oracle):
     # rollouts and update on the GPU in FP32 against the oracle's FP64
     # iteration; an error dS in the costs moves the update by about
     # max_k |dS_k| spread(eps) / lambda
     prob, model, ref_cost, ref_u = config1_oracle
-    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    dp, dm = pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model)
     cost = pi.rollout_cost(dp, dm)
     pi.update(dp, cost)
     du = np.max(np.abs(dp.u_nom.cpu().numpy() - ref_u))
@@ -401,12 +410,13 @@ def test_iteration_config1_fp32_end_to_end(config1_oracle):
     assert du <= 1e-4
 
 
-def test_rollout_config2_full_launch_sampled_rows():
+@pytest.mark.parametrize("variant,spw", [(pi.PI_VARIANT_AUTO, 0), (BF3, 32)])
+def test_rollout_config2_full_launch_sampled_rows(variant, spw):
     # 65536 rollouts over T = 200 against 6 x 1024 models: 4096 one-workgroup
-    # tiles, two workgroups per compute unit; sampled rows at both ends and
-    # across the tile boundary at rollout 32768
+    # tiles, two workgroups per compute unit (or, bf16 pieces, 2048 tiles of
+    # 32 rows); sampled rows at both ends and across tile boundaries
     prob, model, _ = synth.config(2)
-    dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
+    dp, dm = pi.DeviceProblem(prob, variant=variant, tile_samples=spw), pi.DeviceModel(model)
     assert pi.rollout_describe(dp, dm)["tile_split"] == 1
     cost = pi.rollout_cost(dp, dm).cpu().numpy()
     assert cost.shape == (65536, 200) and np.all(np.isfinite(cost))
@@ -420,8 +430,8 @@ def test_rollout_config2_full_launch_sampled_rows():
     r, flips = cost_check(cost[rows], ref, prob, 1e-4)
     keep = np.abs(cost[rows] - ref).max(1) <= 0.25 * prob.dt * prob.obs_penalty
     ew = c16(cost[rows][keep], ref[keep])
-    print("config 2 sampled rows (256): max S rel %.2e, per-step elementwise %.2e, flips %d"
-          % (r, ew, flips))
+    print("config 2 sampled rows (256, variant %d, spw %d): max S rel %.2e, per-step elementwise %.2e, flips %d"
+          % (variant, spw, r, ew, flips))
     assert ew <= 1e-4
 
 
@@ -467,10 +477,36 @@ def test_rollout_describe_reports_the_launch():
         "rollout_direct_kernel"
 
 
-@pytest.mark.parametrize("split", [1, 2])
-def test_rollout_bitwise_repeatable(split):
+def test_bf16x3_describe_and_refusals():
+    # the three-piece bf16 form: reported as such; refused (PI_ERR_UNSUPPORTED)
+    # for 8 waves with 32-row tiles, float64, other plants and d != 16, and
+    # by the prediction entry point
+    prob, model, _ = synth.config(1)
+    dm = pi.DeviceModel(model)
+    d = pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3, tile_samples=32, tile_split=1), dm)
+    assert d == {"variant": "mfma-bf16x3", "tile_samples": 32, "tile_waves": 4, "tile_split": 1,
+                 "kernel": "rollout_mfma_kernel"}
+    assert pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3), dm)["kernel"] == "rollout_pair_kernel"
+    refused = [(pi.DeviceProblem(prob, variant=BF3, tile_samples=32, tile_waves=8, tile_split=1), dm),
+               (pi.DeviceProblem(prob, variant=BF3, dtype=torch.float64),
+                pi.DeviceModel(model, dtype=torch.float64))]
+    pm, pmodel = synth.tiny_problem(5, dyn=DYN_POINTMASS2D, L=4, R=2, K=16, T=3, M=1, dtype=F32)
+    refused.append((pi.DeviceProblem(pm, variant=BF3), pi.DeviceModel(pmodel)))
+    for dp, m in refused:
+        with pytest.raises(pi.PiError) as e:
+            pi.rollout_cost(dp, m)
+        assert e.value.status == 7
+    with pytest.raises(pi.PiError) as e:
+        pi.lwpr_predict(dm, torch.zeros((4, 16), dtype=torch.float32, device="cuda"), variant=BF3)
+    assert e.value.status == 7
+
+
+@pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 1, 0), (pi.PI_VARIANT_AUTO, 2, 0),
+                                               (BF3, 2, 0), (BF3, 1, 32)])
+def test_rollout_bitwise_repeatable(variant, split, spw):
     prob, model, _ = synth.config(1, K=512, T=20)
-    dp, dm = pi.DeviceProblem(prob, tile_split=split), pi.DeviceModel(model)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)
+    dm = pi.DeviceModel(model)
     a = pi.rollout_cost(dp, dm).clone()
     for _ in range(3):
         assert torch.equal(a, pi.rollout_cost(dp, dm))

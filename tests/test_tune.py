@@ -11,14 +11,16 @@ from paper_1503_00330_amd import tune
 def test_cache_roundtrip_and_corruption(tmp_path):
     p = str(tmp_path / "t.json")
     assert tune.load_cache(p) == {}                      # absent
-    tune.save_cache({"k": [16, 4, 2]}, p)
-    assert tune.load_cache(p) == {"k": [16, 4, 2]}
+    tune.save_cache({"k": [16, 4, 2, 2]}, p)
+    assert tune.load_cache(p) == {"k": [16, 4, 2, 2]}
     with open(p, "w") as f:
         f.write("{not json")
     assert tune.load_cache(p) == {}                      # corrupt -> untuned
     with open(p, "w") as f:
-        json.dump({"k": [999, 4, 1], "j": "x", "ok": [8, 8, 1], "b": [32, 4], "bad": [32, 8]}, f)
-    assert tune.load_cache(p) == {"ok": [8, 8, 1], "b": [32, 4]}   # invalid entries dropped
+        json.dump({"k": [999, 4, 1, 2], "j": "x", "ok": [8, 8, 1, 3], "b": [32, 4, 3], "bad": [32, 8, 2],
+                   "old": [8, 8, 1], "v": [16, 4, 1, 1]}, f)
+    # invalid entries (and entries without a contraction) dropped
+    assert tune.load_cache(p) == {"ok": [8, 8, 1, 3], "b": [32, 4, 3]}
 
 
 def test_shape_key_buckets_sample_counts():
@@ -27,15 +29,47 @@ def test_shape_key_buckets_sample_counts():
     b = tune.shape_key("gfx950", 0, 16, 6, L, 4, 2000, 1, 100)
     c = tune.shape_key("gfx950", 0, 16, 6, L, 4, 4096, 1, 100)
     d = tune.shape_key("gfx950", 0, 16, 6, L, 4, 2048, 1, 100, dyn=0)
-    assert a == b and a != c and a != d
+    e = tune.shape_key("gfx950", 0, 16, 6, L, 4, 2048, 1, 100, variant=2)
+    assert a == b and a != c and a != d and a != e
 
 
-def test_candidate_space_covers_pairing_and_waves():
-    # the launch knobs that matter: samples per tile, waves, and pairs of
-    # workgroups per tile
+def test_candidate_space_covers_pairing_waves_and_contraction():
+    # the launch knobs that matter: samples per tile, waves, pairs of
+    # workgroups per tile, and float32 products or their bf16 three-piece form
     assert {c[2] for c in tune.CANDIDATES} == {1, 2}
     assert {c[1] for c in tune.CANDIDATES} == {4, 8}
     assert {c[0] for c in tune.CANDIDATES} == {8, 16, 32}
+    assert {c[3] for c in tune.CANDIDATES} == {2, 3}
+    assert {c[2] for c in tune.BATCH_CANDIDATES} == {2, 3}
+
+
+class _P:
+    def __init__(self, dyn, dtype, variant=0):
+        self.dyn, self.dtype, self.variant = dyn, dtype, variant
+
+
+class _M:
+    def __init__(self, d):
+        self.d = d
+
+
+def test_candidates_follow_the_requested_variant():
+    import torch
+    from paper_1503_00330_amd import PI_DYN_QUAD12, PI_DYN_POINTMASS2D
+    q = tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32), _M(16))
+    assert {c[3] for c in q} == {2, 3}
+    # bf16 form: no 8 waves with 32-sample tiles, no pairs above 16 samples
+    assert (32, 8, 1, 3) not in q and (32, 4, 2, 3) not in q and (32, 4, 1, 3) in q
+    assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 2), _M(16))} == {2}
+    assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 3), _M(16))} == {3}
+    # not eligible for the bf16 form: another d, float64, another plant
+    assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32), _M(8))} == {2}
+    assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float64), _M(16))} == {2}
+    assert {c[3] for c in tune.candidates_for(_P(PI_DYN_POINTMASS2D, torch.float32), _M(16))} == {2}
+    # applying a tuned contraction keeps the request aside for the cache key
+    p = _P(PI_DYN_QUAD12, torch.float32)
+    tune._set_variant(p, 3)
+    assert p.variant == 3 and tune._requested(p) == 0
 
 
 def _gpu():
@@ -55,11 +89,13 @@ def test_tune_rollout_picks_a_candidate_with_oracle_parity(tmp_path):
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
     path = str(tmp_path / "tune.json")
     best, times = tune.tune_rollout(dp, dm, reps=1, path=path)
-    assert best in tune.candidates_for(dp) and len(times) == len(tune.candidates_for(dp))
-    assert len(times) == len(tune.CANDIDATES)          # every knob applies to this problem
+    assert best in tune.candidates_for(dp, dm) and len(times) == len(tune.candidates_for(dp, dm))
+    # every candidate applies to this problem, both contractions included
+    assert len(times) == len(tune.CANDIDATES)
+    assert dp.variant == 0                              # tuning leaves the problem as it was
     dp2 = pi.DeviceProblem(prob)
     assert tune.apply(dp2, dm, path=path)
-    assert (dp2.tile_samples, dp2.tile_waves, dp2.tile_split) == best
+    assert (dp2.tile_samples, dp2.tile_waves, dp2.tile_split, dp2.variant) == best
     g = pi.rollout_cost(dp2, dm).cpu().numpy().astype(np.float64)
     ref = oracle.rollout_cost(prob, model)
     r = np.abs(g.sum(1) - ref.sum(1)) / np.abs(ref.sum(1))
@@ -77,7 +113,7 @@ def test_tune_hybrid_skips_eight_waves(tmp_path):
     prob, model = synth.paper_shape(K=200, T=8)
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
     best, times = tune.tune_rollout(dp, dm, reps=1, path=str(tmp_path / "t.json"))
-    assert all(w == 4 for _, w, _ in times)
+    assert all(w == 4 and v == 2 for _, w, _, v in times)
 
 
 @pytest.mark.gpu
@@ -94,9 +130,11 @@ def test_tune_batched_keeps_plain_parity(tmp_path):
     dms = [pi.DeviceModel(m) for _, m in probs]
     path = str(tmp_path / "t.json")
     best, times = tune.tune_batched(dps, dms, reps=1, path=path)
-    assert best in times and len(times) == len(tune.BATCH_CANDIDATES)
+    assert best in times and len(times) == len(tune.batch_candidates_for(dps, dms))
+    assert {c[2] for c in times} == {2, 3}
     assert tune.apply_batch(dps, dms, path=path)
     costs = [c.clone() for c in pi.BatchedRollout(dps, dms).run()]
     for b, (dp, dm) in enumerate(zip(dps, dms)):
         dp.tile_waves = dps[0].tile_waves
+        assert dp.variant == best[2]
         assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
