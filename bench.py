@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rollouts", type=int, default=1024, help="oracle sample: rollouts 0..n-1")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--extras", default="config1,batched_vs_plain,adjoint_vs_forward",
+                    help="comma-separated secondary workloads to run")
     ap.add_argument("--no-tune", action="store_true", help="library default launch shapes (no autotuner)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the control steps directly instead of replaying graphs "
@@ -333,8 +335,11 @@ def main():
         out["calibration_copy_bytes"] = src.numel() * 4
     del run_roll, run_upd, run_shift, cost
     if not args.no_extras:
+        wanted = set(args.extras.split(","))
         for key, fn, n in (("config1", extra_config1, 20), ("batched_vs_plain", extra_batched, 2),
                            ("adjoint_vs_forward", extra_adjoint, 3)):
+            if key not in wanted:
+                continue
             try:
                 out[key] = fn(n)
             except Exception as exc:   # a secondary figure never hides the headline
