@@ -81,7 +81,9 @@ enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
  * contraction on the bf16 matrix instructions: every float32 operand is the
  * exact sum of three bf16 pieces and the six piece products of weight at
  * least 2^-24 are summed in float32, which reproduces the float32 products
- * to within float32 rounding.                                               */
+ * to within float32 rounding.  With it, tiles of 33..128 samples (4 waves)
+ * select the shared-tile launch: each wave holds 32 rows and the workgroup
+ * stages every model tile once in LDS (for problems with many rollouts).    */
 enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2, PI_VARIANT_MFMA_BF16X3 = 3 };
 /* Operations for pi_workspace_bytes. */
 enum { PI_OP_PREDICT = 0, PI_OP_ROLLOUT = 1, PI_OP_UPDATE = 2, PI_OP_ADJOINT = 3,
@@ -131,7 +133,8 @@ typedef struct {
   uint32_t problem_id;             /* counter word of the random stream      */
   uint64_t seed;                   /* Philox key                             */
   int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
-  int32_t tile_samples;            /* samples per workgroup, <= 32 (0 = library's choice) */
+  int32_t tile_samples;            /* samples per workgroup, <= 32, or <= 128 with
+                                    * PI_VARIANT_MFMA_BF16X3 (0 = library's choice) */
   int32_t tile_waves;              /* waves per workgroup, 4 or 8 (8: 12-state
                                     * quadrotor only); 0 = library's choice:
                                     * 8 for the quadrotor when the launch has

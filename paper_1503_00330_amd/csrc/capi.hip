@@ -90,8 +90,10 @@ pi_status check_problem(const pi_problem *p) {
     return fail(PI_ERR_VALUE, "unknown weighting %d", p->weighting);
   if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA_BF16X3)
     return fail(PI_ERR_VALUE, "unknown variant %d", p->variant);
-  if (p->tile_samples < 0 || p->tile_samples > 32)
-    return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,32]", p->tile_samples);
+  // 128 only for the bf16 form (its shared-tile launch: 32 rows per wave)
+  const int max_spw = p->variant == PI_VARIANT_MFMA_BF16X3 ? 128 : 32;
+  if (p->tile_samples < 0 || p->tile_samples > max_spw)
+    return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,%d]", p->tile_samples, max_spw);
   if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8)
     return fail(PI_ERR_VALUE, "tile_waves=%d must be 0, 4 or 8", p->tile_waves);
   if (p->tile_split < 0 || p->tile_split > 2)
@@ -463,6 +465,7 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
     L.max_spw = std::max(L.max_spw, L.spw[b]);
     L.n_tiles[b] = ((int64_t)p[b].K * (p[b].M > 0 ? p[b].M : 1) + L.spw[b] - 1) / L.spw[b];
   }
+  if (L.max_spw > 32) return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32");
   if (L.waves == 8 && L.max_spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
   L.bf = p[0].variant == PI_VARIANT_MFMA_BF16X3;
   if (L.bf) {
@@ -577,9 +580,10 @@ pi_status check_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, c
   const RolloutPlan pl = rollout_plan(p, m);
   if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
     return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
-  if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && p->tile_waves == 8)))
+  if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)))
     return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
-                                    "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 samples");
+                                    "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 or more than 32 "
+                                    "samples");
   return check_folded(m, pl.mfma);
 }
 
@@ -651,9 +655,10 @@ pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *ou
     const RolloutPlan pl = rollout_plan(p, m);
     if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
       return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
-    if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && p->tile_waves == 8)))
+    if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)))
       return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
-                                      "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 samples");
+                                      "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 or more than "
+                                      "32 samples");
   }
   PI_TRY(check_device());
   const RolloutLaunch rl = rollout_launch(p, m);

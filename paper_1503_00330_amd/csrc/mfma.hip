@@ -258,14 +258,27 @@ __device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
 // BF: the samples' fragments in the three-piece bf16 form (d = 16): per row
 // tile, 32-feature block and piece, 64 lanes x 8 bf16 (16 bytes per lane,
 // kept in the float4 slots), sample lane%16, features 8 (lane/16) .. +7.
+//
+// SH (the bf16 form with MT > 2 row tiles, MT / NW = 1 or 2 per wave): the
+// shared-tile form.  Each wave owns its row tiles and runs every model tile;
+// the workgroup stages each model tile once in LDS (ring, three tiles deep)
+// instead of every wave streaming its own range, and each wave's sums are
+// final (NPART = 1).  The samples' pieces are built in registers by their
+// wave (no A).
 template <int D, int MT, int NW, bool BF = false>
 struct MixSmem {
-  static_assert(!BF || (D == kBfD && MT <= 2), "the bf16 form covers d = 16, one or two row tiles");
+  static constexpr bool SH = BF && MT > 2;
+  static_assert(!BF || (D == kBfD && (MT <= 2 || (MT % NW == 0 && MT / NW <= 2))),
+                "the bf16 form covers d = 16, one or two row tiles per wave");
   static constexpr int ROWS = 16 * MT;
   static constexpr int NFRAG = BF ? kBfNKB * 3 : Geo<D>::KB4;   // 16-byte fragments per lane and row tile
   static constexpr int NSRC = BF ? kBfNKB * 32 : Geo<D>::NE;
-  float4 A[MT][NFRAG][64];               // sample fragments, lane-major (anchor slots 0)
-  Acc part[NW][kMaxOut][ROWS];           // per-wave partial sums
+  static constexpr int NPART = SH ? 1 : NW;
+  // ring slot: the tile's 18 piece chunks (1 KiB each, lane-major) and its 16 sigma^2
+  static constexpr int kRingChunks = kBfNKB * 3 + 1;
+  std::conditional_t<SH, char[16], float4[MT][NFRAG][64]> A;   // sample fragments, lane-major (anchor slots 0)
+  std::conditional_t<SH, u32x4[3][kRingChunks][64], char[16]> ring;
+  Acc part[NPART][kMaxOut][ROWS];        // per-wave partial sums
   float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
   float mprev[ROWS][kMaxOut];            // previous step's largest activation
@@ -332,7 +345,9 @@ __device__ void mix_setup(MixSmem<D, MT, NW, BF> &sm) {
 template <int D, int MT, int NW, bool BF>
 __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
   using G = Geo<D>;
-  if constexpr (BF) {
+  if constexpr (MixSmem<D, MT, NW, BF>::SH) {
+    return;   // built in registers by mixture_tiles_sh
+  } else if constexpr (BF) {
     // one (block, lane group, row) per thread: the group's 8 features of the
     // row, each split into three bf16 pieces, one 16-byte store per piece
     constexpr int NWORK = MT * kBfNKB * 4 * 16;
@@ -354,24 +369,24 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
       for (int p = 0; p < 3; ++p)
         Ab[((mt * kBfNKB + kb) * 3 + p) * 64 + 16 * grp + r16] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
     }
-    return;
-  }
-  float *Af = (float *)&sm.A[0][0][0];
-  // fixed trip count, fully unrolled: every thread's reads go out together
-  // (a rolled loop waits for two dependent LDS round trips per element)
-  constexpr int NIT = (MT * G::NE + NW * 64 - 1) / (NW * 64);
-  unsigned src[NIT];
+  } else {
+    float *Af = (float *)&sm.A[0][0][0];
+    // fixed trip count, fully unrolled: every thread's reads go out together
+    // (a rolled loop waits for two dependent LDS round trips per element)
+    constexpr int NIT = (MT * G::NE + NW * 64 - 1) / (NW * 64);
+    unsigned src[NIT];
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = threadIdx.x + it * NW * 64;
-    src[it] = e < MT * G::NE ? sm.fsrc[e % G::NE] : 0u;
-  }
+    for (int it = 0; it < NIT; ++it) {
+      const int e = threadIdx.x + it * NW * 64;
+      src[it] = e < MT * G::NE ? sm.fsrc[e % G::NE] : 0u;
+    }
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = threadIdx.x + it * NW * 64;
-    if (e < MT * G::NE) {
-      const int row = 16 * (e / G::NE) + (((e % G::NE) >> 2) & 15);
-      Af[e] = sm.z[row][src[it] >> 8] * sm.z[row][src[it] & 0xFF];
+    for (int it = 0; it < NIT; ++it) {
+      const int e = threadIdx.x + it * NW * 64;
+      if (e < MT * G::NE) {
+        const int row = 16 * (e / G::NE) + (((e % G::NE) >> 2) & 15);
+        Af[e] = sm.z[row][src[it] >> 8] * sm.z[row][src[it] & 0xFF];
+      }
     }
   }
 }
@@ -381,7 +396,8 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
 template <int D, int MT, int NW, bool BF>
 __device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, BF> &sm) {
   Acc *pp = &sm.part[0][0][0];
-  for (int i = threadIdx.x; i < NW * kMaxOut * MixSmem<D, MT, NW, BF>::ROWS; i += NW * 64)
+  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, BF>::NPART * kMaxOut * MixSmem<D, MT, NW, BF>::ROWS;
+       i += NW * 64)
     pp[i] = acc_empty();
 }
 
@@ -797,6 +813,219 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
   flush(o);
 }
 
+// The shared-tile form of the bf16 stage (MixSmem::SH: RT = MT / NW row tiles
+// per wave, one or two).  Every wave runs all model tiles [T0, T1) for its own
+// 16 RT rows, so the workgroup reads each model tile from L2 once per step
+// instead of once per wave: the tile's 18 piece chunks and its sigma^2 go
+// straight from memory into a three-slot LDS ring (buffer loads to LDS, two
+// tiles ahead, each wave issuing every NW-th chunk), and each wave reads the
+// chunks of the tile in hand from LDS.  With 8 waves (one row tile each) two
+// waves share a SIMD, so one's vector work runs under the other's products.  Per tile a wave waits for its own loads of that
+// tile (the next tile's may stay in flight) and then for the other waves at a
+// barrier: past it the tile is complete in LDS and every wave is done with the
+// slot the next load overwrites.  The per-tile arithmetic is mixture_tiles_bf's
+// for one wave's two row tiles, in tile order.
+template <int D, int MT, int NW, bool BF>
+__device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
+  using SM = MixSmem<D, MT, NW, BF>;
+  static_assert(SM::SH && (NW == 4 || NW == 8), "shared-tile form: four or eight waves");
+  using G = Geo<D>;
+  constexpr int RT = MT / NW;   // row tiles per wave
+  constexpr int RW = 16 * RT;   // rows per wave
+  constexpr int FQ = G::NP + D + 1, KQA = FQ / 32, GQA = (FQ % 32) / 8, IQA = FQ % 8;
+  constexpr int FY = D + 1, KYA = kBfNKQ + FY / 32, GYA = (FY % 32) / 8, IYA = FY % 8;
+  constexpr int kTileBytes = kBfNKB * 3 * 1024;
+  constexpr int kSig = SM::kRingChunks - 1;   // ring chunk of sigma^2
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int n = T1 - T0;
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.Wb, md.n_tiles * kTileBytes);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
+  // this wave's loads of one tile: chunks wave, wave + NW, ... below 19 (the
+  // sigma^2 chunk is number 18): 5, 5, 5, 4 loads per wave with 4 waves,
+  // 3, 3, 3, 2, 2, 2, 2, 2 with 8
+  constexpr int kJobs = SM::kRingChunks, kMaxJob = (kJobs + NW - 1) / NW;
+  const int njob = (kJobs - wave + NW - 1) / NW;
+  auto issue = [&](int tile, int slot) {
+#pragma unroll
+    for (int q = 0; q < kMaxJob; ++q) {
+      const int c = wave + NW * q;
+      if (c < kSig)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (__attribute__((address_space(3))) void *)&sm.ring[slot][c][0],
+                                                 16, lane * 16, tile * kTileBytes + c * 1024, 0, 0);
+      else if (c == kSig)
+        // 64 lanes x 4 bytes from the tile's 16 values on (the lanes past
+        // them read the next tiles', or zeros past the last: unused)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, (__attribute__((address_space(3))) void *)&sm.ring[slot][c][0],
+                                                 4, lane * 4, tile * 64, 0, 0);
+    }
+  };
+  if (n > 0) issue(T0, 0);
+  if (n > 1) issue(T0 + 1, 1);
+  // the wave's sample pieces, built in registers (rows RW wave + 16 mt + lane%16,
+  // features 32 kb + 8 (lane/16) .. +7 of block kb)
+  u32x4 Bs[RT][kBfNKB][3];
+  {
+    const int r16 = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) {
+      const int row = RW * wave + 16 * mt + r16;
+#pragma unroll
+      for (int kb = 0; kb < kBfNKB; ++kb) {
+        uint32_t pk[3][4];
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+          uint16_t lo[3], hi[3];
+          const unsigned s0 = sm.fsrc[32 * kb + 8 * grp + i], s1 = sm.fsrc[32 * kb + 8 * grp + i + 1];
+          bf16_split3(sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], lo);
+          bf16_split3(sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF], hi);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) Bs[mt][kb][p] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
+      }
+    }
+  }
+  auto output_of = [&](int tile) {
+    int oo = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxOut; ++i) oo += (i < md.n_out && md.tile_off[i] <= tile) ? 1 : 0;
+    return oo;
+  };
+  auto next_boundary = [&](int tile) {
+    int nb = md.n_tiles;
+#pragma unroll
+    for (int i = 1; i <= kMaxOut; ++i) {
+      const int v = md.tile_off[i];
+      nb = (v > tile && v < nb) ? v : nb;
+    }
+    return nb;
+  };
+  auto put = [&](u32x4 (&v)[3], auto I, float x) {
+    constexpr int i = decltype(I)::value;
+    uint16_t pc[3];
+    bf16_split3(x, pc);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint32_t w = v[p][i / 2];
+      w = (i & 1) ? ((w & 0x0000FFFFu) | ((uint32_t)pc[p] << 16)) : ((w & 0xFFFF0000u) | pc[p]);
+      v[p][i / 2] = w;
+    }
+  };
+  auto set_anchor = [&](int oo) {
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) {
+      const int row = RW * wave + 16 * mt + (lane & 15);
+      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo]);
+      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo]);
+    }
+  };
+  Acc st[RT][4];
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
+  auto flush = [&](int oo) {
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) {
+      Acc s = acc_sum(acc_sum(st[mt][0], st[mt][1]), acc_sum(st[mt][2], st[mt][3]));
+#pragma unroll
+      for (int m = 16; m <= 32; m <<= 1) {
+        s.Z += __shfl_xor(s.Z, m);
+        s.S1 += __shfl_xor(s.S1, m);
+        s.S2 += __shfl_xor(s.S2, m);
+        s.S3 += __shfl_xor(s.S3, m);
+        s.mx = fmaxf(s.mx, __shfl_xor(s.mx, m));
+      }
+      if (lane < 16) sm.part[0][oo][RW * wave + 16 * mt + lane] = s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
+    }
+  };
+  auto mm = [&](const u32x4 &a, const u32x4 &b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+  };
+  int o = output_of(T0);
+  int nb = next_boundary(T0);
+  set_anchor(o);
+  for (int j = 0; j < n; ++j) {
+    // this wave's loads of tile j are complete once no more than the next
+    // tile's are outstanding (nothing else in this loop is a vector memory
+    // access; a later access would only make the wait longer)
+    if (j + 1 < n) {
+      // vmcnt(njob), expcnt and lgkmcnt untouched (the count must be an immediate)
+      if (njob == 5)
+        __builtin_amdgcn_s_waitcnt(0x0F70 | 5);
+      else if (njob == 4)
+        __builtin_amdgcn_s_waitcnt(0x0F70 | 4);
+      else if (njob == 3)
+        __builtin_amdgcn_s_waitcnt(0x0F70 | 3);
+      else
+        __builtin_amdgcn_s_waitcnt(0x0F70 | 2);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
+    }
+    // no memory access moves across the barrier (compiler fences on both sides)
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    __asm__ __volatile__("" ::: "memory");
+    if (j + 2 < n) issue(T0 + j + 2, (j + 2) % 3);
+    const int tile = T0 + j, slot = j % 3;
+    if (tile >= nb) {
+      flush(o);
+      o = output_of(tile);
+      nb = next_boundary(tile);
+      set_anchor(o);
+    }
+    const u32x4(*W)[64] = sm.ring[slot];
+    const f32x4 s2 = ((const f32x4 *)&sm.ring[slot][kSig][0])[lane >> 4];
+    f32x4 qa[RT], qb[RT], ya[RT], yb[RT];
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) {
+      qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      qb[mt] = qa[mt];
+      ya[mt] = qa[mt];
+      yb[mt] = qa[mt];
+    }
+#pragma unroll
+    for (int kb = 0; kb < kBfNKB; ++kb) {
+      const u32x4 w[3] = {W[kb * 3 + 0][lane], W[kb * 3 + 1][lane], W[kb * 3 + 2][lane]};
+      // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
+      // y hm, hl, lh; with two row tiles the four chains go round-robin
+      constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) {
+          f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
+          f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
+          x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
+          y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
+        // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+        // largest term of at least 2^-100) need none of exp2f's denormal scaling
+        const float e = __builtin_amdgcn_exp2f(a);
+        const float te = e * dd;
+        st[mt][i].Z += e;
+        st[mt][i].S1 += te;
+        st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+        st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+        st[mt][i].mx = fmaxf(st[mt][i].mx, a);
+      }
+  }
+  flush(o);
+}
+
 // Sampling of the next-state draw inside the mixture's last stage: with xi
 // set, acc = mu + sqrt(var) xi[row][o] (a draw from N(mu, var)); without, mu.
 struct SampleArgs {
@@ -847,7 +1076,7 @@ template <int D, int MT, int NW, bool BF>
 __device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW, BF> &sm, int row, int o) {
   Acc s = sm.part[0][o][row];
 #pragma unroll
-  for (int w = 1; w < NW; ++w) s = acc_sum(s, sm.part[w][o][row]);
+  for (int w = 1; w < MixSmem<D, MT, NW, BF>::NPART; ++w) s = acc_sum(s, sm.part[w][o][row]);
   return s;
 }
 
@@ -964,7 +1193,9 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
     build_fragments(sm);
     clear_parts(sm);
     __syncthreads();
-    if constexpr (BF)
+    if constexpr (MixSmem<D, MT, NW, BF>::SH)
+      mixture_tiles_sh(md, sm, T0, T1);
+    else if constexpr (BF)
       mixture_tiles_bf(md, sm, T0, T1);
     else
       mixture_tiles(md, sm, T0, T1);
@@ -1077,16 +1308,18 @@ constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
 template <int DYN, int MT, int NW, bool BF = false>
 struct RollSmem {
   static constexpr int ROWS = 16 * MT;
+  // steps per noise chunk: 2 for the 128-row shared-tile form (its LDS holds the tile ring)
+  static constexpr int CH = MixSmem<Dims<DYN>::D, MT, NW, BF>::SH ? 2 : kNoiseChunk;
   MixSmem<Dims<DYN>::D, MT, NW, BF> sm;
   float xs[ROWS][Dims<DYN>::NX];
-  float us_s[kNoiseChunk][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
-  float xi_s[kNoiseChunk][ROWS][8];
-  float xc[kNoiseChunk][ROWS][Dims<DYN>::NX];   // x_{t+1} of the chunk's steps, for the costs
+  float us_s[CH][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
+  float xi_s[CH][ROWS][8];
+  float xc[CH][ROWS][Dims<DYN>::NX];   // x_{t+1} of the chunk's steps, for the costs
   float obs_s[kMaxObs * 3];
 };
 
 // Rollouts s_base .. s_base + spw - 1 of one problem for its whole horizon.
-// Every kNoiseChunk steps all lanes draw the chunk's eps and xi, store the
+// Every CH steps (kNoiseChunk, or 2) all lanes draw the chunk's eps and xi, store the
 // applied controls u_nom + sigma eps in LDS (no global read is left on the
 // per-step critical section) and evaluate the previous chunk's step costs
 // dt*q(x_{t+1}) from the states kept in LDS (the cost feeds nothing on the
@@ -1117,6 +1350,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float>
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
+  constexpr int CH = RollSmem<DYN, MT, NW, BF>::CH;
   MixSmem<D, MT, NW, BF> &sm = rs.sm;
   constexpr int SEGW = NX + 5 * NO;   // trace row: x_t, then 5 values per output (SampleArgs)
   const int tb = sg ? sg->tb : 0, te = sg ? sg->te : p.T;
@@ -1164,18 +1398,18 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float>
     }
   };
   for (int t = tb; t < te; ++t) {
-    const int tc = (t - tb) % kNoiseChunk;
+    const int tc = (t - tb) % CH;
     if (tc == 0) {
       if (t > tb) {
         __syncthreads();  // the chunk's states are in rs.xc
-        flush_costs(t - kNoiseChunk, kNoiseChunk);
+        flush_costs(t - CH, CH);
         // the control terms of the flushed chunk are read from the draw slots
         // the next chunk overwrites
         if (DYN == kDynQuadHybrid && p.ctrl_cost) __syncthreads();
       }
       // draw the next chunk: one lane per (step, row, counter block)
       constexpr int NB = 1 + (NO + 3) / 4;
-      for (int i = threadIdx.x; i < kNoiseChunk * ROWS * NB; i += NW * 64) {
+      for (int i = threadIdx.x; i < CH * ROWS * NB; i += NW * 64) {
         const int blk = i % NB, rr = (i / NB) % ROWS, cc = i / (NB * ROWS);
         const int64_t ss = s_base + rr;
         const bool act = rr < spw && ss < (int64_t)p.K * p.Ms && t + cc < te;
@@ -1267,7 +1501,7 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float>
     for (int a = 0; a < NX; ++a) trace[row * tstride + (int64_t)(te - tb) * SEGW + a] = rs.xs[row][a];
   }
   __syncthreads();
-  const int tl = tb + ((te - tb - 1) / kNoiseChunk) * kNoiseChunk;
+  const int tl = tb + ((te - tb - 1) / CH) * CH;
   flush_costs(tl, te - tl);
 }
 
@@ -1365,7 +1599,11 @@ hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
   const MfmaModel md = mfma_view(l, base);
   const int spw = tile_samples;
   if (bf) {
-    if (ra.p.dyn != kDynQuad12 || md.Wb == nullptr || (waves == 8 && spw > 16)) return hipErrorInvalidValue;
+    if (ra.p.dyn != kDynQuad12 || md.Wb == nullptr || (waves == 8 && spw > 16 && spw <= 32) || spw > 128)
+      return hipErrorInvalidValue;
+    if (spw > 32)   // shared-tile form: 128 rows, two row tiles on each of 4 waves or one on each of 8
+      return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, true>(ra, md, spw, s)
+                        : rollout_mfma_t<kDynQuad12, 8, 4, true>(ra, md, spw, s);
     if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, true>(ra, md, spw, s);
     if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, true>(ra, md, spw, s);
     return rollout_mfma_t<kDynQuad12, 2, 4, true>(ra, md, spw, s);

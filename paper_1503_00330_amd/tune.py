@@ -28,8 +28,10 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 _MF, _BF = 2, 3
 _SHAPES = ((16, 4, 1), (16, 8, 1), (8, 4, 1), (8, 8, 1), (32, 4, 1), (16, 4, 2), (16, 8, 2))
 _BATCH_SHAPES = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
-# (samples per tile, waves per workgroup, workgroups per tile, contraction)
-CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
+# (samples per tile, waves per workgroup, workgroups per tile, contraction);
+# 128-sample tiles are the bf16 form's shared-tile launch
+CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
+                                                     + ((128, 4, 1, _BF), (128, 8, 1, _BF)))
 # uniform launches of a batch: (samples per tile, waves per workgroup, contraction)
 BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
 
@@ -116,9 +118,10 @@ def _variants_for(prob, models) -> Tuple[int, ...]:
 
 def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
     """The candidates the library accepts for this problem: 8 waves only on the
-    12-state quadrotor and tiles of <= 16 samples, pairs of workgroups only
-    for tiles of <= 16 samples (float32), the bf16 form as _variants_for says
-    (without a model: only the float32 products)."""
+    12-state quadrotor with tiles of <= 16 samples (or the bf16 form's
+    128-sample shared tiles), pairs of workgroups only for tiles of <= 16
+    samples (float32), the bf16 form as _variants_for says (without a model:
+    only the float32 products)."""
     from . import PI_DYN_QUAD12
     import torch
     variants = _variants_for(prob, [model]) if model is not None else (_MF,)
@@ -126,7 +129,7 @@ def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
     for spw, waves, split, v in CANDIDATES:
         if v not in variants:
             continue
-        if waves == 8 and (prob.dyn != PI_DYN_QUAD12 or spw > 16):
+        if waves == 8 and (prob.dyn != PI_DYN_QUAD12 or 16 < spw <= 32):
             continue
         if split == 2 and (spw > 16 or prob.dtype != torch.float32):
             continue

@@ -192,3 +192,13 @@ def test_batched_control_step_full_workload():
         _plain_control_step(dp, dm)
         assert torch.equal(dp.x0, after[b][0]) and torch.equal(dp.u_nom, after[b][1]), b
         assert torch.equal(dp.iter, after[b][2]), b
+
+
+def test_batched_refuses_shared_tile_launch():
+    # 128-row tiles are the plain bf16 launch's shared-tile form; the
+    # persistent launch holds at most two row tiles per workgroup
+    host, dps, dms = _batch(variant=BF3)
+    for dp in dps:
+        dp.tile_samples = 128
+    with pytest.raises(pi.PiError, match="tile_samples <= 32"):
+        pi.BatchedRollout(dps, dms)

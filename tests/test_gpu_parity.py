@@ -206,12 +206,14 @@ def test_rollout_fp64_config0_strict():
 # 0 = library's choice.  MFMA tiles of 16 rows on a pair of workgroups (split
 # 0 = library's choice, which pairs these small problems, or 2 = forced) or on
 # one (split 1), 8 rows, 32 rows; the same with the products in three bf16
-# pieces (one or two 16-row tiles per wave); and the direct kernel
+# pieces (one or two 16-row tiles per wave, and the shared-tile launch of 128
+# or 64 rows on 4 waves, 128 on 8); and the direct kernel
 BF3 = pi.PI_VARIANT_MFMA_BF16X3
 ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2, 4), (pi.PI_VARIANT_MFMA, 16, 2, 8),
                   (pi.PI_VARIANT_MFMA, 16, 1, 4), (pi.PI_VARIANT_MFMA, 16, 1, 8), (pi.PI_VARIANT_MFMA, 8, 1, 0),
                   (pi.PI_VARIANT_MFMA, 32, 0, 0), (BF3, 0, 0, 0), (BF3, 16, 2, 4), (BF3, 16, 1, 4),
-                  (BF3, 16, 1, 8), (BF3, 8, 1, 8), (BF3, 32, 1, 4), (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
+                  (BF3, 16, 1, 8), (BF3, 8, 1, 8), (BF3, 32, 1, 4), (BF3, 128, 1, 4), (BF3, 64, 1, 4), (BF3, 128, 1, 8),
+                  (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("shape", ROLLOUT_SHAPES)
@@ -228,7 +230,7 @@ def test_rollout_fp32_ragged(shape, M):
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_MFMA, 1, 0), (pi.PI_VARIANT_MFMA, 2, 0),
-                                               (BF3, 2, 0), (BF3, 1, 32)])
+                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128)])
 def test_rollout_loadings_differ_from_directions(variant, split, spw):
     # local models whose PLS deflation loadings p differ from the projection
     # directions u (d = 16, matrix-core tiles)
@@ -376,7 +378,7 @@ def config1_oracle():
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 0, 0), (pi.PI_VARIANT_AUTO, 1, 0),
-                                               (BF3, 0, 0), (BF3, 1, 32)])
+                                               (BF3, 0, 0), (BF3, 1, 32), (BF3, 1, 128)])
 def test_rollout_config1_full_launch_all_rows(variant, split, spw, config1_oracle):
     # the benchmarked 2048-rollout launch (split 0: 128 tiles of 16 rollouts
     # on 256 paired workgroups) and the one-workgroup-per-tile form, with
@@ -410,11 +412,12 @@ def test_iteration_config1_fp32_end_to_end(variant, config1_oracle):
     assert du <= 1e-4
 
 
-@pytest.mark.parametrize("variant,spw", [(pi.PI_VARIANT_AUTO, 0), (BF3, 32)])
+@pytest.mark.parametrize("variant,spw", [(pi.PI_VARIANT_AUTO, 0), (BF3, 32), (BF3, 128)])
 def test_rollout_config2_full_launch_sampled_rows(variant, spw):
     # 65536 rollouts over T = 200 against 6 x 1024 models: 4096 one-workgroup
     # tiles, two workgroups per compute unit (or, bf16 pieces, 2048 tiles of
-    # 32 rows); sampled rows at both ends and across tile boundaries
+    # 32 rows, or 512 shared-tile workgroups of 128); sampled rows at both
+    # ends and across tile boundaries
     prob, model, _ = synth.config(2)
     dp, dm = pi.DeviceProblem(prob, variant=variant, tile_samples=spw), pi.DeviceModel(model)
     assert pi.rollout_describe(dp, dm)["tile_split"] == 1
@@ -487,6 +490,13 @@ def test_bf16x3_describe_and_refusals():
     assert d == {"variant": "mfma-bf16x3", "tile_samples": 32, "tile_waves": 4, "tile_split": 1,
                  "kernel": "rollout_mfma_kernel"}
     assert pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3), dm)["kernel"] == "rollout_pair_kernel"
+    d = pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3, tile_samples=128, tile_split=1), dm)
+    assert d["tile_samples"] == 128 and d["tile_waves"] == 4 and d["kernel"] == "rollout_mfma_kernel"
+    with pytest.raises(pi.PiError) as e:      # 128-row tiles: the bf16 form only
+        pi.rollout_cost(pi.DeviceProblem(prob, variant=pi.PI_VARIANT_MFMA, tile_samples=128), dm)
+    assert "tile_samples=128 outside [0,32]" in str(e.value)
+    d = pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3, tile_samples=128, tile_waves=8), dm)
+    assert d["tile_samples"] == 128 and d["tile_waves"] == 8 and d["tile_split"] == 1
     refused = [(pi.DeviceProblem(prob, variant=BF3, tile_samples=32, tile_waves=8, tile_split=1), dm),
                (pi.DeviceProblem(prob, variant=BF3, dtype=torch.float64),
                 pi.DeviceModel(model, dtype=torch.float64))]
@@ -502,7 +512,7 @@ def test_bf16x3_describe_and_refusals():
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 1, 0), (pi.PI_VARIANT_AUTO, 2, 0),
-                                               (BF3, 2, 0), (BF3, 1, 32)])
+                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128)])
 def test_rollout_bitwise_repeatable(variant, split, spw):
     prob, model, _ = synth.config(1, K=512, T=20)
     dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)

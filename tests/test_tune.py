@@ -38,7 +38,8 @@ def test_candidate_space_covers_pairing_waves_and_contraction():
     # workgroups per tile, and float32 products or their bf16 three-piece form
     assert {c[2] for c in tune.CANDIDATES} == {1, 2}
     assert {c[1] for c in tune.CANDIDATES} == {4, 8}
-    assert {c[0] for c in tune.CANDIDATES} == {8, 16, 32}
+    assert {c[0] for c in tune.CANDIDATES} == {8, 16, 32, 128}
+    assert all(c[3] == 3 for c in tune.CANDIDATES if c[0] > 32)   # shared-tile launch: bf16 form only
     assert {c[3] for c in tune.CANDIDATES} == {2, 3}
     assert {c[2] for c in tune.BATCH_CANDIDATES} == {2, 3}
 
@@ -60,6 +61,7 @@ def test_candidates_follow_the_requested_variant():
     assert {c[3] for c in q} == {2, 3}
     # bf16 form: no 8 waves with 32-sample tiles, no pairs above 16 samples
     assert (32, 8, 1, 3) not in q and (32, 4, 2, 3) not in q and (32, 4, 1, 3) in q
+    assert (128, 4, 1, 3) in q and (128, 8, 1, 3) in q
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 2), _M(16))} == {2}
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 3), _M(16))} == {3}
     # not eligible for the bf16 form: another d, float64, another plant
