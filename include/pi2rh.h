@@ -297,7 +297,8 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
  * arrays are host arrays of B device pointers: x0[b] [n_x], u_nom[b]
  * [T_b][n_u], iter[b] (one uint32), cost[b] [K_b][T_b].  All problems must be
  * PI_F32 and PI_DYN_QUAD12 with matrix-core models (PI_ERR_UNSUPPORTED
- * otherwise).  A problem's tile_samples (<= 32; 0 = 16) sets its tile;
+ * otherwise).  A problem's tile_samples (<= 32, or <= 128 when the batch
+ * runs the bf16x3 form; 0 = 16) sets its tile;
  * tile_waves of problem 0 applies to the batch (8 needs every tile <= 16).
  * Models given pre-folded (pi_lwpr.folded) are read in place; the others are
  * folded into the workspace on every call.  The launch plan (descriptors and

@@ -33,6 +33,14 @@ pi_status fail(pi_status st, const char *fmt, ...) {
   return st;
 }
 
+// The current message prefixed by "problem b: " (the message is copied first:
+// formatting g_err into itself would overlap).
+pi_status fail_problem(pi_status st, int b) {
+  char msg[sizeof(g_err)];
+  snprintf(msg, sizeof(msg), "%s", g_err);
+  return fail(st, "problem %d: %s", b, msg);
+}
+
 pi_status ok() {
   g_err[0] = 0;
   return PI_OK;
@@ -447,13 +455,13 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
   if (!p || !m) return fail(PI_ERR_NULL, "problem and model arrays must be non-NULL");
   for (int b = 0; b < B; ++b) {
     pi_status st = check_pair(&p[b], &m[b]);
-    if (st != PI_OK) return fail(st, "problem %d: %s", b, g_err);
+    if (st != PI_OK) return fail_problem(st, b);
     if (p[b].dtype != PI_F32 || p[b].dyn != PI_DYN_QUAD12)
       return fail(PI_ERR_UNSUPPORTED, "problem %d: batched rollouts need float32 quadrotor problems", b);
     if (!mfma_model_ok(&m[b]))
       return fail(PI_ERR_UNSUPPORTED, "problem %d: the model's matrix-core tiles must stay under 2 GiB", b);
     st = check_folded(&m[b], true);
-    if (st != PI_OK) return fail(st, "problem %d: %s", b, g_err);
+    if (st != PI_OK) return fail_problem(st, b);
   }
   BatchLayout L;
   L.waves = p[0].tile_waves > 0 ? p[0].tile_waves : 4;
@@ -465,9 +473,12 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
     L.max_spw = std::max(L.max_spw, L.spw[b]);
     L.n_tiles[b] = ((int64_t)p[b].K * (p[b].M > 0 ? p[b].M : 1) + L.spw[b] - 1) / L.spw[b];
   }
-  if (L.max_spw > 32) return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32");
-  if (L.waves == 8 && L.max_spw > 16) return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16");
   L.bf = p[0].variant == PI_VARIANT_MFMA_BF16X3;
+  // tiles of 33..128 samples: the bf16 form's shared-tile launch
+  if (L.max_spw > (L.bf ? 128 : 32))
+    return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32 (<= 128 with the bf16x3 form)");
+  if (L.waves == 8 && L.max_spw > 16 && L.max_spw <= 32)
+    return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16 (or > 32 with the bf16x3 form)");
   if (L.bf) {
     for (int b = 0; b < B; ++b)
       if (!bf_model_ok(&m[b])) return fail(PI_ERR_UNSUPPORTED, "problem %d: no bf16x3 form of its model", b);
@@ -554,7 +565,7 @@ hipError_t run_batched_rollouts(int32_t B, const pi_problem *p, const pi_lwpr *m
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = L.waves == 8 ? 1 : 2;
+    const int per_cu = L.waves == 8 || L.max_spw > 32 ? 1 : 2;
     const int grid = std::max(1, std::min(L.n_items, ncu * per_cu));
     e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, L.bf, grid, queue, s);
   }

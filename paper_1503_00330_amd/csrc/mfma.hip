@@ -1700,8 +1700,15 @@ hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem
                                   int max_spw, int waves, bool bf, int grid, int *queue, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   if (bf) {
-    if (waves == 8 && max_spw > 16) return hipErrorInvalidValue;
-    if (waves == 8)
+    if ((waves == 8 && max_spw > 16 && max_spw <= 32) || max_spw > 128) return hipErrorInvalidValue;
+    if (max_spw > 32) {   // shared-tile form: 128 rows per workgroup
+      if (waves == 8)
+        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, true>), dim3(grid), dim3(512), 0, s, probs,
+                           items, n_items, queue);
+      else
+        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, true>), dim3(grid), dim3(256), 0, s, probs,
+                           items, n_items, queue);
+    } else if (waves == 8)
       hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, true>), dim3(grid), dim3(512), 0, s, probs,
                          items, n_items, queue);
     else if (max_spw <= 16)

@@ -33,7 +33,8 @@ _BATCH_SHAPES = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
 CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
                                                      + ((128, 4, 1, _BF), (128, 8, 1, _BF)))
 # uniform launches of a batch: (samples per tile, waves per workgroup, contraction)
-BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
+BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
+                                                      + ((128, 4, _BF), (128, 8, _BF)))
 
 
 def cache_path() -> str:
@@ -225,12 +226,13 @@ def apply_batch(problems: Sequence, models: Sequence, path: Optional[str] = None
 
 def batch_candidates_for(problems: Sequence, models: Sequence) -> Tuple[Tuple[int, int, int], ...]:
     """Uniform launches the batched kernel accepts for these problems (8 waves
-    only with tiles of <= 16 samples; the bf16 form when every problem allows
-    it and asks for the library's choice)."""
+    only with tiles of <= 16 samples or the bf16 form's 128-sample shared
+    tiles; the bf16 form when every problem allows it and asks for the
+    library's choice)."""
     vs = set(_variants_for(problems[0], models))
     for p in problems[1:]:
         vs &= set(_variants_for(p, models))
-    return tuple(c for c in BATCH_CANDIDATES if c[2] in vs and not (c[1] == 8 and c[0] > 16))
+    return tuple(c for c in BATCH_CANDIDATES if c[2] in vs and not (c[1] == 8 and 16 < c[0] <= 32))
 
 
 def tune_batched(problems: Sequence, models: Sequence,
@@ -244,7 +246,7 @@ def tune_batched(problems: Sequence, models: Sequence,
     times = {}
     try:
         for c in cands:
-            if c[1] == 8 and c[0] > 16:
+            if c[1] == 8 and 16 < c[0] <= 32:
                 continue
             _set_batch(problems, c)
             br = BatchedRollout(problems, models)

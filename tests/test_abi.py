@@ -193,6 +193,30 @@ class TestValidation:
         ps.K = 0
         assert call() == 2
 
+    def test_batched_validation_names_the_problem(self):
+        # the batch's messages carry the problem index once, ahead of the
+        # problem's own message (copied, not formatted into itself)
+        lib = pi.load()
+        ps0, ms0 = _structs()
+        ps1, ms1 = _structs()
+        ps1.tile_samples = 128                     # float32 products: 32 at most
+        PS, MS = pi.pi_problem * 2, pi.pi_lwpr * 2
+        n = lib.pi_batched_workspace_bytes(2, PS(ps0, ps1), MS(ms0, ms1))
+        assert n == C.c_size_t(-1).value
+        assert pi.last_error() == "problem 1: tile_samples=128 outside [0,32]"
+        ps1.tile_samples, ps1.variant = 128, pi.PI_VARIANT_MFMA_BF16X3   # bf16 form: 128 allowed
+        ps0.variant = pi.PI_VARIANT_MFMA_BF16X3
+        assert lib.pi_batched_workspace_bytes(2, PS(ps0, ps1), MS(ms0, ms1)) != C.c_size_t(-1).value
+
+    def test_bf16x3_tile_limits(self):
+        ps, ms = _structs()
+        ps.variant, ps.tile_samples = pi.PI_VARIANT_MFMA_BF16X3, 129
+        assert _rollout(ps, ms) == 3 and "outside [0,128]" in pi.last_error()
+        ps.tile_samples, ps.tile_waves = 32, 8        # 8 waves: <= 16 or the 128-row shared tile
+        assert _rollout(ps, ms) == 7
+        ps.tile_samples = 128
+        assert _rollout(ps, ms) == 6 and "device" in pi.last_error()   # valid: only the device is missing
+
     def test_mfma_needs_float32(self):
         ps, ms = _structs(dtype=np.float64)
         ps.variant = pi.PI_VARIANT_MFMA

@@ -47,7 +47,8 @@ BF3 = 3   # PI_VARIANT_MFMA_BF16X3: the contraction in three bf16 pieces
 
 
 @pytest.mark.parametrize("spw,waves,variant", [(0, 0, 0), (8, 4, 0), (16, 8, 0), (32, 4, 0),
-                                               (0, 0, BF3), (16, 8, BF3), (32, 4, BF3)])
+                                               (0, 0, BF3), (16, 8, BF3), (32, 4, BF3), (128, 8, BF3),
+                                               (128, 4, BF3)])
 def test_batched_equals_plain_launches(spw, waves, variant):
     host, dps, dms = _batch(spw, waves, variant)
     for dp in dps:
@@ -194,11 +195,16 @@ def test_batched_control_step_full_workload():
         assert torch.equal(dp.iter, after[b][2]), b
 
 
-def test_batched_refuses_shared_tile_launch():
-    # 128-row tiles are the plain bf16 launch's shared-tile form; the
-    # persistent launch holds at most two row tiles per workgroup
+def test_batched_refuses_unsupported_tiles():
+    # 33..128-row tiles only with the bf16 form (its shared-tile launch), and
+    # 8 waves not with 17..32-row tiles
     host, dps, dms = _batch(variant=BF3)
     for dp in dps:
-        dp.tile_samples = 128
-    with pytest.raises(pi.PiError, match="tile_samples <= 32"):
+        dp.tile_samples, dp.variant = 128, 2
+    with pytest.raises(pi.PiError, match="tile_samples=128 outside"):
+        pi.BatchedRollout(dps, dms)
+    for dp in dps:
+        dp.tile_samples, dp.variant = 32, BF3
+    dps[0].tile_waves = 8
+    with pytest.raises(pi.PiError, match="tile_waves 8"):
         pi.BatchedRollout(dps, dms)
