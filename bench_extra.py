@@ -110,10 +110,13 @@ def w_rh_graph(args):
 def w_batched(args):
     """64 independent controllers with uneven K, L, T and obstacles.  Tiles
     are picked by the autotuner (uniform tile shape over the batch; cached).
-    Reported: the batched rollouts against 64 plain rollout launches, and one
-    batched control step (rollouts, updates, plant steps and shifts; one HIP
-    graph) against 64 plain control steps (one HIP graph of all 64), with the
-    bitwise check that both leave every problem's state the same."""
+    Reported: the batched rollouts against 64 plain rollout launches with the
+    library's default tile shape (`speedup`) and with the batch's own tile
+    shape (`speedup_same_tiles`: bitwise the same costs), and one batched
+    control step (rollouts, updates, plant steps and shifts; one HIP graph)
+    against 64 plain control steps with the batch's tiles (one HIP graph of
+    all 64), with the bitwise check that both leave every problem's state the
+    same."""
     import torch
     import paper_1503_00330_amd as pi
     from paper_1503_00330_amd import tune
@@ -146,6 +149,17 @@ def w_batched(args):
     tb = timed(br.run, args.steps or 3, stream)
     ts = timed(seq, args.steps or 3, stream)
     same_cost = all(torch.equal(a, c) for a, c in zip(br.costs, costs))
+    # the plain baseline a caller would run: each problem on its own with the
+    # library's default tile shape (16 rollouts per tile, workgroup pairs when
+    # the tiles leave compute units idle) in the batch's contraction
+    dflt = [pi.DeviceProblem(p, variant=dps[0].variant) for p, _ in batch]
+
+    def seq_default():
+        for dp, dm, c in zip(dflt, dms, costs):
+            pi.rollout_cost(dp, dm, out=c)
+    seq_default()
+    torch.cuda.synchronize()
+    td = timed(seq_default, args.steps or 3, stream)
 
     def seq_step():
         for dp, dm, c in zip(dps, dms, costs):
@@ -182,11 +196,14 @@ def w_batched(args):
             "tiles": {"tile_samples": tiles[0], "tile_waves": tiles[1],
                       "mfma": "bf16x3" if tiles[2] == pi.PI_VARIANT_MFMA_BF16X3 else "f32",
                       "autotuned": not args.tile_samples},
-            "batched_ms": mb, "sequential_ms": float(np.median(ts)),
-            "speedup": float(np.median(ts) / mb),
+            "batched_ms": mb,
+            "sequential_default_ms": float(np.median(td)),
+            "speedup": float(np.median(td) / mb),
+            "sequential_same_tiles_ms": float(np.median(ts)),
+            "speedup_same_tiles": float(np.median(ts) / mb),
             "control_step_batched_ms": float(np.median(tcb)),
-            "control_step_sequential_ms": float(np.median(tcs)),
-            "control_step_speedup": float(np.median(tcs) / np.median(tcb)),
+            "control_step_sequential_same_tiles_ms": float(np.median(tcs)),
+            "control_step_speedup_same_tiles": float(np.median(tcs) / np.median(tcb)),
             "batched_rollout_steps_per_s": ss / (mb * 1e-3),
             "batched_tflops": flop / (mb * 1e-3) / 1e12,
             "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,   # float32-equivalent for bf16x3

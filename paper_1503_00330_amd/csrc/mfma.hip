@@ -276,8 +276,9 @@ struct MixSmem {
   static constexpr int NPART = SH ? 1 : NW;
   // ring slot: the tile's 18 piece chunks (1 KiB each, lane-major) and its 16 sigma^2
   static constexpr int kRingChunks = kBfNKB * 3 + 1;
+  static constexpr int kRingSlots = 4;   // two stages of two tiles
   std::conditional_t<SH, char[16], float4[MT][NFRAG][64]> A;   // sample fragments, lane-major (anchor slots 0)
-  std::conditional_t<SH, u32x4[3][kRingChunks][64], char[16]> ring;
+  std::conditional_t<SH, u32x4[kRingSlots][kRingChunks][64], char[16]> ring;
   Acc part[NPART][kMaxOut][ROWS];        // per-wave partial sums
   float z[ROWS][D + 2];                  // [z, 1, 0]: fragment entries are products of two
   float mref[ROWS][kMaxOut], yref[ROWS][kMaxOut];
@@ -817,14 +818,16 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
 // per wave, one or two).  Every wave runs all model tiles [T0, T1) for its own
 // 16 RT rows, so the workgroup reads each model tile from L2 once per step
 // instead of once per wave: the tile's 18 piece chunks and its sigma^2 go
-// straight from memory into a three-slot LDS ring (buffer loads to LDS, two
-// tiles ahead, each wave issuing every NW-th chunk), and each wave reads the
-// chunks of the tile in hand from LDS.  With 8 waves (one row tile each) two
-// waves share a SIMD, so one's vector work runs under the other's products.  Per tile a wave waits for its own loads of that
-// tile (the next tile's may stay in flight) and then for the other waves at a
-// barrier: past it the tile is complete in LDS and every wave is done with the
-// slot the next load overwrites.  The per-tile arithmetic is mixture_tiles_bf's
-// for one wave's two row tiles, in tile order.
+// straight from memory into a four-slot LDS ring (buffer loads to LDS, each
+// wave issuing every NW-th chunk), and each wave reads the chunks of the tile
+// in hand from LDS.  The tiles go in stages of two: a stage's loads are issued
+// one stage ahead, and the waves meet once per stage, so the two waves of a
+// SIMD (8 waves, one row tile each) can drift apart within it and one's
+// vector work runs under the other's products.  Per stage a wave waits for
+// its own loads of that stage and then for the other waves at a barrier: past
+// it the stage is complete in LDS and every wave is done with the slots the
+// next loads overwrite (the previous stage's).  The per-tile arithmetic is
+// mixture_tiles_bf's for the wave's row tiles, in tile order.
 template <int D, int MT, int NW, bool BF>
 __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
   using SM = MixSmem<D, MT, NW, BF>;
@@ -842,10 +845,8 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
   const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.Wb, md.n_tiles * kTileBytes);
   const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
   // this wave's loads of one tile: chunks wave, wave + NW, ... below 19 (the
-  // sigma^2 chunk is number 18): 5, 5, 5, 4 loads per wave with 4 waves,
-  // 3, 3, 3, 2, 2, 2, 2, 2 with 8
+  // sigma^2 chunk is number 18)
   constexpr int kJobs = SM::kRingChunks, kMaxJob = (kJobs + NW - 1) / NW;
-  const int njob = (kJobs - wave + NW - 1) / NW;
   auto issue = [&](int tile, int slot) {
 #pragma unroll
     for (int q = 0; q < kMaxJob; ++q) {
@@ -860,8 +861,12 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
                                                  4, lane * 4, tile * 64, 0, 0);
     }
   };
-  if (n > 0) issue(T0, 0);
-  if (n > 1) issue(T0 + 1, 1);
+  // stage st_i: tiles 2 st_i and 2 st_i + 1 in slots 2 (st_i & 1) and + 1
+  auto issue_stage = [&](int st_i) {
+    issue(T0 + 2 * st_i, 2 * (st_i & 1));
+    if (2 * st_i + 1 < n) issue(T0 + 2 * st_i + 1, 2 * (st_i & 1) + 1);
+  };
+  if (n > 0) issue_stage(0);
   // the wave's sample pieces, built in registers (rows RW wave + 16 mt + lane%16,
   // features 32 kb + 8 (lane/16) .. +7 of block kb)
   u32x4 Bs[RT][kBfNKB][3];
@@ -950,78 +955,70 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
   int o = output_of(T0);
   int nb = next_boundary(T0);
   set_anchor(o);
-  for (int j = 0; j < n; ++j) {
-    // this wave's loads of tile j are complete once no more than the next
-    // tile's are outstanding (nothing else in this loop is a vector memory
-    // access; a later access would only make the wait longer)
-    if (j + 1 < n) {
-      // vmcnt(njob), expcnt and lgkmcnt untouched (the count must be an immediate)
-      if (njob == 5)
-        __builtin_amdgcn_s_waitcnt(0x0F70 | 5);
-      else if (njob == 4)
-        __builtin_amdgcn_s_waitcnt(0x0F70 | 4);
-      else if (njob == 3)
-        __builtin_amdgcn_s_waitcnt(0x0F70 | 3);
-      else
-        __builtin_amdgcn_s_waitcnt(0x0F70 | 2);
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
-    }
-    // no memory access moves across the barrier (compiler fences on both sides)
+  const int n_st = (n + 1) / 2;
+  for (int st_i = 0; st_i < n_st; ++st_i) {
+    // this wave's loads of the stage (issued one stage ago) are complete; no
+    // memory access moves across the barrier (compiler fences on both sides)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt untouched
     __asm__ __volatile__("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
     __asm__ __volatile__("" ::: "memory");
-    if (j + 2 < n) issue(T0 + j + 2, (j + 2) % 3);
-    const int tile = T0 + j, slot = j % 3;
-    if (tile >= nb) {
-      flush(o);
-      o = output_of(tile);
-      nb = next_boundary(tile);
-      set_anchor(o);
-    }
-    const u32x4(*W)[64] = sm.ring[slot];
-    const f32x4 s2 = ((const f32x4 *)&sm.ring[slot][kSig][0])[lane >> 4];
-    f32x4 qa[RT], qb[RT], ya[RT], yb[RT];
+    if (st_i + 1 < n_st) issue_stage(st_i + 1);
 #pragma unroll
-    for (int mt = 0; mt < RT; ++mt) {
-      qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      qb[mt] = qa[mt];
-      ya[mt] = qa[mt];
-      yb[mt] = qa[mt];
-    }
+    for (int u = 0; u < 2; ++u) {
+      const int j = 2 * st_i + u;
+      if (j >= n) break;
+      const int tile = T0 + j, slot = 2 * (st_i & 1) + u;
+      if (tile >= nb) {
+        flush(o);
+        o = output_of(tile);
+        nb = next_boundary(tile);
+        set_anchor(o);
+      }
+      const u32x4(*W)[64] = sm.ring[slot];
+      const f32x4 s2 = ((const f32x4 *)&sm.ring[slot][kSig][0])[lane >> 4];
+      f32x4 qa[RT], qb[RT], ya[RT], yb[RT];
 #pragma unroll
-    for (int kb = 0; kb < kBfNKB; ++kb) {
-      const u32x4 w[3] = {W[kb * 3 + 0][lane], W[kb * 3 + 1][lane], W[kb * 3 + 2][lane]};
-      // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
-      // y hm, hl, lh; with two row tiles the four chains go round-robin
-      constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
+      for (int mt = 0; mt < RT; ++mt) {
+        qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        qb[mt] = qa[mt];
+        ya[mt] = qa[mt];
+        yb[mt] = qa[mt];
+      }
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int kb = 0; kb < kBfNKB; ++kb) {
+        const u32x4 w[3] = {W[kb * 3 + 0][lane], W[kb * 3 + 1][lane], W[kb * 3 + 2][lane]};
+        // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
+        // y hm, hl, lh; with two row tiles the four chains go round-robin
+        constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
 #pragma unroll
-        for (int mt = 0; mt < RT; ++mt) {
-          f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
-          f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
-          x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
-          y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int mt = 0; mt < RT; ++mt) {
+            f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
+            f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
+            x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
+            y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+          }
+      }
+#pragma unroll
+      for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
+          // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+          // largest term of at least 2^-100) need none of exp2f's denormal scaling
+          const float e = __builtin_amdgcn_exp2f(a);
+          const float te = e * dd;
+          st[mt][i].Z += e;
+          st[mt][i].S1 += te;
+          st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+          st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+          st[mt][i].mx = fmaxf(st[mt][i].mx, a);
         }
     }
-#pragma unroll
-    for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
-        // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
-        // largest term of at least 2^-100) need none of exp2f's denormal scaling
-        const float e = __builtin_amdgcn_exp2f(a);
-        const float te = e * dd;
-        st[mt][i].Z += e;
-        st[mt][i].S1 += te;
-        st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
-        st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
-        st[mt][i].mx = fmaxf(st[mt][i].mx, a);
-      }
   }
   flush(o);
 }
@@ -1308,8 +1305,8 @@ constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
 template <int DYN, int MT, int NW, bool BF = false>
 struct RollSmem {
   static constexpr int ROWS = 16 * MT;
-  // steps per noise chunk: 2 for the 128-row shared-tile form (its LDS holds the tile ring)
-  static constexpr int CH = MixSmem<Dims<DYN>::D, MT, NW, BF>::SH ? 2 : kNoiseChunk;
+  // steps per noise chunk: 1 for the 128-row shared-tile form (its LDS holds the tile ring)
+  static constexpr int CH = MixSmem<Dims<DYN>::D, MT, NW, BF>::SH ? 1 : kNoiseChunk;
   MixSmem<Dims<DYN>::D, MT, NW, BF> sm;
   float xs[ROWS][Dims<DYN>::NX];
   float us_s[CH][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
@@ -1319,7 +1316,7 @@ struct RollSmem {
 };
 
 // Rollouts s_base .. s_base + spw - 1 of one problem for its whole horizon.
-// Every CH steps (kNoiseChunk, or 2) all lanes draw the chunk's eps and xi, store the
+// Every CH steps (kNoiseChunk, or 1) all lanes draw the chunk's eps and xi, store the
 // applied controls u_nom + sigma eps in LDS (no global read is left on the
 // per-step critical section) and evaluate the previous chunk's step costs
 // dt*q(x_{t+1}) from the states kept in LDS (the cost feeds nothing on the
