@@ -79,10 +79,25 @@ def test_noalloc_folded_models_and_other_families():
     assert torch.equal(c3, _with_workspace(pi.DeviceProblem(p3), pi.DeviceModel(m3)))
 
 
+def test_noalloc_bf16x3_launches():
+    # the three-piece bf16 contraction (model pieces folded into the scratch):
+    # the paired 2048-rollout launch, then a smaller ragged problem on the
+    # 128-row shared-tile launch with 8 waves
+    prob, model, _ = synth.config(1)
+    bf = pi.PI_VARIANT_MFMA_BF16X3
+    first = (pi.DeviceProblem(prob, variant=bf), pi.DeviceModel(model))
+    assert pi.rollout_describe(*first)["variant"] == "mfma-bf16x3"
+    p2, m2 = synth.tiny_problem(6, dyn=DYN_QUAD12, L=[19, 16, 33, 8, 16, 17], R=4, K=301, T=37, M=1,
+                                dtype=np.float32, n_obs=7)
+    second = (pi.DeviceProblem(p2, variant=bf, tile_samples=128, tile_waves=8), pi.DeviceModel(m2))
+    assert pi.rollout_describe(*second)["tile_samples"] == 128
+    _pair(first, second)
+
+
 def test_noalloc_rejects_requests_past_the_scratch():
     # 4096 rollouts x 120 sub-rollouts x 20 steps need 39 MB of sub-rollout
-    # costs (and the 6 x 1024-model fold 4 MB): refused before any device
-    # work, the output untouched
+    # costs (and the 6 x 1024-model fold, float32 tiles and bf16 pieces,
+    # 16 MB): refused before any device work, the output untouched
     prob, model, _ = synth.config(2, K=4096, T=20)
     prob.M = 120
     dp, dm = pi.DeviceProblem(prob), pi.DeviceModel(model)
