@@ -814,6 +814,15 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
   flush(o);
 }
 
+// f(integral_constant<int, i>) for i = B .. E-1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // The shared-tile form of the bf16 stage (MixSmem::SH: RT = MT / NW row tiles
 // per wave, one or two).  Every wave runs all model tiles [T0, T1) for its own
 // 16 RT rows, so the workgroup reads each model tile from L2 once per step
@@ -966,59 +975,87 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     __builtin_amdgcn_sched_barrier(0);
     __asm__ __volatile__("" ::: "memory");
     if (st_i + 1 < n_st) issue_stage(st_i + 1);
+    const bool two = 2 * st_i + 1 < n;   // the stage holds a second tile
+    // the stage's 12 (or 6) blocks of model pieces go through a ring of three
+    // blocks in registers, each read from LDS two blocks before its products:
+    // with 8 waves reading, an LDS round trip outlasts one block's products
+    u32x4 wb[3][3];
+    auto ldb = [&](auto Q) {
+      constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
+      const u32x4(*W)[64] = sm.ring[2 * (st_i & 1) + u];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = 2 * st_i + u;
-      if (j >= n) break;
-      const int tile = T0 + j, slot = 2 * (st_i & 1) + u;
-      if (tile >= nb) {
-        flush(o);
-        o = output_of(tile);
-        nb = next_boundary(tile);
-        set_anchor(o);
+      for (int p = 0; p < 3; ++p) wb[q % 3][p] = W[kb * 3 + p][lane];
+    };
+    ldb(std::integral_constant<int, 0>{});
+    ldb(std::integral_constant<int, 1>{});
+    f32x4 qa[RT], qb[RT], ya[RT], yb[RT], s2;
+    auto step = [&](auto Q) {
+      constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
+      if constexpr (q + 2 < 2 * kBfNKB) {
+        if (q + 2 < kBfNKB || two) ldb(std::integral_constant<int, q + 2>{});
       }
-      const u32x4(*W)[64] = sm.ring[slot];
-      const f32x4 s2 = ((const f32x4 *)&sm.ring[slot][kSig][0])[lane >> 4];
-      f32x4 qa[RT], qb[RT], ya[RT], yb[RT];
+      __builtin_amdgcn_sched_barrier(0);   // the reads go out ahead of this block's products
+      if constexpr (kb == 0) {
+        // the two waves of a SIMD (w and w + 4 of 8) take turns leading the
+        // matrix pipe, one tile each per stage: left to age order, the older
+        // wave would finish the stage first and the younger run alone
+        if constexpr (NW == 8) {
+          if ((wave >= 4) == (u == 0))
+            __builtin_amdgcn_s_setprio(1);
+          else
+            __builtin_amdgcn_s_setprio(0);
+        }
+        const int tile = T0 + 2 * st_i + u;
+        if (tile >= nb) {
+          flush(o);
+          o = output_of(tile);
+          nb = next_boundary(tile);
+          set_anchor(o);
+        }
+        s2 = ((const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0])[lane >> 4];
 #pragma unroll
-      for (int mt = 0; mt < RT; ++mt) {
-        qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        qb[mt] = qa[mt];
-        ya[mt] = qa[mt];
-        yb[mt] = qa[mt];
+        for (int mt = 0; mt < RT; ++mt) {
+          qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+          qb[mt] = qa[mt];
+          ya[mt] = qa[mt];
+          yb[mt] = qa[mt];
+        }
       }
+      const u32x4 *w = wb[q % 3];
+      // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
+      // y hm, hl, lh; with two row tiles the four chains go round-robin
+      constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
 #pragma unroll
-      for (int kb = 0; kb < kBfNKB; ++kb) {
-        const u32x4 w[3] = {W[kb * 3 + 0][lane], W[kb * 3 + 1][lane], W[kb * 3 + 2][lane]};
-        // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
-        // y hm, hl, lh; with two row tiles the four chains go round-robin
-        constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+        for (int mt = 0; mt < RT; ++mt) {
+          f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
+          f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
+          x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
+          y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (kb == kBfNKB - 1) {
 #pragma unroll
-          for (int mt = 0; mt < RT; ++mt) {
-            f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
-            f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
-            x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
-            y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
+            // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+            // largest term of at least 2^-100) need none of exp2f's denormal scaling
+            const float e = __builtin_amdgcn_exp2f(a);
+            const float te = e * dd;
+            st[mt][i].Z += e;
+            st[mt][i].S1 += te;
+            st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+            st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+            st[mt][i].mx = fmaxf(st[mt][i].mx, a);
           }
       }
-#pragma unroll
-      for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
-          // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
-          // largest term of at least 2^-100) need none of exp2f's denormal scaling
-          const float e = __builtin_amdgcn_exp2f(a);
-          const float te = e * dd;
-          st[mt][i].Z += e;
-          st[mt][i].S1 += te;
-          st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
-          st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
-          st[mt][i].mx = fmaxf(st[mt][i].mx, a);
-        }
-    }
+    };
+    static_for<0, kBfNKB>(step);
+    if (two) static_for<kBfNKB, 2 * kBfNKB>(step);
+    if constexpr (NW == 8) __builtin_amdgcn_s_setprio(0);
   }
   flush(o);
 }
