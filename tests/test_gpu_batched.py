@@ -126,9 +126,9 @@ def test_batched_tiles_per_problem(variant):
         assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
 
 
-@pytest.mark.parametrize("prefold", [False, True])
-def test_batched_control_step_equals_plain_control_steps(prefold):
-    host, dps, dms = _batch()
+@pytest.mark.parametrize("prefold,launch", [(False, (0, 0, 0)), (True, (0, 0, 0)), (False, (128, 8, BF3))])
+def test_batched_control_step_equals_plain_control_steps(prefold, launch):
+    host, dps, dms = _batch(*launch)
     if prefold:          # models read in place from their pi_model_fold buffers
         for dm in dms[::2]:
             dm.fold()
@@ -155,10 +155,12 @@ def test_batched_control_step_equals_plain_control_steps(prefold):
         assert np.max(np.abs(after[b][0].cpu().numpy() - x)) <= 1e-4 * max(1.0, np.abs(x).max()), b
 
 
-def test_batched_control_step_graph_replays():
+@pytest.mark.parametrize("launch", [(0, 0, 0), (128, 8, BF3)])
+def test_batched_control_step_graph_replays(launch):
     # one batched control step captured once and replayed three times, each
     # replay checked against the same step run eagerly from the same state
-    _, dps, dms = _batch()
+    # (the library's default tiles, and the bf16 form's shared tile)
+    _, dps, dms = _batch(*launch)
     br = pi.BatchedRollout(dps, dms)
     br.capture()
     for rep in range(3):
