@@ -582,8 +582,8 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // per 32-feature block, six bf16 16x16x32 instructions take the piece pairs hi hi,
 // hi mid, mid hi, hi lo, mid mid, lo hi (model tile as the A operand, the
 // samples' pieces as the B operand), which reproduce the float32 products to
-// within float32 rounding; five blocks of quadratic-form features into two
-// accumulators, one block of prediction features into two more.  With two row
+// within float32 rounding; five blocks of quadratic-form features into one
+// accumulator, one block of prediction features into another.  With two row
 // tiles every model piece loaded serves both, halving the loads per product
 // (the loads, not the matrix cores, bound the one-tile form).  The model
 // tile's pieces (18 KB) are held in registers once: as each block's products
@@ -685,14 +685,15 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
                                                    0, 0);
   };
-  // the six piece pairs of block kb of row tile mt into two accumulators
-  auto block6 = [&](int mt, int kb, f32x4 &x, f32x4 &y) {
+  // the six piece pairs hh, hm, mh, hl, mm, lh of block kb of row tile mt into
+  // one accumulator (the pipe takes a dependent product at full rate)
+  auto block6 = [&](int mt, int kb, f32x4 &x) {
     x = mm(W[kb][0], Bs[mt][kb][0], x);
-    y = mm(W[kb][0], Bs[mt][kb][1], y);
+    x = mm(W[kb][0], Bs[mt][kb][1], x);
     x = mm(W[kb][1], Bs[mt][kb][0], x);
-    y = mm(W[kb][0], Bs[mt][kb][2], y);
+    x = mm(W[kb][0], Bs[mt][kb][2], x);
     x = mm(W[kb][1], Bs[mt][kb][1], x);
-    y = mm(W[kb][2], Bs[mt][kb][0], y);
+    x = mm(W[kb][2], Bs[mt][kb][0], x);
   };
   // With two row tiles (one wave per SIMD, nothing else to overlap with) two
   // accumulator sets take turns: while the matrix cores take tile i into one,
@@ -703,21 +704,19 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
   // one row tile two waves per SIMD overlap instead, and the epilogue follows
   // the products.
   constexpr bool PIPE = MT == 2;
-  f32x4 qa[2][MT], qb[2][MT], ya[2][MT], yb[2][MT], s2[2];
+  f32x4 qa[2][MT], ya[2][MT], s2[2];
   auto clear_pending = [&](auto PI) {
     constexpr int p = decltype(PI)::value;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       qa[p][mt] = f32x4{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-      qb[p][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      ya[p][mt] = qb[p][mt];
-      yb[p][mt] = qb[p][mt];
+      ya[p][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     s2[p] = f32x4{0.f, 0.f, 0.f, 0.f};
   };
   auto epi = [&](auto PI, int mt, int i) {
     constexpr int p = decltype(PI)::value;
-    const float a = qa[p][mt][i] + qb[p][mt][i], dd = ya[p][mt][i] + yb[p][mt][i];
+    const float a = qa[p][mt][i], dd = ya[p][mt][i];
     // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
     // largest term of at least 2^-100) need none of exp2f's denormal scaling
     const float e = __builtin_amdgcn_exp2f(a);
@@ -756,20 +755,13 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       qa[c][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      qb[c][mt] = qa[c][mt];
       ya[c][mt] = qa[c][mt];
-      yb[c][mt] = qa[c][mt];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < kBfNKB; ++kb) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        if (kb < kBfNKQ)
-          block6(mt, kb, qa[c][mt], qb[c][mt]);
-        else
-          block6(mt, kb, ya[c][mt], yb[c][mt]);
-      }
+      for (int mt = 0; mt < MT; ++mt) block6(mt, kb, kb < kBfNKQ ? qa[c][mt] : ya[c][mt]);
       if constexpr (PIPE) {
         // this block's share of the pending epilogue, between its products
 #pragma unroll
@@ -988,7 +980,7 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     };
     ldb(std::integral_constant<int, 0>{});
     ldb(std::integral_constant<int, 1>{});
-    f32x4 qa[RT], qb[RT], ya[RT], yb[RT], s2;
+    f32x4 qa[RT], ya[RT], s2;
     auto step = [&](auto Q) {
       constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
       if constexpr (q + 2 < 2 * kBfNKB) {
@@ -1016,23 +1008,20 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-          qb[mt] = qa[mt];
           ya[mt] = qa[mt];
-          yb[mt] = qa[mt];
         }
       }
       const u32x4 *w = wb[q % 3];
-      // piece pairs (model, sample) of the two chains: x takes hh, mh, mm and
-      // y hm, hl, lh; with two row tiles the four chains go round-robin
-      constexpr int XA[3] = {0, 1, 1}, XB[3] = {0, 0, 1}, YA[3] = {0, 0, 2}, YB[3] = {1, 2, 0};
+      // the six piece pairs (model, sample) hh, hm, mh, hl, mm, lh into one
+      // accumulator per row tile and sum (the pipe takes a dependent product
+      // at full rate); with two row tiles the chains alternate
+      constexpr int PA[6] = {0, 0, 1, 0, 1, 2}, PB[6] = {0, 1, 0, 2, 1, 0};
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < 6; ++r)
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
-          f32x4 &y = kb < kBfNKQ ? qb[mt] : yb[mt];
-          x = mm(w[XA[r]], Bs[mt][kb][XB[r]], x);
-          y = mm(w[YA[r]], Bs[mt][kb][YB[r]], y);
+          x = mm(w[PA[r]], Bs[mt][kb][PB[r]], x);
         }
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (kb == kBfNKB - 1) {
@@ -1040,7 +1029,7 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float a = qa[mt][i] + qb[mt][i], dd = ya[mt][i] + yb[mt][i];
+            const float a = qa[mt][i], dd = ya[mt][i];
             // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
             // largest term of at least 2^-100) need none of exp2f's denormal scaling
             const float e = __builtin_amdgcn_exp2f(a);
