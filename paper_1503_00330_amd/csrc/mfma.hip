@@ -784,8 +784,15 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
+  // the first tile's loads in the loop's own order (block 0 first): the
+  // loop's first wait is the merge of this order and the loop body's, and a
+  // block 0 issued last here would make it wait for every load in flight on
+  // every tile, the next tile's prefetch included
 #pragma unroll
-  for (int kb = 0; kb < kBfNKB; ++kb) load_blk(t0, kb);
+  for (int kb = 0; kb < kBfNKB; ++kb) {
+    load_blk(t0, kb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   s2[0] = buffer_f32x4(srs, grp_off, t0 * 64);
   if constexpr (PIPE) {
     clear_pending(I1{});
