@@ -40,8 +40,8 @@ def nrel(g, o):
 
 
 def c16(g, o):
-    """Elementwise error under the survey's operational reading of relative
-    error: |g - o| / max(|o|, 1e-3 max|o|), worst element of the array."""
+    """Elementwise relative error with a floor for elements near zero:
+    |g - o| / max(|o|, 1e-3 max|o|), worst element of the array."""
     g, o = np.asarray(g, np.float64).ravel(), np.asarray(o, np.float64).ravel()
     return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), 1e-3 * max(np.abs(o).max(), 1e-300))))
 
