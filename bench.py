@@ -33,7 +33,9 @@ if ROOT not in sys.path:
 
 METRIC = "LWPR rollout steps/s + PI^2 update p50/p99 latency; fwd+adjoint & batched vs plain"
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
-PEAK_BF16_MFMA = 2.5e15        # MI355X dense bf16 matrix peak, FLOP/s
+PEAK_BF16_MFMA = 2.5e15        # MI355X dense bf16 (and fp16) matrix peak, FLOP/s
+# the pieces forms of the d = 16 contraction: matrix dtype and piece products per block
+PIECES = {"mfma-bf16x3": ("bf16x3", 6), "mfma-f16x2": ("f16x2", 3)}
 PEAK_HBM = 8.0e12              # bytes/s
 TRAFFIC_SUMMARY = {
     "rollout_mfma_kernel": os.path.join(ROOT, "profiles", "rollout_mfma_kernel.quad_k65536_t200.traffic.txt"),
@@ -53,34 +55,34 @@ def flops_per_sample_step(model):
     return model.Ltot * (d * d + 5 * d + 8)
 
 
-def bf16x3_flops_per_launch(model, n_samples, T):
-    """Matrix-core work the three-piece bf16 contraction executes: per 16-row
-    tile of samples, 16-model tile and step, 6 blocks of 32 features x 6
-    piece products, each a 16x16x32 product of 2*16*16*32 flop (the padded
-    feature layout and the piece products it takes to reach float32 accuracy,
-    not algorithmic work)."""
+def pieces_flops_per_launch(model, n_samples, T, products):
+    """Matrix-core work a pieces form of the contraction executes: per 16-row
+    tile of samples, 16-model tile and step, 6 blocks of 32 features x the
+    form's piece products (6 for bf16x3, 3 for f16x2), each a 16x16x32 product
+    of 2*16*16*32 flop (the padded feature layout and the piece products it
+    takes to reach float32 accuracy, not algorithmic work)."""
     n_model_tiles = sum((int(model.L_off[i + 1]) - int(model.L_off[i]) + 15) // 16 for i in range(model.n_out))
-    return ((n_samples + 15) // 16) * n_model_tiles * T * 36 * (2 * 16 * 16 * 32)
+    return ((n_samples + 15) // 16) * n_model_tiles * T * 6 * products * (2 * 16 * 16 * 32)
 
 
 def roofline(model, plan, n_samples, T, flop, seconds, traffic, autotuned):
     """The rollout kernel's roofline entry: algorithmic FLOP over the measured
     duration against the peak of the matrix instructions it runs (float32, or
-    bf16 for the three-piece form, which also reports its executed bf16 rate
-    and the float32-equivalent fraction)."""
+    bf16 / fp16 for the pieces forms, which also report their executed matrix
+    rate and the float32-equivalent fraction)."""
     achieved = flop / seconds
-    bf = plan["variant"] == "mfma-bf16x3"
-    peak = PEAK_BF16_MFMA if bf else PEAK_FP32_MFMA
-    r = {"bound": "mfma", "kernel": plan["kernel"], "mfma_dtype": "bf16x3" if bf else "f32",
+    pieces = PIECES.get(plan["variant"])
+    peak = PEAK_BF16_MFMA if pieces else PEAK_FP32_MFMA
+    r = {"bound": "mfma", "kernel": plan["kernel"], "mfma_dtype": pieces[0] if pieces else "f32",
          "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
          "traffic": traffic, "flop_per_launch": flop, "flop_per_sample_step": flops_per_sample_step(model),
          "sample_steps_per_launch": n_samples * T,
          "launch": dict({k: plan[k] for k in ("variant", "tile_samples", "tile_waves", "tile_split")},
                         autotuned=autotuned)}
-    if bf:
-        ex = bf16x3_flops_per_launch(model, n_samples, T)
-        r.update({"executed_bf16_flop_per_launch": ex, "executed_bf16": ex / seconds / 1e12,
-                  "executed_bf16_frac": ex / seconds / PEAK_BF16_MFMA,
+    if pieces:
+        ex = pieces_flops_per_launch(model, n_samples, T, pieces[1])
+        r.update({"executed_flop_per_launch": ex, "executed": ex / seconds / 1e12,
+                  "executed_frac": ex / seconds / PEAK_BF16_MFMA,
                   "fp32_equivalent_peak": PEAK_FP32_MFMA / 1e12,
                   "fp32_equivalent_frac": achieved / PEAK_FP32_MFMA})
     return r
@@ -296,7 +298,7 @@ def main():
     from paper_1503_00330_amd.profiling import launch_tag, traffic_from_summary
     summ = TRAFFIC_SUMMARY.get(plan["kernel"])
     traffic = traffic_from_summary(summ, launch_tag(plan)) if summ else None
-    bf = plan["variant"] == "mfma-bf16x3"
+    pieces = PIECES.get(plan["variant"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -316,8 +318,11 @@ def main():
                                "models, R=4, 20 obstacles, FP32",
                    "K": prob.K, "T": prob.T, "M": prob.M, "d": model.d, "n_out": model.n_out,
                    "L_per_output": int(model.L_off[1]), "R": model.R, "graph": not args.eager,
-                   "mfma": ("bf16x3: float32 mixture products as six bf16 piece products, float32 "
-                            "accumulation" if bf else "f32")},
+                   "mfma": {"bf16x3": "bf16x3: float32 mixture products as six bf16 piece products, "
+                                      "float32 accumulation",
+                            "f16x2": "f16x2: float32 mixture products of power-of-two scaled values as "
+                                     "three fp16 piece products, float32 accumulation"}.get(
+                                pieces[0] if pieces else None, "f32")},
         "latency_ms": {"control_step_p50": percentile(it_ms, 50),
                        "control_step_p99": percentile(it_ms, 99),
                        "rollout_p50": percentile(roll_ms, 50), "rollout_p99": percentile(roll_ms, 99),

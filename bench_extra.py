@@ -194,7 +194,8 @@ def w_batched(args):
     return {"workload": "64 quadrotor problems, K in 512..16384, L in 64..1024 per output, "
                         "T in 50..200, 10..40 obstacles",
             "tiles": {"tile_samples": tiles[0], "tile_waves": tiles[1],
-                      "mfma": "bf16x3" if tiles[2] == pi.PI_VARIANT_MFMA_BF16X3 else "f32",
+                      "mfma": {pi.PI_VARIANT_MFMA_BF16X3: "bf16x3", pi.PI_VARIANT_MFMA_F16X2: "f16x2"}.get(
+                          tiles[2], "f32"),
                       "autotuned": not args.tile_samples},
             "batched_ms": mb,
             "sequential_default_ms": float(np.median(td)),
@@ -206,7 +207,7 @@ def w_batched(args):
             "control_step_speedup_same_tiles": float(np.median(tcs) / np.median(tcb)),
             "batched_rollout_steps_per_s": ss / (mb * 1e-3),
             "batched_tflops": flop / (mb * 1e-3) / 1e12,
-            "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,   # float32-equivalent for bf16x3
+            "batched_frac_fp32_peak": flop / (mb * 1e-3) / PEAK_FP32,   # float32-equivalent for the pieces forms
             "bitwise_equal_to_plain": bool(same_cost), "control_step_bitwise_equal": bool(same_step),
             "dtype": "f32"}
 

@@ -83,8 +83,18 @@ enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
  * least 2^-24 are summed in float32, which reproduces the float32 products
  * to within float32 rounding.  With it, tiles of 33..128 samples (4 waves)
  * select the shared-tile launch: each wave holds 32 rows and the workgroup
- * stages every model tile once in LDS (for problems with many rollouts).    */
-enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2, PI_VARIANT_MFMA_BF16X3 = 3 };
+ * stages every model tile once in LDS (for problems with many rollouts).
+ * PI_VARIANT_MFMA_F16X2 (the same rollouts, shared-tile launch only: tiles
+ * of 33..128 samples, 128 by default, 4 or 8 waves, 8 by default, never
+ * split) runs it on the fp16 matrix instructions: each model's coefficients
+ * and each sample row's features are scaled by powers of two that keep them
+ * below 2^14, every scaled value is the sum of two fp16 pieces (hi, lo; lo
+ * may be subnormal) and the three piece products hi hi, hi lo, lo hi are
+ * summed in float32, half the products of the bf16 form, to about 2^-22
+ * relative per product; the scales are undone exactly in float32.  Neither
+ * form has a prediction entry point (lwpr_predict: PI_ERR_UNSUPPORTED).     */
+enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2, PI_VARIANT_MFMA_BF16X3 = 3,
+       PI_VARIANT_MFMA_F16X2 = 4 };
 /* Operations for pi_workspace_bytes. */
 enum { PI_OP_PREDICT = 0, PI_OP_ROLLOUT = 1, PI_OP_UPDATE = 2, PI_OP_ADJOINT = 3,
        PI_OP_RH_SHIFT = 4 };
@@ -134,7 +144,8 @@ typedef struct {
   uint64_t seed;                   /* Philox key                             */
   int32_t variant;                 /* PI_VARIANT_* (0 = library's choice)    */
   int32_t tile_samples;            /* samples per workgroup, <= 32, or <= 128 with
-                                    * PI_VARIANT_MFMA_BF16X3 (0 = library's choice) */
+                                    * PI_VARIANT_MFMA_BF16X3 or _F16X2 (0 =
+                                    * library's choice) */
   int32_t tile_waves;              /* waves per workgroup, 4 or 8 (8: 12-state
                                     * quadrotor only); 0 = library's choice:
                                     * 8 for the quadrotor when the launch has
@@ -298,8 +309,10 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
  * [T_b][n_u], iter[b] (one uint32), cost[b] [K_b][T_b].  All problems must be
  * PI_F32 and PI_DYN_QUAD12 with matrix-core models (PI_ERR_UNSUPPORTED
  * otherwise).  A problem's tile_samples (<= 32, or <= 128 when the batch
- * runs the bf16x3 form; 0 = 16) sets its tile;
- * tile_waves of problem 0 applies to the batch (8 needs every tile <= 16).
+ * runs the bf16x3 or f16x2 form; 0 = 16, or 128 in the f16x2 form, which
+ * needs the largest tile above 32) sets its tile; the variant and tile_waves
+ * of problem 0 apply to the batch (8 waves need every tile <= 16, or the
+ * largest above 32 in the pieces forms).
  * Models given pre-folded (pi_lwpr.folded) are read in place; the others are
  * folded into the workspace on every call.  The launch plan (descriptors and
  * work list) is written into the workspace by kernels on `stream`, so these

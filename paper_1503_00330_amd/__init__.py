@@ -24,7 +24,7 @@ PI_F32, PI_F64 = 0, 1
 PI_DYN_POINTMASS2D, PI_DYN_QUAD12, PI_DYN_QUAD_HYBRID = 0, 1, 2
 PI_OBS_INDICATOR, PI_OBS_SMOOTH = 0, 1
 PI_W_COST_TO_GO, PI_W_TRAJECTORY = 0, 1
-PI_VARIANT_AUTO, PI_VARIANT_DIRECT, PI_VARIANT_MFMA, PI_VARIANT_MFMA_BF16X3 = 0, 1, 2, 3
+PI_VARIANT_AUTO, PI_VARIANT_DIRECT, PI_VARIANT_MFMA, PI_VARIANT_MFMA_BF16X3, PI_VARIANT_MFMA_F16X2 = 0, 1, 2, 3, 4
 PI_OP_PREDICT, PI_OP_ROLLOUT, PI_OP_UPDATE, PI_OP_ADJOINT, PI_OP_RH_SHIFT = 0, 1, 2, 3, 4
 PI_MAX_OUT, PI_MAX_U = 8, 4
 STATUS = {0: "PI_OK", 1: "PI_ERR_NULL", 2: "PI_ERR_SHAPE", 3: "PI_ERR_VALUE", 4: "PI_ERR_DTYPE",
@@ -309,8 +309,9 @@ def rollout_describe(prob: DeviceProblem, model: DeviceModel) -> dict:
     out = (C.c_int32 * 4)()
     ps, ms = prob.struct(), model.struct()
     _check(load().pi_rollout_describe(C.byref(ps), C.byref(ms), out))
-    mfma = out[0] in (PI_VARIANT_MFMA, PI_VARIANT_MFMA_BF16X3)
-    return {"variant": {PI_VARIANT_MFMA: "mfma", PI_VARIANT_MFMA_BF16X3: "mfma-bf16x3"}.get(out[0], "direct"),
+    mfma = out[0] in (PI_VARIANT_MFMA, PI_VARIANT_MFMA_BF16X3, PI_VARIANT_MFMA_F16X2)
+    return {"variant": {PI_VARIANT_MFMA: "mfma", PI_VARIANT_MFMA_BF16X3: "mfma-bf16x3",
+                        PI_VARIANT_MFMA_F16X2: "mfma-f16x2"}.get(out[0], "direct"),
             "tile_samples": out[1], "tile_waves": out[2], "tile_split": out[3],
             "kernel": ("rollout_pair_kernel" if out[3] == 2 else "rollout_mfma_kernel")
             if mfma else "rollout_direct_kernel"}

@@ -96,10 +96,10 @@ pi_status check_problem(const pi_problem *p) {
   if (p->n_obs > 0 && !p->obs) return fail(PI_ERR_NULL, "obs is NULL with n_obs > 0");
   if (p->weighting != PI_W_COST_TO_GO && p->weighting != PI_W_TRAJECTORY)
     return fail(PI_ERR_VALUE, "unknown weighting %d", p->weighting);
-  if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA_BF16X3)
+  if (p->variant < PI_VARIANT_AUTO || p->variant > PI_VARIANT_MFMA_F16X2)
     return fail(PI_ERR_VALUE, "unknown variant %d", p->variant);
-  // 128 only for the bf16 form (its shared-tile launch: 32 rows per wave)
-  const int max_spw = p->variant == PI_VARIANT_MFMA_BF16X3 ? 128 : 32;
+  // 128 only for the pieces forms (their shared-tile launch)
+  const int max_spw = p->variant == PI_VARIANT_MFMA_BF16X3 || p->variant == PI_VARIANT_MFMA_F16X2 ? 128 : 32;
   if (p->tile_samples < 0 || p->tile_samples > max_spw)
     return fail(PI_ERR_VALUE, "tile_samples=%d outside [0,%d]", p->tile_samples, max_spw);
   if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8)
@@ -216,11 +216,17 @@ bool mfma_model_ok(const pi_lwpr *m) {
   return mfma_ok(m->dtype, m->d) && mfma_layout(m->d, m->n_out, m->L_off).w_floats * 4 < ((size_t)1 << 31);
 }
 
-// The three-piece bf16 contraction: float32, d = 16, its pieces (18 KB per
-// tile of 16 models) addressable with 32-bit offsets.
+// The three-piece bf16 and two-piece fp16 contractions: float32, d = 16,
+// their pieces (18 and 12 KB per tile of 16 models) addressable with 32-bit
+// offsets.
 bool bf_model_ok(const pi_lwpr *m) {
   if (!mfma_model_ok(m) || m->d != kBfD) return false;
   return mfma_layout(m->d, m->n_out, m->L_off).wb_u32 * 4 < ((size_t)1 << 31);
+}
+
+// Piece format of a requested variant (0: float32 products).
+int variant_pf(int variant) {
+  return variant == PI_VARIANT_MFMA_BF16X3 ? kPfBf16x3 : variant == PI_VARIANT_MFMA_F16X2 ? kPfF16x2 : kPfF32;
 }
 
 // Rollout variant, samples per workgroup and whether tiles may be split over
@@ -228,8 +234,8 @@ bool bf_model_ok(const pi_lwpr *m) {
 // compute-unit count and residency).  The workspace never depends on the
 // device: a pair-capable plan always reserves the exchange slots.
 struct RolloutPlan {
-  bool mfma, bf, pair_ok;
-  int spw, waves;
+  bool mfma, bf, pair_ok;   // bf: a pieces form (pf != 0)
+  int pf, spw, waves;
   int64_t groups;
 };
 
@@ -237,15 +243,18 @@ constexpr int64_t kMaxPairGroups = 2048;
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   RolloutPlan r;
-  r.mfma = p->variant == PI_VARIANT_MFMA || p->variant == PI_VARIANT_MFMA_BF16X3 ||
-           (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
-  r.bf = p->variant == PI_VARIANT_MFMA_BF16X3;
+  r.pf = variant_pf(p->variant);
+  r.mfma = p->variant == PI_VARIANT_MFMA || r.pf != kPfF32 || (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
+  r.bf = r.pf != kPfF32;
+  const bool hf = r.pf == kPfF16x2;   // the fp16 form: shared-tile launch only (128 rows, 8 waves by default)
   const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
-  r.waves = p->tile_waves > 0 ? p->tile_waves : 4;
-  const bool split_allowed = r.mfma && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
+  r.waves = p->tile_waves > 0 ? p->tile_waves : hf ? 8 : 4;
+  const bool split_allowed = r.mfma && !hf && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
                              p->tile_split != 1 && p->dtype == PI_F32;
   if (p->tile_samples > 0) {
     r.spw = p->tile_samples;
+  } else if (hf) {
+    r.spw = 128;
   } else if (split_allowed) {
     r.spw = 16;   // full 16-row tiles; small problems are spread by pairing
   } else {
@@ -255,6 +264,24 @@ RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   r.groups = (n + r.spw - 1) / r.spw;
   r.pair_ok = split_allowed && r.spw <= 16 && r.groups <= kMaxPairGroups;
   return r;
+}
+
+// The pieces forms' requirements (rollouts): the float32 12-state quadrotor
+// with d = 16 pieces under 2 GiB; the bf16x3 form on 8 waves takes tiles of at
+// most 16 or more than 32 samples, the f16x2 form tiles of 33..128 samples
+// (its shared-tile launch), never split.
+pi_status check_pieces(const pi_problem *p, const pi_lwpr *m, const RolloutPlan &pl) {
+  if (!pl.bf) return PI_OK;
+  if (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m))
+    return fail(PI_ERR_UNSUPPORTED, "the %s contraction needs the float32 12-state quadrotor (d = 16) and pieces "
+                                    "under 2 GiB", pl.pf == kPfF16x2 ? "f16x2" : "bf16x3");
+  if (pl.pf == kPfBf16x3 && pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)
+    return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction on 8 waves takes tiles of at most 16 or more than 32 "
+                                    "samples");
+  if (pl.pf == kPfF16x2 && (pl.spw <= 32 || p->tile_split == 2))
+    return fail(PI_ERR_UNSUPPORTED, "the f16x2 contraction runs the shared-tile launch: tile_samples 33..128, "
+                                    "tile_split 0 or 1");
+  return PI_OK;
 }
 
 // Compute units of the current device (0 if the query fails).
@@ -440,7 +467,7 @@ pi_status noalloc_scratch(void **out) {
 // The descriptors and items are written by kernels on the stream, so a call
 // never copies host memory and may be captured into a HIP graph.
 struct BatchLayout {
-  int max_spw, waves, n_items;
+  int max_spw, waves, n_items, pf;
   bool bf;
   size_t probs_off, items_off, queue_off, upd_off, shift_off, bytes;
   std::vector<size_t> fold_off, sub_off;   // (size_t)-1: none
@@ -448,7 +475,9 @@ struct BatchLayout {
   std::vector<int64_t> n_tiles, item_off;
 };
 
-int batch_spw(const pi_problem &p) { return p.tile_samples > 0 ? p.tile_samples : 16; }
+int batch_spw(const pi_problem &p) {
+  return p.tile_samples > 0 ? p.tile_samples : p.variant == PI_VARIANT_MFMA_F16X2 ? 128 : 16;
+}
 
 pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLayout *out) {
   if (B < 1 || B > (1 << 20)) return fail(PI_ERR_SHAPE, "B=%d outside [1, 2^20]", B);
@@ -473,15 +502,18 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
     L.max_spw = std::max(L.max_spw, L.spw[b]);
     L.n_tiles[b] = ((int64_t)p[b].K * (p[b].M > 0 ? p[b].M : 1) + L.spw[b] - 1) / L.spw[b];
   }
-  L.bf = p[0].variant == PI_VARIANT_MFMA_BF16X3;
-  // tiles of 33..128 samples: the bf16 form's shared-tile launch
+  L.pf = variant_pf(p[0].variant);
+  L.bf = L.pf != kPfF32;
+  // tiles of 33..128 samples: the pieces forms' shared-tile launch
   if (L.max_spw > (L.bf ? 128 : 32))
-    return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32 (<= 128 with the bf16x3 form)");
+    return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32 (<= 128 with the pieces forms)");
+  if (L.pf == kPfF16x2 && L.max_spw <= 32)
+    return fail(PI_ERR_UNSUPPORTED, "the f16x2 form runs the shared-tile launch: tile_samples 33..128");
   if (L.waves == 8 && L.max_spw > 16 && L.max_spw <= 32)
-    return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16 (or > 32 with the bf16x3 form)");
+    return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16 (or > 32 with the pieces forms)");
   if (L.bf) {
     for (int b = 0; b < B; ++b)
-      if (!bf_model_ok(&m[b])) return fail(PI_ERR_UNSUPPORTED, "problem %d: no bf16x3 form of its model", b);
+      if (!bf_model_ok(&m[b])) return fail(PI_ERR_UNSUPPORTED, "problem %d: no pieces form of its model", b);
   }
   // work list: problems by decreasing per-tile work (T * model tiles), each
   // problem's tiles in order
@@ -567,7 +599,7 @@ hipError_t run_batched_rollouts(int32_t B, const pi_problem *p, const pi_lwpr *m
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int per_cu = L.waves == 8 || L.max_spw > 32 ? 1 : 2;
     const int grid = std::max(1, std::min(L.n_items, ncu * per_cu));
-    e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, L.bf, grid, queue, s);
+    e = launch_rollout_batched(probs, items, L.n_items, L.max_spw, L.waves, L.pf, grid, queue, s);
   }
   for (int b = 0; b < B && e == hipSuccess; ++b)
     if (L.sub_off[b] != (size_t)-1)
@@ -591,10 +623,7 @@ pi_status check_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, c
   const RolloutPlan pl = rollout_plan(p, m);
   if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
     return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
-  if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)))
-    return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
-                                    "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 or more than 32 "
-                                    "samples");
+  PI_TRY(check_pieces(p, m, pl));
   return check_folded(m, pl.mfma);
 }
 
@@ -621,7 +650,7 @@ hipError_t run_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, co
         if (rl.pair)
           e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, rl.pl.bf, (char *)ws + fb + sub_bytes(p), s);
         else
-          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, rl.pl.bf, s);
+          e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, rl.pl.pf, s);
       } else {
         e = launch_rollout_direct(PI_F32, &ra, a, base, s);
       }
@@ -666,15 +695,15 @@ pi_status pi_rollout_describe(const pi_problem *p, const pi_lwpr *m, int32_t *ou
     const RolloutPlan pl = rollout_plan(p, m);
     if (pl.mfma && (p->dtype != PI_F32 || !mfma_model_ok(m)))
       return fail(PI_ERR_UNSUPPORTED, "MFMA rollout needs float32, d in {4,6,16} and folded tiles under 2 GiB");
-    if (pl.bf && (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m) || (pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)))
-      return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction needs the float32 12-state quadrotor (d = 16), "
-                                      "bf16 pieces under 2 GiB and, with 8 waves, tiles of at most 16 or more than "
-                                      "32 samples");
+    PI_TRY(check_pieces(p, m, pl));
   }
   PI_TRY(check_device());
   const RolloutLaunch rl = rollout_launch(p, m);
   const RolloutPlan &pl = rl.pl;
-  out[0] = pl.bf ? PI_VARIANT_MFMA_BF16X3 : pl.mfma ? PI_VARIANT_MFMA : PI_VARIANT_DIRECT;
+  out[0] = pl.pf == kPfF16x2    ? PI_VARIANT_MFMA_F16X2
+           : pl.pf == kPfBf16x3 ? PI_VARIANT_MFMA_BF16X3
+           : pl.mfma            ? PI_VARIANT_MFMA
+                                : PI_VARIANT_DIRECT;
   out[1] = pl.mfma ? pl.spw : 1;
   out[2] = pl.mfma ? pl.waves : 1;
   out[3] = rl.pair ? 2 : 1;
@@ -710,8 +739,8 @@ pi_status lwpr_predict(const pi_lwpr *m, const void *Z, int64_t N, void *mean, v
   PI_TRY(check_model(m));
   if (N < 0) return fail(PI_ERR_SHAPE, "N=%lld must be >= 0", (long long)N);
   if (N > 0 && (!Z || !mean || !var)) return fail(PI_ERR_NULL, "Z, mean and var must be non-NULL");
-  if (variant == PI_VARIANT_MFMA_BF16X3)
-    return fail(PI_ERR_UNSUPPORTED, "prediction has no bf16x3 form (use PI_VARIANT_MFMA)");
+  if (variant == PI_VARIANT_MFMA_BF16X3 || variant == PI_VARIANT_MFMA_F16X2)
+    return fail(PI_ERR_UNSUPPORTED, "prediction has no pieces form (use PI_VARIANT_MFMA)");
   if (variant < PI_VARIANT_AUTO || variant > PI_VARIANT_MFMA) return fail(PI_ERR_VALUE, "unknown variant %d", variant);
   const bool use_mfma = variant == PI_VARIANT_MFMA || (variant == PI_VARIANT_AUTO && mfma_model_ok(m));
   if (use_mfma && !mfma_model_ok(m))

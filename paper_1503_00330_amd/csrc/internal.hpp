@@ -68,6 +68,17 @@ constexpr int kBfNKQ = (kBfD * (kBfD + 1) / 2 + kBfD + 2 + 31) / 32;   // 5
 constexpr int kBfNKY = (kBfD + 2 + 31) / 32;                            // 1
 constexpr int kBfNKB = kBfNKQ + kBfNKY;
 constexpr size_t kBfTileU32 = (size_t)kBfNKB * 3 * 64 * 4;              // 18 KB per tile
+// The two-piece fp16 form of the same blocks (fp16 16x16x32 matrix
+// instructions): per tile, block and piece (hi, lo) 64 lanes x 8 fp16 of the
+// values scaled per model by a power of two, and per tile 48 floats: the 16
+// models' sigma^2, then the powers of two that undo the quadratic-form and
+// the prediction scales.
+constexpr size_t kHfTileU32 = (size_t)kBfNKB * 2 * 64 * 4;              // 12 KB per tile
+constexpr int kHfMeta = 48;
+// Piece formats of the contraction: float32 products, or the d = 16 features
+// and coefficients as three bf16 pieces (bf16 16x16x32 products), or as two
+// fp16 pieces of power-of-two scaled values (fp16 16x16x32 products).
+constexpr int kPfF32 = 0, kPfBf16x3 = 1, kPfF16x2 = 2;
 
 struct MfmaLayout {
   int d, n_out, n_tiles;
@@ -75,6 +86,8 @@ struct MfmaLayout {
   size_t w_floats;             // n_tiles * KB4 * 64 * 4
   size_t sig_floats;           // n_tiles * 16
   size_t wb_u32;               // the bf16 pieces (d = 16 only, else 0): n_tiles * kBfTileU32
+  size_t wh_u32;               // the fp16 pieces (d = 16 only, else 0): n_tiles * kHfTileU32
+  size_t hm_floats;            // their per-tile sigma^2 and scales (d = 16 only): n_tiles * kHfMeta
   size_t bytes;
 };
 
@@ -90,7 +103,10 @@ inline MfmaLayout mfma_layout(int d, int n_out, const int *L_off) {
   l.w_floats = (size_t)l.n_tiles * g.KB4 * 64 * 4;
   l.sig_floats = (size_t)l.n_tiles * 16;
   l.wb_u32 = d == kBfD ? (size_t)l.n_tiles * kBfTileU32 : 0;
-  l.bytes = align_up(l.w_floats * 4, 256) + align_up(l.sig_floats * 4, 256) + align_up(l.wb_u32 * 4, 256);
+  l.wh_u32 = d == kBfD ? (size_t)l.n_tiles * kHfTileU32 : 0;
+  l.hm_floats = d == kBfD ? (size_t)l.n_tiles * kHfMeta : 0;
+  l.bytes = align_up(l.w_floats * 4, 256) + align_up(l.sig_floats * 4, 256) + align_up(l.wb_u32 * 4, 256) +
+            align_up(l.wh_u32 * 4, 256) + align_up(l.hm_floats * 4, 256);
   return l;
 }
 
@@ -99,6 +115,8 @@ struct MfmaModel {
   const float4 *W;     // [n_tiles][KB4][64] float4
   const float *sig2;   // [n_tiles*16]
   const uint4 *Wb;     // [n_tiles][kBfNKB][3][64] (8 bf16 each), or null
+  const uint4 *Wh;     // [n_tiles][kBfNKB][2][64] (8 fp16 each), or null
+  const float *hmeta;  // [n_tiles][kHfMeta], or null
   int n_out, n_tiles;
   int tile_off[kMaxOut + 1];
 };
@@ -135,11 +153,12 @@ struct RolloutArgs {
 
 hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
                                  const void *rec, hipStream_t s);
-// bf: the contraction in the three-piece bf16 form (d = 16 quadrotor, tiles
-// of <= 16 samples, a layout with the bf16 pieces).
+// pf: the contraction's piece format (0 float32 products, 1 three bf16
+// pieces, 2 two fp16 pieces: d = 16 quadrotor, a layout with the pieces; the
+// fp16 form only on tiles of 33..128 samples).
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
                                const MfmaLayout &l, const void *base, int tile_samples,
-                               int waves, bool bf, hipStream_t s);
+                               int waves, int pf, hipStream_t s);
 hipError_t launch_subcost_reduce(int dtype, const void *sub, void *cost, int K, int Ms, int T,
                                  hipStream_t s);
 
@@ -172,9 +191,10 @@ MfmaModel mfma_model_view(const MfmaLayout &l, const void *base);
 // (tiles of spw sub-rollouts, in order) to items[item_off ..], on the stream.
 hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *probs, BatchedItem *items, int b,
                                    int64_t item_off, int64_t n_tiles, int spw, hipStream_t s);
-// max_spw: the largest tile of any item (<= 32); waves 8 needs max_spw <= 16.
+// max_spw: the largest tile of any item (<= 32, or 33..128 for the pieces
+// forms' shared tile); waves 8 needs max_spw <= 16 or > 32; pf as above.
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int max_spw, int waves, bool bf, int grid, int *queue, hipStream_t s);
+                                  int max_spw, int waves, int pf, int grid, int *queue, hipStream_t s);
 hipError_t launch_zero_int(int *p, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // Paired-workgroup rollout (MFMA, 16 rows per pair of workgroups).

@@ -43,6 +43,7 @@ namespace pi2rh {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 template <int D>
 struct Geo {
@@ -102,6 +103,19 @@ __host__ __device__ __forceinline__ void bf16_split3(float v, uint16_t *pc) {
   pc[2] = bf16_rn(r1 - m, &l);
 }
 
+// Two fp16 pieces hi + lo of a float32 value of magnitude below 2^15, each
+// rounded to nearest (ties to even): hi holds the top 11 significand bits, lo
+// the next 11 (lo may be subnormal: the matrix cores keep fp16 subnormal
+// inputs, so its absolute precision stays 2^-24).  The three piece products
+// hi hi, hi lo, lo hi of two such values give the float32 product to about
+// 2^-22 relative (lo lo, below 2^-22, is left out).
+__device__ __forceinline__ void f16_split2(float v, uint16_t *pc) {
+  const _Float16 h = (_Float16)v;
+  const _Float16 l = (_Float16)(v - (float)h);
+  pc[0] = __builtin_bit_cast(uint16_t, h);
+  pc[1] = __builtin_bit_cast(uint16_t, l);
+}
+
 // ----------------------------------------------------------------- fold
 // One block per tile of 16 model slots.  Phase 1: one lane per model computes
 // in double the derived vectors (h = -(D + D^T) c, kappa = c^T D c, the folded
@@ -112,7 +126,9 @@ constexpr int kFoldThreads = 256;
 __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, MfmaLayout l,
                                                                  float *__restrict__ W,
                                                                  float *__restrict__ sig2,
-                                                                 uint32_t *__restrict__ Wb) {
+                                                                 uint32_t *__restrict__ Wb,
+                                                                 uint32_t *__restrict__ Wh,
+                                                                 float *__restrict__ hmeta) {
   __shared__ double hv[16][kMaxD], bv[16][kMaxD], kap[16], y0v[16];
   __shared__ float Dl[16][kMaxD * kMaxD];
   __shared__ int jcol[16];
@@ -222,13 +238,50 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
 #pragma unroll
     for (int p = 0; p < 3; ++p) dstb[((size_t)(kb * 3 + p) * 64 + lane) * 8 + i] = pc[p];
   }
+  if (Wh == nullptr) return;
+  // the two-piece fp16 form: each model's quadratic-form values and its
+  // prediction values scaled by powers of two 2^-eq, 2^-ey that bring the
+  // largest magnitude of each to [2^13, 2^14) (fp16 holds up to 65504; the
+  // padded models' -1e30 included), then split into hi + lo fp16 pieces
+  __shared__ int eq[16], ey[16];
+  if (threadIdx.x < 32) {
+    const int col = threadIdx.x & 15;
+    const bool quad = threadIdx.x < 16;
+    float mx = 0.0f;
+    for (int k = 0; k < (quad ? g.KQ : g.KY); ++k) mx = fmaxf(mx, fabsf(value(quad ? k : 4 * g.KQB + k, col)));
+    int ex = 0;
+    if (mx > 0.0f) frexpf(mx, &ex);   // mx < 2^ex
+    (quad ? eq : ey)[col] = mx > 0.0f ? ex - 14 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int col = threadIdx.x;
+    hmeta[(size_t)tile * kHfMeta + col] = jcol[col] >= 0 ? ((const float *)m.sigma2)[jcol[col]] : 0.0f;
+    hmeta[(size_t)tile * kHfMeta + 16 + col] = ldexpf(1.0f, eq[col]);
+    hmeta[(size_t)tile * kHfMeta + 32 + col] = ldexpf(1.0f, ey[col]);
+  }
+  uint16_t *dsth = (uint16_t *)(Wh + (size_t)tile * kHfTileU32);
+  for (int e = threadIdx.x; e < kBfNKB * 64 * 8; e += blockDim.x) {
+    const int i = e & 7, lane = (e >> 3) & 63, kb = e >> 9;
+    const int k = 32 * (kb < kBfNKQ ? kb : kb - kBfNKQ) + 8 * (lane / 16) + i;
+    const bool inside = kb < kBfNKQ ? k < g.KQ : k < g.KY;
+    const int col = lane & 15;
+    const float v = inside ? ldexpf(value(kb < kBfNKQ ? k : 4 * g.KQB + k, col), -(kb < kBfNKQ ? eq[col] : ey[col]))
+                           : 0.0f;
+    uint16_t pc[2];
+    f16_split2(v, pc);
+    dsth[((size_t)(kb * 2 + 0) * 64 + lane) * 8 + i] = pc[0];
+    dsth[((size_t)(kb * 2 + 1) * 64 + lane) * 8 + i] = pc[1];
+  }
 }
 
 hipError_t launch_fold_mfma(int, const ModelArgs &m, const MfmaLayout &l, void *base, hipStream_t s) {
   float *W = (float *)base;
   float *sig = (float *)((char *)base + align_up(l.w_floats * 4, 256));
   uint32_t *Wb = l.wb_u32 ? (uint32_t *)((char *)sig + align_up(l.sig_floats * 4, 256)) : nullptr;
-  hipLaunchKernelGGL(fold_mfma_kernel, dim3(l.n_tiles), dim3(kFoldThreads), 0, s, m, l, W, sig, Wb);
+  uint32_t *Wh = l.wh_u32 ? (uint32_t *)((char *)Wb + align_up(l.wb_u32 * 4, 256)) : nullptr;
+  float *hm = l.hm_floats ? (float *)((char *)Wh + align_up(l.wh_u32 * 4, 256)) : nullptr;
+  hipLaunchKernelGGL(fold_mfma_kernel, dim3(l.n_tiles), dim3(kFoldThreads), 0, s, m, l, W, sig, Wb, Wh, hm);
   return hipGetLastError();
 }
 
@@ -237,6 +290,8 @@ static MfmaModel mfma_view(const MfmaLayout &l, const void *base) {
   md.W = (const float4 *)base;
   md.sig2 = (const float *)((const char *)base + align_up(l.w_floats * 4, 256));
   md.Wb = l.wb_u32 ? (const uint4 *)((const char *)md.sig2 + align_up(l.sig_floats * 4, 256)) : nullptr;
+  md.Wh = l.wh_u32 ? (const uint4 *)((const char *)md.Wb + align_up(l.wb_u32 * 4, 256)) : nullptr;
+  md.hmeta = l.hm_floats ? (const float *)((const char *)md.Wh + align_up(l.wh_u32 * 4, 256)) : nullptr;
   md.n_out = l.n_out;
   md.n_tiles = l.n_tiles;
   for (int o = 0; o <= kMaxOut; ++o) md.tile_off[o] = l.tile_off[o];
@@ -255,27 +310,31 @@ __device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
   return Acc{a.Z + b.Z, a.S1 + b.S1, a.S2 + b.S2, a.S3 + b.S3, fmaxf(a.mx, b.mx)};
 }
 
-// BF: the samples' fragments in the three-piece bf16 form (d = 16): per row
+// BF (a pieces form): the samples' fragments as pieces (d = 16): per row
 // tile, 32-feature block and piece, 64 lanes x 8 bf16 (16 bytes per lane,
 // kept in the float4 slots), sample lane%16, features 8 (lane/16) .. +7.
 //
-// SH (the bf16 form with MT > 2 row tiles, MT / NW = 1 or 2 per wave): the
+// SH (a pieces form with MT > 2 row tiles, MT / NW = 1 or 2 per wave): the
 // shared-tile form.  Each wave owns its row tiles and runs every model tile;
 // the workgroup stages each model tile once in LDS (ring, three tiles deep)
 // instead of every wave streaming its own range, and each wave's sums are
 // final (NPART = 1).  The samples' pieces are built in registers by their
-// wave (no A).
-template <int D, int MT, int NW, bool BF = false>
+// wave (no A).  The fp16 form has this launch only.
+template <int D, int MT, int NW, int PF = 0>
 struct MixSmem {
+  static constexpr bool BF = PF != kPfF32;
   static constexpr bool SH = BF && MT > 2;
   static_assert(!BF || (D == kBfD && (MT <= 2 || (MT % NW == 0 && MT / NW <= 2))),
-                "the bf16 form covers d = 16, one or two row tiles per wave");
+                "the pieces forms cover d = 16, one or two row tiles per wave");
+  static_assert(PF != kPfF16x2 || SH, "the fp16 form runs the shared-tile launch only");
+  static constexpr int NPC = PF == kPfF16x2 ? 2 : 3;   // pieces per value
   static constexpr int ROWS = 16 * MT;
-  static constexpr int NFRAG = BF ? kBfNKB * 3 : Geo<D>::KB4;   // 16-byte fragments per lane and row tile
+  static constexpr int NFRAG = BF ? kBfNKB * NPC : Geo<D>::KB4;   // 16-byte fragments per lane and row tile
   static constexpr int NSRC = BF ? kBfNKB * 32 : Geo<D>::NE;
   static constexpr int NPART = SH ? 1 : NW;
-  // ring slot: the tile's 18 piece chunks (1 KiB each, lane-major) and its 16 sigma^2
-  static constexpr int kRingChunks = kBfNKB * 3 + 1;
+  // ring slot: the tile's piece chunks (1 KiB each, lane-major), then one of
+  // its per-model values (the 16 sigma^2; fp16 form: sigma^2 and scales)
+  static constexpr int kRingChunks = kBfNKB * NPC + 1;
   static constexpr int kRingSlots = 4;   // two stages of two tiles
   std::conditional_t<SH, char[16], float4[MT][NFRAG][64]> A;   // sample fragments, lane-major (anchor slots 0)
   std::conditional_t<SH, u32x4[kRingSlots][kRingChunks][64], char[16]> ring;
@@ -296,12 +355,12 @@ struct MixSmem {
 // In the bf16 form (BF) entry e is feature slot e: slots 0 .. 32 kBfNKQ - 1
 // the quadratic-form features (f = e), the last block's the prediction
 // features (f = 4 KQB + e - 32 kBfNKQ in the numbering above).
-template <int D, int MT, int NW, bool BF>
-__device__ void mix_setup(MixSmem<D, MT, NW, BF> &sm) {
+template <int D, int MT, int NW, int PF>
+__device__ void mix_setup(MixSmem<D, MT, NW, PF> &sm) {
   using G = Geo<D>;
-  for (int e = threadIdx.x; e < MixSmem<D, MT, NW, BF>::NSRC; e += NW * 64) {
+  for (int e = threadIdx.x; e < MixSmem<D, MT, NW, PF>::NSRC; e += NW * 64) {
     int f;
-    if constexpr (BF) {
+    if constexpr (MixSmem<D, MT, NW, PF>::BF) {
       const int g = e - 32 * kBfNKQ;
       f = e < 32 * kBfNKQ ? (e < G::KQ ? e : -1) : (g < G::KY ? 4 * G::KQB + g : -1);
     } else {
@@ -343,12 +402,12 @@ __device__ void mix_setup(MixSmem<D, MT, NW, BF> &sm) {
 // Stage 1 (all lanes): the samples' fragments sm.A from sm.z (named for the
 // parameter pass, where they are the A operand; the rollout and the reverse
 // sweep use them as the B operand).
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, PF> &sm) {
   using G = Geo<D>;
-  if constexpr (MixSmem<D, MT, NW, BF>::SH) {
+  if constexpr (MixSmem<D, MT, NW, PF>::SH) {
     return;   // built in registers by mixture_tiles_sh
-  } else if constexpr (BF) {
+  } else if constexpr (MixSmem<D, MT, NW, PF>::BF) {
     // one (block, lane group, row) per thread: the group's 8 features of the
     // row, each split into three bf16 pieces, one 16-byte store per piece
     constexpr int NWORK = MT * kBfNKB * 4 * 16;
@@ -394,10 +453,10 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, BF> &sm) {
 
 // Empty per-wave partial sums: a wave flushes only the outputs its tiles
 // meet, and the merge adds every wave's slot in order.
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, BF> &sm) {
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, PF> &sm) {
   Acc *pp = &sm.part[0][0][0];
-  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, BF>::NPART * kMaxOut * MixSmem<D, MT, NW, BF>::ROWS;
+  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, PF>::NPART * kMaxOut * MixSmem<D, MT, NW, PF>::ROWS;
        i += NW * 64)
     pp[i] = acc_empty();
 }
@@ -406,8 +465,8 @@ __device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, BF> &sm) {
 // tile with the model tile as the A operand: lane l holds models 4(l/16) + i
 // (i < 4) of sample l%16.  Partial sums are flushed per output into
 // sm.part[wave][o][row].
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
   using G = Geo<D>;
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
@@ -589,9 +648,9 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // tile's pieces (18 KB) are held in registers once: as each block's products
 // issue, the registers of that block take the next tile's block (loads one
 // tile ahead).  The softmax epilogue and the flush are the float32 form's.
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
-  static_assert(BF && D == kBfD && (MT == 1 || MT == 2), "bf16 form: d = 16, one or two row tiles");
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
+  static_assert(PF == kPfBf16x3 && D == kBfD && (MT == 1 || MT == 2), "bf16 form: d = 16, one or two row tiles");
   using G = Geo<D>;
   // the activation anchor and the prediction reference: block, lane group, element
   constexpr int FQ = G::NP + D + 1, KQA = FQ / 32, GQA = (FQ % 32) / 8, IQA = FQ % 8;
@@ -836,24 +895,29 @@ __device__ __forceinline__ void static_for(F &f) {
 // it the stage is complete in LDS and every wave is done with the slots the
 // next loads overwrite (the previous stage's).  The per-tile arithmetic is
 // mixture_tiles_bf's for the wave's row tiles, in tile order.
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, int T0, int T1) {
-  using SM = MixSmem<D, MT, NW, BF>;
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
+  using SM = MixSmem<D, MT, NW, PF>;
   static_assert(SM::SH && (NW == 4 || NW == 8), "shared-tile form: four or eight waves");
   using G = Geo<D>;
+  constexpr bool HF = PF == kPfF16x2;   // two fp16 pieces (else three bf16 pieces)
+  constexpr int NPC = SM::NPC;
   constexpr int RT = MT / NW;   // row tiles per wave
   constexpr int RW = 16 * RT;   // rows per wave
   constexpr int FQ = G::NP + D + 1, KQA = FQ / 32, GQA = (FQ % 32) / 8, IQA = FQ % 8;
   constexpr int FY = D + 1, KYA = kBfNKQ + FY / 32, GYA = (FY % 32) / 8, IYA = FY % 8;
-  constexpr int kTileBytes = kBfNKB * 3 * 1024;
-  constexpr int kSig = SM::kRingChunks - 1;   // ring chunk of sigma^2
+  constexpr int kTileBytes = kBfNKB * NPC * 1024;
+  constexpr int kSig = SM::kRingChunks - 1;   // ring chunk of the per-model values
+  // bytes of per-model values per tile: sigma^2, or (fp16 form) sigma^2 and the two scales
+  constexpr int kMetaBytes = HF ? kHfMeta * 4 : 16 * 4;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int n = T1 - T0;
-  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.Wb, md.n_tiles * kTileBytes);
-  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
-  // this wave's loads of one tile: chunks wave, wave + NW, ... below 19 (the
-  // sigma^2 chunk is number 18)
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(HF ? (const void *)md.Wh : (const void *)md.Wb,
+                                                 md.n_tiles * kTileBytes);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(HF ? md.hmeta : md.sig2, md.n_tiles * kMetaBytes);
+  // this wave's loads of one tile: chunks wave, wave + NW, ... up to kSig (the
+  // chunk of per-model values)
   constexpr int kJobs = SM::kRingChunks, kMaxJob = (kJobs + NW - 1) / NW;
   auto issue = [&](int tile, int slot) {
 #pragma unroll
@@ -863,10 +927,10 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (__attribute__((address_space(3))) void *)&sm.ring[slot][c][0],
                                                  16, lane * 16, tile * kTileBytes + c * 1024, 0, 0);
       else if (c == kSig)
-        // 64 lanes x 4 bytes from the tile's 16 values on (the lanes past
-        // them read the next tiles', or zeros past the last: unused)
+        // 64 lanes x 4 bytes from the tile's 16 (or 48) values on (the lanes
+        // past them read the next tiles', or zeros past the last: unused)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, (__attribute__((address_space(3))) void *)&sm.ring[slot][c][0],
-                                                 4, lane * 4, tile * 64, 0, 0);
+                                                 4, lane * 4, tile * kMetaBytes, 0, 0);
     }
   };
   // stage st_i: tiles 2 st_i and 2 st_i + 1 in slots 2 (st_i & 1) and + 1
@@ -875,9 +939,41 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     if (2 * st_i + 1 < n) issue(T0 + 2 * st_i + 1, 2 * (st_i & 1) + 1);
   };
   if (n > 0) issue_stage(0);
+  // fp16 form: each row's features (and its anchors) scaled by a power of two
+  // 2^-e (e >= 0) that keeps them below 2^14 in magnitude; rsc[mt] = 2^e
+  // undoes it in the epilogue
+  float rsc[RT], rsi[RT];
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt) {
+    rsc[mt] = 1.0f;
+    rsi[mt] = 1.0f;
+    if constexpr (HF) {
+      const int row = RW * wave + 16 * mt + (lane & 15);
+      float mx = 1.0f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const float za = fabsf(sm.z[row][a]);
+        mx = fmaxf(mx, fmaxf(za, za * za));
+      }
+#pragma unroll
+      for (int oo = 0; oo < kMaxOut; ++oo) mx = fmaxf(mx, fmaxf(fabsf(sm.mref[row][oo]), fabsf(sm.yref[row][oo])));
+      int ex = 0;
+      frexpf(mx, &ex);   // mx < 2^ex
+      const int e = ex > 14 ? ex - 14 : 0;
+      rsc[mt] = ldexpf(1.0f, e);
+      rsi[mt] = ldexpf(1.0f, -e);
+    }
+  }
+  // the pieces of one feature value (scaled in the fp16 form)
+  auto split = [&](float x, int mt, uint16_t *pc) {
+    if constexpr (HF)
+      f16_split2(x * rsi[mt], pc);
+    else
+      bf16_split3(x, pc);
+  };
   // the wave's sample pieces, built in registers (rows RW wave + 16 mt + lane%16,
   // features 32 kb + 8 (lane/16) .. +7 of block kb)
-  u32x4 Bs[RT][kBfNKB][3];
+  u32x4 Bs[RT][kBfNKB][NPC];
   {
     const int r16 = lane & 15, grp = lane >> 4;
 #pragma unroll
@@ -885,18 +981,18 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
       const int row = RW * wave + 16 * mt + r16;
 #pragma unroll
       for (int kb = 0; kb < kBfNKB; ++kb) {
-        uint32_t pk[3][4];
+        uint32_t pk[NPC][4];
 #pragma unroll
         for (int i = 0; i < 8; i += 2) {
           uint16_t lo[3], hi[3];
           const unsigned s0 = sm.fsrc[32 * kb + 8 * grp + i], s1 = sm.fsrc[32 * kb + 8 * grp + i + 1];
-          bf16_split3(sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], lo);
-          bf16_split3(sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF], hi);
+          split(sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], mt, lo);
+          split(sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF], mt, hi);
 #pragma unroll
-          for (int p = 0; p < 3; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
+          for (int p = 0; p < NPC; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
         }
 #pragma unroll
-        for (int p = 0; p < 3; ++p) Bs[mt][kb][p] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
+        for (int p = 0; p < NPC; ++p) Bs[mt][kb][p] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
       }
     }
   }
@@ -915,12 +1011,12 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     }
     return nb;
   };
-  auto put = [&](u32x4 (&v)[3], auto I, float x) {
+  auto put = [&](u32x4 (&v)[NPC], auto I, float x, int mt) {
     constexpr int i = decltype(I)::value;
     uint16_t pc[3];
-    bf16_split3(x, pc);
+    split(x, mt, pc);
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < NPC; ++p) {
       uint32_t w = v[p][i / 2];
       w = (i & 1) ? ((w & 0x0000FFFFu) | ((uint32_t)pc[p] << 16)) : ((w & 0xFFFF0000u) | pc[p]);
       v[p][i / 2] = w;
@@ -930,8 +1026,8 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
 #pragma unroll
     for (int mt = 0; mt < RT; ++mt) {
       const int row = RW * wave + 16 * mt + (lane & 15);
-      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo]);
-      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo]);
+      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo], mt);
+      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo], mt);
     }
   };
   Acc st[RT][4];
@@ -957,8 +1053,12 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     }
   };
   auto mm = [&](const u32x4 &a, const u32x4 &b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
-                                                   0, 0);
+    if constexpr (HF)
+      return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                    0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                     0, 0, 0);
   };
   int o = output_of(T0);
   int nb = next_boundary(T0);
@@ -978,16 +1078,16 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     // the stage's 12 (or 6) blocks of model pieces go through a ring of three
     // blocks in registers, each read from LDS two blocks before its products:
     // with 8 waves reading, an LDS round trip outlasts one block's products
-    u32x4 wb[3][3];
+    u32x4 wb[3][NPC];
     auto ldb = [&](auto Q) {
       constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
       const u32x4(*W)[64] = sm.ring[2 * (st_i & 1) + u];
 #pragma unroll
-      for (int p = 0; p < 3; ++p) wb[q % 3][p] = W[kb * 3 + p][lane];
+      for (int p = 0; p < NPC; ++p) wb[q % 3][p] = W[kb * NPC + p][lane];
     };
     ldb(std::integral_constant<int, 0>{});
     ldb(std::integral_constant<int, 1>{});
-    f32x4 qa[RT], ya[RT], s2;
+    f32x4 qa[RT], ya[RT], s2, qs, ys;
     auto step = [&](auto Q) {
       constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
       if constexpr (q + 2 < 2 * kBfNKB) {
@@ -1011,7 +1111,12 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
           nb = next_boundary(tile);
           set_anchor(o);
         }
-        s2 = ((const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0])[lane >> 4];
+        const f32x4 *meta = (const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0];
+        s2 = meta[lane >> 4];
+        if constexpr (HF) {   // the models' scales 2^eq, 2^ey
+          qs = meta[4 + (lane >> 4)];
+          ys = meta[8 + (lane >> 4)];
+        }
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -1019,12 +1124,13 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         }
       }
       const u32x4 *w = wb[q % 3];
-      // the six piece pairs (model, sample) hh, hm, mh, hl, mm, lh into one
-      // accumulator per row tile and sum (the pipe takes a dependent product
-      // at full rate); with two row tiles the chains alternate
+      // the piece pairs (model, sample) into one accumulator per row tile and
+      // sum (the pipe takes a dependent product at full rate; with two row
+      // tiles the chains alternate): bf16 hh, hm, mh, hl, mm, lh; fp16 hh, hl, lh
+      constexpr int NPR = HF ? 3 : 6;
       constexpr int PA[6] = {0, 0, 1, 0, 1, 2}, PB[6] = {0, 1, 0, 2, 1, 0};
 #pragma unroll
-      for (int r = 0; r < 6; ++r)
+      for (int r = 0; r < NPR; ++r)
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
@@ -1036,7 +1142,9 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float a = qa[mt][i], dd = ya[mt][i];
+            // fp16 form: the model's and the row's powers of two undone (exact)
+            const float a = HF ? qa[mt][i] * (qs[i] * rsc[mt]) : qa[mt][i];
+            const float dd = HF ? ya[mt][i] * (ys[i] * rsc[mt]) : ya[mt][i];
             // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
             // largest term of at least 2^-100) need none of exp2f's denormal scaling
             const float e = __builtin_amdgcn_exp2f(a);
@@ -1076,8 +1184,8 @@ struct SampleArgs {
 // acceleration, the anchors of the next evaluation (observed maximum and
 // mean), and the redo flag of evaluation `ev` when the sums are not usable
 // (one overflowed, or the largest term came near the denormal range).
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW, BF> &sm, int row, int o, const Acc &s, uint32_t ev,
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW, PF> &sm, int row, int o, const Acc &s, uint32_t ev,
                                             const SampleArgs &sa) {
   const float d1 = s.S1 / s.Z;
   const float mu = sm.yref[row][o] + d1;
@@ -1102,19 +1210,19 @@ __device__ __forceinline__ void finish_sums(MixSmem<D, MT, NW, BF> &sm, int row,
 }
 
 
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW, BF> &sm, int row, int o) {
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ Acc sum_waves(const MixSmem<D, MT, NW, PF> &sm, int row, int o) {
   Acc s = sm.part[0][o][row];
 #pragma unroll
-  for (int w = 1; w < MixSmem<D, MT, NW, BF>::NPART; ++w) s = acc_sum(s, sm.part[w][o][row]);
+  for (int w = 1; w < MixSmem<D, MT, NW, PF>::NPART; ++w) s = acc_sum(s, sm.part[w][o][row]);
   return s;
 }
 
 // Stage 3 (lanes < ROWS * n_out): fixed-order sums over waves, then the
 // moments.
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW, BF> &sm, int n_out, uint32_t ev, const SampleArgs &sa) {
-  constexpr int ROWS = MixSmem<D, MT, NW, BF>::ROWS;
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void merge_waves(MixSmem<D, MT, NW, PF> &sm, int n_out, uint32_t ev, const SampleArgs &sa) {
+  constexpr int ROWS = MixSmem<D, MT, NW, PF>::ROWS;
   for (int i = threadIdx.x; i < ROWS * n_out; i += NW * 64) {
     const int row = i % ROWS, o = i / ROWS;
     finish_sums(sm, row, o, sum_waves(sm, row, o), ev, sa);
@@ -1163,8 +1271,8 @@ __device__ __forceinline__ void put_word(uint64_t *p, float v, uint32_t seq) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW, BF> &sm, int n_out, const PairCtx &pc, uint32_t seq,
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW, PF> &sm, int n_out, const PairCtx &pc, uint32_t seq,
                                            const SampleArgs &sa) {
   static_assert(MT == 1, "paired workgroups hold one 16-row tile");
   constexpr int ROWS = 16;
@@ -1215,17 +1323,17 @@ __device__ __forceinline__ void merge_pair(MixSmem<D, MT, NW, BF> &sm, int n_out
 // the pair exchanges and selects the redo flag, double-buffered so that one
 // barrier per evaluation suffices); with a pair context the two halves' sums
 // are exchanged every pass.
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW, BF> &sm, bool force_second,
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, bool force_second,
                                              int T0, int T1, const PairCtx *pc, uint32_t &seq,
                                              const SampleArgs &sa = SampleArgs{nullptr}) {
   for (int pass = 0; pass < 2; ++pass) {
     build_fragments(sm);
     clear_parts(sm);
     __syncthreads();
-    if constexpr (MixSmem<D, MT, NW, BF>::SH)
+    if constexpr (MixSmem<D, MT, NW, PF>::SH)
       mixture_tiles_sh(md, sm, T0, T1);
-    else if constexpr (BF)
+    else if constexpr (PF == kPfBf16x3)
       mixture_tiles_bf(md, sm, T0, T1);
     else
       mixture_tiles(md, sm, T0, T1);
@@ -1249,7 +1357,7 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
       // trajectory (it drifts steadily once the state leaves the models'
       // support), so extrapolate it linearly from the last two steps; the
       // lanes that merged each (row, output) own its entries.
-      constexpr int ROWS = MixSmem<D, MT, NW, BF>::ROWS;
+      constexpr int ROWS = MixSmem<D, MT, NW, PF>::ROWS;
       for (int i = threadIdx.x; i < ROWS * md.n_out; i += NW * 64) {
         const int row = i % ROWS, o = i / ROWS;
         const float M = sm.mref[row][o];
@@ -1262,9 +1370,9 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
   }
 }
 
-template <int D, int MT, int NW, bool BF>
-__device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW, BF> &sm) {
-  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, BF>::ROWS * kMaxOut; i += NW * 64) {
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ void reset_anchors(MixSmem<D, MT, NW, PF> &sm) {
+  for (int i = threadIdx.x; i < MixSmem<D, MT, NW, PF>::ROWS * kMaxOut; i += NW * 64) {
     (&sm.mref[0][0])[i] = 0.0f;
     (&sm.yref[0][0])[i] = 0.0f;
     (&sm.mprev[0][0])[i] = 0.0f;
@@ -1335,12 +1443,12 @@ struct Dims<kDynQuadHybrid> {
 
 constexpr int kNoiseChunk = 16;   // steps of noise drawn ahead into LDS
 
-template <int DYN, int MT, int NW, bool BF = false>
+template <int DYN, int MT, int NW, int PF = 0>
 struct RollSmem {
   static constexpr int ROWS = 16 * MT;
   // steps per noise chunk: 1 for the 128-row shared-tile form (its LDS holds the tile ring)
-  static constexpr int CH = MixSmem<Dims<DYN>::D, MT, NW, BF>::SH ? 1 : kNoiseChunk;
-  MixSmem<Dims<DYN>::D, MT, NW, BF> sm;
+  static constexpr int CH = MixSmem<Dims<DYN>::D, MT, NW, PF>::SH ? 1 : kNoiseChunk;
+  MixSmem<Dims<DYN>::D, MT, NW, PF> sm;
   float xs[ROWS][Dims<DYN>::NX];
   float us_s[CH][ROWS][4];           // applied controls u_nom + sigma eps of the chunk
   float xi_s[CH][ROWS][8];
@@ -1371,8 +1479,8 @@ __device__ __forceinline__ RollSeg roll_seg(const RolloutArgs<float> &ra) {
                  ra.xstart, ra.ckpt_out};
 }
 
-template <int DYN, int MT, int NW, bool BF>
-__device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float> &p,
+template <int DYN, int MT, int NW, int PF>
+__device__ void rollout_tile(RollSmem<DYN, MT, NW, PF> &rs, const ProbDev<float> &p,
                              const float *__restrict__ x0, const float *__restrict__ u_nom,
                              uint32_t it, float *__restrict__ cost, const MfmaModel &md,
                              int64_t s_base, int spw, const PairCtx *pc = nullptr, float *tr = nullptr,
@@ -1380,8 +1488,8 @@ __device__ void rollout_tile(RollSmem<DYN, MT, NW, BF> &rs, const ProbDev<float>
   using DD = Dims<DYN>;
   constexpr int D = DD::D, NX = DD::NX, NU = DD::NU, NO = DD::NO;
   constexpr int ROWS = 16 * MT;
-  constexpr int CH = RollSmem<DYN, MT, NW, BF>::CH;
-  MixSmem<D, MT, NW, BF> &sm = rs.sm;
+  constexpr int CH = RollSmem<DYN, MT, NW, PF>::CH;
+  MixSmem<D, MT, NW, PF> &sm = rs.sm;
   constexpr int SEGW = NX + 5 * NO;   // trace row: x_t, then 5 values per output (SampleArgs)
   const int tb = sg ? sg->tb : 0, te = sg ? sg->te : p.T;
   const int ck = sg ? sg->ckpt : 0;
@@ -1544,16 +1652,16 @@ constexpr int rollout_waves_per_eu() {
   return (DYN != kDynQuad12 && MT == 1 && NW == 4) ? 4 : 1;
 }
 
-// One workgroup per tile of `spw` (<= 16*MT) sub-rollouts; BF: the contraction
+// One workgroup per tile of `spw` (<= 16*MT) sub-rollouts; PF: the contraction
 // in the three-piece bf16 form.
-template <int DYN, int MT, int NW, bool BF>
+template <int DYN, int MT, int NW, int PF>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, MT, NW>())))
 rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
                                                                int spw) {
-  __shared__ RollSmem<DYN, MT, NW, BF> rs;
+  __shared__ RollSmem<DYN, MT, NW, PF> rs;
   mix_setup(rs.sm);
   const RollSeg sg = roll_seg(ra);
-  rollout_tile<DYN, MT, NW, BF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
+  rollout_tile<DYN, MT, NW, PF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md,
                                 (int64_t)blockIdx.x * spw, spw, nullptr, ra.trace, &sg);
 }
 
@@ -1561,18 +1669,18 @@ rollout_mfma_kernel(RolloutArgs<float> ra, MfmaModel md,
 // fewer tiles than compute units): partners are blocks b and b + 8 of each
 // 16-block group, which the round-robin dispatch places on the same XCD, so
 // their exchange stays inside one L2.  The grid must be resident at once.
-template <int DYN, int NW, bool BF>
+template <int DYN, int NW, int PF>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu<DYN, 1, NW>())))
 rollout_pair_kernel(RolloutArgs<float> ra, MfmaModel md, int spw,
                                                                int n_groups, uint64_t *__restrict__ xbuf,
                                                                uint32_t spin_limit) {
-  __shared__ RollSmem<DYN, 1, NW, BF> rs;
+  __shared__ RollSmem<DYN, 1, NW, PF> rs;
   const int blk = blockIdx.x;
   const int g = (blk / 16) * 8 + (blk % 8);
   if (g >= n_groups) return;  // both halves of an unused pair leave
   const PairCtx pc{xbuf + (size_t)g * kPairWords, (blk / 8) & 1, spin_limit};
   mix_setup(rs.sm);
-  rollout_tile<DYN, 1, NW, BF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
+  rollout_tile<DYN, 1, NW, PF>(rs, ra.p, ra.x0, ra.u_nom, *ra.iter, ra.cost, md, (int64_t)g * spw, spw, &pc,
                                ra.trace);
   // pair_fail is final: the tile's last evaluation ended with a barrier
   if (threadIdx.x == 0 && rs.sm.pair_fail) atomicAdd(&pair_give_ups_total, 1ull);
@@ -1583,11 +1691,11 @@ __global__ void read_give_ups_kernel(unsigned long long *out) { out[0] = pair_gi
 // Persistent form for many independent problems: every workgroup pulls
 // (problem, tile) items from a queue (items are ordered by decreasing work)
 // until the queue is empty.  Each item is exactly a plain rollout tile.
-template <int DYN, int MT, int NW, bool BF>
+template <int DYN, int MT, int NW, int PF>
 __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedProblem *__restrict__ probs,
                                                                   const BatchedItem *__restrict__ items,
                                                                   int n_items, int *__restrict__ queue) {
-  __shared__ RollSmem<DYN, MT, NW, BF> rs;
+  __shared__ RollSmem<DYN, MT, NW, PF> rs;
   __shared__ int item_s;
   mix_setup(rs.sm);
   for (;;) {
@@ -1600,7 +1708,7 @@ __global__ void __launch_bounds__(NW * 64) rollout_batched_kernel(const BatchedP
     const BatchedProblem &bp = probs[it.b];
     const ProbDev<float> p = bp.p;
     const MfmaModel md = bp.md;
-    rollout_tile<DYN, MT, NW, BF>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, it.spw);
+    rollout_tile<DYN, MT, NW, PF>(rs, p, bp.x0, bp.u_nom, *bp.iter, bp.cost, md, it.s_base, it.spw);
   }
 }
 
@@ -1614,29 +1722,34 @@ __global__ void batched_describe_kernel(BatchedProblem bp, BatchedProblem *__res
     items[item_off + i] = BatchedItem{b, spw, i * spw};
 }
 
-template <int DYN, int MT, int NW, bool BF = false>
+template <int DYN, int MT, int NW, int PF = 0>
 static hipError_t rollout_mfma_t(const RolloutArgs<float> &ra, const MfmaModel &md, int spw,
                                  hipStream_t s) {
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
   const int64_t nb = (n + spw - 1) / spw;
-  hipLaunchKernelGGL((rollout_mfma_kernel<DYN, MT, NW, BF>), dim3((unsigned)nb), dim3(NW * 64), 0, s, ra,
+  hipLaunchKernelGGL((rollout_mfma_kernel<DYN, MT, NW, PF>), dim3((unsigned)nb), dim3(NW * 64), 0, s, ra,
                      md, spw);
   return hipGetLastError();
 }
 
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m, const MfmaLayout &l,
-                               const void *base, int tile_samples, int waves, bool bf, hipStream_t s) {
+                               const void *base, int tile_samples, int waves, int pf, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
   const int spw = tile_samples;
-  if (bf) {
+  if (pf == kPfF16x2) {   // shared-tile launch only
+    if (ra.p.dyn != kDynQuad12 || md.Wh == nullptr || spw <= 32 || spw > 128) return hipErrorInvalidValue;
+    return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, kPfF16x2>(ra, md, spw, s)
+                      : rollout_mfma_t<kDynQuad12, 8, 4, kPfF16x2>(ra, md, spw, s);
+  }
+  if (pf == kPfBf16x3) {
     if (ra.p.dyn != kDynQuad12 || md.Wb == nullptr || (waves == 8 && spw > 16 && spw <= 32) || spw > 128)
       return hipErrorInvalidValue;
     if (spw > 32)   // shared-tile form: 128 rows, two row tiles on each of 4 waves or one on each of 8
-      return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, true>(ra, md, spw, s)
-                        : rollout_mfma_t<kDynQuad12, 8, 4, true>(ra, md, spw, s);
-    if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, true>(ra, md, spw, s);
-    if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, true>(ra, md, spw, s);
-    return rollout_mfma_t<kDynQuad12, 2, 4, true>(ra, md, spw, s);
+      return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, kPfBf16x3>(ra, md, spw, s)
+                        : rollout_mfma_t<kDynQuad12, 8, 4, kPfBf16x3>(ra, md, spw, s);
+    if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, kPfBf16x3>(ra, md, spw, s);
+    if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, kPfBf16x3>(ra, md, spw, s);
+    return rollout_mfma_t<kDynQuad12, 2, 4, kPfBf16x3>(ra, md, spw, s);
   }
   if (ra.p.dyn == kDynQuad12) {
     if (waves == 8) {
@@ -1662,16 +1775,16 @@ int pair_blocks_per_cu(int dyn, int waves, bool bf) {
   int nb = 0;
   hipError_t e;
   if (dyn == kDynQuad12 && bf)
-    e = waves == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, true>, 512, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, true>, 256, 0);
+    e = waves == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, kPfBf16x3>, 512, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, kPfBf16x3>, 256, 0);
   else if (dyn == kDynQuad12 && waves == 8)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, false>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, kPfF32>, 512, 0);
   else if (dyn == kDynQuad12)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, kPfF32>, 256, 0);
   else if (dyn == kDynQuadHybrid)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuadHybrid, 4, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuadHybrid, 4, kPfF32>, 256, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynPointMass2D, 4, kPfF32>, 256, 0);
   return e == hipSuccess ? nb : 0;
 }
 
@@ -1691,23 +1804,23 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
   const dim3 grid((unsigned)pair_grid(n_groups));
   if (ra.p.dyn == kDynQuad12 && bf) {
     if (waves == 8)
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, true>), grid, dim3(512), 0, s, ra, md, spw,
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, kPfBf16x3>), grid, dim3(512), 0, s, ra, md, spw,
                          (int)n_groups, xbuf, spin);
     else
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, true>), grid, dim3(256), 0, s, ra, md, spw,
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, kPfBf16x3>), grid, dim3(256), 0, s, ra, md, spw,
                          (int)n_groups, xbuf, spin);
   } else if (ra.p.dyn == kDynQuad12) {
     if (waves == 8)
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, false>), grid, dim3(512), 0, s, ra, md, spw,
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, kPfF32>), grid, dim3(512), 0, s, ra, md, spw,
                          (int)n_groups, xbuf, spin);
     else
-      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, kPfF32>), grid, dim3(256), 0, s, ra, md, spw,
                          (int)n_groups, xbuf, spin);
   } else if (ra.p.dyn == kDynQuadHybrid) {
-    hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynQuadHybrid, 4, kPfF32>), grid, dim3(256), 0, s, ra, md, spw,
                        (int)n_groups, xbuf, spin);
   } else {
-    hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4, false>), grid, dim3(256), 0, s, ra, md, spw,
+    hipLaunchKernelGGL((rollout_pair_kernel<kDynPointMass2D, 4, kPfF32>), grid, dim3(256), 0, s, ra, md, spw,
                        (int)n_groups, xbuf, spin);
   }
   return hipGetLastError();
@@ -1727,35 +1840,43 @@ hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *pro
 }
 
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
-                                  int max_spw, int waves, bool bf, int grid, int *queue, hipStream_t s) {
+                                  int max_spw, int waves, int pf, int grid, int *queue, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  if (bf) {
+  if (pf == kPfF16x2) {   // shared-tile launch only
+    if (max_spw <= 32 || max_spw > 128) return hipErrorInvalidValue;
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, kPfF16x2>), dim3(grid), dim3(512), 0, s, probs,
+                         items, n_items, queue);
+    else
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, kPfF16x2>), dim3(grid), dim3(256), 0, s, probs,
+                         items, n_items, queue);
+  } else if (pf == kPfBf16x3) {
     if ((waves == 8 && max_spw > 16 && max_spw <= 32) || max_spw > 128) return hipErrorInvalidValue;
     if (max_spw > 32) {   // shared-tile form: 128 rows per workgroup
       if (waves == 8)
-        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, true>), dim3(grid), dim3(512), 0, s, probs,
+        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, kPfBf16x3>), dim3(grid), dim3(512), 0, s, probs,
                            items, n_items, queue);
       else
-        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, true>), dim3(grid), dim3(256), 0, s, probs,
+        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
                            items, n_items, queue);
     } else if (waves == 8)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, true>), dim3(grid), dim3(512), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, kPfBf16x3>), dim3(grid), dim3(512), 0, s, probs,
                          items, n_items, queue);
     else if (max_spw <= 16)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, true>), dim3(grid), dim3(256), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
                          items, n_items, queue);
     else
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, true>), dim3(grid), dim3(256), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
                          items, n_items, queue);
   } else if (max_spw <= 16) {
     if (waves == 8)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, false>), dim3(grid), dim3(512), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, kPfF32>), dim3(grid), dim3(512), 0, s, probs,
                          items, n_items, queue);
     else
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, false>), dim3(grid), dim3(256), 0, s, probs,
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, kPfF32>), dim3(grid), dim3(256), 0, s, probs,
                          items, n_items, queue);
   } else {
-    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, false>), dim3(grid), dim3(256), 0, s, probs,
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, kPfF32>), dim3(grid), dim3(256), 0, s, probs,
                        items, n_items, queue);
   }
   return hipGetLastError();

@@ -2,7 +2,8 @@
 
 For a given problem shape the tuner times pi_rollout_cost for every candidate
 launch (samples per tile, waves per workgroup, workgroups per tile, and the
-contraction: float32 matrix-core products or their three-piece bf16 form)
+contraction: float32 matrix-core products, their three-piece bf16 form or
+their two-piece fp16 form)
 with HIP events and caches the fastest in a JSON file keyed by the device
 architecture, the shape and the requested variant; for a batch of problems it
 times the batched launch for every uniform tile shape and contraction.  A
@@ -24,17 +25,18 @@ import json
 import os
 from typing import Dict, Iterable, Optional, Sequence, Tuple
 
-# contraction codes, as PI_VARIANT_MFMA and PI_VARIANT_MFMA_BF16X3
-_MF, _BF = 2, 3
+# contraction codes, as PI_VARIANT_MFMA, PI_VARIANT_MFMA_BF16X3 and PI_VARIANT_MFMA_F16X2
+_MF, _BF, _HF = 2, 3, 4
 _SHAPES = ((16, 4, 1), (16, 8, 1), (8, 4, 1), (8, 8, 1), (32, 4, 1), (16, 4, 2), (16, 8, 2))
 _BATCH_SHAPES = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
 # (samples per tile, waves per workgroup, workgroups per tile, contraction);
-# 128-sample tiles are the bf16 form's shared-tile launch
+# 128-sample tiles are the pieces forms' shared-tile launch (the fp16 form has
+# no other)
 CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
-                                                     + ((128, 4, 1, _BF), (128, 8, 1, _BF)))
+                                                     + tuple((128, w, 1, v) for v in (_BF, _HF) for w in (4, 8)))
 # uniform launches of a batch: (samples per tile, waves per workgroup, contraction)
 BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
-                                                      + ((128, 4, _BF), (128, 8, _BF)))
+                                                      + tuple((128, w, v) for v in (_BF, _HF) for w in (4, 8)))
 
 
 def cache_path() -> str:
@@ -107,14 +109,14 @@ def batch_key(problems, models) -> str:
 def _variants_for(prob, models) -> Tuple[int, ...]:
     """Contractions to search: the named one, or with PI_VARIANT_AUTO float32
     products and, for float32 12-state quadrotor problems on d = 16 models,
-    their three-piece bf16 form."""
+    their three-piece bf16 and two-piece fp16 forms."""
     from . import PI_DYN_QUAD12
     import torch
     req = _requested(prob)
-    if req in (_MF, _BF):
+    if req in (_MF, _BF, _HF):
         return (req,)
     bf_ok = prob.dyn == PI_DYN_QUAD12 and prob.dtype == torch.float32 and all(m.d == 16 for m in models)
-    return (_MF, _BF) if bf_ok else (_MF,)
+    return (_MF, _BF, _HF) if bf_ok else (_MF,)
 
 
 def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
@@ -133,6 +135,8 @@ def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
         if waves == 8 and (prob.dyn != PI_DYN_QUAD12 or 16 < spw <= 32):
             continue
         if split == 2 and (spw > 16 or prob.dtype != torch.float32):
+            continue
+        if v == _HF and (spw <= 32 or split != 1):
             continue
         out.append((spw, waves, split, v))
     return tuple(out)
@@ -178,7 +182,7 @@ def tune_rollout(prob, model, candidates: Optional[Iterable[Tuple[int, int, int,
     ((samples, waves, split, variant), {candidate: ms})."""
     import torch
     from . import rollout_cost
-    if _requested(prob) not in (0, _MF, _BF):
+    if _requested(prob) not in (0, _MF, _BF, _HF):
         raise ValueError("launch shapes apply to the matrix-core rollout kernels")
     cands = tuple(candidates) if candidates is not None else candidates_for(prob, model)
     saved = _launch(prob)
@@ -226,8 +230,8 @@ def apply_batch(problems: Sequence, models: Sequence, path: Optional[str] = None
 
 def batch_candidates_for(problems: Sequence, models: Sequence) -> Tuple[Tuple[int, int, int], ...]:
     """Uniform launches the batched kernel accepts for these problems (8 waves
-    only with tiles of <= 16 samples or the bf16 form's 128-sample shared
-    tiles; the bf16 form when every problem allows it and asks for the
+    only with tiles of <= 16 samples or the pieces forms' 128-sample shared
+    tiles; the pieces forms when every problem allows them and asks for the
     library's choice)."""
     vs = set(_variants_for(problems[0], models))
     for p in problems[1:]:

@@ -217,6 +217,19 @@ class TestValidation:
         ps.tile_samples = 128
         assert _rollout(ps, ms) == 6 and "device" in pi.last_error()   # valid: only the device is missing
 
+    def test_f16x2_runs_the_shared_tile_only(self):
+        # the two-piece fp16 form: tiles of 33..128 samples, never split
+        for fields, code in ((dict(tile_samples=32), 7), (dict(tile_samples=16, tile_waves=8), 7),
+                             (dict(tile_split=2), 7), (dict(tile_samples=129), 3),
+                             (dict(tile_samples=64, tile_waves=4), 6), (dict(), 6)):
+            ps, ms = _structs()
+            ps.variant = pi.PI_VARIANT_MFMA_F16X2
+            for k, v in fields.items():
+                setattr(ps, k, v)
+            assert _rollout(ps, ms) == code, (fields, pi.last_error())
+            if code == 7:
+                assert "f16x2" in pi.last_error()
+
     def test_mfma_needs_float32(self):
         ps, ms = _structs(dtype=np.float64)
         ps.variant = pi.PI_VARIANT_MFMA
@@ -232,7 +245,9 @@ class TestValidation:
         ps, ms = _structs()
         assert lib.pi_update(C.byref(ps), None, FAKE, FAKE, None, FAKE, 1 << 30, None) == 1
         assert lib.lwpr_predict(C.byref(ms), FAKE, -1, FAKE, FAKE, 0, FAKE, 1 << 30, None) == 2
-        assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, 4, FAKE, 1 << 30, None) == 3
+        assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, 5, FAKE, 1 << 30, None) == 3
+        for v in (pi.PI_VARIANT_MFMA_BF16X3, pi.PI_VARIANT_MFMA_F16X2):   # rollouts only
+            assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, v, FAKE, 1 << 30, None) == 7
         ms.d = 5
         assert lib.lwpr_predict(C.byref(ms), FAKE, 5, FAKE, FAKE, pi.PI_VARIANT_MFMA, FAKE,
                                 1 << 30, None) == 7

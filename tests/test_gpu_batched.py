@@ -44,11 +44,12 @@ def _batch(spw=0, waves=0, variant=0):
 
 
 BF3 = 3   # PI_VARIANT_MFMA_BF16X3: the contraction in three bf16 pieces
+HF2 = 4   # PI_VARIANT_MFMA_F16X2: in two fp16 pieces (the shared-tile launch only)
 
 
 @pytest.mark.parametrize("spw,waves,variant", [(0, 0, 0), (8, 4, 0), (16, 8, 0), (32, 4, 0),
                                                (0, 0, BF3), (16, 8, BF3), (32, 4, BF3), (128, 8, BF3),
-                                               (128, 4, BF3)])
+                                               (128, 4, BF3), (0, 0, HF2), (128, 8, HF2), (64, 4, HF2)])
 def test_batched_equals_plain_launches(spw, waves, variant):
     host, dps, dms = _batch(spw, waves, variant)
     for dp in dps:
@@ -126,7 +127,8 @@ def test_batched_tiles_per_problem(variant):
         assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
 
 
-@pytest.mark.parametrize("prefold,launch", [(False, (0, 0, 0)), (True, (0, 0, 0)), (False, (128, 8, BF3))])
+@pytest.mark.parametrize("prefold,launch", [(False, (0, 0, 0)), (True, (0, 0, 0)), (False, (128, 8, BF3)),
+                                            (False, (128, 8, HF2))])
 def test_batched_control_step_equals_plain_control_steps(prefold, launch):
     host, dps, dms = _batch(*launch)
     if prefold:          # models read in place from their pi_model_fold buffers
@@ -155,7 +157,7 @@ def test_batched_control_step_equals_plain_control_steps(prefold, launch):
         assert np.max(np.abs(after[b][0].cpu().numpy() - x)) <= 1e-4 * max(1.0, np.abs(x).max()), b
 
 
-@pytest.mark.parametrize("launch", [(0, 0, 0), (128, 8, BF3)])
+@pytest.mark.parametrize("launch", [(0, 0, 0), (128, 8, BF3), (128, 8, HF2)])
 def test_batched_control_step_graph_replays(launch):
     # one batched control step captured once and replayed three times, each
     # replay checked against the same step run eagerly from the same state
@@ -198,8 +200,8 @@ def test_batched_control_step_full_workload():
 
 
 def test_batched_refuses_unsupported_tiles():
-    # 33..128-row tiles only with the bf16 form (its shared-tile launch), and
-    # 8 waves not with 17..32-row tiles
+    # 33..128-row tiles only with the pieces forms (their shared-tile launch),
+    # 8 waves not with 17..32-row tiles, the fp16 form only on the shared tile
     host, dps, dms = _batch(variant=BF3)
     for dp in dps:
         dp.tile_samples, dp.variant = 128, 2
@@ -209,4 +211,8 @@ def test_batched_refuses_unsupported_tiles():
         dp.tile_samples, dp.variant = 32, BF3
     dps[0].tile_waves = 8
     with pytest.raises(pi.PiError, match="tile_waves 8"):
+        pi.BatchedRollout(dps, dms)
+    for dp in dps:
+        dp.tile_samples, dp.tile_waves, dp.variant = 32, 4, HF2
+    with pytest.raises(pi.PiError, match="f16x2 form runs the shared-tile launch"):
         pi.BatchedRollout(dps, dms)

@@ -39,9 +39,10 @@ def test_candidate_space_covers_pairing_waves_and_contraction():
     assert {c[2] for c in tune.CANDIDATES} == {1, 2}
     assert {c[1] for c in tune.CANDIDATES} == {4, 8}
     assert {c[0] for c in tune.CANDIDATES} == {8, 16, 32, 128}
-    assert all(c[3] == 3 for c in tune.CANDIDATES if c[0] > 32)   # shared-tile launch: bf16 form only
-    assert {c[3] for c in tune.CANDIDATES} == {2, 3}
-    assert {c[2] for c in tune.BATCH_CANDIDATES} == {2, 3}
+    assert all(c[3] in (3, 4) for c in tune.CANDIDATES if c[0] > 32)   # shared-tile launch: the pieces forms
+    assert all(c[0] == 128 and c[2] == 1 for c in tune.CANDIDATES if c[3] == 4)   # fp16 form: shared tile only
+    assert {c[3] for c in tune.CANDIDATES} == {2, 3, 4}
+    assert {c[2] for c in tune.BATCH_CANDIDATES} == {2, 3, 4}
 
 
 class _P:
@@ -58,12 +59,14 @@ def test_candidates_follow_the_requested_variant():
     import torch
     from paper_1503_00330_amd import PI_DYN_QUAD12, PI_DYN_POINTMASS2D
     q = tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32), _M(16))
-    assert {c[3] for c in q} == {2, 3}
+    assert {c[3] for c in q} == {2, 3, 4}
+    assert (128, 8, 1, 4) in q and (128, 4, 1, 4) in q
     # bf16 form: no 8 waves with 32-sample tiles, no pairs above 16 samples
     assert (32, 8, 1, 3) not in q and (32, 4, 2, 3) not in q and (32, 4, 1, 3) in q
     assert (128, 4, 1, 3) in q and (128, 8, 1, 3) in q
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 2), _M(16))} == {2}
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 3), _M(16))} == {3}
+    assert tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 4), _M(16)) == ((128, 4, 1, 4), (128, 8, 1, 4))
     # not eligible for the bf16 form: another d, float64, another plant
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32), _M(8))} == {2}
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float64), _M(16))} == {2}
@@ -133,7 +136,7 @@ def test_tune_batched_keeps_plain_parity(tmp_path):
     path = str(tmp_path / "t.json")
     best, times = tune.tune_batched(dps, dms, reps=1, path=path)
     assert best in times and len(times) == len(tune.batch_candidates_for(dps, dms))
-    assert {c[2] for c in times} == {2, 3}
+    assert {c[2] for c in times} == {2, 3, 4}
     assert tune.apply_batch(dps, dms, path=path)
     costs = [c.clone() for c in pi.BatchedRollout(dps, dms).run()]
     for b, (dp, dm) in enumerate(zip(dps, dms)):

@@ -94,6 +94,19 @@ def test_noalloc_bf16x3_launches():
     _pair(first, second)
 
 
+def test_noalloc_f16x2_launch():
+    # the two-piece fp16 contraction on the shared tile (its pieces and scales
+    # folded into the scratch), then a smaller ragged problem on 4 waves
+    prob, model, _ = synth.config(1, K=1024, T=40)
+    hf = pi.PI_VARIANT_MFMA_F16X2
+    first = (pi.DeviceProblem(prob, variant=hf), pi.DeviceModel(model))
+    assert pi.rollout_describe(*first)["variant"] == "mfma-f16x2"
+    p2, m2 = synth.tiny_problem(7, dyn=DYN_QUAD12, L=[19, 16, 33, 8, 16, 17], R=4, K=301, T=37, M=1,
+                                dtype=np.float32, n_obs=7)
+    second = (pi.DeviceProblem(p2, variant=hf, tile_samples=64, tile_waves=4), pi.DeviceModel(m2))
+    _pair(first, second)
+
+
 def test_noalloc_rejects_requests_past_the_scratch():
     # 4096 rollouts x 120 sub-rollouts x 20 steps need 39 MB of sub-rollout
     # costs (and the 6 x 1024-model fold, float32 tiles and bf16 pieces,
