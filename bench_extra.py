@@ -110,9 +110,10 @@ def w_rh_graph(args):
 def w_batched(args):
     """64 independent controllers with uneven K, L, T and obstacles.  Tiles
     are picked by the autotuner (uniform tile shape over the batch; cached).
-    Reported: the batched rollouts against 64 plain rollout launches with the
-    library's default tile shape (`speedup`) and with the batch's own tile
-    shape (`speedup_same_tiles`: bitwise the same costs), and one batched
+    Reported: the batched rollouts against 64 plain rollout launches, each
+    problem in the fastest of the library's default launches of the three
+    contractions (`speedup`), and with the batch's own tile shape and
+    contraction (`speedup_same_tiles`: bitwise the same costs), and one batched
     control step (rollouts, updates, plant steps and shifts; one HIP graph)
     against 64 plain control steps with the batch's tiles (one HIP graph of
     all 64), with the bitwise check that both leave every problem's state the
@@ -149,17 +150,23 @@ def w_batched(args):
     tb = timed(br.run, args.steps or 3, stream)
     ts = timed(seq, args.steps or 3, stream)
     same_cost = all(torch.equal(a, c) for a, c in zip(br.costs, costs))
-    # the plain baseline a caller would run: each problem on its own with the
-    # library's default tile shape (16 rollouts per tile, workgroup pairs when
-    # the tiles leave compute units idle) in the batch's contraction
-    dflt = [pi.DeviceProblem(p, variant=dps[0].variant) for p, _ in batch]
-
-    def seq_default():
-        for dp, dm, c in zip(dflt, dms, costs):
-            pi.rollout_cost(dp, dm, out=c)
-    seq_default()
-    torch.cuda.synchronize()
-    td = timed(seq_default, args.steps or 3, stream)
+    # the plain baseline a caller would run: each problem on its own in the
+    # fastest of the library's default launches of the three contractions
+    # (float32 products or bf16 pieces: 16 rollouts per tile, workgroup pairs
+    # when the tiles leave compute units idle; fp16 pieces: the 128-rollout
+    # shared tile), timed problem by problem
+    forms = (pi.PI_VARIANT_MFMA, pi.PI_VARIANT_MFMA_BF16X3, pi.PI_VARIANT_MFMA_F16X2)
+    best, picks = [], {}
+    for (p, _), dm, c in zip(batch, dms, costs):
+        t_form = {}
+        for v in forms:
+            dp1 = pi.DeviceProblem(p, variant=v)
+            pi.rollout_cost(dp1, dm, out=c)
+            t_form[v] = float(np.median(timed(lambda: pi.rollout_cost(dp1, dm, out=c), args.steps or 3, stream)))
+        v = min(t_form, key=t_form.get)
+        best.append(t_form[v])
+        picks[v] = picks.get(v, 0) + 1
+    td = [sum(best)]
 
     def seq_step():
         for dp, dm, c in zip(dps, dms, costs):
@@ -199,6 +206,8 @@ def w_batched(args):
                       "autotuned": not args.tile_samples},
             "batched_ms": mb,
             "sequential_default_ms": float(np.median(td)),
+            "sequential_default_forms": {{pi.PI_VARIANT_MFMA: "f32", pi.PI_VARIANT_MFMA_BF16X3: "bf16x3",
+                                          pi.PI_VARIANT_MFMA_F16X2: "f16x2"}[v]: n for v, n in picks.items()},
             "speedup": float(np.median(td) / mb),
             "sequential_same_tiles_ms": float(np.median(ts)),
             "speedup_same_tiles": float(np.median(ts) / mb),

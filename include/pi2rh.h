@@ -81,18 +81,19 @@ enum { PI_W_COST_TO_GO = 0, PI_W_TRAJECTORY = 1 };
  * contraction on the bf16 matrix instructions: every float32 operand is the
  * exact sum of three bf16 pieces and the six piece products of weight at
  * least 2^-24 are summed in float32, which reproduces the float32 products
- * to within float32 rounding.  With it, tiles of 33..128 samples (4 waves)
- * select the shared-tile launch: each wave holds 32 rows and the workgroup
- * stages every model tile once in LDS (for problems with many rollouts).
- * PI_VARIANT_MFMA_F16X2 (the same rollouts, shared-tile launch only: tiles
- * of 33..128 samples, 128 by default, 4 or 8 waves, 8 by default, never
- * split) runs it on the fp16 matrix instructions: each model's coefficients
- * and each sample row's features are scaled by powers of two that keep them
+ * to within float32 rounding.  With it, tiles of 33..128 samples select the
+ * shared-tile launch: 128 rows, 16 per wave on 8 waves or 32 on 4, and the
+ * workgroup stages every model tile once in LDS (for problems with many
+ * rollouts).  PI_VARIANT_MFMA_F16X2 (the same rollouts and launch shapes)
+ * runs it on the fp16 matrix instructions: each model's coefficients and
+ * each sample row's features are scaled by powers of two that keep them
  * below 2^14, every scaled value is the sum of two fp16 pieces (hi, lo; lo
  * may be subnormal) and the three piece products hi hi, hi lo, lo hi are
  * summed in float32, half the products of the bf16 form, to about 2^-22
- * relative per product; the scales are undone exactly in float32.  Neither
- * form has a prediction entry point (lwpr_predict: PI_ERR_UNSUPPORTED).     */
+ * relative per product; the scales are undone exactly in float32.  For
+ * both, tile_samples 0 means the shared tile (128 samples, 8 waves) when
+ * K max(M,1) >= 32768, else the 16-sample tiles.  Neither form has a
+ * prediction entry point (lwpr_predict: PI_ERR_UNSUPPORTED).                */
 enum { PI_VARIANT_AUTO = 0, PI_VARIANT_DIRECT = 1, PI_VARIANT_MFMA = 2, PI_VARIANT_MFMA_BF16X3 = 3,
        PI_VARIANT_MFMA_F16X2 = 4 };
 /* Operations for pi_workspace_bytes. */
@@ -309,10 +310,9 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
  * [T_b][n_u], iter[b] (one uint32), cost[b] [K_b][T_b].  All problems must be
  * PI_F32 and PI_DYN_QUAD12 with matrix-core models (PI_ERR_UNSUPPORTED
  * otherwise).  A problem's tile_samples (<= 32, or <= 128 when the batch
- * runs the bf16x3 or f16x2 form; 0 = 16, or 128 in the f16x2 form, which
- * needs the largest tile above 32) sets its tile; the variant and tile_waves
- * of problem 0 apply to the batch (8 waves need every tile <= 16, or the
- * largest above 32 in the pieces forms).
+ * runs the bf16x3 or f16x2 form; 0 = 16, or 128 in the f16x2 form) sets
+ * its tile; the variant and tile_waves of problem 0 apply to the batch (8
+ * waves need every tile <= 16, or the largest above 32 in the pieces forms).
  * Models given pre-folded (pi_lwpr.folded) are read in place; the others are
  * folded into the workspace on every call.  The launch plan (descriptors and
  * work list) is written into the workspace by kernels on `stream`, so these

@@ -240,20 +240,23 @@ struct RolloutPlan {
 };
 
 constexpr int64_t kMaxPairGroups = 2048;
+constexpr int64_t kSharedTileMinSamples = 128 * 256;
 
 RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
   RolloutPlan r;
   r.pf = variant_pf(p->variant);
   r.mfma = p->variant == PI_VARIANT_MFMA || r.pf != kPfF32 || (p->variant == PI_VARIANT_AUTO && mfma_model_ok(m));
   r.bf = r.pf != kPfF32;
-  const bool hf = r.pf == kPfF16x2;   // the fp16 form: shared-tile launch only (128 rows, 8 waves by default)
   const int64_t n = (int64_t)p->K * (p->M > 0 ? p->M : 1);
-  r.waves = p->tile_waves > 0 ? p->tile_waves : hf ? 8 : 4;
-  const bool split_allowed = r.mfma && !hf && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
+  // the pieces forms' default for problems that fill a 256-unit device with
+  // 128-sample tiles: the shared-tile launch on 8 waves
+  const bool shared = r.bf && p->tile_samples == 0 && n >= (int64_t)kSharedTileMinSamples;
+  r.waves = p->tile_waves > 0 ? p->tile_waves : shared ? 8 : 4;
+  const bool split_allowed = r.mfma && (r.waves == 4 || (r.waves == 8 && p->dyn == PI_DYN_QUAD12)) &&
                              p->tile_split != 1 && p->dtype == PI_F32;
   if (p->tile_samples > 0) {
     r.spw = p->tile_samples;
-  } else if (hf) {
+  } else if (shared) {
     r.spw = 128;
   } else if (split_allowed) {
     r.spw = 16;   // full 16-row tiles; small problems are spread by pairing
@@ -267,20 +270,16 @@ RolloutPlan rollout_plan(const pi_problem *p, const pi_lwpr *m) {
 }
 
 // The pieces forms' requirements (rollouts): the float32 12-state quadrotor
-// with d = 16 pieces under 2 GiB; the bf16x3 form on 8 waves takes tiles of at
-// most 16 or more than 32 samples, the f16x2 form tiles of 33..128 samples
-// (its shared-tile launch), never split.
+// with d = 16 pieces under 2 GiB; on 8 waves, tiles of at most 16 or more
+// than 32 samples.
 pi_status check_pieces(const pi_problem *p, const pi_lwpr *m, const RolloutPlan &pl) {
   if (!pl.bf) return PI_OK;
   if (p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m))
     return fail(PI_ERR_UNSUPPORTED, "the %s contraction needs the float32 12-state quadrotor (d = 16) and pieces "
                                     "under 2 GiB", pl.pf == kPfF16x2 ? "f16x2" : "bf16x3");
-  if (pl.pf == kPfBf16x3 && pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)
-    return fail(PI_ERR_UNSUPPORTED, "the bf16x3 contraction on 8 waves takes tiles of at most 16 or more than 32 "
-                                    "samples");
-  if (pl.pf == kPfF16x2 && (pl.spw <= 32 || p->tile_split == 2))
-    return fail(PI_ERR_UNSUPPORTED, "the f16x2 contraction runs the shared-tile launch: tile_samples 33..128, "
-                                    "tile_split 0 or 1");
+  if (pl.spw > 16 && pl.spw <= 32 && p->tile_waves == 8)
+    return fail(PI_ERR_UNSUPPORTED, "the %s contraction on 8 waves takes tiles of at most 16 or more than 32 "
+                                    "samples", pl.pf == kPfF16x2 ? "f16x2" : "bf16x3");
   return PI_OK;
 }
 
@@ -302,14 +301,16 @@ bool use_pair(const pi_problem *p, const RolloutPlan &pl) {
   const int n_cu = device_cus(&dev);
   if (n_cu == 0) return false;
   static std::mutex mu;
-  static int per_cu[kMaxDevices][6];  // resident pair workgroups per compute unit, +1 (0 = unknown)
+  // resident pair workgroups per compute unit, +1 (0 = unknown), by kernel:
+  // point mass 0, hybrid 3, quadrotor 1 + (8 waves) + 3 pf (1..2, 4..5, 7..8)
+  static int per_cu[kMaxDevices][9];
   if (dev < 0 || dev >= kMaxDevices) return false;
-  const int di = p->dyn == PI_DYN_QUAD12 ? (pl.waves == 8 ? 2 : 1) + (pl.bf ? 3 : 0)
+  const int di = p->dyn == PI_DYN_QUAD12 ? (pl.waves == 8 ? 2 : 1) + 3 * pl.pf
                                          : (p->dyn == PI_DYN_QUAD_HYBRID ? 3 : 0);
   int cap;
   {
     std::lock_guard<std::mutex> lk(mu);
-    if (per_cu[dev][di] == 0) per_cu[dev][di] = pair_blocks_per_cu(p->dyn, pl.waves, pl.bf) + 1;
+    if (per_cu[dev][di] == 0) per_cu[dev][di] = pair_blocks_per_cu(p->dyn, pl.waves, pl.pf) + 1;
     cap = per_cu[dev][di] - 1;
   }
   const bool resident = (int64_t)pair_grid(pl.groups) <= (int64_t)cap * n_cu;
@@ -507,8 +508,6 @@ pi_status batch_layout(int32_t B, const pi_problem *p, const pi_lwpr *m, BatchLa
   // tiles of 33..128 samples: the pieces forms' shared-tile launch
   if (L.max_spw > (L.bf ? 128 : 32))
     return fail(PI_ERR_UNSUPPORTED, "batched launches take tile_samples <= 32 (<= 128 with the pieces forms)");
-  if (L.pf == kPfF16x2 && L.max_spw <= 32)
-    return fail(PI_ERR_UNSUPPORTED, "the f16x2 form runs the shared-tile launch: tile_samples 33..128");
   if (L.waves == 8 && L.max_spw > 16 && L.max_spw <= 32)
     return fail(PI_ERR_UNSUPPORTED, "tile_waves 8 needs tile_samples <= 16 (or > 32 with the pieces forms)");
   if (L.bf) {
@@ -648,7 +647,7 @@ hipError_t run_rollout(const pi_problem *p, const pi_lwpr *m, const void *x0, co
         const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
         const RolloutLaunch rl = rollout_launch(p, m);
         if (rl.pair)
-          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, rl.pl.bf, (char *)ws + fb + sub_bytes(p), s);
+          e = launch_rollout_pair(ra, l, base, rl.pl.spw, rl.pl.waves, rl.pl.pf, (char *)ws + fb + sub_bytes(p), s);
         else
           e = launch_rollout_mfma(ra, a, l, base, rl.pl.spw, rl.pl.waves, rl.pl.pf, s);
       } else {

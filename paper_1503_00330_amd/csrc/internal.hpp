@@ -154,8 +154,7 @@ struct RolloutArgs {
 hipError_t launch_rollout_direct(int dtype, const void *rargs, const ModelArgs &m,
                                  const void *rec, hipStream_t s);
 // pf: the contraction's piece format (0 float32 products, 1 three bf16
-// pieces, 2 two fp16 pieces: d = 16 quadrotor, a layout with the pieces; the
-// fp16 form only on tiles of 33..128 samples).
+// pieces, 2 two fp16 pieces: d = 16 quadrotor, a layout with the pieces).
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m,
                                const MfmaLayout &l, const void *base, int tile_samples,
                                int waves, int pf, hipStream_t s);
@@ -200,9 +199,9 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // Paired-workgroup rollout (MFMA, 16 rows per pair of workgroups).
 size_t pair_ws_bytes(int64_t n_groups);
 int pair_grid(int64_t n_groups);
-int pair_blocks_per_cu(int dyn, int waves, bool bf);
+int pair_blocks_per_cu(int dyn, int waves, int pf);
 hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
-                               int waves, bool bf, void *pair_ws, hipStream_t s);
+                               int waves, int pf, void *pair_ws, hipStream_t s);
 // The device's count of paired workgroups that gave up a wait, to out[0].
 hipError_t launch_read_give_ups(uint64_t *out, hipStream_t s);
 

@@ -326,7 +326,6 @@ struct MixSmem {
   static constexpr bool SH = BF && MT > 2;
   static_assert(!BF || (D == kBfD && (MT <= 2 || (MT % NW == 0 && MT / NW <= 2))),
                 "the pieces forms cover d = 16, one or two row tiles per wave");
-  static_assert(PF != kPfF16x2 || SH, "the fp16 form runs the shared-tile launch only");
   static constexpr int NPC = PF == kPfF16x2 ? 2 : 3;   // pieces per value
   static constexpr int ROWS = 16 * MT;
   static constexpr int NFRAG = BF ? kBfNKB * NPC : Geo<D>::KB4;   // 16-byte fragments per lane and row tile
@@ -348,6 +347,25 @@ struct MixSmem {
   int redo[2];                           // second-pass requests, by evaluation parity
   int pair_fail;                         // a partner wait ran out (results invalid)
 };
+
+// fp16 form: the exponent e >= 0 of the power of two 2^-e that scales every
+// feature of sample row `row` (products of two entries of [z, 1]) and its
+// anchors below 2^14 in magnitude; the fragment build, the anchors and the
+// epilogue all take it from here, so they agree.
+template <int D, int MT, int NW, int PF>
+__device__ __forceinline__ int row_scale_exp(const MixSmem<D, MT, NW, PF> &sm, int row) {
+  float mx = 1.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float za = fabsf(sm.z[row][a]);
+    mx = fmaxf(mx, fmaxf(za, za * za));
+  }
+#pragma unroll
+  for (int o = 0; o < kMaxOut; ++o) mx = fmaxf(mx, fmaxf(fabsf(sm.mref[row][o]), fabsf(sm.yref[row][o])));
+  int ex = 0;
+  frexpf(mx, &ex);   // mx < 2^ex
+  return ex > 14 ? ex - 14 : 0;
+}
 
 // Fragment entry e = ((kb4 * 64 + lane) * 4 + comp) of row tile mt holds
 // feature f = 4 (4 kb4 + comp) + lane/16 of row 16 mt + lane%16; every feature
@@ -409,25 +427,34 @@ __device__ __forceinline__ void build_fragments(MixSmem<D, MT, NW, PF> &sm) {
     return;   // built in registers by mixture_tiles_sh
   } else if constexpr (MixSmem<D, MT, NW, PF>::BF) {
     // one (block, lane group, row) per thread: the group's 8 features of the
-    // row, each split into three bf16 pieces, one 16-byte store per piece
+    // row, each split into its pieces (three bf16, or two fp16 of the value
+    // scaled by the row's power of two), one 16-byte store per piece
+    constexpr int NPC = MixSmem<D, MT, NW, PF>::NPC;
     constexpr int NWORK = MT * kBfNKB * 4 * 16;
     u32x4 *Ab = (u32x4 *)&sm.A[0][0][0];
     for (int w = threadIdx.x; w < NWORK; w += NW * 64) {
       const int r16 = w & 15, grp = (w >> 4) & 3, kb = (w >> 6) % kBfNKB, mt = (w >> 6) / kBfNKB;
       const int row = 16 * mt + r16;
-      uint32_t pk[3][4];
+      const float rsi = PF == kPfF16x2 ? ldexpf(1.0f, -row_scale_exp(sm, row)) : 1.0f;
+      uint32_t pk[NPC][4];
 #pragma unroll
       for (int i = 0; i < 8; i += 2) {
         uint16_t lo[3], hi[3];
         const unsigned s0 = sm.fsrc[32 * kb + 8 * grp + i], s1 = sm.fsrc[32 * kb + 8 * grp + i + 1];
-        bf16_split3(sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], lo);
-        bf16_split3(sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF], hi);
+        const float v0 = sm.z[row][s0 >> 8] * sm.z[row][s0 & 0xFF], v1 = sm.z[row][s1 >> 8] * sm.z[row][s1 & 0xFF];
+        if constexpr (PF == kPfF16x2) {
+          f16_split2(v0 * rsi, lo);
+          f16_split2(v1 * rsi, hi);
+        } else {
+          bf16_split3(v0, lo);
+          bf16_split3(v1, hi);
+        }
 #pragma unroll
-        for (int p = 0; p < 3; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
+        for (int p = 0; p < NPC; ++p) pk[p][i / 2] = (uint32_t)lo[p] | ((uint32_t)hi[p] << 16);
       }
 #pragma unroll
-      for (int p = 0; p < 3; ++p)
-        Ab[((mt * kBfNKB + kb) * 3 + p) * 64 + 16 * grp + r16] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
+      for (int p = 0; p < NPC; ++p)
+        Ab[((mt * kBfNKB + kb) * NPC + p) * 64 + 16 * grp + r16] = u32x4{pk[p][0], pk[p][1], pk[p][2], pk[p][3]};
     }
   } else {
     float *Af = (float *)&sm.A[0][0][0];
@@ -467,6 +494,7 @@ __device__ __forceinline__ void clear_parts(MixSmem<D, MT, NW, PF> &sm) {
 // sm.part[wave][o][row].
 template <int D, int MT, int NW, int PF>
 __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
+  static_assert(PF == kPfF32, "float32 products: the pieces forms have their own tile loops");
   using G = Geo<D>;
   constexpr int KQS = G::FQS / 4, GQS = G::FQS % 4;   // kblock / lane group of the anchors
   constexpr int KYS = G::FYS / 4, GYS = G::FYS % 4;
@@ -650,17 +678,21 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // tile ahead).  The softmax epilogue and the flush are the float32 form's.
 template <int D, int MT, int NW, int PF>
 __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
-  static_assert(PF == kPfBf16x3 && D == kBfD && (MT == 1 || MT == 2), "bf16 form: d = 16, one or two row tiles");
+  static_assert(PF != kPfF32 && D == kBfD && (MT == 1 || MT == 2), "pieces forms: d = 16, one or two row tiles");
   using G = Geo<D>;
+  constexpr bool HF = PF == kPfF16x2;   // two fp16 pieces (else three bf16 pieces)
+  constexpr int NPC = MixSmem<D, MT, NW, PF>::NPC;
+  // bytes of per-model values per tile: sigma^2, or (fp16 form) sigma^2 and the two scales
+  constexpr int kMetaBytes = HF ? kHfMeta * 4 : 16 * 4;
   // the activation anchor and the prediction reference: block, lane group, element
   constexpr int FQ = G::NP + D + 1, KQA = FQ / 32, GQA = (FQ % 32) / 8, IQA = FQ % 8;
   constexpr int FY = D + 1, KYA = kBfNKQ + FY / 32, GYA = (FY % 32) / 8, IYA = FY % 8;
-  constexpr int kTileBytes = kBfNKB * 3 * 1024;
+  constexpr int kTileBytes = kBfNKB * NPC * 1024;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t0 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)wave * (T1 - T0) / NW));
   const int t1 = __builtin_amdgcn_readfirstlane(T0 + (int)((int64_t)(wave + 1) * (T1 - T0) / NW));
   if (t0 >= t1) return;
-  u32x4 Bs[MT][kBfNKB][3];
+  u32x4 Bs[MT][kBfNKB][NPC];
   {
     const u32x4 *Ab = (const u32x4 *)&sm.A[0][0][0];
 #pragma unroll
@@ -668,7 +700,19 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
 #pragma unroll
       for (int kb = 0; kb < kBfNKB; ++kb)
 #pragma unroll
-        for (int p = 0; p < 3; ++p) Bs[mt][kb][p] = Ab[((mt * kBfNKB + kb) * 3 + p) * 64 + lane];
+        for (int p = 0; p < NPC; ++p) Bs[mt][kb][p] = Ab[((mt * kBfNKB + kb) * NPC + p) * 64 + lane];
+  }
+  // fp16 form: the lane's rows' powers of two (as in the fragment build)
+  float rsc[MT], rsi[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    rsc[mt] = 1.0f;
+    rsi[mt] = 1.0f;
+    if constexpr (HF) {
+      const int e = row_scale_exp(sm, 16 * mt + (lane & 15));
+      rsc[mt] = ldexpf(1.0f, e);
+      rsi[mt] = ldexpf(1.0f, -e);
+    }
   }
   auto output_of = [&](int tile) {
     int oo = 0;
@@ -686,12 +730,15 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
     return nb;
   };
   // element I of the three pieces (blocks of 8 bf16) takes the pieces of x
-  auto put = [&](u32x4 (&v)[3], auto I, float x) {
+  auto put = [&](u32x4 (&v)[NPC], auto I, float x, int mt) {
     constexpr int i = decltype(I)::value;
     uint16_t pc[3];
-    bf16_split3(x, pc);
+    if constexpr (HF)
+      f16_split2(x * rsi[mt], pc);
+    else
+      bf16_split3(x, pc);
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < NPC; ++p) {
       uint32_t w = v[p][i / 2];
       w = (i & 1) ? ((w & 0x0000FFFFu) | ((uint32_t)pc[p] << 16)) : ((w & 0xFFFF0000u) | pc[p]);
       v[p][i / 2] = w;
@@ -703,8 +750,8 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = 16 * mt + (lane & 15);
-      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo]);
-      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo]);
+      if ((lane >> 4) == GQA) put(Bs[mt][KQA], std::integral_constant<int, IQA>{}, -sm.mref[row][oo], mt);
+      if ((lane >> 4) == GYA) put(Bs[mt][KYA], std::integral_constant<int, IYA>{}, -sm.yref[row][oo], mt);
     }
   };
   set_anchor(o);
@@ -730,29 +777,37 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
       for (int i = 0; i < 4; ++i) st[mt][i] = acc_empty();
     }
   };
-  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(md.Wb, md.n_tiles * kTileBytes);
-  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(md.sig2, md.n_tiles * 16 * 4);
+  const __amdgpu_buffer_rsrc_t wrs = buffer_rsrc(HF ? (const void *)md.Wh : (const void *)md.Wb,
+                                                 md.n_tiles * kTileBytes);
+  const __amdgpu_buffer_rsrc_t srs = buffer_rsrc(HF ? md.hmeta : md.sig2, md.n_tiles * kMetaBytes);
   const int lane_off = lane * 16, grp_off = 16 * (lane >> 4);
-  u32x4 W[kBfNKB][3];
+  u32x4 W[kBfNKB][NPC];
   auto load_blk = [&](int tile, int kb) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-      W[kb][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, lane_off,
-                                                                                tile * kTileBytes + (kb * 3 + p) * 1024, 0));
+    for (int p = 0; p < NPC; ++p)
+      W[kb][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               wrs, lane_off, tile * kTileBytes + (kb * NPC + p) * 1024, 0));
   };
   auto mm = [&](const u32x4 &a, const u32x4 &b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
-                                                   0, 0);
+    if constexpr (HF)
+      return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                    0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                     0, 0, 0);
   };
-  // the six piece pairs hh, hm, mh, hl, mm, lh of block kb of row tile mt into
-  // one accumulator (the pipe takes a dependent product at full rate)
+  // the piece pairs of block kb of row tile mt into one accumulator (the pipe
+  // takes a dependent product at full rate): bf16 hh, hm, mh, hl, mm, lh;
+  // fp16 hh, hl, lh
   auto block6 = [&](int mt, int kb, f32x4 &x) {
     x = mm(W[kb][0], Bs[mt][kb][0], x);
     x = mm(W[kb][0], Bs[mt][kb][1], x);
     x = mm(W[kb][1], Bs[mt][kb][0], x);
-    x = mm(W[kb][0], Bs[mt][kb][2], x);
-    x = mm(W[kb][1], Bs[mt][kb][1], x);
-    x = mm(W[kb][2], Bs[mt][kb][0], x);
+    if constexpr (!HF) {
+      x = mm(W[kb][0], Bs[mt][kb][2], x);
+      x = mm(W[kb][1], Bs[mt][kb][1], x);
+      x = mm(W[kb][2], Bs[mt][kb][0], x);
+    }
   };
   // With two row tiles (one wave per SIMD, nothing else to overlap with) two
   // accumulator sets take turns: while the matrix cores take tile i into one,
@@ -763,7 +818,8 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
   // one row tile two waves per SIMD overlap instead, and the epilogue follows
   // the products.
   constexpr bool PIPE = MT == 2;
-  f32x4 qa[2][MT], ya[2][MT], s2[2];
+  // per accumulator set: sigma^2 of the tile's models and (fp16 form) their scales
+  f32x4 qa[2][MT], ya[2][MT], s2[2], qsc[2], ysc[2];
   auto clear_pending = [&](auto PI) {
     constexpr int p = decltype(PI)::value;
 #pragma unroll
@@ -772,10 +828,14 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
       ya[p][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     s2[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+    qsc[p] = f32x4{1.f, 1.f, 1.f, 1.f};
+    ysc[p] = qsc[p];
   };
   auto epi = [&](auto PI, int mt, int i) {
     constexpr int p = decltype(PI)::value;
-    const float a = qa[p][mt][i], dd = ya[p][mt][i];
+    // fp16 form: the model's and the row's powers of two undone (exact)
+    const float a = HF ? qa[p][mt][i] * (qsc[p][i] * rsc[mt]) : qa[p][mt][i];
+    const float dd = HF ? ya[p][mt][i] * (ysc[p][i] * rsc[mt]) : ya[p][mt][i];
     // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
     // largest term of at least 2^-100) need none of exp2f's denormal scaling
     const float e = __builtin_amdgcn_exp2f(a);
@@ -810,7 +870,12 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
     // prefetches are unconditional (the last tile re-reads itself) so that
     // every wait counts a fixed number of loads
     const int tn = min(tile + 1, t1 - 1);
-    const f32x4 s2n = buffer_f32x4(srs, grp_off, tn * 64);
+    const f32x4 s2n = buffer_f32x4(srs, grp_off, tn * kMetaBytes);
+    f32x4 qsn, ysn;
+    if constexpr (HF) {
+      qsn = buffer_f32x4(srs, grp_off + 64, tn * kMetaBytes);
+      ysn = buffer_f32x4(srs, grp_off + 128, tn * kMetaBytes);
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       qa[c][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -830,16 +895,20 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
       load_blk(tn, kb);
       if constexpr (PIPE) {
 #pragma unroll
-        for (int j = 0; j < 6 * MT; ++j) {
+        for (int j = 0; j < (HF ? 3 : 6) * MT; ++j) {
           __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
           __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two vector ALU ops
         }
-        __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);    // the three piece loads
+        __builtin_amdgcn_sched_group_barrier(0x020, NPC, 0);  // the piece loads
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (!PIPE) epi_all(CI);
     s2[p] = s2n;
+    if constexpr (HF) {
+      qsc[p] = qsn;
+      ysc[p] = ysn;
+    }
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -852,7 +921,11 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
     load_blk(t0, kb);
     __builtin_amdgcn_sched_barrier(0);
   }
-  s2[0] = buffer_f32x4(srs, grp_off, t0 * 64);
+  s2[0] = buffer_f32x4(srs, grp_off, t0 * kMetaBytes);
+  if constexpr (HF) {
+    qsc[0] = buffer_f32x4(srs, grp_off + 64, t0 * kMetaBytes);
+    ysc[0] = buffer_f32x4(srs, grp_off + 128, t0 * kMetaBytes);
+  }
   if constexpr (PIPE) {
     clear_pending(I1{});
     int tile = t0;
@@ -948,18 +1021,7 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
     rsc[mt] = 1.0f;
     rsi[mt] = 1.0f;
     if constexpr (HF) {
-      const int row = RW * wave + 16 * mt + (lane & 15);
-      float mx = 1.0f;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const float za = fabsf(sm.z[row][a]);
-        mx = fmaxf(mx, fmaxf(za, za * za));
-      }
-#pragma unroll
-      for (int oo = 0; oo < kMaxOut; ++oo) mx = fmaxf(mx, fmaxf(fabsf(sm.mref[row][oo]), fabsf(sm.yref[row][oo])));
-      int ex = 0;
-      frexpf(mx, &ex);   // mx < 2^ex
-      const int e = ex > 14 ? ex - 14 : 0;
+      const int e = row_scale_exp(sm, RW * wave + 16 * mt + (lane & 15));
       rsc[mt] = ldexpf(1.0f, e);
       rsi[mt] = ldexpf(1.0f, -e);
     }
@@ -1333,7 +1395,7 @@ __device__ __forceinline__ void mixture_step(const MfmaModel &md, MixSmem<D, MT,
     __syncthreads();
     if constexpr (MixSmem<D, MT, NW, PF>::SH)
       mixture_tiles_sh(md, sm, T0, T1);
-    else if constexpr (PF == kPfBf16x3)
+    else if constexpr (PF != kPfF32)
       mixture_tiles_bf(md, sm, T0, T1);
     else
       mixture_tiles(md, sm, T0, T1);
@@ -1732,24 +1794,30 @@ static hipError_t rollout_mfma_t(const RolloutArgs<float> &ra, const MfmaModel &
   return hipGetLastError();
 }
 
+// A pieces form's plain launch: the shared tile for tiles of 33..128 rows (128
+// rows, two row tiles on each of 4 waves or one on each of 8), else one or two
+// 16-row tiles per wave.
+template <int PF>
+static hipError_t rollout_pieces_t(const RolloutArgs<float> &ra, const MfmaModel &md, int spw, int waves,
+                                   hipStream_t s) {
+  if (spw > 32)
+    return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, PF>(ra, md, spw, s)
+                      : rollout_mfma_t<kDynQuad12, 8, 4, PF>(ra, md, spw, s);
+  if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, PF>(ra, md, spw, s);
+  if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, PF>(ra, md, spw, s);
+  return rollout_mfma_t<kDynQuad12, 2, 4, PF>(ra, md, spw, s);
+}
+
 hipError_t launch_rollout_mfma(const RolloutArgs<float> &ra, const ModelArgs &m, const MfmaLayout &l,
                                const void *base, int tile_samples, int waves, int pf, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
   const int spw = tile_samples;
-  if (pf == kPfF16x2) {   // shared-tile launch only
-    if (ra.p.dyn != kDynQuad12 || md.Wh == nullptr || spw <= 32 || spw > 128) return hipErrorInvalidValue;
-    return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, kPfF16x2>(ra, md, spw, s)
-                      : rollout_mfma_t<kDynQuad12, 8, 4, kPfF16x2>(ra, md, spw, s);
-  }
-  if (pf == kPfBf16x3) {
-    if (ra.p.dyn != kDynQuad12 || md.Wb == nullptr || (waves == 8 && spw > 16 && spw <= 32) || spw > 128)
+  if (pf != kPfF32) {
+    if (ra.p.dyn != kDynQuad12 || (pf == kPfF16x2 ? md.Wh : md.Wb) == nullptr ||
+        (waves == 8 && spw > 16 && spw <= 32) || spw > 128)
       return hipErrorInvalidValue;
-    if (spw > 32)   // shared-tile form: 128 rows, two row tiles on each of 4 waves or one on each of 8
-      return waves == 8 ? rollout_mfma_t<kDynQuad12, 8, 8, kPfBf16x3>(ra, md, spw, s)
-                        : rollout_mfma_t<kDynQuad12, 8, 4, kPfBf16x3>(ra, md, spw, s);
-    if (waves == 8) return rollout_mfma_t<kDynQuad12, 1, 8, kPfBf16x3>(ra, md, spw, s);
-    if (spw <= 16) return rollout_mfma_t<kDynQuad12, 1, 4, kPfBf16x3>(ra, md, spw, s);
-    return rollout_mfma_t<kDynQuad12, 2, 4, kPfBf16x3>(ra, md, spw, s);
+    return pf == kPfF16x2 ? rollout_pieces_t<kPfF16x2>(ra, md, spw, waves, s)
+                          : rollout_pieces_t<kPfBf16x3>(ra, md, spw, waves, s);
   }
   if (ra.p.dyn == kDynQuad12) {
     if (waves == 8) {
@@ -1771,10 +1839,13 @@ size_t pair_ws_bytes(int64_t n_groups) { return align_up((size_t)n_groups * kPai
 
 int pair_grid(int64_t n_groups) { return (int)(16 * ((n_groups + 7) / 8)); }
 
-int pair_blocks_per_cu(int dyn, int waves, bool bf) {
+int pair_blocks_per_cu(int dyn, int waves, int pf) {
   int nb = 0;
   hipError_t e;
-  if (dyn == kDynQuad12 && bf)
+  if (dyn == kDynQuad12 && pf == kPfF16x2)
+    e = waves == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, kPfF16x2>, 512, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, kPfF16x2>, 256, 0);
+  else if (dyn == kDynQuad12 && pf == kPfBf16x3)
     e = waves == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 8, kPfBf16x3>, 512, 0)
                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rollout_pair_kernel<kDynQuad12, 4, kPfBf16x3>, 256, 0);
   else if (dyn == kDynQuad12 && waves == 8)
@@ -1789,9 +1860,10 @@ int pair_blocks_per_cu(int dyn, int waves, bool bf) {
 }
 
 hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l, const void *base, int spw,
-                               int waves, bool bf, void *pair_ws, hipStream_t s) {
+                               int waves, int pf, void *pair_ws, hipStream_t s) {
   const MfmaModel md = mfma_view(l, base);
-  if (bf && (ra.p.dyn != kDynQuad12 || md.Wb == nullptr)) return hipErrorInvalidValue;
+  if (pf != kPfF32 && (ra.p.dyn != kDynQuad12 || (pf == kPfF16x2 ? md.Wh : md.Wb) == nullptr))
+    return hipErrorInvalidValue;
   const int64_t n = (int64_t)ra.p.K * ra.p.Ms;
   const int64_t n_groups = (n + spw - 1) / spw;
   uint64_t *xbuf = (uint64_t *)pair_ws;
@@ -1802,7 +1874,14 @@ hipError_t launch_rollout_pair(const RolloutArgs<float> &ra, const MfmaLayout &l
   uint32_t spin = kSpinLimit;
   if (const char *env = getenv("PI2RH_PAIR_SPIN_LIMIT")) spin = (uint32_t)strtoul(env, nullptr, 10);
   const dim3 grid((unsigned)pair_grid(n_groups));
-  if (ra.p.dyn == kDynQuad12 && bf) {
+  if (pf == kPfF16x2) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, kPfF16x2>), grid, dim3(512), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
+    else
+      hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 4, kPfF16x2>), grid, dim3(256), 0, s, ra, md, spw,
+                         (int)n_groups, xbuf, spin);
+  } else if (pf == kPfBf16x3) {
     if (waves == 8)
       hipLaunchKernelGGL((rollout_pair_kernel<kDynQuad12, 8, kPfBf16x3>), grid, dim3(512), 0, s, ra, md, spw,
                          (int)n_groups, xbuf, spin);
@@ -1839,35 +1918,38 @@ hipError_t launch_batched_describe(const BatchedProblem &bp, BatchedProblem *pro
   return hipGetLastError();
 }
 
+// A pieces form's batched launch (tile shape as in rollout_pieces_t).
+template <int PF>
+static void batched_pieces_t(const BatchedProblem *probs, const BatchedItem *items, int n_items, int max_spw,
+                             int waves, int grid, int *queue, hipStream_t s) {
+  if (max_spw > 32) {
+    if (waves == 8)
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, PF>), dim3(grid), dim3(512), 0, s, probs, items,
+                         n_items, queue);
+    else
+      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, PF>), dim3(grid), dim3(256), 0, s, probs, items,
+                         n_items, queue);
+  } else if (waves == 8) {
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, PF>), dim3(grid), dim3(512), 0, s, probs, items,
+                       n_items, queue);
+  } else if (max_spw <= 16) {
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, PF>), dim3(grid), dim3(256), 0, s, probs, items,
+                       n_items, queue);
+  } else {
+    hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, PF>), dim3(grid), dim3(256), 0, s, probs, items,
+                       n_items, queue);
+  }
+}
+
 hipError_t launch_rollout_batched(const BatchedProblem *probs, const BatchedItem *items, int n_items,
                                   int max_spw, int waves, int pf, int grid, int *queue, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  if (pf == kPfF16x2) {   // shared-tile launch only
-    if (max_spw <= 32 || max_spw > 128) return hipErrorInvalidValue;
-    if (waves == 8)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, kPfF16x2>), dim3(grid), dim3(512), 0, s, probs,
-                         items, n_items, queue);
-    else
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, kPfF16x2>), dim3(grid), dim3(256), 0, s, probs,
-                         items, n_items, queue);
-  } else if (pf == kPfBf16x3) {
+  if (pf != kPfF32) {
     if ((waves == 8 && max_spw > 16 && max_spw <= 32) || max_spw > 128) return hipErrorInvalidValue;
-    if (max_spw > 32) {   // shared-tile form: 128 rows per workgroup
-      if (waves == 8)
-        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 8, kPfBf16x3>), dim3(grid), dim3(512), 0, s, probs,
-                           items, n_items, queue);
-      else
-        hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 8, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
-                           items, n_items, queue);
-    } else if (waves == 8)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, kPfBf16x3>), dim3(grid), dim3(512), 0, s, probs,
-                         items, n_items, queue);
-    else if (max_spw <= 16)
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
-                         items, n_items, queue);
+    if (pf == kPfF16x2)
+      batched_pieces_t<kPfF16x2>(probs, items, n_items, max_spw, waves, grid, queue, s);
     else
-      hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 2, 4, kPfBf16x3>), dim3(grid), dim3(256), 0, s, probs,
-                         items, n_items, queue);
+      batched_pieces_t<kPfBf16x3>(probs, items, n_items, max_spw, waves, grid, queue, s);
   } else if (max_spw <= 16) {
     if (waves == 8)
       hipLaunchKernelGGL((rollout_batched_kernel<kDynQuad12, 1, 8, kPfF32>), dim3(grid), dim3(512), 0, s, probs,

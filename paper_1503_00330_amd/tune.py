@@ -30,12 +30,12 @@ _MF, _BF, _HF = 2, 3, 4
 _SHAPES = ((16, 4, 1), (16, 8, 1), (8, 4, 1), (8, 8, 1), (32, 4, 1), (16, 4, 2), (16, 8, 2))
 _BATCH_SHAPES = ((16, 4), (8, 4), (32, 4), (16, 8), (8, 8))
 # (samples per tile, waves per workgroup, workgroups per tile, contraction);
-# 128-sample tiles are the pieces forms' shared-tile launch (the fp16 form has
-# no other)
-CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _SHAPES)
+# 128-sample tiles are the pieces forms' shared-tile launch
+CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF, _HF) for s in _SHAPES)
                                                      + tuple((128, w, 1, v) for v in (_BF, _HF) for w in (4, 8)))
 # uniform launches of a batch: (samples per tile, waves per workgroup, contraction)
-BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF) for s in _BATCH_SHAPES)
+BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = (tuple(s + (v,) for v in (_MF, _BF, _HF)
+                                                            for s in _BATCH_SHAPES)
                                                       + tuple((128, w, v) for v in (_BF, _HF) for w in (4, 8)))
 
 
@@ -135,8 +135,6 @@ def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
         if waves == 8 and (prob.dyn != PI_DYN_QUAD12 or 16 < spw <= 32):
             continue
         if split == 2 and (spw > 16 or prob.dtype != torch.float32):
-            continue
-        if v == _HF and (spw <= 32 or split != 1):
             continue
         out.append((spw, waves, split, v))
     return tuple(out)

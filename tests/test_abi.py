@@ -217,11 +217,11 @@ class TestValidation:
         ps.tile_samples = 128
         assert _rollout(ps, ms) == 6 and "device" in pi.last_error()   # valid: only the device is missing
 
-    def test_f16x2_runs_the_shared_tile_only(self):
-        # the two-piece fp16 form: tiles of 33..128 samples, never split
-        for fields, code in ((dict(tile_samples=32), 7), (dict(tile_samples=16, tile_waves=8), 7),
-                             (dict(tile_split=2), 7), (dict(tile_samples=129), 3),
-                             (dict(tile_samples=64, tile_waves=4), 6), (dict(), 6)):
+    def test_f16x2_tile_limits(self):
+        # the two-piece fp16 form: the bf16 form's launch shapes
+        for fields, code in ((dict(tile_samples=32, tile_waves=8), 7), (dict(tile_samples=129), 3),
+                             (dict(tile_samples=32), 6), (dict(tile_samples=16, tile_waves=8), 6),
+                             (dict(tile_split=2), 6), (dict(tile_samples=64, tile_waves=4), 6), (dict(), 6)):
             ps, ms = _structs()
             ps.variant = pi.PI_VARIANT_MFMA_F16X2
             for k, v in fields.items():

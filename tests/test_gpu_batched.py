@@ -44,12 +44,13 @@ def _batch(spw=0, waves=0, variant=0):
 
 
 BF3 = 3   # PI_VARIANT_MFMA_BF16X3: the contraction in three bf16 pieces
-HF2 = 4   # PI_VARIANT_MFMA_F16X2: in two fp16 pieces (the shared-tile launch only)
+HF2 = 4   # PI_VARIANT_MFMA_F16X2: in two fp16 pieces
 
 
 @pytest.mark.parametrize("spw,waves,variant", [(0, 0, 0), (8, 4, 0), (16, 8, 0), (32, 4, 0),
                                                (0, 0, BF3), (16, 8, BF3), (32, 4, BF3), (128, 8, BF3),
-                                               (128, 4, BF3), (0, 0, HF2), (128, 8, HF2), (64, 4, HF2)])
+                                               (128, 4, BF3), (0, 0, HF2), (16, 8, HF2), (32, 4, HF2), (128, 8, HF2),
+                                               (64, 4, HF2)])
 def test_batched_equals_plain_launches(spw, waves, variant):
     host, dps, dms = _batch(spw, waves, variant)
     for dp in dps:
@@ -201,7 +202,7 @@ def test_batched_control_step_full_workload():
 
 def test_batched_refuses_unsupported_tiles():
     # 33..128-row tiles only with the pieces forms (their shared-tile launch),
-    # 8 waves not with 17..32-row tiles, the fp16 form only on the shared tile
+    # and 8 waves not with 17..32-row tiles
     host, dps, dms = _batch(variant=BF3)
     for dp in dps:
         dp.tile_samples, dp.variant = 128, 2
@@ -211,8 +212,4 @@ def test_batched_refuses_unsupported_tiles():
         dp.tile_samples, dp.variant = 32, BF3
     dps[0].tile_waves = 8
     with pytest.raises(pi.PiError, match="tile_waves 8"):
-        pi.BatchedRollout(dps, dms)
-    for dp in dps:
-        dp.tile_samples, dp.tile_waves, dp.variant = 32, 4, HF2
-    with pytest.raises(pi.PiError, match="f16x2 form runs the shared-tile launch"):
         pi.BatchedRollout(dps, dms)

@@ -207,16 +207,16 @@ def test_rollout_fp64_config0_strict():
 # 0 = library's choice, which pairs these small problems, or 2 = forced) or on
 # one (split 1), 8 rows, 32 rows; the same with the products in three bf16
 # pieces (one or two 16-row tiles per wave, and the shared-tile launch of 128
-# or 64 rows on 4 waves, 128 on 8); the shared-tile launch with the products in
-# two fp16 pieces (the library's 128 rows on 8 waves, 128 and 64 on 4); and
-# the direct kernel
+# or 64 rows on 4 waves, 128 on 8); the same launches with the products in two
+# fp16 pieces; and the direct kernel
 BF3 = pi.PI_VARIANT_MFMA_BF16X3
 HF2 = pi.PI_VARIANT_MFMA_F16X2
 ROLLOUT_SHAPES = [(pi.PI_VARIANT_MFMA, 0, 0, 0), (pi.PI_VARIANT_MFMA, 16, 2, 4), (pi.PI_VARIANT_MFMA, 16, 2, 8),
                   (pi.PI_VARIANT_MFMA, 16, 1, 4), (pi.PI_VARIANT_MFMA, 16, 1, 8), (pi.PI_VARIANT_MFMA, 8, 1, 0),
                   (pi.PI_VARIANT_MFMA, 32, 0, 0), (BF3, 0, 0, 0), (BF3, 16, 2, 4), (BF3, 16, 1, 4),
                   (BF3, 16, 1, 8), (BF3, 8, 1, 8), (BF3, 32, 1, 4), (BF3, 128, 1, 4), (BF3, 64, 1, 4), (BF3, 128, 1, 8),
-                  (HF2, 0, 0, 0), (HF2, 128, 1, 4), (HF2, 64, 1, 4),
+                  (HF2, 0, 0, 0), (HF2, 16, 2, 4), (HF2, 16, 1, 8), (HF2, 8, 1, 8), (HF2, 32, 1, 4),
+                  (HF2, 128, 1, 4), (HF2, 64, 1, 4), (HF2, 128, 1, 8),
                   (pi.PI_VARIANT_DIRECT, 0, 0, 0)]
 
 
@@ -234,7 +234,8 @@ def test_rollout_fp32_ragged(shape, M):
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_MFMA, 1, 0), (pi.PI_VARIANT_MFMA, 2, 0),
-                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 0, 0)])
+                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 2, 0), (HF2, 1, 32),
+                                               (HF2, 1, 128)])
 def test_rollout_loadings_differ_from_directions(variant, split, spw):
     # local models whose PLS deflation loadings p differ from the projection
     # directions u (d = 16, matrix-core tiles)
@@ -382,7 +383,8 @@ def config1_oracle():
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 0, 0), (pi.PI_VARIANT_AUTO, 1, 0),
-                                               (BF3, 0, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 0, 0)])
+                                               (BF3, 0, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 0, 0), (HF2, 1, 32),
+                                               (HF2, 1, 128)])
 def test_rollout_config1_full_launch_all_rows(variant, split, spw, config1_oracle):
     # the benchmarked 2048-rollout launch (split 0: 128 tiles of 16 rollouts
     # on 256 paired workgroups) and the one-workgroup-per-tile form, with
@@ -416,7 +418,7 @@ def test_iteration_config1_fp32_end_to_end(variant, config1_oracle):
     assert du <= 1e-4
 
 
-@pytest.mark.parametrize("variant,spw", [(pi.PI_VARIANT_AUTO, 0), (BF3, 32), (BF3, 128), (HF2, 0)])
+@pytest.mark.parametrize("variant,spw", [(pi.PI_VARIANT_AUTO, 0), (BF3, 32), (BF3, 128), (HF2, 0), (HF2, 32)])
 def test_rollout_config2_full_launch_sampled_rows(variant, spw):
     # 65536 rollouts over T = 200 against 6 x 1024 models: 4096 one-workgroup
     # tiles, two workgroups per compute unit (or, bf16 pieces, 2048 tiles of
@@ -501,14 +503,19 @@ def test_bf16x3_describe_and_refusals():
     assert "tile_samples=128 outside [0,32]" in str(e.value)
     d = pi.rollout_describe(pi.DeviceProblem(prob, variant=BF3, tile_samples=128, tile_waves=8), dm)
     assert d["tile_samples"] == 128 and d["tile_waves"] == 8 and d["tile_split"] == 1
-    # the fp16 form: the shared tile, 128 rows on 8 waves unless asked otherwise
+    # the fp16 form: the bf16 form's launches; by default 16-row tiles on
+    # pairs here, the shared tile (128 rows, 8 waves) from 32768 rollouts on
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     d = pi.rollout_describe(pi.DeviceProblem(prob, variant=HF2), dm)
-    assert d == {"variant": "mfma-f16x2", "tile_samples": 128, "tile_waves": 8, "tile_split": 1,
-                 "kernel": "rollout_mfma_kernel"}
-    for kw in (dict(tile_samples=32), dict(tile_split=2)):
-        with pytest.raises(pi.PiError) as e:
-            pi.rollout_describe(pi.DeviceProblem(prob, variant=HF2, **kw), dm)
-        assert e.value.status == 7 and "f16x2" in str(e.value)
+    assert d == {"variant": "mfma-f16x2", "tile_samples": 16, "tile_waves": 8 if n_cu >= 256 else 4,
+                 "tile_split": 2, "kernel": "rollout_pair_kernel"}
+    big, _, _ = synth.config(1, K=32768, T=2)
+    for v in (BF3, HF2):
+        d = pi.rollout_describe(pi.DeviceProblem(big, variant=v), dm)
+        assert (d["tile_samples"], d["tile_waves"], d["tile_split"]) == (128, 8, 1)
+    with pytest.raises(pi.PiError) as e:
+        pi.rollout_describe(pi.DeviceProblem(prob, variant=HF2, tile_samples=32, tile_waves=8), dm)
+    assert e.value.status == 7 and "f16x2" in str(e.value)
     refused = [(pi.DeviceProblem(prob, variant=BF3, tile_samples=32, tile_waves=8, tile_split=1), dm),
                (pi.DeviceProblem(prob, variant=BF3, dtype=torch.float64),
                 pi.DeviceModel(model, dtype=torch.float64))]
@@ -525,7 +532,7 @@ def test_bf16x3_describe_and_refusals():
 
 
 @pytest.mark.parametrize("variant,split,spw", [(pi.PI_VARIANT_AUTO, 1, 0), (pi.PI_VARIANT_AUTO, 2, 0),
-                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 0, 0)])
+                                               (BF3, 2, 0), (BF3, 1, 32), (BF3, 1, 128), (HF2, 2, 0), (HF2, 1, 128)])
 def test_rollout_bitwise_repeatable(variant, split, spw):
     prob, model, _ = synth.config(1, K=512, T=20)
     dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)

@@ -46,11 +46,12 @@ def _prefix_then_nan(got, ref):
     return bad
 
 
-@pytest.mark.parametrize("waves", [4, 8])
-def test_forced_pair_give_up_never_leaves_finite_wrong_costs(waves, monkeypatch):
+@pytest.mark.parametrize("waves,variant", [(4, pi.PI_VARIANT_AUTO), (8, pi.PI_VARIANT_AUTO),
+                                           (4, pi.PI_VARIANT_MFMA_F16X2)])
+def test_forced_pair_give_up_never_leaves_finite_wrong_costs(waves, variant, monkeypatch):
     prob, model, _ = synth.config(1, T=40)
     prob.u_nom = np.random.default_rng(9).normal(0.0, 0.2, prob.u_nom.shape).astype(F32)
-    dp = pi.DeviceProblem(prob, tile_split=2, tile_waves=waves)
+    dp = pi.DeviceProblem(prob, tile_split=2, tile_waves=waves, variant=variant)
     dm = pi.DeviceModel(model).fold()
     assert pi.rollout_describe(dp, dm)["tile_split"] == 2
     ref = pi.rollout_cost(dp, dm).cpu().numpy()

@@ -40,7 +40,8 @@ def test_candidate_space_covers_pairing_waves_and_contraction():
     assert {c[1] for c in tune.CANDIDATES} == {4, 8}
     assert {c[0] for c in tune.CANDIDATES} == {8, 16, 32, 128}
     assert all(c[3] in (3, 4) for c in tune.CANDIDATES if c[0] > 32)   # shared-tile launch: the pieces forms
-    assert all(c[0] == 128 and c[2] == 1 for c in tune.CANDIDATES if c[3] == 4)   # fp16 form: shared tile only
+    # the fp16 form at every launch shape of the bf16 form
+    assert {c[:3] for c in tune.CANDIDATES if c[3] == 4} == {c[:3] for c in tune.CANDIDATES if c[3] == 3}
     assert {c[3] for c in tune.CANDIDATES} == {2, 3, 4}
     assert {c[2] for c in tune.BATCH_CANDIDATES} == {2, 3, 4}
 
@@ -66,7 +67,8 @@ def test_candidates_follow_the_requested_variant():
     assert (128, 4, 1, 3) in q and (128, 8, 1, 3) in q
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 2), _M(16))} == {2}
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 3), _M(16))} == {3}
-    assert tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 4), _M(16)) == ((128, 4, 1, 4), (128, 8, 1, 4))
+    q4 = tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32, 4), _M(16))
+    assert {c[3] for c in q4} == {4} and (16, 8, 2, 4) in q4 and (128, 8, 1, 4) in q4 and (32, 8, 1, 4) not in q4
     # not eligible for the bf16 form: another d, float64, another plant
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float32), _M(8))} == {2}
     assert {c[3] for c in tune.candidates_for(_P(PI_DYN_QUAD12, torch.float64), _M(16))} == {2}
