@@ -644,7 +644,7 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
         st[mt][i].S1 += te;
         st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
         st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
-        st[mt][i].mx = fmaxf(st[mt][i].mx, a);
+        st[mt][0].mx = fmaxf(st[mt][0].mx, a);   // one running max per row
       }
   };
 
@@ -844,7 +844,7 @@ __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D,
     st[mt][i].S1 += te;
     st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
     st[mt][i].S3 = fmaf(e, s2[p][i], st[mt][i].S3);
-    st[mt][i].mx = fmaxf(st[mt][i].mx, a);
+    st[mt][0].mx = fmaxf(st[mt][0].mx, a);   // one running max per row
   };
   auto epi_all = [&](auto PI) {
 #pragma unroll
@@ -1126,103 +1126,115 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
   int nb = next_boundary(T0);
   set_anchor(o);
   const int n_st = (n + 1) / 2;
-  for (int st_i = 0; st_i < n_st; ++st_i) {
-    // this wave's loads of the stage (issued one stage ago) are complete; no
-    // memory access moves across the barrier (compiler fences on both sides)
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt untouched
-    __asm__ __volatile__("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    __asm__ __volatile__("" ::: "memory");
-    if (st_i + 1 < n_st) issue_stage(st_i + 1);
-    const bool two = 2 * st_i + 1 < n;   // the stage holds a second tile
-    // the stage's 12 (or 6) blocks of model pieces go through a ring of three
-    // blocks in registers, each read from LDS two blocks before its products:
-    // with 8 waves reading, an LDS round trip outlasts one block's products
-    u32x4 wb[3][NPC];
-    auto ldb = [&](auto Q) {
-      constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
-      const u32x4(*W)[64] = sm.ring[2 * (st_i & 1) + u];
-#pragma unroll
-      for (int p = 0; p < NPC; ++p) wb[q % 3][p] = W[kb * NPC + p][lane];
-    };
-    ldb(std::integral_constant<int, 0>{});
-    ldb(std::integral_constant<int, 1>{});
-    f32x4 qa[RT], ya[RT], s2, qs, ys;
-    auto step = [&](auto Q) {
-      constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
-      if constexpr (q + 2 < 2 * kBfNKB) {
-        if (q + 2 < kBfNKB || two) ldb(std::integral_constant<int, q + 2>{});
-      }
-      __builtin_amdgcn_sched_barrier(0);   // the reads go out ahead of this block's products
-      if constexpr (kb == 0) {
-        // the two waves of a SIMD (w and w + 4 of 8) take turns leading the
-        // matrix pipe, one tile each per stage: left to age order, the older
-        // wave would finish the stage first and the younger run alone
-        if constexpr (NW == 8) {
-          if ((wave >= 4) == (u == 0))
-            __builtin_amdgcn_s_setprio(1);
-          else
-            __builtin_amdgcn_s_setprio(0);
-        }
-        const int tile = T0 + 2 * st_i + u;
-        if (tile >= nb) {
-          flush(o);
-          o = output_of(tile);
-          nb = next_boundary(tile);
-          set_anchor(o);
-        }
-        const f32x4 *meta = (const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0];
-        s2 = meta[lane >> 4];
-        if constexpr (HF) {   // the models' scales 2^eq, 2^ey
-          qs = meta[4 + (lane >> 4)];
-          ys = meta[8 + (lane >> 4)];
-        }
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt) {
-          qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-          ya[mt] = qa[mt];
-        }
-      }
-      const u32x4 *w = wb[q % 3];
-      // the piece pairs (model, sample) into one accumulator per row tile and
-      // sum (the pipe takes a dependent product at full rate; with two row
-      // tiles the chains alternate): bf16 hh, hm, mh, hl, mm, lh; fp16 hh, hl, lh
-      constexpr int NPR = HF ? 3 : 6;
-      constexpr int PA[6] = {0, 0, 1, 0, 1, 2}, PB[6] = {0, 1, 0, 2, 1, 0};
-#pragma unroll
-      for (int r = 0; r < NPR; ++r)
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt) {
-          f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
-          x = mm(w[PA[r]], Bs[mt][kb][PB[r]], x);
-        }
+  // RS: the wave's rows carry powers of two (fp16 form); without, as for
+  // nearly every state, the epilogue skips their products
+  auto stages = [&](auto RS) {
+    constexpr bool kRowScale = decltype(RS)::value;
+    for (int st_i = 0; st_i < n_st; ++st_i) {
+      // this wave's loads of the stage (issued one stage ago) are complete; no
+      // memory access moves across the barrier (compiler fences on both sides)
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt untouched
+      __asm__ __volatile__("" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (kb == kBfNKB - 1) {
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            // fp16 form: the model's and the row's powers of two undone (exact)
-            const float a = HF ? qa[mt][i] * (qs[i] * rsc[mt]) : qa[mt][i];
-            const float dd = HF ? ya[mt][i] * (ys[i] * rsc[mt]) : ya[mt][i];
-            // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
-            // largest term of at least 2^-100) need none of exp2f's denormal scaling
-            const float e = __builtin_amdgcn_exp2f(a);
-            const float te = e * dd;
-            st[mt][i].Z += e;
-            st[mt][i].S1 += te;
-            st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
-            st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
-            st[mt][i].mx = fmaxf(st[mt][i].mx, a);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      __asm__ __volatile__("" ::: "memory");
+      if (st_i + 1 < n_st) issue_stage(st_i + 1);
+      const bool two = 2 * st_i + 1 < n;   // the stage holds a second tile
+      // the stage's 12 (or 6) blocks of model pieces go through a ring of three
+      // blocks in registers, each read from LDS two blocks before its products:
+      // with 8 waves reading, an LDS round trip outlasts one block's products
+      u32x4 wb[3][NPC];
+      auto ldb = [&](auto Q) {
+        constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
+        const u32x4(*W)[64] = sm.ring[2 * (st_i & 1) + u];
+  #pragma unroll
+        for (int p = 0; p < NPC; ++p) wb[q % 3][p] = W[kb * NPC + p][lane];
+      };
+      ldb(std::integral_constant<int, 0>{});
+      ldb(std::integral_constant<int, 1>{});
+      f32x4 qa[RT], ya[RT], s2, qs, ys;
+      auto step = [&](auto Q) {
+        constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
+        if constexpr (q + 2 < 2 * kBfNKB) {
+          if (q + 2 < kBfNKB || two) ldb(std::integral_constant<int, q + 2>{});
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the reads go out ahead of this block's products
+        if constexpr (kb == 0) {
+          // the two waves of a SIMD (w and w + 4 of 8) take turns leading the
+          // matrix pipe, one tile each per stage: left to age order, the older
+          // wave would finish the stage first and the younger run alone
+          if constexpr (NW == 8) {
+            if ((wave >= 4) == (u == 0))
+              __builtin_amdgcn_s_setprio(1);
+            else
+              __builtin_amdgcn_s_setprio(0);
           }
-      }
-    };
-    static_for<0, kBfNKB>(step);
-    if (two) static_for<kBfNKB, 2 * kBfNKB>(step);
-    if constexpr (NW == 8) __builtin_amdgcn_s_setprio(0);
-  }
+          const int tile = T0 + 2 * st_i + u;
+          if (tile >= nb) {
+            flush(o);
+            o = output_of(tile);
+            nb = next_boundary(tile);
+            set_anchor(o);
+          }
+          const f32x4 *meta = (const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0];
+          s2 = meta[lane >> 4];
+          if constexpr (HF) {   // the models' scales 2^eq, 2^ey
+            qs = meta[4 + (lane >> 4)];
+            ys = meta[8 + (lane >> 4)];
+          }
+  #pragma unroll
+          for (int mt = 0; mt < RT; ++mt) {
+            qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            ya[mt] = qa[mt];
+          }
+        }
+        const u32x4 *w = wb[q % 3];
+        // the piece pairs (model, sample) into one accumulator per row tile and
+        // sum (the pipe takes a dependent product at full rate; with two row
+        // tiles the chains alternate): bf16 hh, hm, mh, hl, mm, lh; fp16 hh, hl, lh
+        constexpr int NPR = HF ? 3 : 6;
+        constexpr int PA[6] = {0, 0, 1, 0, 1, 2}, PB[6] = {0, 1, 0, 2, 1, 0};
+  #pragma unroll
+        for (int r = 0; r < NPR; ++r)
+  #pragma unroll
+          for (int mt = 0; mt < RT; ++mt) {
+            f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
+            x = mm(w[PA[r]], Bs[mt][kb][PB[r]], x);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kb == kBfNKB - 1) {
+  #pragma unroll
+          for (int mt = 0; mt < RT; ++mt)
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              // fp16 form: the model's and the row's powers of two undone (exact)
+              const float a = !HF ? qa[mt][i] : kRowScale ? qa[mt][i] * (qs[i] * rsc[mt]) : qa[mt][i] * qs[i];
+              const float dd = !HF ? ya[mt][i] : kRowScale ? ya[mt][i] * (ys[i] * rsc[mt]) : ya[mt][i] * ys[i];
+              // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+              // largest term of at least 2^-100) need none of exp2f's denormal scaling
+              const float e = __builtin_amdgcn_exp2f(a);
+              const float te = e * dd;
+              st[mt][i].Z += e;
+              st[mt][i].S1 += te;
+              st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+              st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+              st[mt][0].mx = fmaxf(st[mt][0].mx, a);   // one running max per row
+            }
+        }
+      };
+      static_for<0, kBfNKB>(step);
+      if (two) static_for<kBfNKB, 2 * kBfNKB>(step);
+      if constexpr (NW == 8) __builtin_amdgcn_s_setprio(0);
+    }
+  };
+  bool scaled = false;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt) scaled = scaled || rsc[mt] != 1.0f;
+  if (HF && __builtin_amdgcn_ballot_w64(scaled) != 0)
+    stages(std::true_type{});
+  else
+    stages(std::false_type{});
   flush(o);
 }
 
