@@ -70,11 +70,13 @@ constexpr int kBfNKB = kBfNKQ + kBfNKY;
 constexpr size_t kBfTileU32 = (size_t)kBfNKB * 3 * 64 * 4;              // 18 KB per tile
 // The two-piece fp16 form of the same blocks (fp16 16x16x32 matrix
 // instructions): per tile, block and piece (hi, lo) 64 lanes x 8 fp16 of the
-// values scaled per model by a power of two, and per tile 48 floats: the 16
+// values scaled per model by a power of two, and per tile 64 floats: the 16
 // models' sigma^2, then the powers of two that undo the quadratic-form and
-// the prediction scales.
+// the prediction scales, then at kHfPlain 1.0 when every scale of the tile
+// is 1 (else 0.0), and zeros.
 constexpr size_t kHfTileU32 = (size_t)kBfNKB * 2 * 64 * 4;              // 12 KB per tile
-constexpr int kHfMeta = 48;
+constexpr int kHfMeta = 64;
+constexpr int kHfPlain = 48;
 // Piece formats of the contraction: float32 products, or the d = 16 features
 // and coefficients as three bf16 pieces (bf16 16x16x32 products), or as two
 // fp16 pieces of power-of-two scaled values (fp16 16x16x32 products).

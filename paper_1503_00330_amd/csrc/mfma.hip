@@ -240,9 +240,12 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
   }
   if (Wh == nullptr) return;
   // the two-piece fp16 form: each model's quadratic-form values and its
-  // prediction values scaled by powers of two 2^-eq, 2^-ey that bring the
-  // largest magnitude of each to [2^13, 2^14) (fp16 holds up to 65504; the
-  // padded models' -1e30 included), then split into hi + lo fp16 pieces
+  // prediction values, then split into hi + lo fp16 pieces.  A set whose
+  // largest magnitude m is 2^-2 <= m < 2^14 is taken as it is (the pieces of
+  // m then hold 22 bits, and every smaller value of the set is kept to
+  // within 2^-25 absolute, 2^-23 of m, the lo piece's subnormal step); any
+  // other set is scaled by the power of two 2^-e that brings m to [2^13,
+  // 2^14) (fp16 holds up to 65504; the padded models' -1e30 included).
   __shared__ int eq[16], ey[16];
   if (threadIdx.x < 32) {
     const int col = threadIdx.x & 15;
@@ -251,14 +254,22 @@ __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, Mf
     for (int k = 0; k < (quad ? g.KQ : g.KY); ++k) mx = fmaxf(mx, fabsf(value(quad ? k : 4 * g.KQB + k, col)));
     int ex = 0;
     if (mx > 0.0f) frexpf(mx, &ex);   // mx < 2^ex
-    (quad ? eq : ey)[col] = mx > 0.0f ? ex - 14 : 0;
+    (quad ? eq : ey)[col] = (ex > 14 || ex < -1) ? ex - 14 : 0;
   }
   __syncthreads();
-  if (threadIdx.x < 16) {
-    const int col = threadIdx.x;
-    hmeta[(size_t)tile * kHfMeta + col] = jcol[col] >= 0 ? ((const float *)m.sigma2)[jcol[col]] : 0.0f;
-    hmeta[(size_t)tile * kHfMeta + 16 + col] = ldexpf(1.0f, eq[col]);
-    hmeta[(size_t)tile * kHfMeta + 32 + col] = ldexpf(1.0f, ey[col]);
+  if (threadIdx.x < 64) {
+    const int col = threadIdx.x & 15, part = threadIdx.x >> 4;
+    float v = 0.0f;
+    if (part == 0) {
+      v = jcol[col] >= 0 ? ((const float *)m.sigma2)[jcol[col]] : 0.0f;
+    } else if (part < 3) {
+      v = ldexpf(1.0f, part == 1 ? eq[col] : ey[col]);
+    } else if (col == kHfPlain - 48) {
+      int any = 0;
+      for (int c = 0; c < 16; ++c) any |= eq[c] | ey[c];
+      v = any == 0 ? 1.0f : 0.0f;
+    }
+    hmeta[(size_t)tile * kHfMeta + threadIdx.x] = v;
   }
   uint16_t *dsth = (uint16_t *)(Wh + (size_t)tile * kHfTileU32);
   for (int e = threadIdx.x; e < kBfNKB * 64 * 8; e += blockDim.x) {
@@ -1148,12 +1159,13 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
       auto ldb = [&](auto Q) {
         constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
         const u32x4(*W)[64] = sm.ring[2 * (st_i & 1) + u];
-  #pragma unroll
+#pragma unroll
         for (int p = 0; p < NPC; ++p) wb[q % 3][p] = W[kb * NPC + p][lane];
       };
       ldb(std::integral_constant<int, 0>{});
       ldb(std::integral_constant<int, 1>{});
       f32x4 qa[RT], ya[RT], s2, qs, ys;
+      bool plain[2] = {false, false};
       auto step = [&](auto Q) {
         constexpr int q = decltype(Q)::value, u = q / kBfNKB, kb = q % kBfNKB;
         if constexpr (q + 2 < 2 * kBfNKB) {
@@ -1179,11 +1191,12 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
           }
           const f32x4 *meta = (const f32x4 *)&sm.ring[2 * (st_i & 1) + u][kSig][0];
           s2 = meta[lane >> 4];
-          if constexpr (HF) {   // the models' scales 2^eq, 2^ey
+          if constexpr (HF) {   // the models' scales 2^eq, 2^ey, and whether all are 1
             qs = meta[4 + (lane >> 4)];
             ys = meta[8 + (lane >> 4)];
+            plain[u] = __builtin_amdgcn_readfirstlane(__float_as_int(((const float *)meta)[kHfPlain])) != 0;
           }
-  #pragma unroll
+#pragma unroll
           for (int mt = 0; mt < RT; ++mt) {
             qa[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
             ya[mt] = qa[mt];
@@ -1195,32 +1208,45 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         // tiles the chains alternate): bf16 hh, hm, mh, hl, mm, lh; fp16 hh, hl, lh
         constexpr int NPR = HF ? 3 : 6;
         constexpr int PA[6] = {0, 0, 1, 0, 1, 2}, PB[6] = {0, 1, 0, 2, 1, 0};
-  #pragma unroll
+#pragma unroll
         for (int r = 0; r < NPR; ++r)
-  #pragma unroll
+#pragma unroll
           for (int mt = 0; mt < RT; ++mt) {
             f32x4 &x = kb < kBfNKQ ? qa[mt] : ya[mt];
             x = mm(w[PA[r]], Bs[mt][kb][PB[r]], x);
           }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (kb == kBfNKB - 1) {
-  #pragma unroll
-          for (int mt = 0; mt < RT; ++mt)
-  #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              // fp16 form: the model's and the row's powers of two undone (exact)
-              const float a = !HF ? qa[mt][i] : kRowScale ? qa[mt][i] * (qs[i] * rsc[mt]) : qa[mt][i] * qs[i];
-              const float dd = !HF ? ya[mt][i] : kRowScale ? ya[mt][i] * (ys[i] * rsc[mt]) : ya[mt][i] * ys[i];
-              // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
-              // largest term of at least 2^-100) need none of exp2f's denormal scaling
-              const float e = __builtin_amdgcn_exp2f(a);
-              const float te = e * dd;
-              st[mt][i].Z += e;
-              st[mt][i].S1 += te;
-              st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
-              st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
-              st[mt][0].mx = fmaxf(st[mt][0].mx, a);   // one running max per row
-            }
+          // SC: which powers of two the fp16 form undoes here (exact): none
+          // (bf16 pieces, or a tile whose models' scales are all 1 and rows
+          // without scale), the models', or the models' and the rows'
+          auto epilogue = [&](auto SC) {
+            constexpr int sc = decltype(SC)::value;
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float a = sc == 0 ? qa[mt][i] : sc == 1 ? qa[mt][i] * qs[i] : qa[mt][i] * (qs[i] * rsc[mt]);
+                const float dd = sc == 0 ? ya[mt][i] : sc == 1 ? ya[mt][i] * ys[i] : ya[mt][i] * (ys[i] * rsc[mt]);
+                // bare v_exp_f32: arguments below -126 (weights under 2^-126 next to a
+                // largest term of at least 2^-100) need none of exp2f's denormal scaling
+                const float e = __builtin_amdgcn_exp2f(a);
+                const float te = e * dd;
+                st[mt][i].Z += e;
+                st[mt][i].S1 += te;
+                st[mt][i].S2 = fmaf(te, dd, st[mt][i].S2);
+                st[mt][i].S3 = fmaf(e, s2[i], st[mt][i].S3);
+                st[mt][0].mx = fmaxf(st[mt][0].mx, a);   // one running max per row
+              }
+          };
+          if constexpr (!HF)
+            epilogue(std::integral_constant<int, 0>{});
+          else if constexpr (kRowScale)
+            epilogue(std::integral_constant<int, 2>{});
+          else if (plain[u])
+            epilogue(std::integral_constant<int, 0>{});
+          else
+            epilogue(std::integral_constant<int, 1>{});
         }
       };
       static_for<0, kBfNKB>(step);
