@@ -330,7 +330,7 @@ __device__ __forceinline__ Acc acc_sum(const Acc &a, const Acc &b) {
 // the workgroup stages each model tile once in LDS (ring, three tiles deep)
 // instead of every wave streaming its own range, and each wave's sums are
 // final (NPART = 1).  The samples' pieces are built in registers by their
-// wave (no A).  The fp16 form has this launch only.
+// wave (no A).
 template <int D, int MT, int NW, int PF = 0>
 struct MixSmem {
   static constexpr bool BF = PF != kPfF32;
