@@ -248,6 +248,36 @@ def test_rollout_loadings_differ_from_directions(variant, split, spw):
     assert nrel(cost, ref) <= 1e-4
 
 
+@pytest.mark.parametrize("variant,spw,split,waves", [(HF2, 0, 0, 0), (HF2, 16, 1, 8), (HF2, 32, 1, 4), (HF2, 128, 1, 8),
+                                                     (HF2, 128, 1, 4), (BF3, 128, 1, 8), (pi.PI_VARIANT_MFMA, 0, 0, 0),
+                                                     (pi.PI_VARIANT_DIRECT, 0, 0, 0)])
+@pytest.mark.parametrize("far", [False, True])
+def test_f16x2_power_of_two_scales(variant, spw, split, waves, far):
+    # The fp16 form's powers of two.  Near: every third model's metric scaled
+    # by 3000, so that its quadratic-form values pass 2^14 and its tile runs
+    # the epilogue with the models' scales (the other models of those tiles
+    # keep scale 1 and carry the weight).  Far: the plant starts 200 m out and
+    # each output's first model is centred there, so that every row's
+    # features z_a z_b pass 2^14 (row scales) and the models that carry the
+    # weight have scaled values (c^T D c past 2^14).  The other contractions
+    # run the same instances for comparison.
+    prob, model = synth.tiny_problem(23, dyn=DYN_QUAD12, L=[20, 17, 33, 16, 1, 40], R=4, K=37, T=9, M=1,
+                                     dtype=F32, n_obs=6)
+    if far:   # goal and obstacles moved with the plant: costs of the dynamics, not of the offset
+        prob.x0[:3] += np.float32(200.0)
+        prob.goal[:3] += prob.goal.dtype.type(200.0)
+        prob.obs[:, :2] += prob.obs.dtype.type(200.0)
+        model.centre[model.L_off[:-1], :3] += np.float32(200.0)
+    else:
+        model.metric[::3] *= np.float32(3000.0)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_samples=spw, tile_split=split, tile_waves=waves)
+    cost = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
+    ref = oracle.rollout_cost(prob, model)
+    r, _ = cost_check(cost, ref, prob, 1e-4)
+    print("f16x2 scales (far %s, %s): max S rel %.2e" % (far, (variant, spw, split, waves), r))
+    assert nrel(cost, ref) <= 1e-4
+
+
 @pytest.mark.parametrize("dtype,split", [(F32, 1), (F32, 2), (F64, 0)])
 def test_rollout_pointmass(dtype, split):
     prob, model = synth.tiny_problem(12, dyn=DYN_POINTMASS2D, L=[9, 23], R=2, K=70, T=15, M=2,
