@@ -1175,8 +1175,10 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
         if constexpr (kb == 0) {
           // the two waves of a SIMD (w and w + 4 of 8) take turns leading the
           // matrix pipe, one tile each per stage: left to age order, the older
-          // wave would finish the stage first and the younger run alone
-          if constexpr (NW == 8) {
+          // wave would finish the stage first and the younger run alone (the
+          // bf16 form; the fp16 form, half the products per tile, runs faster
+          // in age order)
+          if constexpr (NW == 8 && !HF) {
             if ((wave >= 4) == (u == 0))
               __builtin_amdgcn_s_setprio(1);
             else
@@ -1251,7 +1253,7 @@ __device__ __forceinline__ void mixture_tiles_sh(const MfmaModel &md, MixSmem<D,
       };
       static_for<0, kBfNKB>(step);
       if (two) static_for<kBfNKB, 2 * kBfNKB>(step);
-      if constexpr (NW == 8) __builtin_amdgcn_s_setprio(0);
+      if constexpr (NW == 8 && !HF) __builtin_amdgcn_s_setprio(0);
     }
   };
   bool scaled = false;
