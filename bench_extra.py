@@ -238,6 +238,15 @@ def w_adjoint(args):
     # recompute, the workspace of every step
     pi.rollout_adjoint(dp, dm, ckpt_every=prob.T)
     tw = timed(lambda: pi.rollout_adjoint(dp, dm, ckpt_every=prob.T), args.steps or 3, stream)
+    # the forward and the segment recomputes in the two-piece fp16 contraction
+    # (the reverse sweep and the parameter pass stay float32), against the
+    # plain forward in the same contraction
+    dph = pi.DeviceProblem(prob, variant=pi.PI_VARIANT_MFMA_F16X2)
+    pi.rollout_cost(dph, dm, out=cost)
+    pi.rollout_adjoint(dph, dm, ckpt_every=extra["ckpt"])
+    torch.cuda.synchronize()
+    tfh = timed(lambda: pi.rollout_cost(dph, dm, out=cost), args.steps or 3, stream)
+    tah = timed(lambda: pi.rollout_adjoint(dph, dm, ckpt_every=extra["ckpt"]), args.steps or 3, stream)
     ss = prob.K * prob.T
     d = model.d
     f_fwd = flops_per_sample_step(model) * ss
@@ -258,6 +267,9 @@ def w_adjoint(args):
             "fused_rollout_steps_per_s": ss / (float(np.median(ta)) * 1e-3),
             "forward_tflops": f_fwd / (float(np.median(tf)) * 1e-3) / 1e12,
             "fused_algorithmic_tflops": (f_fwd + f_adj) / (float(np.median(ta)) * 1e-3) / 1e12,
+            "f16x2_forward": {"forward_ms": float(np.median(tfh)), "fused_forward_adjoint_ms": float(np.median(tah)),
+                              "ratio": float(np.median(tah) / np.median(tfh)),
+                              "fused_vs_float32_fused": float(np.median(tah) / np.median(ta))},
             "dtype": "f32"}
 
 

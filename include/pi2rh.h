@@ -291,8 +291,13 @@ pi_status pi_rh_shift(const pi_problem *p, const pi_lwpr *m, void *x0, void *u_n
  * problems whose model has a matrix-core form (see PI_VARIANT_MFMA; variant
  * not PI_VARIANT_DIRECT) run the forward, the recompute and the reverse sweep
  * on the matrix cores and keep per-step records for one segment only; the
- * direct kernels (float64, PI_VARIANT_DIRECT) keep them for every step.  The
- * indicator obstacle term has zero derivative almost everywhere.
+ * direct kernels (float64, PI_VARIANT_DIRECT) keep them for every step.
+ * With PI_VARIANT_MFMA_BF16X3 or PI_VARIANT_MFMA_F16X2 (the float32 12-state
+ * quadrotor with d = 16; PI_ERR_UNSUPPORTED otherwise) the forward and the
+ * segment recomputes run that contraction, the reverse sweep and the
+ * parameter pass the float32 one, with the forward's traced anchors and
+ * normalisers.  The indicator obstacle term has zero derivative almost
+ * everywhere.
  * (PI_DYN_POINTMASS2D and PI_DYN_QUAD12 without ctrl_cost;
  * PI_ERR_UNSUPPORTED otherwise.)                                             */
 size_t pi_adjoint_workspace_bytes(const pi_problem *p, const pi_lwpr *m, int32_t ckpt_every);

@@ -605,7 +605,7 @@ size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d
 template <typename Real, int DYN>
 static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Real *x0, const Real *u_nom,
                             const uint32_t *iter, int ckpt, const double *gJ, double *J, Real *gu, Real *gc,
-                            Real *gD, void *ws, const MfmaLayout *ml, hipStream_t s) {
+                            Real *gD, void *ws, const MfmaLayout *ml, int pf, hipStream_t s) {
   using G = AdjGeo<Real, DYN>;
   const int64_t S = (int64_t)p.K * p.Ms;
   const bool mfma = ml != nullptr;
@@ -660,7 +660,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
         fa.trace = a.seg;
         fa.trace_T = ckpt;
       }
-      e = launch_rollout_mfma(fa, m, *ml, mbase, spw, 4, false, s);
+      e = launch_rollout_mfma(fa, m, *ml, mbase, spw, 4, pf, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(adj_jsum_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, p.T,
                          (const float *)cost, a.jsum);
@@ -676,7 +676,7 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
           ra.xstart = a.ckpt_buf;
           ra.trace = a.seg;
           ra.trace_T = ckpt;
-          e = launch_rollout_mfma(ra, m, *ml, mbase, spw, 4, false, s);
+          e = launch_rollout_mfma(ra, m, *ml, mbase, spw, 4, pf, s);
           if (e != hipSuccess) break;
         }
         e = launch_adj_reverse_mfma(p, u_nom, iter, *ml, mbase, rfold, a.seg, ckpt, tb, te, xbar, a.recs, s);
@@ -711,21 +711,21 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
 
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
                           const uint32_t *iter, int ckpt, const double *gJ, double *J, void *gu, void *gc,
-                          void *gD, void *ws, const MfmaLayout *ml, hipStream_t s) {
+                          void *gD, void *ws, const MfmaLayout *ml, int pf, hipStream_t s) {
   if (dtype == PI_F64) {
     const ProbDev<double> &p = *(const ProbDev<double> *)pargs;
     if (p.dyn == kDynPointMass2D)
       return adjoint_t<double, kDynPointMass2D>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, gJ,
-                                                J, (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
+                                                J, (double *)gu, (double *)gc, (double *)gD, ws, nullptr, 0, s);
     return adjoint_t<double, kDynQuad12>(p, m, (const double *)x0, (const double *)u_nom, iter, ckpt, gJ, J,
-                                         (double *)gu, (double *)gc, (double *)gD, ws, nullptr, s);
+                                         (double *)gu, (double *)gc, (double *)gD, ws, nullptr, 0, s);
   }
   const ProbDev<float> &p = *(const ProbDev<float> *)pargs;
   if (p.dyn == kDynPointMass2D)
     return adjoint_t<float, kDynPointMass2D>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, gJ, J,
-                                             (float *)gu, (float *)gc, (float *)gD, ws, ml, s);
+                                             (float *)gu, (float *)gc, (float *)gD, ws, ml, 0, s);
   return adjoint_t<float, kDynQuad12>(p, m, (const float *)x0, (const float *)u_nom, iter, ckpt, gJ, J,
-                                      (float *)gu, (float *)gc, (float *)gD, ws, ml, s);
+                                      (float *)gu, (float *)gc, (float *)gD, ws, ml, pf, s);
 }
 
 }  // namespace pi2rh

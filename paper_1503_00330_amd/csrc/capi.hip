@@ -400,6 +400,9 @@ pi_status check_adjoint(const pi_problem *p, const pi_lwpr *m, int32_t ckpt_ever
   if (ckpt_every < 0) return fail(PI_ERR_VALUE, "ckpt_every=%d must be >= 0", ckpt_every);
   if ((int64_t)p->K * (p->M > 0 ? p->M : 1) * p->T > ((int64_t)1 << 36))
     return fail(PI_ERR_SHAPE, "K*max(M,1)*T too large for the adjoint records");
+  if (variant_pf(p->variant) != kPfF32 && (p->dtype != PI_F32 || p->dyn != PI_DYN_QUAD12 || !bf_model_ok(m)))
+    return fail(PI_ERR_UNSUPPORTED, "the adjoint's %s forward needs the float32 12-state quadrotor (d = 16) and "
+                                    "pieces under 2 GiB", p->variant == PI_VARIANT_MFMA_F16X2 ? "f16x2" : "bf16x3");
   *ckpt = ckpt_every == 0 ? adjoint_default_ckpt(p->T) : std::min<int>(ckpt_every, p->T);
   return PI_OK;
 }
@@ -849,12 +852,13 @@ pi_status pi_rollout_adjoint(const pi_problem *p, const pi_lwpr *m, const void *
   if (p->dtype == PI_F64) {
     const ProbDev<double> d = prob_dev<double>(p);
     e = launch_adjoint(PI_F64, &d, a, x0, u_nom, iter, ckpt, (const double *)gJ, (double *)J, g_u_nom, g_centre,
-                       g_metric, ws, nullptr, s);
+                       g_metric, ws, nullptr, kPfF32, s);
   } else {
     const ProbDev<float> d = prob_dev<float>(p);
     const MfmaLayout l = mfma_layout(m->d, m->n_out, m->L_off);
+    const bool mf = adjoint_mfma_bytes(p, m) != 0;
     e = launch_adjoint(PI_F32, &d, a, x0, u_nom, iter, ckpt, (const double *)gJ, (double *)J, g_u_nom, g_centre,
-                       g_metric, ws, adjoint_mfma_bytes(p, m) ? &l : nullptr, s);
+                       g_metric, ws, mf ? &l : nullptr, mf ? variant_pf(p->variant) : kPfF32, s);
   }
   return launched(e, "pi_rollout_adjoint");
 }

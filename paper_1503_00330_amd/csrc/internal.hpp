@@ -234,10 +234,12 @@ hipError_t launch_adj_param_mfma(const MfmaLayout &l, const void *base, const fl
 // segment by segment; 0: the direct kernels.  Both checkpoint the states
 // every `ckpt` steps and recompute each segment.
 size_t adjoint_ws_bytes(int dtype, int dyn, int K, int M, int T, int Ltot, int d, int ckpt, size_t mfma_bytes);
-// gJ (dev, one double, nullable = 1): seed that scales every gradient.
+// gJ (dev, one double, nullable = 1): seed that scales every gradient.  pf:
+// the piece format of the matrix-core forward and segment recomputes (the
+// reverse sweep and the parameter pass contract in float32).
 hipError_t launch_adjoint(int dtype, const void *pargs, const ModelArgs &m, const void *x0, const void *u_nom,
                           const uint32_t *iter, int ckpt, const double *gJ, double *J, void *gu, void *gc,
-                          void *gD, void *ws, const MfmaLayout *ml, hipStream_t s);
+                          void *gD, void *ws, const MfmaLayout *ml, int pf, hipStream_t s);
 
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t N,
                          hipStream_t s);

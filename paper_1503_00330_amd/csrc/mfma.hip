@@ -122,6 +122,7 @@ __device__ __forceinline__ void f16_split2(float v, uint16_t *pc) {
 // PLS map b and y0 = beta0 - b.c) into LDS; phase 2: every lane writes whole
 // fragments, coalesced.
 constexpr int kFoldThreads = 256;
+static_assert(kFoldThreads >= kHfMeta, "one fold thread per per-tile value of the fp16 form");
 
 __global__ void __launch_bounds__(kFoldThreads) fold_mfma_kernel(ModelArgs m, MfmaLayout l,
                                                                  float *__restrict__ W,

@@ -217,6 +217,22 @@ class TestValidation:
         ps.tile_samples = 128
         assert _rollout(ps, ms) == 6 and "device" in pi.last_error()   # valid: only the device is missing
 
+    def test_adjoint_pieces_forward_needs_the_quadrotor(self):
+        # the adjoint runs its forward in the requested pieces form only for
+        # the float32 12-state quadrotor with d = 16
+        lib = pi.load()
+
+        def adjoint(ps, ms):
+            return lib.pi_rollout_adjoint(C.byref(ps), C.byref(ms), FAKE, FAKE, FAKE, 0, None, FAKE, FAKE, FAKE,
+                                          FAKE, FAKE, 1 << 30, None)
+        for v in (pi.PI_VARIANT_MFMA_F16X2, pi.PI_VARIANT_MFMA_BF16X3):
+            ps, ms = _structs(dyn=synth.DYN_POINTMASS2D)
+            ps.variant = v
+            assert adjoint(ps, ms) == 7 and "forward needs the float32 12-state quadrotor" in pi.last_error()
+            ps, ms = _structs()
+            ps.variant = v
+            assert adjoint(ps, ms) == 6 and "device" in pi.last_error()   # valid: only the device is missing
+
     def test_f16x2_tile_limits(self):
         # the two-piece fp16 form: the bf16 form's launch shapes
         for fields, code in ((dict(tile_samples=32, tile_waves=8), 7), (dict(tile_samples=129), 3),

@@ -77,6 +77,21 @@ def test_adjoint_fp32_matrix_core_checkpoints(ckpt):
         assert nrel(g.cpu().numpy(), o) <= 1e-4
 
 
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_MFMA_F16X2, pi.PI_VARIANT_MFMA_BF16X3])
+@pytest.mark.parametrize("M,ckpt", [(0, 0), (1, 5), (3, 16), (1, 1)])
+def test_adjoint_pieces_forward_matches_oracle(variant, M, ckpt):
+    # the forward and the segment recomputes in the fp16 (bf16) pieces, the
+    # reverse sweep and the parameter pass in float32 with the forward's
+    # traced anchors and normalisers
+    prob, model = _case(DYN_QUAD12, M, np.float32, K=40, T=16)
+    dp, dm = pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model)
+    J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=ckpt)
+    oJ, ogu, ogc, ogD = oracle.adjoint(prob, model)
+    assert abs(J.item() - oJ) <= 1e-5 * abs(oJ)
+    for g, o in ((gu, ogu), (gc, ogc), (gD, ogD)):
+        assert nrel(g.cpu().numpy(), o) <= 1e-4
+
+
 def test_adjoint_seed_scales_the_gradients():
     # gJ seeds the reverse pass: gradients of gJ * J, J itself unscaled
     prob, model = _case(DYN_QUAD12, 1, np.float64, K=12, T=9)
@@ -238,7 +253,7 @@ def test_adjoint_full_size_fp32():
     assert np.percentile(e, 90) <= 10 * np.percentile(env, 90)
 
 
-@pytest.mark.parametrize("variant", [pi.PI_VARIANT_AUTO, pi.PI_VARIANT_DIRECT])
+@pytest.mark.parametrize("variant", [pi.PI_VARIANT_AUTO, pi.PI_VARIANT_DIRECT, pi.PI_VARIANT_MFMA_F16X2])
 def test_adjoint_fp32_gradients_over_200_steps(variant):
     # the adjoint workload's batch over 200 steps, where trajectories stay near
     # the models' support: FP32 gradients (matrix-core and direct) against the
