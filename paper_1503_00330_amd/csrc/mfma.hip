@@ -688,6 +688,9 @@ __device__ __forceinline__ void mixture_tiles(const MfmaModel &md, MixSmem<D, MT
 // tile's pieces (18 KB) are held in registers once: as each block's products
 // issue, the registers of that block take the next tile's block (loads one
 // tile ahead).  The softmax epilogue and the flush are the float32 form's.
+// The two-piece fp16 form runs the same loop with three fp16 instructions per
+// block (hi hi, hi lo, lo hi of scaled values; 12 KB of pieces per tile) and
+// undoes the models' and rows' powers of two in the epilogue.
 template <int D, int MT, int NW, int PF>
 __device__ __forceinline__ void mixture_tiles_bf(const MfmaModel &md, MixSmem<D, MT, NW, PF> &sm, int T0, int T1) {
   static_assert(PF != kPfF32 && D == kBfD && (MT == 1 || MT == 2), "pieces forms: d = 16, one or two row tiles");

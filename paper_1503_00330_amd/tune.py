@@ -121,10 +121,10 @@ def _variants_for(prob, models) -> Tuple[int, ...]:
 
 def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
     """The candidates the library accepts for this problem: 8 waves only on the
-    12-state quadrotor with tiles of <= 16 samples (or the bf16 form's
+    12-state quadrotor with tiles of <= 16 samples (or the pieces forms'
     128-sample shared tiles), pairs of workgroups only for tiles of <= 16
-    samples (float32), the bf16 form as _variants_for says (without a model:
-    only the float32 products)."""
+    samples in float32, the pieces forms as _variants_for says (without a
+    model: only the float32 products)."""
     from . import PI_DYN_QUAD12
     import torch
     variants = _variants_for(prob, [model]) if model is not None else (_MF,)
