@@ -123,7 +123,7 @@ def candidates_for(prob, model=None) -> Tuple[Tuple[int, int, int, int], ...]:
     """The candidates the library accepts for this problem: 8 waves only on the
     12-state quadrotor with tiles of <= 16 samples (or the pieces forms'
     128-sample shared tiles), pairs of workgroups only for tiles of <= 16
-    samples in float32, the pieces forms as _variants_for says (without a
+    samples of float32 problems, the pieces forms as _variants_for says (without a
     model: only the float32 products)."""
     from . import PI_DYN_QUAD12
     import torch
