@@ -22,7 +22,10 @@
  *    PI_ERR_DEVICE.  No C++ exception crosses this interface.
  *  - `dtype` of a problem and of its model must agree.  PI_F32 computes in
  *    single precision (the update's normalisation and weighted sums are
- *    always double); PI_F64 runs the same method entirely in double.
+ *    always double; the pieces variants, PI_VARIANT_MFMA_BF16X3 and
+ *    PI_VARIANT_MFMA_F16X2, form the mixture contraction's float32 products
+ *    from 16-bit pieces on the matrix cores, to float32 accuracy); PI_F64
+ *    runs the same method entirely in double.
  *  - Non-finite inputs propagate (NaN/Inf in x0, u_nom or a model parameter
  *    reach the affected costs and updates as they would in exact IEEE
  *    arithmetic).  The one clamp: the spread term sum_j w_j (y_j - mean)^2 of
