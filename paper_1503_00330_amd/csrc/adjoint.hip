@@ -646,7 +646,9 @@ static hipError_t adjoint_t(const ProbDev<Real> &p, const ModelArgs &m, const Re
       float *cost = (float *)w;
       w += align_up((size_t)S * p.T * 4, 256);
       float *xbar = (float *)w;
-      const int spw = S >= 4096 ? 16 : 8;
+      // the pieces forms' forward takes two row tiles per wave (each model
+      // piece loaded serves both) once the tiles still cover the chip
+      const int spw = S >= 4096 ? (pf != kPfF32 ? 32 : 16) : 8;
       e = launch_fold_mfma(PI_F32, m, *ml, mbase, s);
       if (e == hipSuccess) e = launch_adj_rfold(m, *ml, a.model, G::RS, rfold, s);
       if (e != hipSuccess) return e;
