@@ -78,12 +78,13 @@ def test_adjoint_fp32_matrix_core_checkpoints(ckpt):
 
 
 @pytest.mark.parametrize("variant", [pi.PI_VARIANT_MFMA_F16X2, pi.PI_VARIANT_MFMA_BF16X3])
-@pytest.mark.parametrize("M,ckpt", [(0, 0), (1, 5), (3, 16), (1, 1)])
-def test_adjoint_pieces_forward_matches_oracle(variant, M, ckpt):
+@pytest.mark.parametrize("M,ckpt,K,T", [(0, 0, 40, 16), (1, 5, 40, 16), (3, 16, 40, 16), (1, 1, 40, 16),
+                                        (1, 3, 4096, 8)])
+def test_adjoint_pieces_forward_matches_oracle(variant, M, ckpt, K, T):
     # the forward and the segment recomputes in the fp16 (bf16) pieces, the
     # reverse sweep and the parameter pass in float32 with the forward's
-    # traced anchors and normalisers
-    prob, model = _case(DYN_QUAD12, M, np.float32, K=40, T=16)
+    # traced anchors and normalisers (4096 rollouts: the 32-row tiles)
+    prob, model = _case(DYN_QUAD12, M, np.float32, K=K, T=T)
     dp, dm = pi.DeviceProblem(prob, variant=variant), pi.DeviceModel(model)
     J, gu, gc, gD = pi.rollout_adjoint(dp, dm, ckpt_every=ckpt)
     oJ, ogu, ogc, ogD = oracle.adjoint(prob, model)
