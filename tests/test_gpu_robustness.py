@@ -79,15 +79,19 @@ def _nonfinite_match(g, o, tol):
 
 
 INJECT = ["x0_nan", "u_nan", "u_inf", "centre_nan"]
-# (dtype, variant, split): matrix-core paired and single, direct float32, float64
-FORMS = [(F32, pi.PI_VARIANT_MFMA, 2), (F32, pi.PI_VARIANT_MFMA, 1), (F32, pi.PI_VARIANT_DIRECT, 0),
-         (F64, pi.PI_VARIANT_DIRECT, 0)]
+# (dtype, variant, split, samples per tile): matrix-core paired and single,
+# the pieces forms (fp16 pairs and shared tile, bf16 shared tile), direct
+# float32, float64
+FORMS = [(F32, pi.PI_VARIANT_MFMA, 2, 0), (F32, pi.PI_VARIANT_MFMA, 1, 0),
+         (F32, pi.PI_VARIANT_MFMA_F16X2, 2, 0), (F32, pi.PI_VARIANT_MFMA_F16X2, 1, 128),
+         (F32, pi.PI_VARIANT_MFMA_BF16X3, 1, 128), (F32, pi.PI_VARIANT_DIRECT, 0, 0),
+         (F64, pi.PI_VARIANT_DIRECT, 0, 0)]
 
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("inject", INJECT)
 def test_nonfinite_inputs_propagate_like_the_oracle(inject, form):
-    dtype, variant, split = form
+    dtype, variant, split, spw = form
     prob, model = synth.tiny_problem(31, dyn=DYN_QUAD12, L=[17, 12, 20, 9, 16, 11], R=3, K=40, T=23,
                                      M=1, dtype=dtype, n_obs=4)
     prob.u_nom = np.random.default_rng(2).normal(0.0, 0.2, prob.u_nom.shape).astype(dtype)
@@ -99,7 +103,7 @@ def test_nonfinite_inputs_propagate_like_the_oracle(inject, form):
         prob.u_nom[14, 3] = np.inf
     else:
         model.centre[model.L_off[2] + 3, 5] = np.nan
-    dp = pi.DeviceProblem(prob, variant=variant, tile_split=split)
+    dp = pi.DeviceProblem(prob, variant=variant, tile_split=split, tile_samples=spw)
     got = pi.rollout_cost(dp, pi.DeviceModel(model)).cpu().numpy()
     ref = oracle.rollout_cost(prob, model)
     assert not np.isfinite(ref).all()
