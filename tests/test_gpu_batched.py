@@ -116,7 +116,7 @@ def _plain_control_step(dp, dm):
     return cost
 
 
-@pytest.mark.parametrize("variant", [0, BF3])
+@pytest.mark.parametrize("variant", [0, BF3, HF2])
 def test_batched_tiles_per_problem(variant):
     # every problem keeps its own tile size (8, 16, 32 and the default) in one launch
     host, dps, dms = _batch(variant=variant)
@@ -125,7 +125,17 @@ def test_batched_tiles_per_problem(variant):
     br = pi.BatchedRollout(dps, dms)
     costs = [c.clone() for c in br.run()]
     for b, (dp, dm) in enumerate(zip(dps, dms)):
-        assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
+        if variant != HF2:
+            assert torch.equal(pi.rollout_cost(dp, dm), costs[b]), b
+            continue
+        # the fp16 form's 8- and 16-row problems run on the batch's 32-row
+        # instantiation, whose scale products the compiler rounds in another
+        # order than the 16-row one: not bitwise, so against the oracle
+        prob, model = host[b]
+        got, ref = costs[b].double().cpu().numpy(), oracle.rollout_cost(prob, model)
+        flip = np.abs(got - ref).max(1) > 0.25 * prob.dt * prob.obs_penalty
+        r = np.abs(got.sum(1) - ref.sum(1)) / np.abs(ref.sum(1))
+        assert flip.sum() <= 1 and r[~flip].max(initial=0.0) <= 1e-4, (b, r.max())
 
 
 @pytest.mark.parametrize("prefold,launch", [(False, (0, 0, 0)), (True, (0, 0, 0)), (False, (128, 8, BF3)),

@@ -58,13 +58,14 @@ BF3 = pi.PI_VARIANT_MFMA_BF16X3
 @pytest.mark.parametrize("cfg,launch", [(1, {}), (2, {}),
                                         (1, dict(variant=BF3, tile_waves=4, tile_split=2)),
                                         (2, dict(variant=BF3, tile_samples=128, tile_waves=8)),
+                                        (1, dict(variant=pi.PI_VARIANT_MFMA_F16X2, tile_waves=4, tile_split=2)),
                                         (2, dict(variant=pi.PI_VARIANT_MFMA_F16X2))])
 def test_graph_replay_equals_eager_full_size(cfg, launch):
     # the benchmarked launches inside captured control steps: 2048 x 100 on
     # paired workgroups, 65536 x 200 with two workgroups per compute unit (the
     # library's defaults), and the launches the autotuner picks there: the
-    # bf16 pieces on paired 4-wave workgroups, and the 128-rollout shared tile
-    # on 8 waves in bf16 or fp16 pieces
+    # bf16 or fp16 pieces on paired 4-wave workgroups, and the 128-rollout
+    # shared tile on 8 waves in bf16 or fp16 pieces
     def ctrl(graph):
         prob, model, _ = synth.config(cfg)
         return RHController(pi.DeviceProblem(prob, **launch), pi.DeviceModel(model), iterations=1, graph=graph)
